@@ -1,0 +1,225 @@
+/*
+ * neb.h -- C ABI of the Next Event Backtracking hot path on MI355X (gfx950).
+ *
+ * The operation follows the paper's statement of the problem (Jendersie,
+ * "Next Event Backtracking", arXiv 1909.00573, Sec. 3): scene and lights
+ * in, radiance image and NEE-vertex densities out.  One call of
+ * neb_render runs the three passes of Sec. 3 once per iteration: view
+ * paths with stored NEE vertices and emitter hits (Sec. 3.1), density,
+ * NEE, photons traced from every NEE vertex and merged with view vertices
+ * around each photon hit (Sec. 3.2), and weighted self emission (Sec. 3.3),
+ * with the balance-heuristic weights of Sec. 4.  The density comes from the
+ * lock-free sparse octree of Sec. 5 / Appendix B, whose surface is exported
+ * separately (neb_octree_*).
+ *
+ * Conventions shared by every call:
+ *  - every call returns neb_status; NEB_OK is 0.  Nothing throws or aborts
+ *    across the ABI.  neb_last_error() returns a message for the last
+ *    failure of the calling thread.
+ *  - pointers marked "host" are read or written synchronously before the
+ *    call returns; pointers marked "device" must be device memory of the
+ *    current HIP device and are read or written in stream order on `stream`
+ *    (a hipStream_t, NULL = the null stream).
+ *  - the caller owns every buffer it passes in; the library owns everything
+ *    it allocates internally and frees it in the matching destroy call.
+ *  - a context or octree is not thread safe.
+ *  - float layouts are little-endian, xyz (or rgb) interleaved.
+ */
+#ifndef NEB_H
+#define NEB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NEB_OK = 0,
+    NEB_ERR_INVALID_ARG = -1,   /* null pointer, size <= 0 or over a cap, NaN input */
+    NEB_ERR_OUT_OF_MEMORY = -2, /* a device or host allocation failed */
+    NEB_ERR_CAPACITY = -3,      /* a fixed pool is too small for the request */
+    NEB_ERR_DEVICE = -4,        /* a HIP runtime call failed */
+    NEB_ERR_STATE = -5          /* calls made in the wrong order */
+} neb_status;
+
+typedef struct neb_ctx_s* neb_ctx;
+typedef struct neb_octree_s* neb_octree;
+
+/* density providers for the flux conversion Phi = dE / rho (eq. flux) */
+enum {
+    NEB_DENSITY_OCTREE = 0,        /* one octree probe (Appendix B get_density) */
+    NEB_DENSITY_OCTREE_ROBUST = 1, /* median of five probes (Appendix B, default) */
+    NEB_DENSITY_ANALYTIC = 3       /* test hook: rho0 + w * primary-hit density of the camera */
+};
+
+/* neb_params.flags */
+enum {
+    NEB_FLAG_SINGLE_THREAD_OCTREE = 1, /* deposits by one GPU thread in (depth, pixel) order */
+    NEB_FLAG_RECORD_PATHS = 2,         /* record the first iteration's view-path vertices */
+    NEB_FLAG_NO_PHOTONS = 4            /* n_P = 0: path tracing with MIS over e and E only */
+};
+
+/* material types */
+enum { NEB_MAT_LAMBERT = 0, NEB_MAT_MIRROR = 1, NEB_MAT_DIELECTRIC = 2, NEB_MAT_GGX = 3 };
+
+typedef struct {
+    int32_t width, height;     /* image size in pixels, 1 .. 8192 */
+    int32_t max_path_len;      /* maximum path length in segments (camera = vertex 0), 1 .. 16 */
+    int32_t octree_capacity;   /* octree nodes; rounded up to 8n+1 (Appendix B initialize) */
+    float merge_radius;        /* r of the uniform merge kernel 1/(pi r^2), Sec. 3.2 */
+    uint32_t seed, scene_id;   /* Philox-4x32-10 key (seed, scene_id) */
+    int32_t density_mode;      /* NEB_DENSITY_* */
+    float analytic_rho0;       /* NEB_DENSITY_ANALYTIC: constant term (per unit area, per iteration) */
+    float analytic_cam_weight; /* NEB_DENSITY_ANALYTIC: weight of the camera's primary-hit density */
+    int32_t flags;             /* NEB_FLAG_* */
+} neb_params;
+
+/* One material per entry; emission is radiance leaving the front side of
+ * the triangle (the side its counter-clockwise normal points to). */
+typedef struct {
+    int32_t type;        /* NEB_MAT_* */
+    float albedo[3];     /* reflectance (Lambert, mirror, GGX) or transmittance tint (dielectric) */
+    float ior;           /* dielectric index of refraction (outside is 1) */
+    float alpha;         /* GGX roughness parameter, used as alpha directly */
+    float emission[3];   /* radiance; an emitter with zero albedo ends paths */
+} neb_material;
+
+typedef struct {
+    float pos[3];
+    float power[3];      /* watts; isotropic point light of intensity power / (4 pi) */
+} neb_point_light;
+
+typedef struct {
+    float eye[3], look_at[3], up[3];
+    float vfov_deg;      /* vertical field of view of the pinhole camera */
+} neb_camera;
+
+typedef struct {
+    int64_t iterations, paths, vertices, photons, photon_segments, merges, nee_visible, events, rays;
+    /* octree: capacity, nodes allocated, depth, split failures, conserved ledger S
+     * (sum of leaf counts - 4 * sum of the iteration of every allocated block),
+     * counted deposits D (S == D whenever no deposit was lost), rejected
+     * out-of-bounds deposits, deposits that gave up waiting for a split */
+    int64_t oct_capacity, oct_allocated, oct_depth, oct_overflow, oct_ledger, oct_deposits,
+        oct_rejected, oct_lost;
+} neb_stats;
+
+/* view-path record of the first rendered iteration, one per (pixel, depth) */
+typedef struct {
+    int32_t type;   /* 0 none, 1 scatter, 2 specular reflection, 3 refraction,
+                       4 path ended at this hit, 5 ray escaped at this depth */
+    int32_t mat, prim;
+    float pos[3];
+} neb_path_record;
+
+/* ---------------------------------------------------------------------- */
+/* rendering context                                                       */
+/* ---------------------------------------------------------------------- */
+
+/* Validates the parameters and allocates the per-iteration device pools
+ * (queues, NEE-vertex store, photon state, merge grid, images) on the
+ * current device.  NEB_ERR_INVALID_ARG on bad parameters,
+ * NEB_ERR_OUT_OF_MEMORY if the pools do not fit. */
+neb_status neb_create(const neb_params* params, neb_ctx* out);
+
+/* Deep-copies the scene (host arrays) into library-owned device memory,
+ * builds the BVH and the light table (emissive triangles and point lights,
+ * selected in proportion to power), and initialises the octree over the
+ * bounding box of the vertices (Appendix B initialize).  Clears the image
+ * and the iteration counter.  vertices: nv*3 floats; tris: nt*3 indices;
+ * tri_material: nt material indices; materials: nm entries; point_lights:
+ * npl entries (may be NULL when npl == 0); camera: one entry.
+ * NEB_ERR_INVALID_ARG on out-of-range indices, NaN coordinates, a flat
+ * bounding box or a scene without lights. */
+neb_status neb_set_scene(neb_ctx ctx, const float* vertices, int32_t nv, const int32_t* tris,
+                         const int32_t* tri_material, int32_t nt, const neb_material* materials,
+                         int32_t nm, const neb_point_light* point_lights, int32_t npl,
+                         const neb_camera* camera);
+
+/* Runs n_iterations progressive iterations (one sample per pixel each) on
+ * `stream`, continuing from the context's iteration counter; the octree
+ * integrates its counts over the iterations (Sec. 5.3, time integration).
+ * Returns after enqueueing; NEB_ERR_STATE without a scene. */
+neb_status neb_render(neb_ctx ctx, int32_t n_iterations, void* stream);
+
+/* Mean radiance over the rendered iterations, height*width*3 floats,
+ * row-major from the top-left pixel.  rgb is device memory if
+ * is_device_ptr, else host memory (then the call synchronises). */
+neb_status neb_get_image(neb_ctx ctx, float* rgb, int32_t is_device_ptr, void* stream);
+
+/* Mean radiance split by technique: random hits (e), NEE (E) and NEB photon
+ * merges (P), each height*width*3 floats; any pointer may be NULL. */
+neb_status neb_get_technique_images(neb_ctx ctx, float* e, float* E, float* P, int32_t is_device_ptr,
+                                    void* stream);
+
+/* Density of NEE vertices at n surface points from the context's octree in
+ * its current state (robust five-probe query; tangents from the normal).
+ * pos, nrm: n*3 floats; out: n floats; all device memory if is_device_ptr,
+ * else host memory. */
+neb_status neb_query_density(neb_ctx ctx, const float* pos, const float* nrm, int32_t n, float* out,
+                             int32_t is_device_ptr, void* stream);
+
+/* Counters accumulated since the scene was set (synchronises the context's
+ * last stream). */
+neb_status neb_get_stats(neb_ctx ctx, neb_stats* out);
+
+/* Copies the path records of the first rendered iteration to host memory:
+ * width*height*max_path_len records (pixel-major).  NEB_ERR_STATE unless the
+ * context was created with NEB_FLAG_RECORD_PATHS and has rendered. */
+neb_status neb_get_path_records(neb_ctx ctx, neb_path_record* out, int64_t n);
+
+/* Exports the context's octree node array (host, up to cap entries) and
+ * its info (see neb_octree_export). */
+neb_status neb_get_octree(neb_ctx ctx, int32_t* nodes, int32_t cap, int64_t info[8]);
+
+/* Clears the images, the statistics, the octree and the iteration counter. */
+neb_status neb_reset(neb_ctx ctx);
+
+void neb_destroy(neb_ctx ctx);
+const char* neb_status_string(neb_status s);
+const char* neb_last_error(void);
+
+/* ---------------------------------------------------------------------- */
+/* density octree (Sec. 5, Appendix B), batched and stream-ordered         */
+/* ---------------------------------------------------------------------- */
+
+/* Octree over [scene_min, scene_max] (host, 3 floats each; enlarged by 0.1 %
+ * per side as in Appendix B initialize) with `capacity` nodes rounded up to
+ * 8n+1.  The root starts as an empty leaf; iteration 1 is set. */
+neb_status neb_octree_create(const float scene_min[3], const float scene_max[3], int32_t capacity,
+                             neb_octree* out);
+
+/* Sets the iteration (Appendix B set_iteration): split threshold
+ * 4*min(iter,1000), density scale 1/min(iter,1000), filling stops after
+ * iteration 1000.  Iterations must not decrease (NEB_ERR_STATE) unless the
+ * counters were cleared. */
+neb_status neb_octree_set_iteration(neb_octree oct, int32_t iter);
+
+/* Deposits n points (device, n*3 floats) with lock-free counter
+ * increments, compare-and-swap counting and on-the-fly splits (Sec. 5.1,
+ * 5.2).  single_thread != 0 makes one GPU thread insert them in array
+ * order (deterministic; equals a sequential insertion). */
+neb_status neb_octree_increment(neb_octree oct, const float* pos, int32_t n, int32_t single_thread,
+                                void* stream);
+
+/* Densities rho = c / |cell cap tangent plane| (eq. octdensity, eq. area)
+ * at n points with normals (device, n*3 floats each) into out (device, n
+ * floats); robust != 0 selects the five-probe median of Appendix B. */
+neb_status neb_octree_density(neb_octree oct, const float* pos, const float* nrm, int32_t n,
+                              int32_t robust, float* out, void* stream);
+
+/* Zeroes every counter, keeps the child pointers (Appendix B clear_counters). */
+neb_status neb_octree_clear_counters(neb_octree oct, void* stream);
+
+/* Copies up to cap nodes to host memory (may be NULL) and fills info with:
+ * capacity, allocated nodes, depth, ledger S, deposits D, split failures,
+ * rejected deposits, lost deposits.  Synchronises `stream`. */
+neb_status neb_octree_export(neb_octree oct, int32_t* nodes, int32_t cap, int64_t info[8], void* stream);
+
+void neb_octree_destroy(neb_octree oct);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NEB_H */

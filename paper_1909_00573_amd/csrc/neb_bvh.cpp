@@ -1,0 +1,253 @@
+// Host BVH builder: binned SAH over triangle centroids, flattened into
+// 64-byte nodes that hold the boxes of both children (one node fetch tests
+// two boxes).  Subtrees deeper than kSahDepth switch to object-median
+// splits so that the depth stays below the device traversal stack.
+#include "neb_bvh.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace neb {
+
+namespace {
+
+struct Box {
+    float lo[3] = {INFINITY, INFINITY, INFINITY};
+    float hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    void grow(const float* p) {
+        for (int i = 0; i < 3; ++i) {
+            lo[i] = std::min(lo[i], p[i]);
+            hi[i] = std::max(hi[i], p[i]);
+        }
+    }
+    void grow(const Box& b) {
+        for (int i = 0; i < 3; ++i) {
+            lo[i] = std::min(lo[i], b.lo[i]);
+            hi[i] = std::max(hi[i], b.hi[i]);
+        }
+    }
+    float area() const {
+        float d[3];
+        for (int i = 0; i < 3; ++i) d[i] = std::max(0.0f, hi[i] - lo[i]);
+        return 2.0f * (d[0] * d[1] + d[1] * d[2] + d[0] * d[2]);
+    }
+};
+
+struct BuildNode {
+    Box box;
+    int child[2] = {-1, -1};  // internal: build-node indices
+    int first = 0, count = 0; // leaf: range in the prim index array
+};
+
+constexpr int kBins = 16;
+constexpr int kMaxLeaf = 4;
+constexpr int kSahDepth = 20;
+
+struct Builder {
+    std::vector<Box> pbox;
+    std::vector<float> cent;  // 3 per prim
+    std::vector<int> idx;
+    std::vector<BuildNode> nodes;
+    int max_depth = 0;
+
+    int make_leaf(int first, int count, const Box& b) {
+        BuildNode n;
+        n.box = b;
+        n.first = first;
+        n.count = count;
+        nodes.push_back(n);
+        return (int)nodes.size() - 1;
+    }
+
+    // returns build-node index
+    int build(int first, int count, int depth) {
+        Box b, cb;
+        for (int i = first; i < first + count; ++i) {
+            b.grow(pbox[idx[i]]);
+            cb.grow(&cent[3 * idx[i]]);
+        }
+        max_depth = std::max(max_depth, depth);
+        if (count <= 1) return make_leaf(first, count, b);
+        int axis = 0;
+        float ext[3];
+        for (int i = 0; i < 3; ++i) ext[i] = cb.hi[i] - cb.lo[i];
+        if (ext[1] > ext[axis]) axis = 1;
+        if (ext[2] > ext[axis]) axis = 2;
+        int mid = -1;
+        if (ext[axis] <= 0.0f) {
+            if (count <= kMaxLeaf) return make_leaf(first, count, b);
+            mid = first + count / 2;  // identical centroids: split the list
+        } else if (depth >= kSahDepth) {
+            if (count <= kMaxLeaf) return make_leaf(first, count, b);
+            mid = first + count / 2;
+            std::nth_element(idx.begin() + first, idx.begin() + mid, idx.begin() + first + count,
+                             [&](int a, int c) { return cent[3 * a + axis] < cent[3 * c + axis]; });
+        } else {
+            Box bb[kBins];
+            int bc[kBins] = {0};
+            float scale = kBins / ext[axis];
+            auto bin_of = [&](int p) {
+                int k = (int)((cent[3 * p + axis] - cb.lo[axis]) * scale);
+                return std::min(kBins - 1, std::max(0, k));
+            };
+            for (int i = first; i < first + count; ++i) {
+                int k = bin_of(idx[i]);
+                bc[k]++;
+                bb[k].grow(pbox[idx[i]]);
+            }
+            float right_area[kBins];
+            int right_cnt[kBins];
+            Box acc;
+            int n = 0;
+            for (int k = kBins - 1; k > 0; --k) {
+                acc.grow(bb[k]);
+                n += bc[k];
+                right_area[k] = acc.area();
+                right_cnt[k] = n;
+            }
+            Box lacc;
+            int ln = 0;
+            float best = INFINITY;
+            int best_k = -1;
+            for (int k = 1; k < kBins; ++k) {
+                lacc.grow(bb[k - 1]);
+                ln += bc[k - 1];
+                if (ln == 0 || right_cnt[k] == 0) continue;
+                float c = lacc.area() * ln + right_area[k] * right_cnt[k];
+                if (c < best) {
+                    best = c;
+                    best_k = k;
+                }
+            }
+            float leaf_cost = b.area() * count;
+            float split_cost = b.area() * 0.5f + best;  // traversal ~ half a triangle test
+            if (count <= kMaxLeaf && (best_k < 0 || split_cost >= leaf_cost)) return make_leaf(first, count, b);
+            if (best_k < 0) {
+                mid = first + count / 2;
+                std::nth_element(idx.begin() + first, idx.begin() + mid, idx.begin() + first + count,
+                                 [&](int a, int c) { return cent[3 * a + axis] < cent[3 * c + axis]; });
+            } else {
+                auto it = std::partition(idx.begin() + first, idx.begin() + first + count,
+                                         [&](int p) { return bin_of(p) < best_k; });
+                mid = (int)(it - idx.begin());
+                if (mid == first || mid == first + count) mid = first + count / 2;
+            }
+        }
+        int me = (int)nodes.size();
+        nodes.emplace_back();
+        nodes[me].box = b;
+        int l = build(first, mid - first, depth + 1);
+        int r = build(mid, first + count - mid, depth + 1);
+        nodes[me].child[0] = l;
+        nodes[me].child[1] = r;
+        return me;
+    }
+};
+
+void put_box(float* dst, const Box& b) {
+    dst[0] = b.lo[0];
+    dst[1] = b.lo[1];
+    dst[2] = b.lo[2];
+    dst[3] = b.hi[0];
+    dst[4] = b.hi[1];
+    dst[5] = b.hi[2];
+}
+
+}  // namespace
+
+bool build_bvh(const float* vertices, int32_t nv, const int32_t* tris, int32_t nt, BvhHost& out) {
+    (void)nv;
+    Builder B;
+    B.pbox.resize(nt);
+    B.cent.resize(3 * (size_t)nt);
+    B.idx.resize(nt);
+    for (int32_t t = 0; t < nt; ++t) {
+        for (int k = 0; k < 3; ++k) B.pbox[t].grow(vertices + 3 * (size_t)tris[3 * t + k]);
+        for (int i = 0; i < 3; ++i) B.cent[3 * t + i] = 0.5f * (B.pbox[t].lo[i] + B.pbox[t].hi[i]);
+        B.idx[t] = t;
+    }
+    B.nodes.reserve(2 * (size_t)nt);
+    int root = B.build(0, nt, 0);
+    out.max_depth = B.max_depth + 1;
+
+    // flatten: one device node per internal build node (a leaf root gets a
+    // synthetic parent with an empty second child)
+    std::vector<int> dev_of(B.nodes.size(), -1);
+    std::vector<int> order;
+    std::vector<int> stack;
+    int n_internal = 0;
+    bool leaf_root = B.nodes[root].child[0] < 0;
+    if (!leaf_root) {
+        stack.push_back(root);
+        while (!stack.empty()) {
+            int n = stack.back();
+            stack.pop_back();
+            dev_of[n] = n_internal++;
+            order.push_back(n);
+            for (int c = 1; c >= 0; --c)
+                if (B.nodes[B.nodes[n].child[c]].child[0] >= 0) stack.push_back(B.nodes[n].child[c]);
+        }
+    }
+    int n_dev = leaf_root ? 1 : n_internal;
+    out.nodes.assign(16 * (size_t)n_dev, 0.0f);
+    out.tris.assign(12 * (size_t)nt, 0.0f);
+    int tri_cursor = 0;
+    auto emit_leaf = [&](int bn, int& first, int& count) {
+        const BuildNode& L = B.nodes[bn];
+        first = tri_cursor;
+        count = L.count;
+        for (int i = L.first; i < L.first + L.count; ++i) {
+            int p = B.idx[i];
+            float* dst = &out.tris[12 * (size_t)tri_cursor];
+            for (int k = 0; k < 3; ++k) {
+                const float* v = vertices + 3 * (size_t)tris[3 * p + k];
+                dst[4 * k + 0] = v[0];
+                dst[4 * k + 1] = v[1];
+                dst[4 * k + 2] = v[2];
+                dst[4 * k + 3] = 0.0f;
+            }
+            int32_t pid = p;
+            std::memcpy(&dst[3], &pid, 4);
+            ++tri_cursor;
+        }
+    };
+    auto write_node = [&](int d, const Box& b0, const Box& b1, int32_t l0, int32_t l1, int32_t c0, int32_t c1) {
+        float* dst = &out.nodes[16 * (size_t)d];
+        float bx[12];
+        put_box(bx, b0);
+        put_box(bx + 6, b1);
+        std::memcpy(dst, bx, sizeof(bx));
+        int32_t lk[4] = {l0, l1, c0, c1};
+        std::memcpy(dst + 12, lk, sizeof(lk));
+    };
+    if (leaf_root) {
+        int first, count;
+        emit_leaf(root, first, count);
+        Box empty;
+        write_node(0, B.nodes[root].box, empty, first, -1, count, 0);
+    } else {
+        for (int n : order) {
+            int32_t link[2], cnt[2];
+            for (int c = 0; c < 2; ++c) {
+                int ch = B.nodes[n].child[c];
+                if (B.nodes[ch].child[0] < 0) {
+                    int first, count;
+                    emit_leaf(ch, first, count);
+                    link[c] = first;
+                    cnt[c] = count;
+                } else {
+                    link[c] = dev_of[ch];
+                    cnt[c] = 0;
+                }
+            }
+            write_node(dev_of[n], B.nodes[B.nodes[n].child[0]].box, B.nodes[B.nodes[n].child[1]].box, link[0],
+                       link[1], cnt[0], cnt[1]);
+        }
+    }
+    out.n_nodes = n_dev;
+    return tri_cursor == nt;
+}
+
+}  // namespace neb

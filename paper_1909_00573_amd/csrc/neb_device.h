@@ -1,0 +1,481 @@
+// Device helpers of libneb: vector math, Philox, BSDFs, plane-box area,
+// octree addressing and queries, BVH traversal.  gfx950 only.
+#pragma once
+#include "neb_internal.h"
+
+namespace neb {
+
+#define NEB_PI 3.14159265358979323846f
+
+struct f3 {
+    float x, y, z;
+};
+__device__ __forceinline__ f3 mk3(float x, float y, float z) { return f3{x, y, z}; }
+__device__ __forceinline__ f3 operator+(f3 a, f3 b) { return mk3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ f3 operator-(f3 a, f3 b) { return mk3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ f3 operator-(f3 a) { return mk3(-a.x, -a.y, -a.z); }
+__device__ __forceinline__ f3 operator*(f3 a, float s) { return mk3(a.x * s, a.y * s, a.z * s); }
+__device__ __forceinline__ f3 operator*(f3 a, f3 b) { return mk3(a.x * b.x, a.y * b.y, a.z * b.z); }
+__device__ __forceinline__ float dot3(f3 a, f3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ f3 cross3(f3 a, f3 b) {
+    return mk3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ f3 normalize3(f3 a) { return a * rsqrtf(dot3(a, a)); }
+__device__ __forceinline__ f3 xyz(float4 v) { return mk3(v.x, v.y, v.z); }
+__device__ __forceinline__ float4 f4(f3 a, float w) { return make_float4(a.x, a.y, a.z, w); }
+__device__ __forceinline__ float get3(f3 a, int i) { return i == 0 ? a.x : (i == 1 ? a.y : a.z); }
+__device__ __forceinline__ bool is_zero3(f3 a) { return a.x == 0.f && a.y == 0.f && a.z == 0.f; }
+__device__ __forceinline__ f3 load3(const float* p) { return mk3(p[0], p[1], p[2]); }
+
+// ---------------------------------------------------------------------------
+// Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplications with Weyl-sequence key schedule.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+        uint32_t hi0 = __umulhi(m0, c.x), lo0 = m0 * c.x;
+        uint32_t hi1 = __umulhi(m1, c.z), lo1 = m1 * c.z;
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+struct U4 {
+    float u[4];
+};
+// four uniforms in [0,1): the top 24 bits of each output, exact in FP32
+__device__ __forceinline__ U4 uniforms(uint32_t k0, uint32_t k1, uint32_t a, uint32_t b, uint32_t c,
+                                       uint32_t tag) {
+    uint4 x = philox10(make_uint4(a, b, c, tag), k0, k1);
+    const float s = 1.0f / 16777216.0f;
+    U4 r;
+    r.u[0] = (float)(x.x >> 8) * s;
+    r.u[1] = (float)(x.y >> 8) * s;
+    r.u[2] = (float)(x.z >> 8) * s;
+    r.u[3] = (float)(x.w >> 8) * s;
+    return r;
+}
+
+// branchless orthonormal basis around n (Duff et al., JCGT 6(1), 2017)
+__device__ __forceinline__ void basis(f3 n, f3& t1, f3& t2) {
+    float sg = copysignf(1.0f, n.z);
+    float a = -1.0f / (sg + n.z);
+    float b = n.x * n.y * a;
+    t1 = mk3(1.0f + sg * n.x * n.x * a, sg * b, -sg * n.x);
+    t2 = mk3(b, sg + n.y * n.y * a, -n.y);
+}
+
+// ---------------------------------------------------------------------------
+// BSDFs.  Geometric normal only; wi = direction the path arrived from, wo =
+// direction it leaves to, both pointing away from the surface.  Delta lobes
+// report their discrete selection probability as pdf.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool mat_delta(int type) { return type == NEB_MAT_MIRROR || type == NEB_MAT_DIELECTRIC; }
+__device__ __forceinline__ bool mat_black(const neb_material& m) {
+    return m.albedo[0] == 0.f && m.albedo[1] == 0.f && m.albedo[2] == 0.f;
+}
+__device__ __forceinline__ bool mat_emits(const neb_material& m) {
+    return m.emission[0] + m.emission[1] + m.emission[2] > 0.f;
+}
+
+__device__ __forceinline__ float fresnel(float cos_i, float eta) {
+    float s2 = eta * eta * (1.0f - cos_i * cos_i);
+    if (s2 >= 1.0f) return 1.0f;
+    float ct = sqrtf(1.0f - s2);
+    float rs = (eta * cos_i - ct) / (eta * cos_i + ct);
+    float rp = (cos_i - eta * ct) / (cos_i + eta * ct);
+    return 0.5f * (rs * rs + rp * rp);
+}
+
+__device__ __forceinline__ float ggx_d(float a, float c) {
+    if (c <= 0.f) return 0.f;
+    float a2 = a * a;
+    float t = c * c * (a2 - 1.0f) + 1.0f;
+    return a2 / (NEB_PI * t * t);
+}
+__device__ __forceinline__ float ggx_g1(float a, float c) {
+    float c2 = c * c;
+    return 2.0f / (1.0f + sqrtf(1.0f + a * a * (1.0f - c2) / c2));
+}
+
+__device__ __forceinline__ float bsdf_pdf(const neb_material& m, f3 n, f3 wi, f3 wo) {
+    float ci = dot3(n, wi), co = dot3(n, wo);
+    bool same = ci * co > 0.f;
+    switch (m.type) {
+    case NEB_MAT_LAMBERT: return same ? fabsf(co) * (1.0f / NEB_PI) : 0.f;
+    case NEB_MAT_MIRROR: return same ? 1.f : 0.f;
+    case NEB_MAT_DIELECTRIC: {
+        float F = fresnel(fabsf(ci), ci > 0.f ? 1.0f / m.ior : m.ior);
+        return same ? F : 1.0f - F;
+    }
+    case NEB_MAT_GGX: {
+        if (!same) return 0.f;
+        f3 ns = ci > 0.f ? n : -n;
+        f3 h = normalize3(wi + wo);
+        float cm = dot3(h, ns);
+        return ggx_d(m.alpha, cm) * cm / (4.0f * fabsf(dot3(wo, h)));
+    }
+    }
+    return 0.f;
+}
+
+__device__ __forceinline__ f3 bsdf_f(const neb_material& m, f3 n, f3 wi, f3 wo) {
+    float ci = dot3(n, wi), co = dot3(n, wo);
+    f3 alb = load3(m.albedo);
+    if (ci * co <= 0.f) return mk3(0.f, 0.f, 0.f);
+    if (m.type == NEB_MAT_LAMBERT) return alb * (1.0f / NEB_PI);
+    if (m.type == NEB_MAT_GGX) {
+        f3 ns = ci > 0.f ? n : -n;
+        f3 h = normalize3(wi + wo);
+        float D = ggx_d(m.alpha, dot3(h, ns));
+        float G = ggx_g1(m.alpha, fabsf(ci)) * ggx_g1(m.alpha, fabsf(co));
+        return alb * (D * G / (4.0f * fabsf(ci) * fabsf(co)));
+    }
+    return mk3(0.f, 0.f, 0.f);
+}
+
+struct Sample {
+    f3 dir, w;
+    float pdf;
+    int ev;      // 1 scatter, 2 reflect, 3 refract, 0 failed
+};
+
+__device__ __forceinline__ Sample bsdf_sample(const neb_material& m, f3 n, f3 wi, const U4& u) {
+    Sample s;
+    s.ev = 0;
+    s.pdf = 0.f;
+    s.w = mk3(0.f, 0.f, 0.f);
+    s.dir = mk3(0.f, 0.f, 1.f);
+    float ci = dot3(n, wi);
+    if (ci == 0.f) return s;
+    f3 ns = ci > 0.f ? n : -n;
+    f3 alb = load3(m.albedo);
+    if (m.type == NEB_MAT_LAMBERT) {
+        f3 t1, t2;
+        basis(ns, t1, t2);
+        float r = sqrtf(u.u[1]);
+        float sp, cp;
+        sincosf(2.0f * NEB_PI * u.u[2], &sp, &cp);
+        float z = sqrtf(fmaxf(0.f, 1.0f - u.u[1]));
+        s.dir = normalize3(t1 * (r * cp) + t2 * (r * sp) + ns * z);
+        float co = dot3(s.dir, ns);
+        if (co <= 0.f) return s;
+        s.pdf = co * (1.0f / NEB_PI);
+        s.w = alb;
+        s.ev = 1;
+    } else if (m.type == NEB_MAT_MIRROR) {
+        float c = dot3(wi, ns);
+        s.dir = ns * (2.0f * c) - wi;
+        s.pdf = 1.0f;
+        s.w = alb;
+        s.ev = 2;
+    } else if (m.type == NEB_MAT_DIELECTRIC) {
+        float c = dot3(wi, ns);
+        float eta = ci > 0.f ? 1.0f / m.ior : m.ior;
+        float F = fresnel(c, eta);
+        if (u.u[0] < F) {
+            s.dir = ns * (2.0f * c) - wi;
+            s.pdf = F;
+            s.ev = 2;
+        } else {
+            float ct = sqrtf(fmaxf(0.f, 1.0f - eta * eta * (1.0f - c * c)));
+            s.dir = normalize3(ns * (eta * c - ct) - wi * eta);
+            s.pdf = 1.0f - F;
+            s.ev = 3;
+        }
+        s.w = alb;
+    } else if (m.type == NEB_MAT_GGX) {
+        float a = m.alpha;
+        float tt = a * sqrtf(u.u[1] / (1.0f - u.u[1]));
+        float ct = rsqrtf(1.0f + tt * tt);
+        float st = tt * ct;
+        float sp, cp;
+        sincosf(2.0f * NEB_PI * u.u[2], &sp, &cp);
+        f3 t1, t2;
+        basis(ns, t1, t2);
+        f3 h = normalize3(t1 * (st * cp) + t2 * (st * sp) + ns * ct);
+        float wh = dot3(wi, h);
+        if (wh <= 0.f) return s;
+        s.dir = h * (2.0f * wh) - wi;
+        float co = dot3(s.dir, ns);
+        if (co <= 0.f) return s;
+        float cim = fabsf(ci);
+        float G = ggx_g1(a, cim) * ggx_g1(a, co);
+        s.pdf = ggx_d(a, ct) * ct / (4.0f * wh);
+        s.w = alb * (G * wh / (cim * ct));
+        s.ev = 1;
+    }
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// eq. (area): area of the plane (p, n) inside the box [bmin, bmax].  The plane
+// offset is taken relative to the box's min corner; the 3-D case sums in FP64.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float plane_box_area(f3 bmin, f3 bmax, f3 p, f3 n) {
+    f3 s = bmax - bmin;
+    f3 a = mk3(fabsf(n.x), fabsf(n.y), fabsf(n.z));
+    if (fabsf(a.x - 1.0f) < 1e-3f) return s.y * s.z;
+    if (fabsf(a.y - 1.0f) < 1e-3f) return s.x * s.z;
+    if (fabsf(a.z - 1.0f) < 1e-3f) return s.x * s.y;
+    f3 q = p - bmin;
+    for (int d = 0; d < 3; ++d) {
+        if (get3(a, d) < 1e-4f) {
+            int ix = d == 0 ? 1 : (d == 1 ? 2 : 0);
+            int iy = d == 0 ? 2 : (d == 1 ? 0 : 1);
+            float nx = get3(n, ix), ny = get3(n, iy);
+            float ex = nx * get3(s, ix), ey = ny * get3(s, iy);
+            float t = nx * get3(q, ix) + ny * get3(q, iy);
+            float sum = fmaxf(0.f, t) - fmaxf(0.f, t - ex) - fmaxf(0.f, t - ey) + fmaxf(0.f, t - ex - ey);
+            return get3(s, d) * fabsf(sum / (nx * ny));
+        }
+    }
+    double ex = (double)n.x * s.x, ey = (double)n.y * s.y, ez = (double)n.z * s.z;
+    double t = (double)n.x * q.x + (double)n.y * q.y + (double)n.z * q.z;
+    double sum = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        double h = t - ((c & 1) ? ex : 0.0) - ((c & 2) ? ey : 0.0) - ((c & 4) ? ez : 0.0);
+        double v = h > 0.0 ? h * h : 0.0;
+        sum += (__popc(c) & 1) ? -v : v;
+    }
+    return (float)fabs(sum / (2.0 * (double)n.x * (double)n.y * (double)n.z));
+}
+
+// ---------------------------------------------------------------------------
+// Octree addressing (FP32, no contraction, as the class of Appendix B) and
+// the density query of eq. (octdensity).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool oct_norm(const OctParams& P, f3 p, float q[3]) {
+    float pv[3] = {p.x, p.y, p.z};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        float v = __fmul_rn(__fsub_rn(pv[i], P.min_bound[i]), P.size_inv[i]);
+        if (!(v >= 0.0f && v < 1.0f)) return false;
+        q[i] = v;
+    }
+    return true;
+}
+
+__device__ __forceinline__ float oct_query(const int32_t* __restrict__ nodes, const OctParams& P, int depth,
+                                           f3 p, f3 n, bool want_size, float* size_out) {
+    float q[3];
+    if (!oct_norm(P, p, q)) return 0.f;
+    int32_t grid = 1 << depth;
+    int32_t ix = (int32_t)(q[0] * (float)grid), iy = (int32_t)(q[1] * (float)grid),
+            iz = (int32_t)(q[2] * (float)grid);
+    int32_t v = nodes[0];
+    int32_t mask = grid;
+    while (v < 0) {
+        mask >>= 1;
+        int32_t c = ((ix & mask) ? 1 : 0) | ((iy & mask) ? 2 : 0) | ((iz & mask) ? 4 : 0);
+        v = nodes[c - v];
+    }
+    int32_t cnt = v & kOctCountMask;
+    if (cnt <= 0) return 0.f;
+    int32_t res = grid / mask;
+    float csx = 1.0f / ((float)res * P.size_inv[0]);
+    float csy = 1.0f / ((float)res * P.size_inv[1]);
+    float csz = 1.0f / ((float)res * P.size_inv[2]);
+    f3 cmin = mk3((float)(ix / mask) * csx, (float)(iy / mask) * csy, (float)(iz / mask) * csz);
+    f3 cmax = cmin + mk3(csx, csy, csz);
+    f3 off = mk3(p.x - P.min_bound[0], p.y - P.min_bound[1], p.z - P.min_bound[2]);
+    float area = plane_box_area(cmin, cmax, off, n);
+    float diag = P.scene_scale / (float)res;
+    float min_area = diag * diag * (want_size ? 0.1f : 0.01f);
+    if (want_size) *size_out = diag;
+    return P.density_scale * (float)cnt / fmaxf(min_area, area);
+}
+
+// five probes in the tangent plane, upper median of the non-zero ones
+__device__ __forceinline__ float oct_query_robust(const int32_t* __restrict__ nodes, const OctParams& P,
+                                                  int depth, f3 p, f3 n) {
+    f3 tx, ty;
+    basis(n, tx, ty);
+    float diag = 1e-3f;
+    float d[5];
+    int cnt = 0;
+    float c0 = oct_query(nodes, P, depth, p, n, true, &diag);
+    if (c0 > 0.f) d[cnt++] = c0;
+    float off = diag * 1.1f;
+    f3 probe[4] = {p + tx * off, p - tx * off, p + ty * off, p - ty * off};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        float r = oct_query(nodes, P, depth, probe[i], n, false, nullptr);
+        if (r > 0.f) d[cnt++] = r;
+    }
+    if (cnt == 0) return 0.f;
+    // insertion sort of at most five values, then the upper median
+    for (int i = 1; i < cnt; ++i) {
+        float x = d[i];
+        int j = i - 1;
+        while (j >= 0 && d[j] > x) {
+            d[j + 1] = d[j];
+            --j;
+        }
+        d[j + 1] = x;
+    }
+    return d[cnt / 2];
+}
+
+// ---------------------------------------------------------------------------
+// BVH traversal: two child boxes per 64-byte node, per-lane stack in LDS,
+// watertight ray-triangle test (Woop, Benthin, Wald, JCGT 2(1), 2013).
+// ---------------------------------------------------------------------------
+struct RayPre {
+    f3 o, d, inv;
+    int kx, ky, kz;
+    float sx, sy, sz;
+};
+
+__device__ __forceinline__ RayPre ray_pre(f3 o, f3 d) {
+    RayPre r;
+    r.o = o;
+    r.d = d;
+    const float big = 1e30f;
+    r.inv = mk3(fabsf(d.x) > 1e-30f ? 1.0f / d.x : copysignf(big, d.x),
+                fabsf(d.y) > 1e-30f ? 1.0f / d.y : copysignf(big, d.y),
+                fabsf(d.z) > 1e-30f ? 1.0f / d.z : copysignf(big, d.z));
+    float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+    int kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+    int kx = kz == 2 ? 0 : kz + 1;
+    int ky = kx == 2 ? 0 : kx + 1;
+    if (get3(d, kz) < 0.f) {
+        int t = kx;
+        kx = ky;
+        ky = t;
+    }
+    r.kx = kx;
+    r.ky = ky;
+    r.kz = kz;
+    float dz = get3(d, kz);
+    r.sx = get3(d, kx) / dz;
+    r.sy = get3(d, ky) / dz;
+    r.sz = 1.0f / dz;
+    return r;
+}
+
+// returns t in (0, tmax) or -1
+__device__ __forceinline__ float tri_hit(const RayPre& r, f3 v0, f3 v1, f3 v2, float tmax) {
+    f3 A = v0 - r.o, B = v1 - r.o, C = v2 - r.o;
+    float az = get3(A, r.kz), bz = get3(B, r.kz), cz = get3(C, r.kz);
+    float Ax = get3(A, r.kx) - r.sx * az, Ay = get3(A, r.ky) - r.sy * az;
+    float Bx = get3(B, r.kx) - r.sx * bz, By = get3(B, r.ky) - r.sy * bz;
+    float Cx = get3(C, r.kx) - r.sx * cz, Cy = get3(C, r.ky) - r.sy * cz;
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (U == 0.f || V == 0.f || W == 0.f) {
+        U = (float)((double)Cx * By - (double)Cy * Bx);
+        V = (float)((double)Ax * Cy - (double)Ay * Cx);
+        W = (float)((double)Bx * Ay - (double)By * Ax);
+    }
+    if ((U < 0.f || V < 0.f || W < 0.f) && (U > 0.f || V > 0.f || W > 0.f)) return -1.f;
+    float det = U + V + W;
+    if (det == 0.f) return -1.f;
+    float T = U * (r.sz * az) + V * (r.sz * bz) + W * (r.sz * cz);
+    float t = T / det;
+    return (t > 0.f && t < tmax) ? t : -1.f;
+}
+
+__device__ __forceinline__ bool box_hit(const RayPre& r, float lx, float ly, float lz, float hx, float hy,
+                                        float hz, float tmax, float& tn) {
+    float t0x = (lx - r.o.x) * r.inv.x, t1x = (hx - r.o.x) * r.inv.x;
+    float t0y = (ly - r.o.y) * r.inv.y, t1y = (hy - r.o.y) * r.inv.y;
+    float t0z = (lz - r.o.z) * r.inv.z, t1z = (hz - r.o.z) * r.inv.z;
+    float tnear = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
+    float tfar = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
+    tn = tnear;
+    return tnear <= tfar * 1.00000024f;
+}
+
+// closest hit; ties on t go to the lowest primitive id.  stack: this lane's
+// LDS slots, stride kTraceBlock.  any_hit: stop at the first hit below tmax.
+template <bool kAnyHit>
+__device__ __forceinline__ int trace(const SceneView& S, f3 o, f3 d, float tmax, float& t_out, int* stack) {
+    RayPre r = ray_pre(o, d);
+    float best = tmax;
+    int prim = -1;
+    int node = 0, sp = 0;
+    for (;;) {
+        const float4* nd = S.bvh + 4 * node;
+        float4 a = nd[0], b = nd[1], c = nd[2];
+        int4 lk = *reinterpret_cast<const int4*>(nd + 3);
+        float tn0, tn1;
+        bool h0 = box_hit(r, a.x, a.y, a.z, a.w, b.x, b.y, best, tn0);
+        bool h1 = box_hit(r, b.z, b.w, c.x, c.y, c.z, c.w, best, tn1);
+        // leaves are tested in place
+        if (h0 && lk.z > 0) {
+            for (int k = lk.x; k < lk.x + lk.z; ++k) {
+                const float4* tp = S.tri + 3 * k;
+                float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
+                float t = tri_hit(r, xyz(p0), xyz(p1), xyz(p2), kAnyHit ? best : best * 1.0000001f);
+                int id = __float_as_int(p0.w);
+                if (t > 0.f && (t < best || (t == best && id < prim))) {
+                    best = t;
+                    prim = id;
+                    if (kAnyHit) { t_out = t; return prim; }
+                }
+            }
+            h0 = false;
+        }
+        if (h1 && lk.w > 0) {
+            for (int k = lk.y; k < lk.y + lk.w; ++k) {
+                const float4* tp = S.tri + 3 * k;
+                float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
+                float t = tri_hit(r, xyz(p0), xyz(p1), xyz(p2), kAnyHit ? best : best * 1.0000001f);
+                int id = __float_as_int(p0.w);
+                if (t > 0.f && (t < best || (t == best && id < prim))) {
+                    best = t;
+                    prim = id;
+                    if (kAnyHit) { t_out = t; return prim; }
+                }
+            }
+            h1 = false;
+        }
+        h0 = h0 && lk.x >= 0 && tn0 < best;
+        h1 = h1 && lk.y >= 0 && tn1 < best;
+        if (h0 && h1) {
+            int nearc = tn0 <= tn1 ? lk.x : lk.y;
+            int farc = tn0 <= tn1 ? lk.y : lk.x;
+            if (sp < kBvhStack) stack[(sp++) * kTraceBlock] = farc;
+            node = nearc;
+        } else if (h0) {
+            node = lk.x;
+        } else if (h1) {
+            node = lk.y;
+        } else {
+            if (sp == 0) break;
+            node = stack[(--sp) * kTraceBlock];
+        }
+    }
+    t_out = best;
+    return prim;
+}
+
+// device-wide counter add with one atomic per wave
+__device__ __forceinline__ void wave_add_u64(unsigned long long* dst, unsigned v) {
+    unsigned long long s = v;
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(dst, s);
+}
+
+// wave-aggregated slot reservation: returns this lane's index in a queue
+// whose tail is *counter; lanes with take == false get -1
+__device__ __forceinline__ int wave_reserve(int* counter, bool take) {
+    unsigned long long mask = __ballot(take);
+    int lane = threadIdx.x & 63;
+    int leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (mask == 0) return -1;
+    if (lane == leader) base = atomicAdd(counter, __popcll(mask));
+    base = __shfl(base, leader, 64);
+    unsigned long long below = mask & ((1ull << lane) - 1ull);
+    return take ? base + __popcll(below) : -1;
+}
+
+}  // namespace neb

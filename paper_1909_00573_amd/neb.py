@@ -1,0 +1,261 @@
+"""Thin ctypes binding of libneb.so (include/neb.h).
+
+Argument marshalling only: every step of the path runs in the library's
+HIP kernels.  torch is used for device buffers and streams.  The binding
+refuses to run without the built library (no CPU fallback exists).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libneb.so")
+_lib = None
+
+NEB_OK = 0
+DENSITY_OCTREE, DENSITY_OCTREE_ROBUST, DENSITY_ANALYTIC = 0, 1, 3
+FLAG_SINGLE_THREAD_OCTREE, FLAG_RECORD_PATHS, FLAG_NO_PHOTONS = 1, 2, 4
+
+# every symbol the header declares
+EXPORTS = [
+    "neb_create", "neb_set_scene", "neb_render", "neb_get_image", "neb_get_technique_images",
+    "neb_query_density", "neb_get_stats", "neb_get_path_records", "neb_get_octree", "neb_reset",
+    "neb_destroy", "neb_status_string", "neb_last_error",
+    "neb_octree_create", "neb_octree_set_iteration", "neb_octree_increment", "neb_octree_density",
+    "neb_octree_clear_counters", "neb_octree_export", "neb_octree_destroy",
+]
+
+
+class NebError(RuntimeError):
+    pass
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("max_path_len", ctypes.c_int32),
+                ("octree_capacity", ctypes.c_int32), ("merge_radius", ctypes.c_float),
+                ("seed", ctypes.c_uint32), ("scene_id", ctypes.c_uint32), ("density_mode", ctypes.c_int32),
+                ("analytic_rho0", ctypes.c_float), ("analytic_cam_weight", ctypes.c_float),
+                ("flags", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in (
+        "iterations", "paths", "vertices", "photons", "photon_segments", "merges", "nee_visible", "events",
+        "rays", "oct_capacity", "oct_allocated", "oct_depth", "oct_overflow", "oct_ledger", "oct_deposits",
+        "oct_rejected", "oct_lost")]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+RECORD_DTYPE = np.dtype([("type", "<i4"), ("mat", "<i4"), ("prim", "<i4"), ("pos", "<f4", (3,))])
+OCT_INFO_KEYS = ("capacity", "allocated", "depth", "ledger", "deposits", "overflow", "rejected", "lost")
+
+_P = ctypes.c_void_p
+
+
+def lib():
+    """Load libneb.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise NebError(f"{LIB_PATH} is missing: build it with paper_1909_00573_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        i32, i64 = ctypes.c_int32, ctypes.c_int64
+        sig = {
+            "neb_create": ([ctypes.POINTER(Params), ctypes.POINTER(_P)], i32),
+            "neb_set_scene": ([_P, _P, i32, _P, _P, i32, _P, i32, _P, i32, _P], i32),
+            "neb_render": ([_P, i32, _P], i32),
+            "neb_get_image": ([_P, _P, i32, _P], i32),
+            "neb_get_technique_images": ([_P, _P, _P, _P, i32, _P], i32),
+            "neb_query_density": ([_P, _P, _P, i32, _P, i32, _P], i32),
+            "neb_get_stats": ([_P, ctypes.POINTER(Stats)], i32),
+            "neb_get_path_records": ([_P, _P, i64], i32),
+            "neb_get_octree": ([_P, _P, i32, _P], i32),
+            "neb_reset": ([_P], i32),
+            "neb_destroy": ([_P], None),
+            "neb_status_string": ([i32], ctypes.c_char_p),
+            "neb_last_error": ([], ctypes.c_char_p),
+            "neb_octree_create": ([_P, _P, i32, ctypes.POINTER(_P)], i32),
+            "neb_octree_set_iteration": ([_P, i32], i32),
+            "neb_octree_increment": ([_P, _P, i32, i32, _P], i32),
+            "neb_octree_density": ([_P, _P, _P, i32, i32, _P, _P], i32),
+            "neb_octree_clear_counters": ([_P, _P], i32),
+            "neb_octree_export": ([_P, _P, i32, _P, _P], i32),
+            "neb_octree_destroy": ([_P], None),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != NEB_OK:
+        L = lib()
+        raise NebError(f"{L.neb_status_string(status).decode()}: {L.neb_last_error().decode()}")
+
+
+def _np_ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _dev_ptr(t):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
+        raise NebError("expected a contiguous device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def make_params(scene, density_mode=DENSITY_OCTREE_ROBUST, flags=0, rho0=0.0, cam_weight=0.0, **over):
+    p = Params()
+    p.width = over.get("width", scene.width)
+    p.height = over.get("height", scene.height)
+    p.max_path_len = over.get("max_path_len", scene.max_path_len)
+    p.octree_capacity = over.get("octree_capacity", scene.octree_capacity)
+    p.merge_radius = over.get("merge_radius", scene.merge_radius)
+    p.seed = over.get("seed", scene.seed)
+    p.scene_id = over.get("scene_id", scene.scene_id)
+    p.density_mode = density_mode
+    p.analytic_rho0 = rho0
+    p.analytic_cam_weight = cam_weight
+    p.flags = flags
+    return p
+
+
+class Renderer:
+    """One rendering context on the current device."""
+
+    def __init__(self, scene, density_mode=DENSITY_OCTREE_ROBUST, flags=0, rho0=0.0, cam_weight=0.0, **over):
+        self.params = make_params(scene, density_mode, flags, rho0, cam_weight, **over)
+        h = _P()
+        _check(lib().neb_create(ctypes.byref(self.params), ctypes.byref(h)))
+        self.h = h
+        self.scene = scene
+        arrs = [np.ascontiguousarray(scene.vertices, np.float32), np.ascontiguousarray(scene.tris, np.int32),
+                np.ascontiguousarray(scene.tri_mat, np.int32), np.ascontiguousarray(scene.materials),
+                np.ascontiguousarray(scene.point_lights), np.ascontiguousarray(scene.camera)]
+        v, t, m, mats, pl, cam = arrs
+        _check(lib().neb_set_scene(self.h, _np_ptr(v), v.shape[0], _np_ptr(t), _np_ptr(m), t.shape[0],
+                                   _np_ptr(mats), mats.shape[0], _np_ptr(pl) if len(pl) else None, pl.shape[0],
+                                   _np_ptr(cam)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().neb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def render(self, n_iterations, stream=None):
+        _check(lib().neb_render(self.h, int(n_iterations), _stream(stream)))
+
+    def image(self, out=None, stream=None):
+        """Mean radiance: a (H, W, 3) float32 device tensor (written into
+        `out` if given)."""
+        import torch
+        H, W = self.params.height, self.params.width
+        if out is None:
+            out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+        _check(lib().neb_get_image(self.h, _dev_ptr(out), 1, _stream(stream)))
+        return out
+
+    def image_host(self):
+        H, W = self.params.height, self.params.width
+        out = np.zeros((H, W, 3), np.float32)
+        _check(lib().neb_get_image(self.h, _np_ptr(out), 0, None))
+        return out
+
+    def technique_images_host(self):
+        H, W = self.params.height, self.params.width
+        e, E, P = (np.zeros((H, W, 3), np.float32) for _ in range(3))
+        _check(lib().neb_get_technique_images(self.h, _np_ptr(e), _np_ptr(E), _np_ptr(P), 0, None))
+        return {"e": e, "E": E, "P": P}
+
+    def stats(self):
+        s = Stats()
+        _check(lib().neb_get_stats(self.h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def records(self):
+        n = self.params.width * self.params.height * self.params.max_path_len
+        out = np.zeros(n, RECORD_DTYPE)
+        _check(lib().neb_get_path_records(self.h, _np_ptr(out), n))
+        return out.reshape(self.params.width * self.params.height, self.params.max_path_len)
+
+    def octree(self):
+        info = np.zeros(8, np.int64)
+        _check(lib().neb_get_octree(self.h, None, 0, _np_ptr(info)))
+        nodes = np.zeros(int(info[0]), np.int32)
+        _check(lib().neb_get_octree(self.h, _np_ptr(nodes), nodes.size, _np_ptr(info)))
+        return nodes, dict(zip(OCT_INFO_KEYS, (int(x) for x in info)))
+
+    def query_density(self, pos, nrm, stream=None):
+        """pos, nrm: (n, 3) float32 device tensors -> (n,) densities."""
+        import torch
+        out = torch.empty(pos.shape[0], dtype=torch.float32, device=pos.device)
+        _check(lib().neb_query_density(self.h, _dev_ptr(pos), _dev_ptr(nrm), pos.shape[0], _dev_ptr(out), 1,
+                                       _stream(stream)))
+        return out
+
+    def reset(self):
+        _check(lib().neb_reset(self.h))
+
+
+class DeviceOctree:
+    """The density octree of Appendix B on the GPU (batched calls)."""
+
+    def __init__(self, smin, smax, capacity):
+        a = np.ascontiguousarray(smin, np.float32)
+        b = np.ascontiguousarray(smax, np.float32)
+        h = _P()
+        _check(lib().neb_octree_create(_np_ptr(a), _np_ptr(b), int(capacity), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().neb_octree_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_iteration(self, it):
+        _check(lib().neb_octree_set_iteration(self.h, int(it)))
+
+    def increment(self, pos, single_thread=False, stream=None):
+        _check(lib().neb_octree_increment(self.h, _dev_ptr(pos), pos.shape[0], int(single_thread), _stream(stream)))
+
+    def density(self, pos, nrm, robust=True, stream=None):
+        import torch
+        out = torch.empty(pos.shape[0], dtype=torch.float32, device=pos.device)
+        _check(lib().neb_octree_density(self.h, _dev_ptr(pos), _dev_ptr(nrm), pos.shape[0], int(robust),
+                                        _dev_ptr(out), _stream(stream)))
+        return out
+
+    def clear_counters(self, stream=None):
+        _check(lib().neb_octree_clear_counters(self.h, _stream(stream)))
+
+    def export(self, stream=None):
+        info = np.zeros(8, np.int64)
+        _check(lib().neb_octree_export(self.h, None, 0, _np_ptr(info), _stream(stream)))
+        nodes = np.zeros(int(info[0]), np.int32)
+        _check(lib().neb_octree_export(self.h, _np_ptr(nodes), nodes.size, _np_ptr(info), _stream(stream)))
+        return nodes, dict(zip(OCT_INFO_KEYS, (int(x) for x in info)))

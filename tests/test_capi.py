@@ -1,0 +1,52 @@
+"""The C-ABI library loads on the CPU and exports every function that
+include/neb.h declares (no compute call is made without a GPU)."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "neb.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:neb_status|void|const char\*)\s+(neb_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("neb_create", "neb_set_scene", "neb_render", "neb_get_image", "neb_query_density",
+                 "neb_octree_create", "neb_octree_increment", "neb_octree_density", "neb_octree_export"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1909_00573_amd import neb
+    if not os.path.exists(neb.LIB_PATH):
+        pytest.skip("libneb.so not built")
+    L = neb.lib()
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert missing == []
+    assert sorted(neb.EXPORTS) == _declared()
+    assert L.neb_status_string(-1) == b"invalid argument"
+
+
+def test_invalid_arguments_are_rejected_without_a_device():
+    """Argument checks happen before any HIP call."""
+    import ctypes
+    from paper_1909_00573_amd import neb
+    if not os.path.exists(neb.LIB_PATH):
+        pytest.skip("libneb.so not built")
+    L = neb.lib()
+    p = neb.Params()
+    p.width, p.height, p.max_path_len, p.octree_capacity, p.merge_radius = 0, 8, 4, 64, 0.01
+    h = ctypes.c_void_p()
+    assert L.neb_create(ctypes.byref(p), ctypes.byref(h)) == -1
+    p.width, p.max_path_len = 8, 99
+    assert L.neb_create(ctypes.byref(p), ctypes.byref(h)) == -1
+    p.max_path_len, p.merge_radius = 4, -1.0
+    assert L.neb_create(ctypes.byref(p), ctypes.byref(h)) == -1
+    assert L.neb_render(None, 1, None) == -1
+    lo = (ctypes.c_float * 3)(0, 0, 0)
+    assert L.neb_octree_create(lo, lo, 16, ctypes.byref(h)) == -1     # flat bounds
