@@ -103,7 +103,20 @@ typedef struct {
      * out-of-bounds deposits, deposits that gave up waiting for a split */
     int64_t oct_capacity, oct_allocated, oct_depth, oct_overflow, oct_ledger, oct_deposits,
         oct_rejected, oct_lost;
+    /* work counters for algorithmic-byte accounting: photon states read by the
+     * merge kernel (hits and misses), photon states written for the next
+     * bounce, grid cells visited and view vertices tested by the merge gather */
+    int64_t photon_items, photon_continued, grid_cells, candidates;
+    /* rays = camera_rays + shadow_rays + photon rays */
+    int64_t camera_rays, shadow_rays;
 } neb_stats;
+
+/* per-kernel device time, collected with HIP events on the launch stream */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+} neb_kernel_time;
 
 /* view-path record of the first rendered iteration, one per (pixel, depth) */
 typedef struct {
@@ -172,6 +185,15 @@ neb_status neb_get_path_records(neb_ctx ctx, neb_path_record* out, int64_t n);
 /* Exports the context's octree node array (host, up to cap entries) and
  * its info (see neb_octree_export). */
 neb_status neb_get_octree(neb_ctx ctx, int32_t* nodes, int32_t cap, int64_t info[8]);
+
+/* enable != 0 starts recording a HIP event pair around every kernel launch
+ * of this context (clearing earlier records); 0 stops.  Recording adds a
+ * few microseconds per launch. */
+neb_status neb_profile_kernels(neb_ctx ctx, int32_t enable);
+
+/* Per-kernel totals recorded so far (host array of cap entries, *n_out set
+ * to the number of kernels written).  Synchronises the recorded events. */
+neb_status neb_get_kernel_profile(neb_ctx ctx, neb_kernel_time* out, int32_t cap, int32_t* n_out);
 
 /* Clears the images, the statistics, the octree and the iteration counter. */
 neb_status neb_reset(neb_ctx ctx);

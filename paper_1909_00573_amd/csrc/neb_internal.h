@@ -77,7 +77,9 @@ struct Counters {
     int32_t n_vertices;
     int32_t n_events;
     int32_t pad[2];
-    unsigned long long paths, vertices, photons, photon_segments, merges, nee_visible, events, rays;
+    unsigned long long paths, vertices, photons, photon_segments, merges, nee_visible, events;
+    unsigned long long camera_rays, shadow_rays, photon_rays;
+    unsigned long long photon_items, photon_continued, grid_cells, candidates;
 };
 
 // octree kernels (neb_octree.hip)

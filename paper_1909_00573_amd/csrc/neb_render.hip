@@ -396,7 +396,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_nee(RenderArgs A, VertexStore V
     }
     wave_add_u64(&cnt->nee_visible, vis);
     wave_add_u64(&cnt->photons, emitted);
-    wave_add_u64(&cnt->rays, rays);
+    wave_add_u64(&cnt->shadow_rays, rays);
 }
 
 // ---------------------------------------------------------------------------
@@ -509,7 +509,7 @@ __global__ void __launch_bounds__(256) k_photon(RenderArgs A, PhotonQ in, const 
                                                 Counters* cnt) {
     int n = *count_in;
     const SceneView& S = A.S;
-    unsigned segs = 0, merges = 0;
+    unsigned segs = 0, merges = 0, items = 0, cont = 0, cells = 0, cands = 0;
     const float r2 = A.r * A.r;
     const float kern = 1.0f / A.r2pi;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -517,6 +517,7 @@ __global__ void __launch_bounds__(256) k_photon(RenderArgs A, PhotonQ in, const 
         bool go = false;
         Sample s;
         s.ev = 0;
+        ++items;
         float4 b0 = in.p0[i], b1 = in.p1[i], b2 = in.p2[i];
         float U = in.pu[i];
         int code = fbits(b1.w);
@@ -556,7 +557,9 @@ __global__ void __launch_bounds__(256) k_photon(RenderArgs A, PhotonQ in, const 
                             for (int q = 0; q < ns; ++q) dup |= seen[q] == hc;
                             if (dup || ns == 8) continue;
                             seen[ns++] = hc;
+                            ++cells;
                             int e0 = G.start[hc], e1 = G.start[hc + 1];
+                            cands += (unsigned)(e1 - e0);
                             for (int e = e0; e < e1; ++e) {
                                 float4 c = G.sorted[e];
                                 f3 dv = xyz(c) - y;
@@ -588,6 +591,7 @@ __global__ void __launch_bounds__(256) k_photon(RenderArgs A, PhotonQ in, const 
             }
         }
         int slot = wave_reserve(count_out, go);
+        cont += go;
         if (go) {
             const neb_material& my = S.mats[mid];
             f3 wd = -d;
@@ -602,6 +606,10 @@ __global__ void __launch_bounds__(256) k_photon(RenderArgs A, PhotonQ in, const 
     }
     wave_add_u64(&cnt->photon_segments, segs);
     wave_add_u64(&cnt->merges, merges);
+    wave_add_u64(&cnt->photon_items, items);
+    wave_add_u64(&cnt->photon_continued, cont);
+    wave_add_u64(&cnt->grid_cells, cells);
+    wave_add_u64(&cnt->candidates, cands);
 }
 
 // ---------------------------------------------------------------------------
@@ -681,7 +689,54 @@ struct neb_ctx_s {
     hipStream_t last_stream = nullptr;
     std::vector<void*> allocs;
     std::vector<void*> scene_allocs;
+    // kernel profiling
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_ev;
+    std::vector<int> prof_kid;
+    int prof_used = 0;
+    double prof_ms[32] = {0};
+    int64_t prof_launches[32] = {0};
 };
+
+enum KernelId {
+    K_CAMERA, K_EXTEND_CAMERA, K_SHADE, K_OCTREE_INSERT, K_DENSITY, K_NEE, K_GRID_BUILD, K_EXTEND_PHOTON, K_PHOTON,
+    K_FINALIZE, K_MISC, K_COUNT
+};
+static const char* kKernelNames[K_COUNT] = {"camera", "extend_camera", "shade", "octree_insert", "density", "nee",
+                                            "grid_build", "extend_photon", "photon_merge", "finalize", "misc"};
+
+static void prof_harvest(neb_ctx c) {
+    if (c->prof_used == 0) return;
+    (void)hipEventSynchronize(c->prof_ev[c->prof_used - 1]);
+    for (int i = 0; i < c->prof_used; i += 2) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->prof_ev[i], c->prof_ev[i + 1]) == hipSuccess) {
+            c->prof_ms[c->prof_kid[i / 2]] += ms;
+            c->prof_launches[c->prof_kid[i / 2]] += 1;
+        }
+    }
+    c->prof_used = 0;
+}
+
+static void prof_begin(neb_ctx c, int kid, hipStream_t s) {
+    if (!c->prof_on) return;
+    if (c->prof_used + 2 > (int)c->prof_ev.size()) prof_harvest(c);
+    c->prof_kid[c->prof_used / 2] = kid;
+    (void)hipEventRecord(c->prof_ev[c->prof_used], s);
+}
+
+static void prof_end(neb_ctx c, hipStream_t s) {
+    if (!c->prof_on) return;
+    (void)hipEventRecord(c->prof_ev[c->prof_used + 1], s);
+    c->prof_used += 2;
+}
+
+#define TIMED(kid, ...)          \
+    do {                         \
+        prof_begin(c, (kid), s); \
+        __VA_ARGS__;             \
+        prof_end(c, s);          \
+    } while (0)
 
 template <typename T>
 static hipError_t dalloc(std::vector<void*>& list, T** p, size_t count) {
@@ -1013,51 +1068,65 @@ static neb_status render_iteration(neb_ctx c, hipStream_t s) {
     if (record)
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_of((int64_t)npix * L * 6, 256)), dim3(256), 0, s, (int32_t*)c->recs, 0,
                            (int64_t)npix * L * 6);
-    hipLaunchKernelGGL(k_camera, dim3(grid_of(npix, 256)), dim3(256), 0, s, A, c->q[0]);
+    TIMED(K_CAMERA, hipLaunchKernelGGL(k_camera, dim3(grid_of(npix, 256)), dim3(256), 0, s, A, c->q[0]));
     // pass 1
     for (int k = 1; k <= L; ++k) {
         int in = (k - 1) & 1, out = k & 1;
-        hipLaunchKernelGGL(k_extend, dim3(grid_of(npix, kTraceBlock)), dim3(kTraceBlock), 0, s, c->view, c->q[in].q0,
-                           c->q[in].q1, &cnt->qcount[in], &cnt->qcount[out], c->hits, &cnt->rays);
-        hipLaunchKernelGGL(k_shade, dim3(grid_of(npix, 256)), dim3(256), 0, s, A, c->q[in], &cnt->qcount[in], c->hits,
-                           c->q[out], &cnt->qcount[out], c->V, &cnt->n_vertices, c->ev0, c->ev1, &cnt->n_events,
-                           c->slots, record ? c->recs : (neb_path_record*)nullptr);
+        TIMED(K_EXTEND_CAMERA,
+              hipLaunchKernelGGL(k_extend, dim3(grid_of(npix, kTraceBlock)), dim3(kTraceBlock), 0, s, c->view,
+                                 c->q[in].q0, c->q[in].q1, &cnt->qcount[in], &cnt->qcount[out], c->hits,
+                                 &cnt->camera_rays));
+        TIMED(K_SHADE, hipLaunchKernelGGL(k_shade, dim3(grid_of(npix, 256)), dim3(256), 0, s, A, c->q[in],
+                                          &cnt->qcount[in], c->hits, c->q[out], &cnt->qcount[out], c->V,
+                                          &cnt->n_vertices, c->ev0, c->ev1, &cnt->n_events, c->slots,
+                                          record ? c->recs : (neb_path_record*)nullptr));
     }
     // deposits
     if (c->prm.density_mode != NEB_DENSITY_ANALYTIC) {
+        hipError_t e;
+        prof_begin(c, K_OCTREE_INSERT, s);
         if (c->slots)
-            HIP_TRY(octree_increment_slots(c->oct, c->V.v0, c->slots, (int32_t)vcap, s));
+            e = octree_increment_slots(c->oct, c->V.v0, c->slots, (int32_t)vcap, s);
         else
-            HIP_TRY(octree_increment_vertices(c->oct, c->V.v0, &cnt->n_vertices, (int32_t)vcap, s));
+            e = octree_increment_vertices(c->oct, c->V.v0, &cnt->n_vertices, (int32_t)vcap, s);
+        prof_end(c, s);
+        HIP_TRY(e);
     }
     // pass 2
-    hipLaunchKernelGGL(k_density, dim3(grid_of(vcap, 256)), dim3(256), 0, s, A, c->V, &cnt->n_vertices, c->oct.nodes,
-                       c->oct.state, c->oct.prm);
-    hipLaunchKernelGGL(k_nee, dim3(grid_of(vcap, kTraceBlock)), dim3(kTraceBlock), 0, s, A, c->V, &cnt->n_vertices,
-                       Images{c->img, c->img + 3 * (size_t)npix, c->img + 6 * (size_t)npix}, c->pq[0], &cnt->pcount[0],
-                       cnt);
+    TIMED(K_DENSITY, hipLaunchKernelGGL(k_density, dim3(grid_of(vcap, 256)), dim3(256), 0, s, A, c->V,
+                                        &cnt->n_vertices, c->oct.nodes, c->oct.state, c->oct.prm));
+    TIMED(K_NEE, hipLaunchKernelGGL(k_nee, dim3(grid_of(vcap, kTraceBlock)), dim3(kTraceBlock), 0, s, A, c->V,
+                                    &cnt->n_vertices,
+                                    Images{c->img, c->img + 3 * (size_t)npix, c->img + 6 * (size_t)npix}, c->pq[0],
+                                    &cnt->pcount[0], cnt));
     if (A.photons && L >= 3) {
         // merge grid over this iteration's view vertices
-        hipLaunchKernelGGL(k_grid_count, dim3(grid_of(vcap, 256)), dim3(256), 0, s, c->mats, c->V, &cnt->n_vertices, c->G);
         int64_t n = (int64_t)c->G.T + 1;
         int nb = (int)((n + kScanTile - 1) / kScanTile);
+        prof_begin(c, K_GRID_BUILD, s);
+        hipLaunchKernelGGL(k_grid_count, dim3(grid_of(vcap, 256)), dim3(256), 0, s, c->mats, c->V, &cnt->n_vertices, c->G);
         hipLaunchKernelGGL(k_scan_tiles, dim3(nb), dim3(kScanBlock), 0, s, c->G.count, c->G.start, c->G.sums, n);
         hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, s, c->G.sums, nb);
         hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanBlock), 0, s, c->G.start, c->G.sums, n);
         hipLaunchKernelGGL(k_grid_scatter, dim3(grid_of(vcap, 256)), dim3(256), 0, s, c->mats, c->V, &cnt->n_vertices,
                            c->G);
+        prof_end(c, s);
         for (int j = 1; j <= L - 2; ++j) {
             int in = (j - 1) & 1, out = j & 1;
-            hipLaunchKernelGGL(k_extend, dim3(grid_of(vcap, kTraceBlock)), dim3(kTraceBlock), 0, s, c->view,
-                               c->pq[in].p0, c->pq[in].p1, &cnt->pcount[in], &cnt->pcount[out], c->hits, &cnt->rays);
-            hipLaunchKernelGGL(k_photon, dim3(grid_of(vcap, 256)), dim3(256), 0, s, A, c->pq[in], &cnt->pcount[in],
-                               c->hits, c->pq[out], &cnt->pcount[out], c->V, c->G,
-                               Images{c->img, c->img + 3 * (size_t)npix, c->img + 6 * (size_t)npix}, cnt);
+            TIMED(K_EXTEND_PHOTON,
+                  hipLaunchKernelGGL(k_extend, dim3(grid_of(vcap, kTraceBlock)), dim3(kTraceBlock), 0, s, c->view,
+                                     c->pq[in].p0, c->pq[in].p1, &cnt->pcount[in], &cnt->pcount[out], c->hits,
+                                     &cnt->photon_rays));
+            TIMED(K_PHOTON, hipLaunchKernelGGL(k_photon, dim3(grid_of(vcap, 256)), dim3(256), 0, s, A, c->pq[in],
+                                               &cnt->pcount[in], c->hits, c->pq[out], &cnt->pcount[out], c->V, c->G,
+                                               Images{c->img, c->img + 3 * (size_t)npix, c->img + 6 * (size_t)npix},
+                                               cnt));
         }
     }
     // pass 3
-    hipLaunchKernelGGL(k_finalize, dim3(grid_of(c->ecap, 256)), dim3(256), 0, s, A, c->ev0, c->ev1, &cnt->n_events,
-                       c->V.rho, Images{c->img, c->img + 3 * (size_t)npix, c->img + 6 * (size_t)npix});
+    TIMED(K_FINALIZE, hipLaunchKernelGGL(k_finalize, dim3(grid_of(c->ecap, 256)), dim3(256), 0, s, A, c->ev0, c->ev1,
+                                         &cnt->n_events, c->V.rho,
+                                         Images{c->img, c->img + 3 * (size_t)npix, c->img + 6 * (size_t)npix}));
     hipLaunchKernelGGL(k_iter_end, dim3(1), dim3(1), 0, s, cnt);
     HIP_TRY(hipGetLastError());
     if (record) c->first_iter_recorded = c->iter;
@@ -1189,7 +1258,13 @@ extern "C" neb_status neb_get_stats(neb_ctx c, neb_stats* out) {
     out->merges = (int64_t)h.merges;
     out->nee_visible = (int64_t)h.nee_visible;
     out->events = (int64_t)h.events;
-    out->rays = (int64_t)h.rays;
+    out->rays = (int64_t)(h.camera_rays + h.shadow_rays + h.photon_rays);
+    out->camera_rays = (int64_t)h.camera_rays;
+    out->shadow_rays = (int64_t)h.shadow_rays;
+    out->photon_items = (int64_t)h.photon_items;
+    out->photon_continued = (int64_t)h.photon_continued;
+    out->grid_cells = (int64_t)h.grid_cells;
+    out->candidates = (int64_t)h.candidates;
     if (c->has_scene) {
         int64_t info[8];
         neb_status st = octree_info(c->oct, c->last_stream, info);
@@ -1226,6 +1301,40 @@ extern "C" neb_status neb_get_octree(neb_ctx c, int32_t* nodes, int32_t cap, int
     return NEB_OK;
 }
 
+extern "C" neb_status neb_profile_kernels(neb_ctx c, int32_t enable) {
+    if (!c) return fail(NEB_ERR_INVALID_ARG, "null context");
+    if (enable) {
+        if (c->prof_ev.empty()) {
+            c->prof_ev.resize(4096);
+            c->prof_kid.resize(2048);
+            for (auto& e : c->prof_ev) HIP_TRY(hipEventCreate(&e));
+        }
+        prof_harvest(c);
+        for (int k = 0; k < 32; ++k) {
+            c->prof_ms[k] = 0.0;
+            c->prof_launches[k] = 0;
+        }
+    }
+    c->prof_on = enable != 0;
+    return NEB_OK;
+}
+
+extern "C" neb_status neb_get_kernel_profile(neb_ctx c, neb_kernel_time* out, int32_t cap, int32_t* n_out) {
+    if (!c || !n_out || (!out && cap > 0)) return fail(NEB_ERR_INVALID_ARG, "null pointer");
+    prof_harvest(c);
+    int n = 0;
+    for (int k = 0; k < K_COUNT && n < cap; ++k) {
+        if (c->prof_launches[k] == 0) continue;
+        std::memset(out[n].name, 0, sizeof(out[n].name));
+        std::strncpy(out[n].name, kKernelNames[k], sizeof(out[n].name) - 1);
+        out[n].launches = c->prof_launches[k];
+        out[n].total_ms = c->prof_ms[k];
+        ++n;
+    }
+    *n_out = n;
+    return NEB_OK;
+}
+
 extern "C" neb_status neb_reset(neb_ctx c) {
     if (!c) return fail(NEB_ERR_INVALID_ARG, "null context");
     HIP_TRY(hipDeviceSynchronize());
@@ -1247,6 +1356,7 @@ extern "C" void neb_destroy(neb_ctx c) {
     c->oct.nodes = nullptr;   // owned by allocs
     c->oct.state = nullptr;
     octree_release(c->oct);
+    for (auto& e : c->prof_ev) (void)hipEventDestroy(e);
     delete c;
 }
 

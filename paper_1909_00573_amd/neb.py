@@ -20,7 +20,8 @@ FLAG_SINGLE_THREAD_OCTREE, FLAG_RECORD_PATHS, FLAG_NO_PHOTONS = 1, 2, 4
 # every symbol the header declares
 EXPORTS = [
     "neb_create", "neb_set_scene", "neb_render", "neb_get_image", "neb_get_technique_images",
-    "neb_query_density", "neb_get_stats", "neb_get_path_records", "neb_get_octree", "neb_reset",
+    "neb_query_density", "neb_get_stats", "neb_get_path_records", "neb_get_octree", "neb_profile_kernels",
+    "neb_get_kernel_profile", "neb_reset",
     "neb_destroy", "neb_status_string", "neb_last_error",
     "neb_octree_create", "neb_octree_set_iteration", "neb_octree_increment", "neb_octree_density",
     "neb_octree_clear_counters", "neb_octree_export", "neb_octree_destroy",
@@ -43,10 +44,15 @@ class Stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "iterations", "paths", "vertices", "photons", "photon_segments", "merges", "nee_visible", "events",
         "rays", "oct_capacity", "oct_allocated", "oct_depth", "oct_overflow", "oct_ledger", "oct_deposits",
-        "oct_rejected", "oct_lost")]
+        "oct_rejected", "oct_lost", "photon_items", "photon_continued", "grid_cells", "candidates",
+        "camera_rays", "shadow_rays")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
 RECORD_DTYPE = np.dtype([("type", "<i4"), ("mat", "<i4"), ("prim", "<i4"), ("pos", "<f4", (3,))])
@@ -73,6 +79,8 @@ def lib():
             "neb_get_stats": ([_P, ctypes.POINTER(Stats)], i32),
             "neb_get_path_records": ([_P, _P, i64], i32),
             "neb_get_octree": ([_P, _P, i32, _P], i32),
+            "neb_profile_kernels": ([_P, i32], i32),
+            "neb_get_kernel_profile": ([_P, ctypes.POINTER(KernelTime), i32, ctypes.POINTER(i32)], i32),
             "neb_reset": ([_P], i32),
             "neb_destroy": ([_P], None),
             "neb_status_string": ([i32], ctypes.c_char_p),
@@ -211,6 +219,16 @@ class Renderer:
         _check(lib().neb_query_density(self.h, _dev_ptr(pos), _dev_ptr(nrm), pos.shape[0], _dev_ptr(out), 1,
                                        _stream(stream)))
         return out
+
+    def profile_kernels(self, enable=True):
+        _check(lib().neb_profile_kernels(self.h, int(enable)))
+
+    def kernel_profile(self):
+        arr = (KernelTime * 32)()
+        n = ctypes.c_int32()
+        _check(lib().neb_get_kernel_profile(self.h, arr, 32, ctypes.byref(n)))
+        return {arr[i].name.decode(): {"launches": int(arr[i].launches), "total_ms": float(arr[i].total_ms)}
+                for i in range(n.value)}
 
     def reset(self):
         _check(lib().neb_reset(self.h))
