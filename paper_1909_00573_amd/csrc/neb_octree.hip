@@ -24,17 +24,21 @@
 //  - the splitter writes the eight children's start count (the current
 //    iteration, i.e. parent/4) before it publishes the pointer with release
 //    ordering, instead of prefilling every unused node per iteration;
-//  - interior words are first read with cacheable loads: a negative word
-//    never changes again, a stale non-negative one falls through to the
-//    coherent read;
+//  - node words are read with cacheable loads; a negative word never
+//    changes again and every other decision is validated by the CAS;
 //  - nodes at depth 20 never split (FP32 positions cannot resolve finer
 //    cells).
 #include "neb_device.h"
 
 namespace neb {
 
-__device__ __forceinline__ int32_t ld_coherent(int32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Every decision taken on a loaded node word is either safe when the word is
+// stale (a negative word never changes again; a deferral is always allowed)
+// or validated by the compare-and-swap, which is resolved at the device's
+// coherence point and returns the current word.  Loads can therefore be
+// cacheable: no acquire, no L2 invalidation per tree level.
+__device__ __forceinline__ int32_t ld_node(const int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 enum { kInsRejected = 0, kInsCounted = 1, kInsDeferred = 2 };
@@ -45,15 +49,15 @@ __device__ __forceinline__ int oct_insert(int32_t* nodes, OctState* st, const Oc
     if (!oct_norm(P, p, q)) return kInsRejected;
     int32_t idx = 0;
     int level = 0;
+    int32_t v = ld_node(nodes);
     for (int step = 0; step < 4096; ++step) {
-        int32_t v = __hip_atomic_load(nodes + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (v >= 0) v = ld_coherent(nodes + idx);
         if (v < 0) {
             ++level;
             float sc = (float)(1 << level);
             int32_t c = (((int32_t)(q[0] * sc)) & 1) | ((((int32_t)(q[1] * sc)) & 1) << 1) |
                         ((((int32_t)(q[2] * sc)) & 1) << 2);
             idx = c - v;
+            v = ld_node(nodes + idx);
             continue;
         }
         int32_t cnt = v & kOctCountMask;
@@ -61,8 +65,10 @@ __device__ __forceinline__ int oct_insert(int32_t* nodes, OctState* st, const Oc
         if (can_split && cnt >= P.split_count) return kInsDeferred;  // a split is being published
         int32_t expected = v;
         if (!__hip_atomic_compare_exchange_strong(nodes + idx, &expected, v + 1, __ATOMIC_RELAXED,
-                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-            continue;  // another lane changed the word: it made progress
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            v = expected;  // the current word: retry with it
+            continue;
+        }
         if (can_split && cnt + 1 == P.split_count) {
             int32_t child = atomicAdd(&st->alloc, 8);
             if (child >= P.capacity) {
@@ -70,11 +76,17 @@ __device__ __forceinline__ int oct_insert(int32_t* nodes, OctState* st, const Oc
                 __hip_atomic_fetch_or(nodes + idx, kOctFailed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 atomicAdd(&st->overflow, 1);
             } else {
+                // children start at the current iteration (parent / 4).  The
+                // wait retires the eight atomic writes (CDNA tracks them in
+                // vmcnt) before the pointer is published, so a lane that
+                // follows the pointer and CASes a child compares against the
+                // started count, never against the pool's zero.
 #pragma unroll
                 for (int c = 0; c < 8; ++c)
-                    __hip_atomic_store(nodes + child + c, P.iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_exchange(nodes + child + c, P.iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                __hip_atomic_exchange(nodes + idx, -child, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 atomicAdd(&st->block_iter_sum, (unsigned long long)P.iter);
-                __hip_atomic_store(nodes + idx, -child, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 atomicMax(&st->depth, level + 1);
             }
         }

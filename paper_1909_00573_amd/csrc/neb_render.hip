@@ -502,98 +502,170 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_add(int32_t* out, const int
 }
 
 // ---------------------------------------------------------------------------
-// photon bounce: merge with view vertices around the hit, then scatter
+// photon bounce: merge with view vertices around the hit, then scatter.
+// One photon per lane (many independent candidate streams in flight, which
+// is what a gather over cache-resident records needs).  Each lane walks the
+// concatenated candidate ranges of its photon's cells; accepted (lane,
+// vertex) pairs are compacted into an LDS queue and evaluated 64 at a time
+// by the whole wave, so the BSDF, the MIS weight and the image atomics run
+// with every lane busy instead of with the ~10 % of lanes that accepted.
+// One wave per block.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_photon(RenderArgs A, PhotonQ in, const int32_t* count_in, const int2* hits,
-                                                PhotonQ out, int32_t* count_out, VertexStore V, Grid G, Images img,
-                                                Counters* cnt) {
-    int n = *count_in;
+__global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const int32_t* count_in, const int2* hits,
+                                               PhotonQ out, int32_t* count_out, VertexStore V, Grid G, Images img,
+                                               Counters* cnt) {
+    __shared__ int2 queue[128];
+    __shared__ float4 tp[64][2];  // per lane's photon: (-d, h*U), (Phi / (pi r^2), bounce)
+    const int lane = threadIdx.x;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int n = *count_in;
     const SceneView& S = A.S;
     unsigned segs = 0, merges = 0, items = 0, cont = 0, cells = 0, cands = 0;
     const float r2 = A.r * A.r;
     const float kern = 1.0f / A.r2pi;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        int2 h = hits[i];
-        bool go = false;
-        Sample s;
-        s.ev = 0;
-        ++items;
-        float4 b0 = in.p0[i], b1 = in.p1[i], b2 = in.p2[i];
-        float U = in.pu[i];
+    const float cell = 1.0f / G.inv_cell;
+    int qn = 0;  // queue length, identical in every lane
+
+    auto flush = [&](int count) {
+        if (lane < count) {
+            int2 pr = queue[lane];
+            float4 t0 = tp[pr.x][0], t1 = tp[pr.x][1];
+            int vid = pr.y;
+            float4 v1 = V.v1[vid];
+            int packed = fbits(v1.w);
+            int k = packed & 0xFF;
+            if (k + fbits(t1.w) + 1 <= A.L) {
+                const neb_material& mv = S.mats[packed >> 8];
+                float4 v2 = V.v2[vid];
+                f3 nv = xyz(v1), wv = xyz(v2), wd = xyz(t0);
+                f3 f = bsdf_f(mv, nv, wv, wd);
+                if (!is_zero3(f)) {
+                    float4 v3 = V.v3[vid];
+                    float T = bsdf_pdf(mv, nv, wv, wd) * t0.w;
+                    float C = 1.0f + ((k >= 2) ? bsdf_pdf(mv, nv, wd, wv) * v3.w * v2.w : 0.f);
+                    int vpix = fbits(V.v0[vid].w);
+                    atomic_add3(img.P, vpix, xyz(v3) * f * xyz(t1) * (1.0f / (C + T)));
+                    ++merges;
+                }
+            }
+        }
+    };
+
+    for (int base = blockIdx.x * 64; base < n; base += gridDim.x * 64) {
+        int i = base + lane;
+        bool valid = i < n;
+        int2 h = valid ? hits[i] : make_int2(0, -1);
+        float4 b0 = make_float4(0.f, 0.f, 0.f, 0.f), b1 = b0, b2 = b0;
+        float U = 0.f;
+        if (valid) {
+            b0 = in.p0[i];
+            b1 = in.p1[i];
+            b2 = in.p2[i];
+            U = in.pu[i];
+            ++items;
+        }
+        bool hit = h.y >= 0;
         int code = fbits(b1.w);
-        int j = code & 15;
-        int odepth = code >> 4;
-        int opix = fbits(b0.w);
-        f3 y, ny, d = xyz(b1);
+        int j = code & 15, odepth = code >> 4, opix = fbits(b0.w);
+        f3 d = xyz(b1);
+        f3 y = mk3(0.f, 0.f, 0.f), ny = mk3(0.f, 0.f, 1.f);
         float hh = 0.f;
         int mid = 0;
-        if (h.y >= 0) {
+        if (hit) {
             ++segs;
-            float t = ibits(h.x);
-            y = xyz(b0) + d * t;
+            y = xyz(b0) + d * ibits(h.x);
             float4 pn = S.prim_n[h.y];
             ny = xyz(pn);
             mid = fbits(pn.w);
-            const neb_material& my = S.mats[mid];
-            f3 phi = xyz(b2);
             hh = b2.w / fabsf(dot3(ny, d));
-            f3 wd = -d;
-            if (!mat_delta(my.type)) {
-                float rr = A.r * 1.00001f;
-                int lox = (int)floorf((y.x - rr) * G.inv_cell), hix = (int)floorf((y.x + rr) * G.inv_cell);
-                int loy = (int)floorf((y.y - rr) * G.inv_cell), hiy = (int)floorf((y.y + rr) * G.inv_cell);
-                int loz = (int)floorf((y.z - rr) * G.inv_cell), hiz = (int)floorf((y.z + rr) * G.inv_cell);
-                // cells are wider than the ball's diameter: at most two per axis
-                hix = min(hix, lox + 1);
-                hiy = min(hiy, loy + 1);
-                hiz = min(hiz, loz + 1);
-                uint32_t seen[8];
-                int ns = 0;
-                for (int cz = loz; cz <= hiz; ++cz)
-                    for (int cy = loy; cy <= hiy; ++cy)
-                        for (int cx = lox; cx <= hix; ++cx) {
-                            uint32_t hc = cell_hash(cx, cy, cz, G.T);
-                            bool dup = false;
-                            for (int q = 0; q < ns; ++q) dup |= seen[q] == hc;
-                            if (dup || ns == 8) continue;
-                            seen[ns++] = hc;
-                            ++cells;
-                            int e0 = G.start[hc], e1 = G.start[hc + 1];
-                            cands += (unsigned)(e1 - e0);
-                            for (int e = e0; e < e1; ++e) {
-                                float4 c = G.sorted[e];
-                                f3 dv = xyz(c) - y;
-                                if (dot3(dv, dv) >= r2) continue;
-                                int vid = fbits(c.w);
-                                float4 v1 = V.v1[vid];
-                                int packed = fbits(v1.w);
-                                int k = packed & 0xFF;
-                                if (k + j + 1 > A.L) continue;
-                                const neb_material& mv = S.mats[packed >> 8];
-                                float4 v2 = V.v2[vid];
-                                f3 nv = xyz(v1), wv = xyz(v2);
-                                f3 f = bsdf_f(mv, nv, wv, wd);
-                                if (is_zero3(f)) continue;
-                                float4 v3 = V.v3[vid];
-                                float T = bsdf_pdf(mv, nv, wv, wd) * hh * U;
-                                float C = 1.0f + ((k >= 2) ? bsdf_pdf(mv, nv, wd, wv) * v3.w * v2.w : 0.f);
-                                float w = 1.0f / (C + T);
-                                int vpix = fbits(V.v0[vid].w);
-                                atomic_add3(img.P, vpix, xyz(v3) * f * phi * (w * kern));
-                                ++merges;
-                            }
-                        }
+        }
+        const neb_material& my = S.mats[mid];
+        bool mergeable = hit && !mat_delta(my.type);
+        tp[lane][0] = f4(-d, hh * U);
+        tp[lane][1] = f4(xyz(b2) * kern, ibits(j));
+        // candidate ranges of the (at most 8) cells the ball touches
+        int lo[8], pre[9];
+        pre[0] = 0;
+        {
+            float rr = A.r * 1.00001f;
+            int lx = (int)floorf((y.x - rr) * G.inv_cell), hx = min((int)floorf((y.x + rr) * G.inv_cell), lx + 1);
+            int ly = (int)floorf((y.y - rr) * G.inv_cell), hy = min((int)floorf((y.y + rr) * G.inv_cell), ly + 1);
+            int lz = (int)floorf((y.z - rr) * G.inv_cell), hz = min((int)floorf((y.z + rr) * G.inv_cell), lz + 1);
+            uint32_t seen[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                int cx = lx + (c & 1), cy = ly + ((c >> 1) & 1), cz = lz + ((c >> 2) & 1);
+                bool use = mergeable && cx <= hx && cy <= hy && cz <= hz;
+                // skip cells whose box is farther than r from the hit
+                float dx = fmaxf(fmaxf(cx * cell - y.x, y.x - (cx + 1) * cell), 0.f);
+                float dy = fmaxf(fmaxf(cy * cell - y.y, y.y - (cy + 1) * cell), 0.f);
+                float dz = fmaxf(fmaxf(cz * cell - y.z, y.z - (cz + 1) * cell), 0.f);
+                use = use && dx * dx + dy * dy + dz * dz <= r2 * 1.0001f;
+                uint32_t hc = cell_hash(cx, cy, cz, G.T);
+                seen[c] = use ? hc : 0xFFFFFFFFu;
+#pragma unroll
+                for (int q = 0; q < c; ++q) use = use && seen[q] != hc;
+                int e0 = 0, e1 = 0;
+                if (use) {
+                    e0 = G.start[hc];
+                    e1 = G.start[hc + 1];
+                    ++cells;
+                }
+                lo[c] = e0;
+                pre[c + 1] = pre[c] + (e1 - e0);
             }
-            if (j < A.L - 2 && !mat_black(my)) {
-                U4 u = uniforms(A.k0, A.k1, (uint32_t)opix, (uint32_t)A.iter, (uint32_t)(16 * odepth + j), kTagPhoton);
-                s = bsdf_sample(my, ny, wd, u);
-                go = s.ev != 0;
+        }
+        int total = pre[8];
+        cands += (unsigned)total;
+        __syncthreads();
+        for (int k = 0;; ++k) {
+            bool act = k < total;
+            if (!__any(act)) break;
+            bool acc = false;
+            int vid = 0;
+            if (act) {
+                int e = 0;
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    if (k >= pre[c] && k < pre[c + 1]) e = lo[c] + (k - pre[c]);
+                float4 cd = G.sorted[e];
+                f3 dv = xyz(cd) - y;
+                acc = dot3(dv, dv) < r2;
+                vid = fbits(cd.w);
             }
+            unsigned long long m = __ballot(acc);
+            if (m) {
+                if (acc) queue[qn + __popcll(m & below)] = make_int2(lane, vid);
+                qn += __popcll(m);
+                if (qn >= 64) {
+                    __syncthreads();
+                    flush(64);
+                    __syncthreads();
+                    int2 rest = lane < qn - 64 ? queue[64 + lane] : make_int2(0, 0);
+                    __syncthreads();
+                    if (lane < qn - 64) queue[lane] = rest;
+                    qn -= 64;
+                    __syncthreads();
+                }
+            }
+        }
+        if (qn > 0) {
+            __syncthreads();
+            flush(qn);
+            qn = 0;
+        }
+        // scatter
+        bool go = false;
+        Sample s;
+        s.ev = 0;
+        if (hit && j < A.L - 2 && !mat_black(my)) {
+            U4 u = uniforms(A.k0, A.k1, (uint32_t)opix, (uint32_t)A.iter, (uint32_t)(16 * odepth + j), kTagPhoton);
+            s = bsdf_sample(my, ny, -d, u);
+            go = s.ev != 0;
         }
         int slot = wave_reserve(count_out, go);
         cont += go;
         if (go) {
-            const neb_material& my = S.mats[mid];
             f3 wd = -d;
             float prev = bsdf_pdf(my, ny, s.dir, wd);
             float Un = (mat_delta(my.type) ? 0.f : 1.f) + prev * hh * U;
@@ -603,6 +675,7 @@ __global__ void __launch_bounds__(256) k_photon(RenderArgs A, PhotonQ in, const 
             out.p2[slot] = f4(xyz(b2) * s.w, hp);
             out.pu[slot] = Un;
         }
+        __syncthreads();
     }
     wave_add_u64(&cnt->photon_segments, segs);
     wave_add_u64(&cnt->merges, merges);
@@ -1117,7 +1190,7 @@ static neb_status render_iteration(neb_ctx c, hipStream_t s) {
                   hipLaunchKernelGGL(k_extend, dim3(grid_of(vcap, kTraceBlock)), dim3(kTraceBlock), 0, s, c->view,
                                      c->pq[in].p0, c->pq[in].p1, &cnt->pcount[in], &cnt->pcount[out], c->hits,
                                      &cnt->photon_rays));
-            TIMED(K_PHOTON, hipLaunchKernelGGL(k_photon, dim3(grid_of(vcap, 256)), dim3(256), 0, s, A, c->pq[in],
+            TIMED(K_PHOTON, hipLaunchKernelGGL(k_photon, dim3(grid_of(vcap, 256)), dim3(64), 0, s, A, c->pq[in],
                                                &cnt->pcount[in], c->hits, c->pq[out], &cnt->pcount[out], c->V, c->G,
                                                Images{c->img, c->img + 3 * (size_t)npix, c->img + 6 * (size_t)npix},
                                                cnt));
