@@ -36,7 +36,7 @@ def algorithmic_bytes(stats, name, npix, vertices):
         # one packed (pos, id) per candidate, three vertex words + pixel and
         # a 3-float image atomic (read + write) per accepted merge
         return (s["photon_items"] * (48 + 4 + 8) + s["photon_continued"] * 52 + s["grid_cells"] * 8 +
-                s["candidates"] * 16 + s["merges"] * (52 + 24))
+                s["candidates"] * 16 + s["merges"] * (52 + 24))  # a merge reads 52 of its 64-byte record
     if name == "shade":
         rays = s["rays_camera"]
         return rays * (64 + 8) + vertices * 64 + s["continued_camera"] * 64 + s["events"] * 32
@@ -177,6 +177,9 @@ def main():
                    "triangles": sc.n_tris, "octree_capacity": sc.octree_capacity, "merge_radius": sc.merge_radius},
         "octree": {"ledger": st["oct_ledger"], "deposits": st["oct_deposits"], "nodes": st["oct_allocated"],
                    "depth": st["oct_depth"], "overflow": st["oct_overflow"]},
+        "work_per_step": {k: round((st[k] - s0[k]) / args.steps) for k in
+                          ("vertices", "photons", "photon_segments", "merges", "candidates", "grid_cells",
+                           "camera_rays", "shadow_rays", "bvh_nodes", "bvh_tris")},
         "roofline": roof, "kernels": kernels,
     }
     if not args.no_cpu_baseline:

@@ -109,6 +109,8 @@ typedef struct {
     int64_t photon_items, photon_continued, grid_cells, candidates;
     /* rays = camera_rays + shadow_rays + photon rays */
     int64_t camera_rays, shadow_rays;
+    /* BVH nodes fetched and triangles tested by all traversals */
+    int64_t bvh_nodes, bvh_tris;
 } neb_stats;
 
 /* per-kernel device time, collected with HIP events on the launch stream */

@@ -396,13 +396,15 @@ __device__ __forceinline__ bool box_hit(const RayPre& r, float lx, float ly, flo
 // closest hit; ties on t go to the lowest primitive id.  stack: this lane's
 // LDS slots, stride kTraceBlock.  any_hit: stop at the first hit below tmax.
 template <bool kAnyHit>
-__device__ __forceinline__ int trace(const SceneView& S, f3 o, f3 d, float tmax, float& t_out, int* stack) {
+__device__ __forceinline__ int trace(const SceneView& S, f3 o, f3 d, float tmax, float& t_out, int* stack,
+                                     unsigned& nodes, unsigned& tris) {
     RayPre r = ray_pre(o, d);
     float best = tmax;
     int prim = -1;
     int node = 0, sp = 0;
     for (;;) {
         const float4* nd = S.bvh + 4 * node;
+        ++nodes;
         float4 a = nd[0], b = nd[1], c = nd[2];
         int4 lk = *reinterpret_cast<const int4*>(nd + 3);
         float tn0, tn1;
@@ -410,6 +412,7 @@ __device__ __forceinline__ int trace(const SceneView& S, f3 o, f3 d, float tmax,
         bool h1 = box_hit(r, b.z, b.w, c.x, c.y, c.z, c.w, best, tn1);
         // leaves are tested in place
         if (h0 && lk.z > 0) {
+            tris += lk.z;
             for (int k = lk.x; k < lk.x + lk.z; ++k) {
                 const float4* tp = S.tri + 3 * k;
                 float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
@@ -424,6 +427,7 @@ __device__ __forceinline__ int trace(const SceneView& S, f3 o, f3 d, float tmax,
             h0 = false;
         }
         if (h1 && lk.w > 0) {
+            tris += lk.w;
             for (int k = lk.y; k < lk.y + lk.w; ++k) {
                 const float4* tp = S.tri + 3 * k;
                 float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];

@@ -15,6 +15,7 @@ constexpr int32_t kOctCountMask = 0x3FFFFFFF;
 constexpr int kMaxPathLen = 16;
 constexpr int kBvhStack = 48;              // LDS traversal stack entries per lane
 constexpr int kTraceBlock = 64;            // threads per traversal block (one wave)
+constexpr int kTraceBlocksPerCU = 13;      // resident traversal blocks per CU (LDS bound)
 
 constexpr uint32_t kTagCamera = 1, kTagBsdf = 2, kTagNee = 3, kTagPhoton = 4;
 
@@ -80,6 +81,7 @@ struct Counters {
     unsigned long long paths, vertices, photons, photon_segments, merges, nee_visible, events;
     unsigned long long camera_rays, shadow_rays, photon_rays;
     unsigned long long photon_items, photon_continued, grid_cells, candidates;
+    unsigned long long bvh_nodes, bvh_tris;   // traversal work of closest-hit and shadow rays
 };
 
 // octree kernels (neb_octree.hip)

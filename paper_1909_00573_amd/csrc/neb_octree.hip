@@ -43,6 +43,29 @@ __device__ __forceinline__ int32_t ld_node(const int32_t* p) {
 
 enum { kInsRejected = 0, kInsCounted = 1, kInsDeferred = 2 };
 
+// The split of a full leaf: allocate 8 children, start them at the current
+// iteration (parent / 4), publish the pointer.  Called by exactly one lane,
+// the one whose CAS brought the count to the threshold.
+__device__ __forceinline__ void oct_split(int32_t* nodes, OctState* st, const OctParams& P, int32_t idx, int level) {
+    int32_t child = atomicAdd(&st->alloc, 8);
+    if (child >= P.capacity) {
+        atomicExch(&st->alloc, P.capacity + 1);
+        __hip_atomic_fetch_or(nodes + idx, kOctFailed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        atomicAdd(&st->overflow, 1);
+        return;
+    }
+    // the wait retires the eight atomic writes (CDNA tracks them in vmcnt)
+    // before the pointer is published, so a lane that follows the pointer
+    // and CASes a child compares against the started count
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+        __hip_atomic_exchange(nodes + child + c, P.iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __hip_atomic_exchange(nodes + idx, -child, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    atomicAdd(&st->block_iter_sum, (unsigned long long)P.iter);
+    atomicMax(&st->depth, level + 1);
+}
+
 // one deposit attempt; never waits for another lane
 __device__ __forceinline__ int oct_insert(int32_t* nodes, OctState* st, const OctParams& P, f3 p) {
     float q[3];
@@ -69,30 +92,78 @@ __device__ __forceinline__ int oct_insert(int32_t* nodes, OctState* st, const Oc
             v = expected;  // the current word: retry with it
             continue;
         }
-        if (can_split && cnt + 1 == P.split_count) {
-            int32_t child = atomicAdd(&st->alloc, 8);
-            if (child >= P.capacity) {
-                atomicExch(&st->alloc, P.capacity + 1);
-                __hip_atomic_fetch_or(nodes + idx, kOctFailed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                atomicAdd(&st->overflow, 1);
-            } else {
-                // children start at the current iteration (parent / 4).  The
-                // wait retires the eight atomic writes (CDNA tracks them in
-                // vmcnt) before the pointer is published, so a lane that
-                // follows the pointer and CASes a child compares against the
-                // started count, never against the pool's zero.
-#pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    __hip_atomic_exchange(nodes + child + c, P.iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-                __hip_atomic_exchange(nodes + idx, -child, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                atomicAdd(&st->block_iter_sum, (unsigned long long)P.iter);
-                atomicMax(&st->depth, level + 1);
-            }
-        }
+        if (can_split && cnt + 1 == P.split_count) oct_split(nodes, st, P, idx, level);
         return kInsCounted;
     }
     return kInsDeferred;  // heavy contention: try again after the launch
+}
+
+// Wave-cooperative deposit of one point per lane.  Lanes that reach the
+// same node word with the same observed value form a group; its first lane
+// adds the group's size (capped at the split threshold) with one CAS, the
+// lanes beyond the cap defer, and the lane whose addition reaches the
+// threshold splits.  A burst of deposits into one cell (every deposit of
+// the first iteration starts at the root) thus costs one atomic per wave
+// instead of one per lane.  Must be called by all lanes of the wave.
+__device__ __forceinline__ int oct_insert_wave(int32_t* nodes, OctState* st, const OctParams& P, bool has, f3 p) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    float q[3] = {0.f, 0.f, 0.f};
+    bool active = has && oct_norm(P, p, q);
+    int result = (has && !active) ? kInsRejected : kInsDeferred;
+    int32_t idx = 0;
+    int level = 0;
+    int32_t v = active ? ld_node(nodes) : 0;
+    for (int step = 0; step < 4096; ++step) {
+        if (!__any(active)) break;
+        if (active && v < 0) {
+            ++level;
+            float sc = (float)(1 << level);
+            int32_t c = (((int32_t)(q[0] * sc)) & 1) | ((((int32_t)(q[1] * sc)) & 1) << 1) |
+                        ((((int32_t)(q[2] * sc)) & 1) << 2);
+            idx = c - v;
+            v = ld_node(nodes + idx);
+        }
+        bool want = active && v >= 0;
+        unsigned long long pend = __ballot(want);
+        while (pend) {
+            int leader = __ffsll((long long)pend) - 1;
+            int32_t lidx = __shfl(idx, leader, 64);
+            int32_t lv = __shfl(v, leader, 64);
+            int llevel = __shfl(level, leader, 64);
+            bool in = want && idx == lidx && v == lv;
+            unsigned long long gm = __ballot(in);
+            int k = __popcll(gm);
+            int32_t cnt = lv & kOctCountMask;
+            bool can_split = !(lv & kOctFailed) && llevel < kOctMaxDepth;
+            int m = can_split ? min(k, max(0, P.split_count - cnt)) : k;
+            int ok = 0;
+            int32_t cur = lv;
+            if (lane == leader && m > 0) {
+                int32_t e = lv;
+                ok = __hip_atomic_compare_exchange_strong(nodes + lidx, &e, lv + m, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                cur = e;
+                if (ok && can_split && cnt + m == P.split_count) oct_split(nodes, st, P, lidx, llevel);
+            }
+            ok = __shfl(ok, leader, 64);
+            cur = __shfl(cur, leader, 64);
+            if (in) {
+                if (m == 0) {  // full leaf, split in flight: retry after the launch
+                    result = kInsDeferred;
+                    active = false;
+                } else if (ok) {
+                    result = __popcll(gm & below) < m ? kInsCounted : kInsDeferred;
+                    active = false;
+                } else {
+                    v = cur;  // the word changed: retry with its current value
+                }
+            }
+            want = want && !in;
+            pend &= ~gm;
+        }
+    }
+    return result;
 }
 
 __device__ __forceinline__ void oct_account(OctState* st, int counted, int rejected) {
@@ -125,17 +196,20 @@ __global__ void __launch_bounds__(256) k_oct_insert(int32_t* nodes, OctState* st
         int64_t stride_all = (int64_t)gridDim.x * blockDim.x;
         int64_t nn = (n + stride_all - 1) / stride_all * stride_all;  // uniform trip count per wave
         for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += stride_all) {
-            int r = -1;
+            bool has = i < n;
             int32_t item = 0;
-            if (i < n) {
+            f3 pt = mk3(0.f, 0.f, 0.f);
+            if (has) {
                 item = items ? items[i] : (int32_t)i;
                 const float* pp = pos + (size_t)stride * item;
-                r = oct_insert(nodes, st, P, mk3(pp[0], pp[1], pp[2]));
-                counted += r == kInsCounted;
-                rejected += r == kInsRejected;
+                pt = mk3(pp[0], pp[1], pp[2]);
             }
-            int slot = wave_reserve(defer_count, r == kInsDeferred);
-            if (r == kInsDeferred) defer_out[slot] = item;
+            int r = oct_insert_wave(nodes, st, P, has, pt);
+            bool defer = has && r == kInsDeferred;
+            counted += has && r == kInsCounted;
+            rejected += has && r == kInsRejected;
+            int slot = wave_reserve(defer_count, defer);
+            if (defer) defer_out[slot] = item;
         }
     }
     oct_account(st, counted, rejected);

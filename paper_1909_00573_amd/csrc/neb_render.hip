@@ -49,12 +49,18 @@ struct VertexStore {
 struct Images {
     float *e, *E, *P;
 };
+// Merge grid keyed by (cell hash, depth - 1): the records of one cell are
+// ordered by view-vertex depth, so the vertices a photon after j bounces may
+// merge with (depth <= maxlen - 1 - j) form one contiguous prefix.
 struct Grid {
-    int32_t* count;   // T + 1 entries (count[T] stays 0)
-    int32_t* start;   // T + 1 entries
-    float4* sorted;   // (pos, vertex index) in cell order
-    int32_t* sums;    // scan block sums
-    int32_t T;
+    int32_t* count;   // T * D + 1 entries (the last stays 0)
+    int32_t* start;   // T * D + 1 entries
+    float4* sorted;   // (pos, vertex index) in (cell, depth) order
+    float4* mrec;     // 4 per record, same order: what a merge needs of the view vertex:
+                      // (n, depth | material << 8), (wo, B), (tau, g), (pixel, -, -, -)
+    int32_t* sums;    // scan block sums, all levels
+    int32_t T;        // hash buckets (power of two)
+    int32_t D;        // depth classes = maxlen - 1
     float inv_cell;
 };
 
@@ -158,18 +164,20 @@ __global__ void __launch_bounds__(256) k_camera(RenderArgs A, PathQ q) {
 __global__ void __launch_bounds__(kTraceBlock) k_extend(SceneView S, const float4* __restrict__ org,
                                                         const float4* __restrict__ dir, const int32_t* count,
                                                         int32_t* next_count, int2* __restrict__ hits,
-                                                        unsigned long long* rays) {
+                                                        unsigned long long* rays, Counters* cnt) {
     __shared__ int stack[kBvhStack * kTraceBlock];
     int n = *count;
     if (blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
-    unsigned traced = 0;
+    unsigned traced = 0, nodes = 0, tris = 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         float t;
-        int prim = trace<false>(S, xyz(org[i]), xyz(dir[i]), INFINITY, t, stack + threadIdx.x);
+        int prim = trace<false>(S, xyz(org[i]), xyz(dir[i]), INFINITY, t, stack + threadIdx.x, nodes, tris);
         hits[i] = make_int2(fbits(t), prim);
         ++traced;
     }
     wave_add_u64(rays, traced);
+    wave_add_u64(&cnt->bvh_nodes, nodes);
+    wave_add_u64(&cnt->bvh_tris, tris);
 }
 
 __global__ void __launch_bounds__(256) k_shade(RenderArgs A, PathQ in, const int32_t* count_in, const int2* hits,
@@ -338,7 +346,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_nee(RenderArgs A, VertexStore V
     __shared__ int stack[kBvhStack * kTraceBlock];
     int n = *n_vertices;
     const SceneView& S = A.S;
-    unsigned vis = 0, emitted = 0, rays = 0;
+    unsigned vis = 0, emitted = 0, rays = 0, nodes = 0, tris = 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         float4 a0 = V.v0[i], a1 = V.v1[i], a2 = V.v2[i], a3 = V.v3[i];
         float rho = V.rho[i];
@@ -356,7 +364,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_nee(RenderArgs A, VertexStore V
             float sl = sqrtf(dot3(sd, sd));
             float tt;
             ++rays;
-            ok = trace<true>(S, so, sd * (1.0f / sl), (1.0f - 1e-5f) * sl, tt, stack + threadIdx.x) < 0;
+            ok = trace<true>(S, so, sd * (1.0f / sl), (1.0f - 1e-5f) * sl, tt, stack + threadIdx.x, nodes, tris) < 0;
         }
         bool photon = false;
         Sample s;
@@ -397,6 +405,8 @@ __global__ void __launch_bounds__(kTraceBlock) k_nee(RenderArgs A, VertexStore V
     wave_add_u64(&cnt->nee_visible, vis);
     wave_add_u64(&cnt->photons, emitted);
     wave_add_u64(&cnt->shadow_rays, rays);
+    wave_add_u64(&cnt->bvh_nodes, nodes);
+    wave_add_u64(&cnt->bvh_tris, tris);
 }
 
 // ---------------------------------------------------------------------------
@@ -410,13 +420,17 @@ __device__ __forceinline__ uint32_t point_hash(f3 p, float inv_cell, int32_t T) 
     return cell_hash((int)floorf(p.x * inv_cell), (int)floorf(p.y * inv_cell), (int)floorf(p.z * inv_cell), T);
 }
 
+__device__ __forceinline__ int64_t grid_key(const Grid& G, uint32_t h, int depth) {
+    return (int64_t)h * G.D + (depth - 1);
+}
+
 __global__ void __launch_bounds__(256) k_grid_count(const neb_material* mats, VertexStore V, const int32_t* n_vertices,
                                                     Grid G) {
     int n = *n_vertices;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        int mid = fbits(V.v1[i].w) >> 8;
-        if (mat_delta(mats[mid].type)) continue;
-        atomicAdd(&G.count[point_hash(xyz(V.v0[i]), G.inv_cell, G.T)], 1);
+        int packed = fbits(V.v1[i].w);
+        if (mat_delta(mats[packed >> 8].type)) continue;
+        atomicAdd(&G.count[grid_key(G, point_hash(xyz(V.v0[i]), G.inv_cell, G.T), packed & 0xFF)], 1);
     }
 }
 
@@ -424,12 +438,17 @@ __global__ void __launch_bounds__(256) k_grid_scatter(const neb_material* mats, 
                                                       const int32_t* n_vertices, Grid G) {
     int n = *n_vertices;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        int mid = fbits(V.v1[i].w) >> 8;
-        if (mat_delta(mats[mid].type)) continue;
+        int packed = fbits(V.v1[i].w);
+        if (mat_delta(mats[packed >> 8].type)) continue;
         f3 p = xyz(V.v0[i]);
-        uint32_t h = point_hash(p, G.inv_cell, G.T);
-        int pos = G.start[h] + atomicSub(&G.count[h], 1) - 1;
+        int64_t key = grid_key(G, point_hash(p, G.inv_cell, G.T), packed & 0xFF);
+        int pos = G.start[key] + atomicSub(&G.count[key], 1) - 1;
         G.sorted[pos] = f4(p, ibits(i));
+        float4* m = G.mrec + 4 * (size_t)pos;
+        m[0] = V.v1[i];
+        m[1] = V.v2[i];
+        m[2] = V.v3[i];
+        m[3] = make_float4(V.v0[i].w, 0.f, 0.f, 0.f);
     }
 }
 
@@ -501,6 +520,29 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_add(int32_t* out, const int
         if (base + k < n) out[base + k] += add;
 }
 
+// scratch ints needed by scan_exclusive for n elements (all levels)
+static int64_t scan_scratch(int64_t n) {
+    int64_t tot = 0;
+    while (n > 1) {
+        n = (n + kScanTile - 1) / kScanTile;
+        tot += n;
+    }
+    return std::max<int64_t>(tot, 1);
+}
+
+// exclusive prefix sum of n ints (in and out may alias): tiles of 4096,
+// then the tile sums recursively, then the offsets added back
+static void scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* scratch, hipStream_t s) {
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, out, scratch, n);
+    if (nb <= kScanTile) {
+        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, s, scratch, (int32_t)nb);
+    } else {
+        scan_exclusive(scratch, scratch, nb, scratch + nb, s);
+    }
+    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kScanBlock), 0, s, out, scratch, n);
+}
+
 // ---------------------------------------------------------------------------
 // photon bounce: merge with view vertices around the hit, then scatter.
 // One photon per lane (many independent candidate streams in flight, which
@@ -530,20 +572,20 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
         if (lane < count) {
             int2 pr = queue[lane];
             float4 t0 = tp[pr.x][0], t1 = tp[pr.x][1];
-            int vid = pr.y;
-            float4 v1 = V.v1[vid];
+            const float4* mr = G.mrec + 4 * (size_t)pr.y;  // one 64-byte record
+            float4 v1 = mr[0];
             int packed = fbits(v1.w);
             int k = packed & 0xFF;
             if (k + fbits(t1.w) + 1 <= A.L) {
                 const neb_material& mv = S.mats[packed >> 8];
-                float4 v2 = V.v2[vid];
+                float4 v2 = mr[1];
                 f3 nv = xyz(v1), wv = xyz(v2), wd = xyz(t0);
                 f3 f = bsdf_f(mv, nv, wv, wd);
                 if (!is_zero3(f)) {
-                    float4 v3 = V.v3[vid];
+                    float4 v3 = mr[2];
                     float T = bsdf_pdf(mv, nv, wv, wd) * t0.w;
                     float C = 1.0f + ((k >= 2) ? bsdf_pdf(mv, nv, wd, wv) * v3.w * v2.w : 0.f);
-                    int vpix = fbits(V.v0[vid].w);
+                    int vpix = fbits(mr[3].x);
                     atomic_add3(img.P, vpix, xyz(v3) * f * xyz(t1) * (1.0f / (C + T)));
                     ++merges;
                 }
@@ -586,6 +628,7 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
         // candidate ranges of the (at most 8) cells the ball touches
         int lo[8], pre[9];
         pre[0] = 0;
+        const int kmax = A.L - 1 - j;  // deepest view vertex this photon may merge with
         {
             float rr = A.r * 1.00001f;
             int lx = (int)floorf((y.x - rr) * G.inv_cell), hx = min((int)floorf((y.x + rr) * G.inv_cell), lx + 1);
@@ -607,8 +650,9 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
                 for (int q = 0; q < c; ++q) use = use && seen[q] != hc;
                 int e0 = 0, e1 = 0;
                 if (use) {
-                    e0 = G.start[hc];
-                    e1 = G.start[hc + 1];
+                    int64_t key = grid_key(G, hc, 1);
+                    e0 = G.start[key];
+                    e1 = G.start[key + kmax];
                     ++cells;
                 }
                 lo[c] = e0;
@@ -631,7 +675,7 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
                 float4 cd = G.sorted[e];
                 f3 dv = xyz(cd) - y;
                 acc = dot3(dv, dv) < r2;
-                vid = fbits(cd.w);
+                vid = e;  // the record index: its merge data sits at G.mrec[4 e]
             }
             unsigned long long m = __ballot(acc);
             if (m) {
@@ -759,6 +803,7 @@ struct neb_ctx_s {
     Counters* cnt = nullptr;
     int32_t iter = 0;
     int32_t first_iter_recorded = 0;
+    int32_t trace_grid = 4096;  // resident traversal blocks on this device
     hipStream_t last_stream = nullptr;
     std::vector<void*> allocs;
     std::vector<void*> scene_allocs;
@@ -870,6 +915,12 @@ extern "C" neb_status neb_create(const neb_params* p, neb_ctx* out) {
     if (vcap * 4 > (int64_t)INT32_MAX) return fail(NEB_ERR_CAPACITY, "image too large for the vertex pool");
     neb_ctx c = new neb_ctx_s();
     c->prm = *p;
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            c->trace_grid = cus * kTraceBlocksPerCU;
+    }
     c->npix = (int)npix;
     c->L = p->max_path_len;
     c->vcap = vcap;
@@ -897,12 +948,15 @@ extern "C" neb_status neb_create(const neb_params* p, neb_ctx* out) {
     ALLOC(c->ev1, c->ecap);
     if (p->flags & NEB_FLAG_SINGLE_THREAD_OCTREE) ALLOC(c->slots, vcap);
     if (p->flags & NEB_FLAG_RECORD_PATHS) ALLOC(c->recs, npix * p->max_path_len);
-    c->G.T = (int32_t)std::min<uint64_t>(next_pow2((uint64_t)vcap), 1u << 23);
+    c->G.D = std::max(1, p->max_path_len - 1);
+    c->G.T = (int32_t)std::max<uint64_t>(1024, std::min<uint64_t>(next_pow2((uint64_t)vcap) / 2, 1u << 23));
     c->G.inv_cell = 1.0f / (2.0001f * p->merge_radius);  // a little wider than the ball's diameter
-    ALLOC(c->G.count, c->G.T + 1);
-    ALLOC(c->G.start, c->G.T + 1);
+    int64_t gkeys = (int64_t)c->G.T * c->G.D + 1;
+    ALLOC(c->G.count, gkeys);
+    ALLOC(c->G.start, gkeys);
     ALLOC(c->G.sorted, vcap);
-    ALLOC(c->G.sums, kScanTile);
+    ALLOC(c->G.mrec, 4 * vcap);
+    ALLOC(c->G.sums, scan_scratch(gkeys));
     ALLOC(c->img, 9 * npix);
     ALLOC(c->cnt, 1);
     ALLOC(c->oct.nodes, 1 + ((p->octree_capacity + 7) & ~7));
@@ -918,8 +972,7 @@ extern "C" neb_status neb_create(const neb_params* p, neb_ctx* out) {
         delete c;
         return s;
     }
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(c->G.T + 1, 256)), dim3(256), 0, nullptr, c->G.count, 0,
-                       (int64_t)c->G.T + 1);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(gkeys, 256)), dim3(256), 0, nullptr, c->G.count, 0, gkeys);
     hipLaunchKernelGGL(k_fill_f32, dim3(grid_of(9 * npix, 256)), dim3(256), 0, nullptr, c->img, 0.f, 9 * npix);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, nullptr, (int32_t*)c->cnt, 0,
                        (int64_t)(sizeof(Counters) / 4));
@@ -1146,9 +1199,9 @@ static neb_status render_iteration(neb_ctx c, hipStream_t s) {
     for (int k = 1; k <= L; ++k) {
         int in = (k - 1) & 1, out = k & 1;
         TIMED(K_EXTEND_CAMERA,
-              hipLaunchKernelGGL(k_extend, dim3(grid_of(npix, kTraceBlock)), dim3(kTraceBlock), 0, s, c->view,
+              hipLaunchKernelGGL(k_extend, dim3(grid_of(npix, kTraceBlock, 1 << 20)), dim3(kTraceBlock), 0, s, c->view,
                                  c->q[in].q0, c->q[in].q1, &cnt->qcount[in], &cnt->qcount[out], c->hits,
-                                 &cnt->camera_rays));
+                                 &cnt->camera_rays, cnt));
         TIMED(K_SHADE, hipLaunchKernelGGL(k_shade, dim3(grid_of(npix, 256)), dim3(256), 0, s, A, c->q[in],
                                           &cnt->qcount[in], c->hits, c->q[out], &cnt->qcount[out], c->V,
                                           &cnt->n_vertices, c->ev0, c->ev1, &cnt->n_events, c->slots,
@@ -1168,28 +1221,25 @@ static neb_status render_iteration(neb_ctx c, hipStream_t s) {
     // pass 2
     TIMED(K_DENSITY, hipLaunchKernelGGL(k_density, dim3(grid_of(vcap, 256)), dim3(256), 0, s, A, c->V,
                                         &cnt->n_vertices, c->oct.nodes, c->oct.state, c->oct.prm));
-    TIMED(K_NEE, hipLaunchKernelGGL(k_nee, dim3(grid_of(vcap, kTraceBlock)), dim3(kTraceBlock), 0, s, A, c->V,
+    TIMED(K_NEE, hipLaunchKernelGGL(k_nee, dim3(grid_of(vcap, kTraceBlock, 1 << 20)), dim3(kTraceBlock), 0, s, A, c->V,
                                     &cnt->n_vertices,
                                     Images{c->img, c->img + 3 * (size_t)npix, c->img + 6 * (size_t)npix}, c->pq[0],
                                     &cnt->pcount[0], cnt));
     if (A.photons && L >= 3) {
         // merge grid over this iteration's view vertices
-        int64_t n = (int64_t)c->G.T + 1;
-        int nb = (int)((n + kScanTile - 1) / kScanTile);
+        int64_t n = (int64_t)c->G.T * c->G.D + 1;
         prof_begin(c, K_GRID_BUILD, s);
         hipLaunchKernelGGL(k_grid_count, dim3(grid_of(vcap, 256)), dim3(256), 0, s, c->mats, c->V, &cnt->n_vertices, c->G);
-        hipLaunchKernelGGL(k_scan_tiles, dim3(nb), dim3(kScanBlock), 0, s, c->G.count, c->G.start, c->G.sums, n);
-        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, s, c->G.sums, nb);
-        hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(kScanBlock), 0, s, c->G.start, c->G.sums, n);
+        scan_exclusive(c->G.count, c->G.start, n, c->G.sums, s);
         hipLaunchKernelGGL(k_grid_scatter, dim3(grid_of(vcap, 256)), dim3(256), 0, s, c->mats, c->V, &cnt->n_vertices,
                            c->G);
         prof_end(c, s);
         for (int j = 1; j <= L - 2; ++j) {
             int in = (j - 1) & 1, out = j & 1;
             TIMED(K_EXTEND_PHOTON,
-                  hipLaunchKernelGGL(k_extend, dim3(grid_of(vcap, kTraceBlock)), dim3(kTraceBlock), 0, s, c->view,
+                  hipLaunchKernelGGL(k_extend, dim3(grid_of(vcap, kTraceBlock, 1 << 20)), dim3(kTraceBlock), 0, s, c->view,
                                      c->pq[in].p0, c->pq[in].p1, &cnt->pcount[in], &cnt->pcount[out], c->hits,
-                                     &cnt->photon_rays));
+                                     &cnt->photon_rays, cnt));
             TIMED(K_PHOTON, hipLaunchKernelGGL(k_photon, dim3(grid_of(vcap, 256)), dim3(64), 0, s, A, c->pq[in],
                                                &cnt->pcount[in], c->hits, c->pq[out], &cnt->pcount[out], c->V, c->G,
                                                Images{c->img, c->img + 3 * (size_t)npix, c->img + 6 * (size_t)npix},
@@ -1334,6 +1384,8 @@ extern "C" neb_status neb_get_stats(neb_ctx c, neb_stats* out) {
     out->rays = (int64_t)(h.camera_rays + h.shadow_rays + h.photon_rays);
     out->camera_rays = (int64_t)h.camera_rays;
     out->shadow_rays = (int64_t)h.shadow_rays;
+    out->bvh_nodes = (int64_t)h.bvh_nodes;
+    out->bvh_tris = (int64_t)h.bvh_tris;
     out->photon_items = (int64_t)h.photon_items;
     out->photon_continued = (int64_t)h.photon_continued;
     out->grid_cells = (int64_t)h.grid_cells;

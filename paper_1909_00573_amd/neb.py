@@ -45,7 +45,7 @@ class Stats(ctypes.Structure):
         "iterations", "paths", "vertices", "photons", "photon_segments", "merges", "nee_visible", "events",
         "rays", "oct_capacity", "oct_allocated", "oct_depth", "oct_overflow", "oct_ledger", "oct_deposits",
         "oct_rejected", "oct_lost", "photon_items", "photon_continued", "grid_cells", "candidates",
-        "camera_rays", "shadow_rays")]
+        "camera_rays", "shadow_rays", "bvh_nodes", "bvh_tris")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
