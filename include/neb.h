@@ -73,7 +73,20 @@ typedef struct {
     float analytic_rho0;       /* NEB_DENSITY_ANALYTIC: constant term (per unit area, per iteration) */
     float analytic_cam_weight; /* NEB_DENSITY_ANALYTIC: weight of the camera's primary-hit density */
     int32_t flags;             /* NEB_FLAG_* */
+    int32_t spp;               /* iterations this scene takes part in, counted from the last
+                                  reset; 0 = every iteration (progressive) */
 } neb_params;
+
+/* Launch shapes of the traversal and photon kernels (neb_autotune picks
+ * them; results do not depend on them). */
+typedef struct {
+    int32_t bvh_stack;            /* LDS traversal stack entries per lane: 32, 48 or 64; must
+                                     exceed the depth of every scene's BVH */
+    int32_t trace_blocks_per_cu;  /* resident traversal blocks (one wave each) per compute unit;
+                                     0 = one block per 64 queue slots */
+    int32_t photon_blocks_per_cu; /* photon-merge blocks (one wave each) per compute unit, 0..64;
+                                     0 = one block per 256 queue slots */
+} neb_launch_config;
 
 /* One material per entry; emission is radiance leaving the front side of
  * the triangle (the side its counter-clockwise normal points to). */
@@ -135,9 +148,22 @@ typedef struct {
 /* Validates the parameters and allocates the per-iteration device pools
  * (queues, NEE-vertex store, photon state, merge grid, images) on the
  * current device.  NEB_ERR_INVALID_ARG on bad parameters,
- * NEB_ERR_OUT_OF_MEMORY if the pools do not fit. */
+ * NEB_ERR_OUT_OF_MEMORY if the pools do not fit.  Same as
+ * neb_create_batch(params, 1, out). */
 neb_status neb_create(const neb_params* params, neb_ctx* out);
 
+/* A context that renders n_scenes (1..256) independent scenes together:
+ * every stage of an iteration (Sec. 3 passes 1-3) is one launch over all
+ * scenes, which share the BVH pool (one tree per scene), the octree node
+ * pool (scene s owns octree_capacity nodes of params[s], Sec. 5) and the
+ * queues.  params: n_scenes host entries; image size, path length, octree
+ * capacity, merge radius, RNG key, analytic density terms and spp may
+ * differ per scene; density_mode and flags must be equal (else
+ * NEB_ERR_INVALID_ARG).  A scene takes part in iterations 1..spp (all if
+ * spp is 0); its paths and photons use its own key and scene-local pixel
+ * numbers, so it renders the same estimator as alone.  Path records of a
+ * batch are indexed by the pixel numbered over all scenes in order. */
+neb_status neb_create_batch(const neb_params* params, int32_t n_scenes, neb_ctx* out);
 /* Deep-copies the scene (host arrays) into library-owned device memory,
  * builds the BVH and the light table (emissive triangles and point lights,
  * selected in proportion to power), and initialises the octree over the
@@ -152,21 +178,58 @@ neb_status neb_set_scene(neb_ctx ctx, const float* vertices, int32_t nv, const i
                          int32_t nm, const neb_point_light* point_lights, int32_t npl,
                          const neb_camera* camera);
 
+/* neb_set_scene for scene `scene` of a batch (arguments as above; at most
+ * 65536 materials over the batch).  The host copy is validated and its BVH
+ * built here; the pools are uploaded by the next neb_render, neb_reset or
+ * neb_autotune once every scene is set.  Setting a scene restarts the
+ * progression of every scene of the context.  NEB_ERR_STATE from neb_set_scene
+ * on a context of more than one scene. */
+neb_status neb_set_batch_scene(neb_ctx ctx, int32_t scene, const float* vertices, int32_t nv,
+                               const int32_t* tris, const int32_t* tri_material, int32_t nt,
+                               const neb_material* materials, int32_t nm,
+                               const neb_point_light* point_lights, int32_t npl,
+                               const neb_camera* camera);
+
 /* Runs n_iterations progressive iterations (one sample per pixel each) on
  * `stream`, continuing from the context's iteration counter; the octree
  * integrates its counts over the iterations (Sec. 5.3, time integration).
- * Returns after enqueueing; NEB_ERR_STATE without a scene. */
+ * Returns after enqueueing; NEB_ERR_STATE unless every scene is set. */
 neb_status neb_render(neb_ctx ctx, int32_t n_iterations, void* stream);
+
+/* enable != 0: neb_render replays one captured iteration (a HIP graph,
+ * captured on first use) instead of launching its kernels one by one.
+ * The results are those of the eager launches; iterations that record
+ * paths or kernel times are always launched eagerly. */
+neb_status neb_use_graph(neb_ctx ctx, int32_t enable);
+
+/* Times trial_iterations (1..64) real iterations of the context for each
+ * candidate launch shape (traversal stack depth and blocks per CU, then the
+ * photon-merge grid), keeps the fastest, writes it to *chosen (may be NULL)
+ * and resets the context as neb_reset does.  Synchronises `stream`. */
+neb_status neb_autotune(neb_ctx ctx, int32_t trial_iterations, void* stream, neb_launch_config* chosen);
+
+/* Sets or reads the launch shapes (NEB_ERR_INVALID_ARG out of range,
+ * NEB_ERR_CAPACITY if the stack is not deeper than a scene's BVH). */
+neb_status neb_set_launch_config(neb_ctx ctx, const neb_launch_config* cfg);
+neb_status neb_get_launch_config(neb_ctx ctx, neb_launch_config* cfg);
 
 /* Mean radiance over the rendered iterations, height*width*3 floats,
  * row-major from the top-left pixel.  rgb is device memory if
  * is_device_ptr, else host memory (then the call synchronises). */
 neb_status neb_get_image(neb_ctx ctx, float* rgb, int32_t is_device_ptr, void* stream);
 
+/* neb_get_image for scene `scene` of a batch: its own height*width*3
+ * floats, averaged over the iterations it took part in.  neb_get_image is
+ * scene 0.  NEB_ERR_STATE before the pools are uploaded. */
+neb_status neb_get_scene_image(neb_ctx ctx, int32_t scene, float* rgb, int32_t is_device_ptr,
+                               void* stream);
+
 /* Mean radiance split by technique: random hits (e), NEE (E) and NEB photon
  * merges (P), each height*width*3 floats; any pointer may be NULL. */
 neb_status neb_get_technique_images(neb_ctx ctx, float* e, float* E, float* P, int32_t is_device_ptr,
                                     void* stream);
+neb_status neb_get_scene_technique_images(neb_ctx ctx, int32_t scene, float* e, float* E, float* P,
+                                          int32_t is_device_ptr, void* stream);
 
 /* Density of NEE vertices at n surface points from the context's octree in
  * its current state (robust five-probe query; tangents from the normal).
@@ -175,8 +238,9 @@ neb_status neb_get_technique_images(neb_ctx ctx, float* e, float* E, float* P, i
 neb_status neb_query_density(neb_ctx ctx, const float* pos, const float* nrm, int32_t n, float* out,
                              int32_t is_device_ptr, void* stream);
 
-/* Counters accumulated since the scene was set (synchronises the context's
- * last stream). */
+/* Counters accumulated since the last reset, over all scenes of the
+ * context (octree fields summed over the scenes' octrees, depth the
+ * deepest); synchronises the context's last stream. */
 neb_status neb_get_stats(neb_ctx ctx, neb_stats* out);
 
 /* Copies the path records of the first rendered iteration to host memory:
@@ -185,8 +249,13 @@ neb_status neb_get_stats(neb_ctx ctx, neb_stats* out);
 neb_status neb_get_path_records(neb_ctx ctx, neb_path_record* out, int64_t n);
 
 /* Exports the context's octree node array (host, up to cap entries) and
- * its info (see neb_octree_export). */
+ * its info (see neb_octree_export); scene 0 of a batch.  The scene variant
+ * exports the octree of scene `scene` (node links are pool indices: a
+ * child pointer -v of a node in the export is word v - root, where root is
+ * the sum of the rounded capacities of the scenes before it). */
 neb_status neb_get_octree(neb_ctx ctx, int32_t* nodes, int32_t cap, int64_t info[8]);
+neb_status neb_get_scene_octree(neb_ctx ctx, int32_t scene, int32_t* nodes, int32_t cap,
+                                int64_t info[8]);
 
 /* enable != 0 starts recording a HIP event pair around every kernel launch
  * of this context (clearing earlier records); 0 stops.  Recording adds a
@@ -197,7 +266,8 @@ neb_status neb_profile_kernels(neb_ctx ctx, int32_t enable);
  * to the number of kernels written).  Synchronises the recorded events. */
 neb_status neb_get_kernel_profile(neb_ctx ctx, neb_kernel_time* out, int32_t cap, int32_t* n_out);
 
-/* Clears the images, the statistics, the octree and the iteration counter. */
+/* Clears the images, the statistics, every octree and the iteration
+ * counter (uploads the pools first if the scenes changed). */
 neb_status neb_reset(neb_ctx ctx);
 
 void neb_destroy(neb_ctx ctx);

@@ -394,6 +394,13 @@ def batch_rooms(n_scenes=64, seed=4):
     return out
 
 
+def box_room(n_tris=3000, n_lights=4, res=96, spp=4, seed=4, scene_id=0):
+    """One box room of the batch recipe with chosen sizes (the interior
+    boxes and light positions are drawn from `seed` and `scene_id`)."""
+    rng = np.random.default_rng([seed, scene_id])
+    return _box_room_scene(rng, n_tris, n_lights, res, spp, seed, scene_id)
+
+
 def furnace_sphere(radius=1.0, albedo=0.5, emission=1.0, subdiv=4, width=16, height=16,
                    max_path_len=5, spp=4, seed=11):
     """Closed sphere with inward normals; its interior is Lambertian with

@@ -261,14 +261,14 @@ __device__ __forceinline__ bool oct_norm(const OctParams& P, f3 p, float q[3]) {
     return true;
 }
 
-__device__ __forceinline__ float oct_query(const int32_t* __restrict__ nodes, const OctParams& P, int depth,
-                                           f3 p, f3 n, bool want_size, float* size_out) {
+__device__ __forceinline__ float oct_query(const int32_t* __restrict__ nodes, const OctParams& P, float density_scale,
+                                           int depth, f3 p, f3 n, bool want_size, float* size_out) {
     float q[3];
     if (!oct_norm(P, p, q)) return 0.f;
     int32_t grid = 1 << depth;
     int32_t ix = (int32_t)(q[0] * (float)grid), iy = (int32_t)(q[1] * (float)grid),
             iz = (int32_t)(q[2] * (float)grid);
-    int32_t v = nodes[0];
+    int32_t v = nodes[P.root];
     int32_t mask = grid;
     while (v < 0) {
         mask >>= 1;
@@ -288,24 +288,24 @@ __device__ __forceinline__ float oct_query(const int32_t* __restrict__ nodes, co
     float diag = P.scene_scale / (float)res;
     float min_area = diag * diag * (want_size ? 0.1f : 0.01f);
     if (want_size) *size_out = diag;
-    return P.density_scale * (float)cnt / fmaxf(min_area, area);
+    return density_scale * (float)cnt / fmaxf(min_area, area);
 }
 
 // five probes in the tangent plane, upper median of the non-zero ones
 __device__ __forceinline__ float oct_query_robust(const int32_t* __restrict__ nodes, const OctParams& P,
-                                                  int depth, f3 p, f3 n) {
+                                                  float density_scale, int depth, f3 p, f3 n) {
     f3 tx, ty;
     basis(n, tx, ty);
     float diag = 1e-3f;
     float d[5];
     int cnt = 0;
-    float c0 = oct_query(nodes, P, depth, p, n, true, &diag);
+    float c0 = oct_query(nodes, P, density_scale, depth, p, n, true, &diag);
     if (c0 > 0.f) d[cnt++] = c0;
     float off = diag * 1.1f;
     f3 probe[4] = {p + tx * off, p - tx * off, p + ty * off, p - ty * off};
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        float r = oct_query(nodes, P, depth, probe[i], n, false, nullptr);
+        float r = oct_query(nodes, P, density_scale, depth, probe[i], n, false, nullptr);
         if (r > 0.f) d[cnt++] = r;
     }
     if (cnt == 0) return 0.f;
@@ -394,14 +394,15 @@ __device__ __forceinline__ bool box_hit(const RayPre& r, float lx, float ly, flo
 }
 
 // closest hit; ties on t go to the lowest primitive id.  stack: this lane's
-// LDS slots, stride kTraceBlock.  any_hit: stop at the first hit below tmax.
-template <bool kAnyHit>
-__device__ __forceinline__ int trace(const SceneView& S, f3 o, f3 d, float tmax, float& t_out, int* stack,
+// kStack LDS slots, stride kTraceBlock (the BVH must be shallower than
+// kStack).  any_hit: stop at the first hit below tmax.
+template <bool kAnyHit, int kStack>
+__device__ __forceinline__ int trace(const SceneView& S, int root, f3 o, f3 d, float tmax, float& t_out, int* stack,
                                      unsigned& nodes, unsigned& tris) {
     RayPre r = ray_pre(o, d);
     float best = tmax;
     int prim = -1;
-    int node = 0, sp = 0;
+    int node = root, sp = 0;
     for (;;) {
         const float4* nd = S.bvh + 4 * node;
         ++nodes;
@@ -446,7 +447,7 @@ __device__ __forceinline__ int trace(const SceneView& S, f3 o, f3 d, float tmax,
         if (h0 && h1) {
             int nearc = tn0 <= tn1 ? lk.x : lk.y;
             int farc = tn0 <= tn1 ? lk.y : lk.x;
-            if (sp < kBvhStack) stack[(sp++) * kTraceBlock] = farc;
+            if (sp < kStack) stack[(sp++) * kTraceBlock] = farc;
             node = nearc;
         } else if (h0) {
             node = lk.x;

@@ -13,22 +13,29 @@ constexpr int kOctSplitFactor = 4;         // split threshold = 4 * iteration
 constexpr int32_t kOctFailed = 0x40000000; // "split failed" mark on a full leaf
 constexpr int32_t kOctCountMask = 0x3FFFFFFF;
 constexpr int kMaxPathLen = 16;
-constexpr int kBvhStack = 48;              // LDS traversal stack entries per lane
+constexpr int kBvhStackMax = 64;           // deepest LDS traversal stack (entries per lane)
 constexpr int kTraceBlock = 64;            // threads per traversal block (one wave)
-constexpr int kTraceBlocksPerCU = 13;      // resident traversal blocks per CU (LDS bound)
 
 constexpr uint32_t kTagCamera = 1, kTagBsdf = 2, kTagNee = 3, kTagPhoton = 4;
 
-// kernel-argument copy of the octree's scalars (Appendix B members)
+// Static scalars of one octree (the members of the class of Appendix B that
+// do not change with the iteration), passed by value.  Several octrees can
+// share one node pool: each owns the words [root, end).
 struct OctParams {
     float min_bound[3];
     float size_inv[3];
     float scene_scale;
-    float density_scale;
-    int32_t capacity;
-    int32_t split_count;
-    int32_t stop_filling;
+    int32_t root;   // index of the root word in the pool
+    int32_t end;    // root + capacity (capacity = 8n + 1)
+};
+
+// Iteration-dependent scalars (Appendix B set_iteration), device resident so
+// that a captured graph of one iteration can be replayed for every iteration.
+struct OctDyn {
     int32_t iter;
+    int32_t split_count;
+    float density_scale;
+    int32_t stop_filling;
 };
 
 // device-resident octree state updated by atomics
@@ -42,10 +49,14 @@ struct OctState {
     unsigned long long lost;
 };
 
+// a standalone octree (the Appendix-B surface of the C ABI)
 struct Octree {
-    int32_t* nodes = nullptr;   // device
+    int32_t* nodes = nullptr;   // device, capacity words
     OctState* state = nullptr;  // device
+    OctDyn* dyn = nullptr;      // device
+    OctParams* prm_dev = nullptr;  // device copy of prm (the kernels take an array of them)
     OctParams prm{};
+    int32_t capacity = 0;
     int32_t last_iter = 0;
     int32_t* defer[2] = {nullptr, nullptr};  // deferred deposits, ping-pong
     int32_t* defer_cnt = nullptr;            // three rotating counters
@@ -58,17 +69,15 @@ struct CamParams {
     int32_t w, h;
 };
 
-// read-only scene view passed to kernels
+// read-only geometry and light pools shared by every scene of a context
 struct SceneView {
-    const float4* bvh;       // 4 float4 per node (two child boxes + child links)
-    const float4* tri;       // 3 float4 per triangle in leaf order; tri[0].w = prim id bits
-    const float4* prim_n;    // per prim: unit geometric normal, .w = material id bits
-    const int32_t* prim_light; // per prim: light index or -1
+    const float4* bvh;         // 4 float4 per node (two child boxes + child links), all scenes
+    const float4* tri;         // 3 float4 per triangle in leaf order; tri[0].w = global prim id bits
+    const float4* prim_n;      // per prim: unit geometric normal, .w = global material id bits
+    const int32_t* prim_light; // per prim: global light index or -1
     const neb_material* mats;
-    const float4* lights;    // 5 float4 per light
-    const float* light_cdf;  // inclusive cumulative selection probabilities
-    int32_t n_lights;
-    float eps;               // ray origin offset along the normal
+    const float4* lights;      // 5 float4 per light
+    const float* light_cdf;    // per scene: inclusive cumulative selection probabilities
 };
 
 // device counters of one context
@@ -77,26 +86,36 @@ struct Counters {
     int32_t pcount[2];       // photon queues
     int32_t n_vertices;
     int32_t n_events;
-    int32_t pad[2];
+    int32_t iter;            // current iteration (incremented at the start of each one)
+    int32_t pad;
     unsigned long long paths, vertices, photons, photon_segments, merges, nee_visible, events;
     unsigned long long camera_rays, shadow_rays, photon_rays;
     unsigned long long photon_items, photon_continued, grid_cells, candidates;
     unsigned long long bvh_nodes, bvh_tris;   // traversal work of closest-hit and shadow rays
 };
 
-// octree kernels (neb_octree.hip)
-hipError_t octree_init_nodes(Octree& o, hipStream_t s);
+// octree (neb_octree.hip)
+void octree_params_init(OctParams& p, const float smin[3], const float smax[3], int32_t root, int32_t capacity);
+void octree_dyn_for(OctDyn& d, int32_t iter);
+int32_t octree_capacity_rounded(int32_t capacity);
 hipError_t octree_reserve(Octree& o, int64_t n);
 void octree_release(Octree& o);
+hipError_t octree_reset(Octree& o, hipStream_t s);
 hipError_t octree_increment_xyz(Octree& o, const float* pos, int32_t n, int single, hipStream_t s);
-hipError_t octree_increment_vertices(const Octree& o, const float4* vpos, const int32_t* nvert,
-                                     int32_t cap, hipStream_t s);
-hipError_t octree_increment_slots(const Octree& o, const float4* vpos, const int32_t* slots,
-                                  int32_t n_slots, hipStream_t s);
-hipError_t octree_density_xyz(const Octree& o, const float* pos, const float* nrm, int32_t n, int robust,
-                              float* out, hipStream_t s);
+hipError_t octree_density_xyz(const Octree& o, const float* pos, const float* nrm, int32_t n, int robust, float* out,
+                              hipStream_t s);
+hipError_t octree_density_raw(const int32_t* nodes, const OctState* st, const OctParams& P, const OctDyn* dyn,
+                              const float* pos, const float* nrm, int32_t n, int robust, float* out, hipStream_t s);
 hipError_t octree_clear(const Octree& o, hipStream_t s);
-void octree_params_init(OctParams& p, const float smin[3], const float smax[3], int32_t capacity);
-void octree_params_set_iteration(OctParams& p, int32_t iter);
+// deposits of NEE vertices of many scenes: per-vertex scene from the record
+hipError_t octree_insert_rounds(int32_t* nodes, OctState* states, const OctParams* prm, const OctDyn* dyn,
+                                const float* pos, int stride, const int32_t* scene_of_item, int scene_shift,
+                                const int32_t* n_dev, int32_t n_host, int32_t* const defer[2], int32_t* defer_cnt,
+                                hipStream_t s);
+hipError_t octree_insert_single(int32_t* nodes, OctState* states, const OctParams* prm, const OctDyn* dyn,
+                                const float* pos, int stride, const int32_t* scene_of_item, int scene_shift,
+                                const int32_t* order, int32_t n, hipStream_t s);
+hipError_t octree_init_range(int32_t* nodes, OctState* st, int32_t root, int32_t capacity, hipStream_t s);
+hipError_t octree_set_dyn(OctDyn* dyn, const OctDyn& d, hipStream_t s);
 
 }  // namespace neb

@@ -1,7 +1,8 @@
 // Lock-free sparse density octree (Sec. 5 of the paper, class of Appendix B)
 // on gfx950: device-scope atomics on an int32 node pool, compare-and-swap
 // counting and splits allocated with one fetch-add.  No lane ever waits for
-// another lane.
+// another lane.  Several octrees (one per scene of a batch) can share one
+// pool; each owns the words [root, end) and has its own OctState.
 //
 // Node word: >= 0 is a count (bit 30 marks a leaf whose split could not be
 // allocated; it keeps counting), < 0 is minus the index of the first of 8
@@ -17,13 +18,16 @@
 //    kernel boundary guarantees the split has been published.  A deposit
 //    is deferred at most once per level, so kOctMaxDepth + 1 retry rounds
 //    bound the work;
+//  - lanes of a wave that reach the same node word add their count with one
+//    CAS (capped at the split threshold; the rest defer), so a burst of
+//    deposits into one cell costs one atomic per wave;
 //  - no increment is overwritten by the pointer store (deposits never
 //    count past the threshold), so the ledger
 //        S = sum(leaf counts) - 4 * sum(iteration of each allocated block)
 //    equals the number of deposits exactly;
 //  - the splitter writes the eight children's start count (the current
-//    iteration, i.e. parent/4) before it publishes the pointer with release
-//    ordering, instead of prefilling every unused node per iteration;
+//    iteration, i.e. parent/4) before it publishes the pointer, instead of
+//    prefilling every unused node per iteration;
 //  - node words are read with cacheable loads; a negative word never
 //    changes again and every other decision is validated by the CAS;
 //  - nodes at depth 20 never split (FP32 positions cannot resolve finer
@@ -32,24 +36,25 @@
 
 namespace neb {
 
-// Every decision taken on a loaded node word is either safe when the word is
-// stale (a negative word never changes again; a deferral is always allowed)
-// or validated by the compare-and-swap, which is resolved at the device's
-// coherence point and returns the current word.  Loads can therefore be
-// cacheable: no acquire, no L2 invalidation per tree level.
 __device__ __forceinline__ int32_t ld_node(const int32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 enum { kInsRejected = 0, kInsCounted = 1, kInsDeferred = 2 };
 
+__device__ __forceinline__ int child_index(const float q[3], int level) {
+    float sc = (float)(1 << level);
+    return (((int32_t)(q[0] * sc)) & 1) | ((((int32_t)(q[1] * sc)) & 1) << 1) | ((((int32_t)(q[2] * sc)) & 1) << 2);
+}
+
 // The split of a full leaf: allocate 8 children, start them at the current
 // iteration (parent / 4), publish the pointer.  Called by exactly one lane,
 // the one whose CAS brought the count to the threshold.
-__device__ __forceinline__ void oct_split(int32_t* nodes, OctState* st, const OctParams& P, int32_t idx, int level) {
+__device__ __forceinline__ void oct_split(int32_t* nodes, OctState* st, const OctParams& P, const OctDyn& D,
+                                          int32_t idx, int level) {
     int32_t child = atomicAdd(&st->alloc, 8);
-    if (child >= P.capacity) {
-        atomicExch(&st->alloc, P.capacity + 1);
+    if (child >= P.end) {
+        atomicExch(&st->alloc, P.end + 1);
         __hip_atomic_fetch_or(nodes + idx, kOctFailed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         atomicAdd(&st->overflow, 1);
         return;
@@ -59,69 +64,63 @@ __device__ __forceinline__ void oct_split(int32_t* nodes, OctState* st, const Oc
     // and CASes a child compares against the started count
 #pragma unroll
     for (int c = 0; c < 8; ++c)
-        __hip_atomic_exchange(nodes + child + c, P.iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_exchange(nodes + child + c, D.iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __hip_atomic_exchange(nodes + idx, -child, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    atomicAdd(&st->block_iter_sum, (unsigned long long)P.iter);
+    atomicAdd(&st->block_iter_sum, (unsigned long long)D.iter);
     atomicMax(&st->depth, level + 1);
 }
 
-// one deposit attempt; never waits for another lane
-__device__ __forceinline__ int oct_insert(int32_t* nodes, OctState* st, const OctParams& P, f3 p) {
+// one deposit by one thread alone (sequential insertion, the oracle's order)
+__device__ __forceinline__ int oct_insert(int32_t* nodes, OctState* st, const OctParams& P, const OctDyn& D, f3 p) {
     float q[3];
     if (!oct_norm(P, p, q)) return kInsRejected;
-    int32_t idx = 0;
+    int32_t idx = P.root;
     int level = 0;
-    int32_t v = ld_node(nodes);
+    int32_t v = ld_node(nodes + idx);
     for (int step = 0; step < 4096; ++step) {
         if (v < 0) {
             ++level;
-            float sc = (float)(1 << level);
-            int32_t c = (((int32_t)(q[0] * sc)) & 1) | ((((int32_t)(q[1] * sc)) & 1) << 1) |
-                        ((((int32_t)(q[2] * sc)) & 1) << 2);
-            idx = c - v;
+            idx = child_index(q, level) - v;
             v = ld_node(nodes + idx);
             continue;
         }
         int32_t cnt = v & kOctCountMask;
         bool can_split = !(v & kOctFailed) && level < kOctMaxDepth;
-        if (can_split && cnt >= P.split_count) return kInsDeferred;  // a split is being published
+        if (can_split && cnt >= D.split_count) return kInsDeferred;
         int32_t expected = v;
         if (!__hip_atomic_compare_exchange_strong(nodes + idx, &expected, v + 1, __ATOMIC_RELAXED,
                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-            v = expected;  // the current word: retry with it
+            v = expected;
             continue;
         }
-        if (can_split && cnt + 1 == P.split_count) oct_split(nodes, st, P, idx, level);
+        if (can_split && cnt + 1 == D.split_count) oct_split(nodes, st, P, D, idx, level);
         return kInsCounted;
     }
-    return kInsDeferred;  // heavy contention: try again after the launch
+    return kInsDeferred;
 }
 
-// Wave-cooperative deposit of one point per lane.  Lanes that reach the
-// same node word with the same observed value form a group; its first lane
-// adds the group's size (capped at the split threshold) with one CAS, the
-// lanes beyond the cap defer, and the lane whose addition reaches the
-// threshold splits.  A burst of deposits into one cell (every deposit of
-// the first iteration starts at the root) thus costs one atomic per wave
-// instead of one per lane.  Must be called by all lanes of the wave.
-__device__ __forceinline__ int oct_insert_wave(int32_t* nodes, OctState* st, const OctParams& P, bool has, f3 p) {
+// Wave-cooperative deposit of one point per lane (lanes may belong to
+// different octrees of the pool).  Lanes that reach the same node word with
+// the same observed value form a group; its first lane adds the group's
+// size (capped at the split threshold) with one CAS, the lanes beyond the
+// cap defer, and the lane whose addition reaches the threshold splits.
+// Must be called by all lanes of the wave.
+__device__ __forceinline__ int oct_insert_wave(int32_t* nodes, OctState* st, const OctParams& P, const OctDyn& D,
+                                               bool has, f3 p) {
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (1ull << lane) - 1ull;
     float q[3] = {0.f, 0.f, 0.f};
     bool active = has && oct_norm(P, p, q);
     int result = (has && !active) ? kInsRejected : kInsDeferred;
-    int32_t idx = 0;
+    int32_t idx = P.root;
     int level = 0;
-    int32_t v = active ? ld_node(nodes) : 0;
+    int32_t v = active ? ld_node(nodes + idx) : 0;
     for (int step = 0; step < 4096; ++step) {
         if (!__any(active)) break;
         if (active && v < 0) {
             ++level;
-            float sc = (float)(1 << level);
-            int32_t c = (((int32_t)(q[0] * sc)) & 1) | ((((int32_t)(q[1] * sc)) & 1) << 1) |
-                        ((((int32_t)(q[2] * sc)) & 1) << 2);
-            idx = c - v;
+            idx = child_index(q, level) - v;
             v = ld_node(nodes + idx);
         }
         bool want = active && v >= 0;
@@ -131,12 +130,13 @@ __device__ __forceinline__ int oct_insert_wave(int32_t* nodes, OctState* st, con
             int32_t lidx = __shfl(idx, leader, 64);
             int32_t lv = __shfl(v, leader, 64);
             int llevel = __shfl(level, leader, 64);
+            int32_t lsplit = __shfl(D.split_count, leader, 64);
             bool in = want && idx == lidx && v == lv;
             unsigned long long gm = __ballot(in);
             int k = __popcll(gm);
             int32_t cnt = lv & kOctCountMask;
             bool can_split = !(lv & kOctFailed) && llevel < kOctMaxDepth;
-            int m = can_split ? min(k, max(0, P.split_count - cnt)) : k;
+            int m = can_split ? min(k, max(0, lsplit - cnt)) : k;
             int ok = 0;
             int32_t cur = lv;
             if (lane == leader && m > 0) {
@@ -144,7 +144,7 @@ __device__ __forceinline__ int oct_insert_wave(int32_t* nodes, OctState* st, con
                 ok = __hip_atomic_compare_exchange_strong(nodes + lidx, &e, lv + m, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                           __HIP_MEMORY_SCOPE_AGENT);
                 cur = e;
-                if (ok && can_split && cnt + m == P.split_count) oct_split(nodes, st, P, lidx, llevel);
+                if (ok && can_split && cnt + m == lsplit) oct_split(nodes, st, P, D, lidx, llevel);
             }
             ok = __shfl(ok, leader, 64);
             cur = __shfl(cur, leader, 64);
@@ -166,120 +166,143 @@ __device__ __forceinline__ int oct_insert_wave(int32_t* nodes, OctState* st, con
     return result;
 }
 
-__device__ __forceinline__ void oct_account(OctState* st, int counted, int rejected) {
-    // one atomic per wave for each tally (all lanes of the block reach this)
-    unsigned long long c = (unsigned long long)counted;
-    int r = rejected;
-    for (int off = 32; off > 0; off >>= 1) {
-        c += __shfl_xor(c, off, 64);
-        r += __shfl_xor(r, off, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        if (c) atomicAdd(&st->deposits, c);
-        if (r) atomicAdd(&st->rejected, r);
+// one atomic per wave and state for each tally; lanes of a wave may belong
+// to different octree states
+__device__ __forceinline__ void oct_account(OctState* states, int scene, int counted, int rejected) {
+    const int lane = threadIdx.x & 63;
+    unsigned long long pend = __ballot(counted != 0 || rejected != 0);
+    while (pend) {
+        int leader = __ffsll((long long)pend) - 1;
+        int ls = __shfl(scene, leader, 64);
+        bool in = ((pend >> lane) & 1ull) && scene == ls;
+        unsigned long long c = in ? (unsigned long long)counted : 0ull;
+        int r = in ? rejected : 0;
+        for (int off = 32; off > 0; off >>= 1) {
+            c += __shfl_xor(c, off, 64);
+            r += __shfl_xor(r, off, 64);
+        }
+        if (lane == leader) {
+            if (c) atomicAdd(&states[ls].deposits, c);
+            if (r) atomicAdd(&states[ls].rejected, r);
+        }
+        pend &= ~__ballot(in);
     }
 }
 
+__device__ __forceinline__ int item_scene(const int32_t* scene_word, int stride, int shift, int32_t item) {
+    return scene_word ? ((scene_word[(size_t)stride * item] >> shift) & 0xFF) : 0;
+}
+
 // Deposit items [0, n) (round 0, items == nullptr) or the deferred items of
-// the previous round.  Positions are float3 (stride 3) or float4 vertex
-// records (stride 4).  Deferred items go to defer_out; the counter of the
-// round after next is cleared here (three counters rotate).
-__global__ void __launch_bounds__(256) k_oct_insert(int32_t* nodes, OctState* st, OctParams P,
-                                                    const float* __restrict__ pos, int stride,
+// the previous round.  Positions are float3 (stride 3) or the xyz of float4
+// records (stride 4); the octree of an item is read from scene_word.
+// Deferred items go to defer_out; the counter of the round after next is
+// cleared here (three counters rotate).
+__global__ void __launch_bounds__(256) k_oct_insert(int32_t* nodes, OctState* states, const OctParams* prm,
+                                                    const OctDyn* dyn, const float* __restrict__ pos, int stride,
+                                                    const int32_t* __restrict__ scene_word, int shift,
                                                     const int32_t* __restrict__ items, const int32_t* n_dev,
                                                     int32_t n_host, int32_t* __restrict__ defer_out,
                                                     int32_t* defer_count, int32_t* clear_count) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *clear_count = 0;
+    const OctDyn D = *dyn;
     int32_t n = n_dev ? min(*n_dev, n_host) : n_host;
-    int counted = 0, rejected = 0;
-    if (!P.stop_filling) {
-        int64_t stride_all = (int64_t)gridDim.x * blockDim.x;
-        int64_t nn = (n + stride_all - 1) / stride_all * stride_all;  // uniform trip count per wave
-        for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += stride_all) {
-            bool has = i < n;
-            int32_t item = 0;
-            f3 pt = mk3(0.f, 0.f, 0.f);
-            if (has) {
-                item = items ? items[i] : (int32_t)i;
-                const float* pp = pos + (size_t)stride * item;
-                pt = mk3(pp[0], pp[1], pp[2]);
-            }
-            int r = oct_insert_wave(nodes, st, P, has, pt);
-            bool defer = has && r == kInsDeferred;
-            counted += has && r == kInsCounted;
-            rejected += has && r == kInsRejected;
-            int slot = wave_reserve(defer_count, defer);
-            if (defer) defer_out[slot] = item;
+    if (D.stop_filling) return;
+    int64_t stride_all = (int64_t)gridDim.x * blockDim.x;
+    int64_t nn = (n + stride_all - 1) / stride_all * stride_all;  // uniform trip count per wave
+    for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += stride_all) {
+        bool has = i < n;
+        int32_t item = 0;
+        f3 pt = mk3(0.f, 0.f, 0.f);
+        int s = 0;
+        if (has) {
+            item = items ? items[i] : (int32_t)i;
+            const float* pp = pos + (size_t)stride * item;
+            pt = mk3(pp[0], pp[1], pp[2]);
+            s = item_scene(scene_word, stride, shift, item);
         }
+        const OctParams P = prm[s];
+        int r = oct_insert_wave(nodes, states + s, P, D, has, pt);
+        bool defer = has && r == kInsDeferred;
+        oct_account(states, s, has && r == kInsCounted, has && r == kInsRejected);
+        int slot = wave_reserve(defer_count, defer);
+        if (defer) defer_out[slot] = item;
     }
-    oct_account(st, counted, rejected);
 }
 
-__global__ void k_oct_insert_single(int32_t* nodes, OctState* st, OctParams P, const float* __restrict__ pos,
-                                    int stride, const int32_t* __restrict__ order, int32_t n) {
-    if (threadIdx.x != 0 || blockIdx.x != 0 || P.stop_filling) return;
-    unsigned long long counted = 0, lost = 0;
-    int rejected = 0;
+// sequential insertion by one thread; order == nullptr means 0..n-1, else
+// the listed items (negative entries skipped)
+__global__ void k_oct_insert_single(int32_t* nodes, OctState* states, const OctParams* prm, const OctDyn* dyn,
+                                    const float* __restrict__ pos, int stride, const int32_t* __restrict__ scene_word,
+                                    int shift, const int32_t* __restrict__ order, int32_t n) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const OctDyn D = *dyn;
+    if (D.stop_filling) return;
     for (int32_t i = 0; i < n; ++i) {
         int32_t item = order ? order[i] : i;
         if (item < 0) continue;
         const float* pp = pos + (size_t)stride * item;
-        int r = oct_insert(nodes, st, P, mk3(pp[0], pp[1], pp[2]));
-        counted += r == kInsCounted;
-        rejected += r == kInsRejected;
-        lost += r == kInsDeferred;  // impossible without concurrency
+        int s = item_scene(scene_word, stride, shift, item);
+        int r = oct_insert(nodes, states + s, prm[s], D, mk3(pp[0], pp[1], pp[2]));
+        if (r == kInsCounted) states[s].deposits += 1;
+        if (r == kInsRejected) states[s].rejected += 1;
+        if (r == kInsDeferred) states[s].lost += 1;  // impossible without concurrency
     }
-    atomicAdd(&st->deposits, counted);
-    atomicAdd(&st->rejected, rejected);
-    atomicAdd(&st->lost, lost);
 }
 
-// deposits still deferred after the last round are reported as lost
+// deposits still deferred after the last round are reported as lost (to the
+// first state; they cannot occur, see above)
 __global__ void k_oct_report_lost(OctState* st, const int32_t* remaining) {
     if (*remaining) atomicAdd(&st->lost, (unsigned long long)*remaining);
 }
 
 __global__ void __launch_bounds__(256) k_oct_density_xyz(const int32_t* __restrict__ nodes, const OctState* st,
-                                                         OctParams P, const float* __restrict__ pos,
+                                                         OctParams P, const OctDyn* dyn, const float* __restrict__ pos,
                                                          const float* __restrict__ nrm, int32_t n, int robust,
                                                          float* __restrict__ out) {
     int depth = st->depth;
+    float scale = dyn->density_scale;
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         f3 p = load3(pos + 3 * (size_t)i);
         f3 nn = normalize3(load3(nrm + 3 * (size_t)i));
-        out[i] = robust ? oct_query_robust(nodes, P, depth, p, nn) : oct_query(nodes, P, depth, p, nn, false, nullptr);
+        out[i] = robust ? oct_query_robust(nodes, P, scale, depth, p, nn)
+                        : oct_query(nodes, P, scale, depth, p, nn, false, nullptr);
     }
 }
 
-__global__ void k_oct_init(int32_t* nodes, OctState* st, int32_t capacity) {
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < capacity; i += gridDim.x * blockDim.x) nodes[i] = 0;
+__global__ void k_oct_init(int32_t* nodes, OctState* st, OctDyn* dyn, int32_t root, int32_t capacity, OctDyn d0) {
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < capacity; i += gridDim.x * blockDim.x)
+        nodes[root + i] = 0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->alloc = 1;
+        st->alloc = root + 1;
         st->depth = 0;
         st->overflow = 0;
         st->rejected = 0;
         st->block_iter_sum = 0;
         st->deposits = 0;
         st->lost = 0;
+        if (dyn) *dyn = d0;
     }
 }
 
-__global__ void k_oct_clear(int32_t* nodes, OctState* st, int32_t capacity) {
-    int32_t n = min(st->alloc, capacity);
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+__global__ void k_oct_clear(int32_t* nodes, OctState* st, int32_t root, int32_t end) {
+    int32_t n = min(st->alloc, end);
+    for (int32_t i = root + blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         int32_t v = nodes[i];
         if (v > 0) nodes[i] = 0;
     }
 }
 
-// after clear: the ledger restarts (runs as a separate launch so that the
-// clear kernel can read alloc while this one resets the sums)
+// after clear: the ledger restarts (a separate launch so that the clear
+// kernel can read alloc while this one resets the sums)
 __global__ void k_oct_clear_ledger(OctState* st) {
     st->block_iter_sum = 0;
     st->deposits = 0;
 }
 
 __global__ void k_oct_clear_counter(int32_t* c) { *c = 0; }
+
+__global__ void k_oct_set_dyn(OctDyn* dyn, OctDyn d) { *dyn = d; }
 
 static int grid_for(int64_t n, int block) {
     int64_t g = (n + block - 1) / block;
@@ -288,7 +311,9 @@ static int grid_for(int64_t n, int block) {
     return (int)g;
 }
 
-void octree_params_init(OctParams& p, const float smin[3], const float smax[3], int32_t capacity) {
+int32_t octree_capacity_rounded(int32_t capacity) { return 1 + ((capacity + 7) & ~7); }
+
+void octree_params_init(OctParams& p, const float smin[3], const float smax[3], int32_t root, int32_t capacity) {
     float size[3];
     for (int i = 0; i < 3; ++i) {
         size[i] = (smax[i] - smin[i]) * 1.002f;
@@ -300,49 +325,69 @@ void octree_params_init(OctParams& p, const float smin[3], const float smax[3], 
     p.scene_scale = sqrtf(sq);
     const float rel = 0.001f / 1.002f;
     for (int i = 0; i < 3; ++i) p.min_bound[i] = smin[i] - size[i] * rel;
-    p.capacity = 1 + ((capacity + 7) & ~7);
-    octree_params_set_iteration(p, 1);
+    p.root = root;
+    p.end = root + octree_capacity_rounded(capacity);
 }
 
-void octree_params_set_iteration(OctParams& p, int32_t iter) {
+void octree_dyn_for(OctDyn& d, int32_t iter) {
     int32_t ic = iter < kOctFillIterations ? iter : kOctFillIterations;
-    p.stop_filling = iter > kOctFillIterations;
-    p.density_scale = 1.0f / (float)ic;
-    p.split_count = kOctSplitFactor * ic;
-    p.iter = iter;
+    d.iter = iter;
+    d.stop_filling = iter > kOctFillIterations;
+    d.density_scale = 1.0f / (float)ic;
+    d.split_count = kOctSplitFactor * ic;
 }
 
-hipError_t octree_init_nodes(Octree& o, hipStream_t s) {
-    hipLaunchKernelGGL(k_oct_init, dim3(grid_for(o.prm.capacity, 256)), dim3(256), 0, s, o.nodes, o.state,
-                       o.prm.capacity);
-    return hipGetLastError();
-}
-
-static hipError_t insert_rounds(const Octree& o, const float* pos, int stride, const int32_t* n_dev, int32_t n_host,
+hipError_t octree_insert_rounds(int32_t* nodes, OctState* states, const OctParams* prm, const OctDyn* dyn,
+                                const float* pos, int stride, const int32_t* scene_word, int shift,
+                                const int32_t* n_dev, int32_t n_host, int32_t* const defer[2], int32_t* cnt,
                                 hipStream_t s) {
-    int32_t* cnt = o.defer_cnt;
     hipLaunchKernelGGL(k_oct_clear_counter, dim3(1), dim3(1), 0, s, cnt + 1);
-    hipLaunchKernelGGL(k_oct_insert, dim3(grid_for(n_host, 256)), dim3(256), 0, s, o.nodes, o.state, o.prm, pos, stride,
-                       (const int32_t*)nullptr, n_dev, n_host, o.defer[0], cnt + 1, cnt + 2);
+    hipLaunchKernelGGL(k_oct_insert, dim3(grid_for(n_host, 256)), dim3(256), 0, s, nodes, states, prm, dyn, pos, stride,
+                       scene_word, shift, (const int32_t*)nullptr, n_dev, n_host, defer[0], cnt + 1, cnt + 2);
     for (int r = 1; r <= kOctMaxDepth + 1; ++r) {
-        hipLaunchKernelGGL(k_oct_insert, dim3(64), dim3(256), 0, s, o.nodes, o.state, o.prm, pos, stride,
-                           (const int32_t*)o.defer[(r - 1) & 1], (const int32_t*)(cnt + (r % 3)), n_host,
-                           o.defer[r & 1], cnt + ((r + 1) % 3), cnt + ((r + 2) % 3));
+        hipLaunchKernelGGL(k_oct_insert, dim3(64), dim3(256), 0, s, nodes, states, prm, dyn, pos, stride, scene_word,
+                           shift, (const int32_t*)defer[(r - 1) & 1], (const int32_t*)(cnt + (r % 3)), n_host,
+                           defer[r & 1], cnt + ((r + 1) % 3), cnt + ((r + 2) % 3));
     }
-    hipLaunchKernelGGL(k_oct_report_lost, dim3(1), dim3(1), 0, s, o.state,
+    hipLaunchKernelGGL(k_oct_report_lost, dim3(1), dim3(1), 0, s, states,
                        (const int32_t*)(cnt + ((kOctMaxDepth + 2) % 3)));
     return hipGetLastError();
 }
 
+hipError_t octree_insert_single(int32_t* nodes, OctState* states, const OctParams* prm, const OctDyn* dyn,
+                                const float* pos, int stride, const int32_t* scene_word, int shift,
+                                const int32_t* order, int32_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_oct_insert_single, dim3(1), dim3(64), 0, s, nodes, states, prm, dyn, pos, stride, scene_word,
+                       shift, order, n);
+    return hipGetLastError();
+}
+
+hipError_t octree_init_range(int32_t* nodes, OctState* st, int32_t root, int32_t capacity, hipStream_t s) {
+    OctDyn d0;
+    octree_dyn_for(d0, 1);
+    hipLaunchKernelGGL(k_oct_init, dim3(grid_for(capacity, 256)), dim3(256), 0, s, nodes, st, (OctDyn*)nullptr, root,
+                       capacity, d0);
+    return hipGetLastError();
+}
+
+hipError_t octree_set_dyn(OctDyn* dyn, const OctDyn& d, hipStream_t s) {
+    hipLaunchKernelGGL(k_oct_set_dyn, dim3(1), dim3(1), 0, s, dyn, d);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// standalone octree: one octree, root 0, params copied to the device
+// ---------------------------------------------------------------------------
 hipError_t octree_reserve(Octree& o, int64_t n) {
-    if (n <= o.defer_cap) return hipSuccess;
+    hipError_t e = hipSuccess;
+    if (!o.defer_cnt) e = hipMalloc(&o.defer_cnt, 4 * 3);
+    if (e != hipSuccess || n <= o.defer_cap) return e;
     if (o.defer[0]) (void)hipFree(o.defer[0]);
     if (o.defer[1]) (void)hipFree(o.defer[1]);
     o.defer[0] = o.defer[1] = nullptr;
     o.defer_cap = 0;
-    hipError_t e = hipMalloc(&o.defer[0], 4 * (size_t)n);
+    e = hipMalloc(&o.defer[0], 4 * (size_t)n);
     if (e == hipSuccess) e = hipMalloc(&o.defer[1], 4 * (size_t)n);
-    if (e == hipSuccess && !o.defer_cnt) e = hipMalloc(&o.defer_cnt, 4 * 3);
     if (e == hipSuccess) o.defer_cap = n;
     return e;
 }
@@ -353,44 +398,44 @@ void octree_release(Octree& o) {
     if (o.defer_cnt) (void)hipFree(o.defer_cnt);
     if (o.nodes) (void)hipFree(o.nodes);
     if (o.state) (void)hipFree(o.state);
+    if (o.dyn) (void)hipFree(o.dyn);
+    if (o.prm_dev) (void)hipFree(o.prm_dev);
     o = Octree();
+}
+
+hipError_t octree_reset(Octree& o, hipStream_t s) {
+    OctDyn d0;
+    octree_dyn_for(d0, 1);
+    hipLaunchKernelGGL(k_oct_init, dim3(grid_for(o.capacity, 256)), dim3(256), 0, s, o.nodes, o.state, o.dyn, 0,
+                       o.capacity, d0);
+    return hipGetLastError();
 }
 
 hipError_t octree_increment_xyz(Octree& o, const float* pos, int32_t n, int single, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    if (single) {
-        hipLaunchKernelGGL(k_oct_insert_single, dim3(1), dim3(64), 0, s, o.nodes, o.state, o.prm, pos, 3,
-                           (const int32_t*)nullptr, n);
-        return hipGetLastError();
-    }
+    if (single) return octree_insert_single(o.nodes, o.state, o.prm_dev, o.dyn, pos, 3, nullptr, 0, nullptr, n, s);
     hipError_t e = octree_reserve(o, n);
     if (e != hipSuccess) return e;
-    return insert_rounds(o, pos, 3, nullptr, n, s);
+    return octree_insert_rounds(o.nodes, o.state, o.prm_dev, o.dyn, pos, 3, nullptr, 0, nullptr, n, o.defer,
+                                o.defer_cnt, s);
 }
 
-hipError_t octree_increment_vertices(const Octree& o, const float4* vpos, const int32_t* nvert, int32_t cap,
-                                     hipStream_t s) {
-    return insert_rounds(o, reinterpret_cast<const float*>(vpos), 4, nvert, cap, s);
-}
-
-hipError_t octree_increment_slots(const Octree& o, const float4* vpos, const int32_t* slots, int32_t n_slots,
-                                  hipStream_t s) {
-    hipLaunchKernelGGL(k_oct_insert_single, dim3(1), dim3(64), 0, s, o.nodes, o.state, o.prm,
-                       reinterpret_cast<const float*>(vpos), 4, slots, n_slots);
+hipError_t octree_density_raw(const int32_t* nodes, const OctState* st, const OctParams& P, const OctDyn* dyn,
+                              const float* pos, const float* nrm, int32_t n, int robust, float* out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_oct_density_xyz, dim3(grid_for(n, 256)), dim3(256), 0, s, nodes, st, P, dyn, pos, nrm, n,
+                       robust, out);
     return hipGetLastError();
 }
 
 hipError_t octree_density_xyz(const Octree& o, const float* pos, const float* nrm, int32_t n, int robust, float* out,
                               hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_oct_density_xyz, dim3(grid_for(n, 256)), dim3(256), 0, s, o.nodes, o.state, o.prm, pos,
-                       nrm, n, robust, out);
-    return hipGetLastError();
+    return octree_density_raw(o.nodes, o.state, o.prm, o.dyn, pos, nrm, n, robust, out, s);
 }
 
 hipError_t octree_clear(const Octree& o, hipStream_t s) {
-    hipLaunchKernelGGL(k_oct_clear, dim3(grid_for(o.prm.capacity, 256)), dim3(256), 0, s, o.nodes, o.state,
-                       o.prm.capacity);
+    hipLaunchKernelGGL(k_oct_clear, dim3(grid_for(o.capacity, 256)), dim3(256), 0, s, o.nodes, o.state, o.prm.root,
+                       o.prm.end);
     hipLaunchKernelGGL(k_oct_clear_ledger, dim3(1), dim3(1), 0, s, o.state);
     return hipGetLastError();
 }

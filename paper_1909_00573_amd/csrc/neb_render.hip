@@ -14,7 +14,18 @@
 // needs the full path: each view vertex stores B = A_{m-2} + [x_{m-1} not
 // delta] and g = |cos out at x_{m-1}| / (pdf at x_{m-1} * |cos in at x_m|),
 // each photon carries U and h with the same meaning from the light side.
+//
+// A context holds a batch of 1..256 scenes that share every pool: a BVH
+// forest (one root per scene in one node pool), one octree node pool split
+// into per-scene ranges, one set of queues and one merge grid whose key
+// includes the scene.  Every launch covers all scenes; each state word
+// carries its scene in bits 8..15.  Random numbers are drawn with the
+// scene-local pixel and the scene's key, so a scene renders the same paths
+// in a batch as alone.  The iteration number and the octree's iteration
+// scalars live in device memory, so one captured iteration (a hipGraph)
+// replays for every iteration.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -26,14 +37,21 @@
 
 namespace neb {
 
+constexpr int kMaxScenes = 256;
+constexpr int kMaxMaterials = 65536;
+
 // ---------------------------------------------------------------------------
-// state layouts (SoA of float4, ints stored as float bits)
-//   path q0 (o.xyz, pixel)  q1 (d.xyz, depth of the next hit)
+// state layouts (SoA of float4, ints stored as float bits; "tag" words hold
+// a depth code in bits 0..7, the scene in bits 8..15 and, for vertices, the
+// global material id in bits 16..31)
+//   path q0 (o.xyz, global pixel)  q1 (d.xyz, tag: depth of the next hit)
 //        q2 (tau.rgb, pdf of the sampled direction at the last vertex)
 //        q3 (A_{m-1}, |cos out|/pdf at the last vertex, last vertex non-delta, last vertex index)
-//   vertex v0 (pos, pixel)  v1 (n, depth | material << 8)  v2 (wo, B)  v3 (tau, g)
-//   event e0 (tau*Le, p_light/f or 0 for a direct hit)  e1 (A, prev non-delta, prev vertex, pixel)
-//   photon p0 (o, origin pixel)  p1 (d, 16*origin depth + bounce)  p2 (Phi, |cos out|/pdf)  pu (U)
+//   vertex v0 (pos, global pixel)  v1 (n, tag: depth | scene | material)  v2 (wo, B)  v3 (tau, g)
+//   event e0 (tau*Le, p_light/f or 0 for a direct hit)
+//         e1 (pi r^2 A, prev non-delta, prev vertex, global pixel)
+//   photon p0 (o, global origin pixel)  p1 (d, tag: 16*origin depth + bounce)
+//          p2 (Phi, |cos out|/pdf)  pu (U)
 // ---------------------------------------------------------------------------
 struct PathQ {
     float4 *q0, *q1, *q2, *q3;
@@ -49,36 +67,61 @@ struct VertexStore {
 struct Images {
     float *e, *E, *P;
 };
-// Merge grid keyed by (cell hash, depth - 1): the records of one cell are
-// ordered by view-vertex depth, so the vertices a photon after j bounces may
-// merge with (depth <= maxlen - 1 - j) form one contiguous prefix.
+
+// per-scene constants, one entry per scene of the batch (device array)
+struct SceneInfo {
+    CamParams cam;
+    int32_t pix_base;   // first global pixel of the scene
+    int32_t npix;
+    int32_t L;          // maximum path length
+    int32_t spp;        // iterations the scene takes part in (0 = all)
+    int32_t bvh_root;   // root node of the scene's tree in the forest
+    int32_t light_base; // first light of the scene in the light pool
+    int32_t n_lights;
+    int32_t pad;
+    uint32_t k0, k1;    // Philox key
+    float eps;          // ray offset
+    float r, r2pi;      // merge radius and pi r^2
+    float inv_cell;     // 1 / merge-grid cell size
+    float rho0, cam_w;  // analytic density (test hook)
+};
+
+// Merge grid keyed by (hash of scene and cell, depth - 1): the records of
+// one cell are ordered by view-vertex depth, so the vertices a photon after
+// j bounces may merge with (depth <= maxlen - 1 - j) form one contiguous
+// prefix.
 struct Grid {
     int32_t* count;   // T * D + 1 entries (the last stays 0)
     int32_t* start;   // T * D + 1 entries
-    float4* sorted;   // (pos, vertex index) in (cell, depth) order
+    float4* sorted;   // (pos, scene) in (cell, depth) order
     float4* mrec;     // 4 per record, same order: what a merge needs of the view vertex:
-                      // (n, depth | material << 8), (wo, B), (tau, g), (pixel, -, -, -)
+                      // (n, tag), (wo, B), (tau, g), (pixel, -, -, -)
     int32_t* sums;    // scan block sums, all levels
     int32_t T;        // hash buckets (power of two)
-    int32_t D;        // depth classes = maxlen - 1
-    float inv_cell;
+    int32_t D;        // depth classes = longest maxlen - 1
 };
 
 struct RenderArgs {
     SceneView S;
-    CamParams cam;
-    uint32_t k0, k1;
-    int32_t iter;
-    int32_t L;
-    int32_t npix;
-    int32_t photons;     // n_P > 0
-    float r, r2pi;
+    const SceneInfo* sc;
+    const int32_t* pix_base;  // n_scenes + 1 entries
+    Counters* cnt;
+    int32_t n_scenes;
+    int32_t L;                // longest maximum path length of the batch
+    int32_t npix;             // pixels of all scenes
+    int32_t photons;          // n_P > 0
     int32_t density_mode;
-    float rho0, cam_w;
 };
 
 __device__ __forceinline__ int fbits(float f) { return __float_as_int(f); }
 __device__ __forceinline__ float ibits(int i) { return __int_as_float(i); }
+__device__ __forceinline__ int tag_depth(int w) { return w & 0xFF; }
+__device__ __forceinline__ int tag_scene(int w) { return (w >> 8) & 0xFF; }
+__device__ __forceinline__ int tag_mat(int w) { return (int)((uint32_t)w >> 16); }
+__device__ __forceinline__ int make_tag(int depth, int scene) { return depth | (scene << 8); }
+__device__ __forceinline__ int make_vtag(int depth, int scene, int mat) { return depth | (scene << 8) | (mat << 16); }
+
+__device__ __forceinline__ bool scene_active(const SceneInfo& I, int iter) { return I.spp == 0 || iter <= I.spp; }
 
 __device__ __forceinline__ f3 offset_origin(f3 x, f3 n, f3 dir, float eps) {
     return dot3(dir, n) > 0.f ? x + n * eps : x - n * eps;
@@ -111,6 +154,17 @@ __device__ __forceinline__ float cam_hit_density(const CamParams& C, f3 x, f3 n)
     return (float)C.w * (float)C.h / (film * c * c * c) * fabsf(dot3(n, w)) / d2;
 }
 
+// scene of a global pixel: the last s with pix_base[s] <= i
+__device__ __forceinline__ int scene_of_pixel(const int32_t* pix_base, int n_scenes, int i) {
+    int lo = 0, hi = n_scenes - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (pix_base[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // ---------------------------------------------------------------------------
 // small utility kernels
 // ---------------------------------------------------------------------------
@@ -122,14 +176,25 @@ __global__ void k_fill_f32(float* p, float v, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
 }
-__global__ void k_iter_begin(Counters* c, int32_t npix) {
-    c->qcount[0] = npix;
+// Starts an iteration: advances the device iteration counter, sets the
+// octree's iteration scalars (Appendix B set_iteration) and empties the
+// queues.
+__global__ void k_iter_begin(Counters* c, OctDyn* dyn) {
+    int it = c->iter + 1;
+    c->iter = it;
+    c->qcount[0] = 0;
     c->qcount[1] = 0;
     c->pcount[0] = 0;
     c->pcount[1] = 0;
     c->n_vertices = 0;
     c->n_events = 0;
-    c->paths += (unsigned long long)npix;
+    int ic = it < kOctFillIterations ? it : kOctFillIterations;
+    OctDyn d;
+    d.iter = it;
+    d.split_count = kOctSplitFactor * ic;
+    d.density_scale = 1.0f / (float)ic;
+    d.stop_filling = it > kOctFillIterations;
+    *dyn = d;
 }
 __global__ void k_iter_end(Counters* c) {
     c->vertices += (unsigned long long)c->n_vertices;
@@ -147,31 +212,49 @@ __global__ void k_scale_image(const float* a, float* out, int64_t n, float scale
 // ---------------------------------------------------------------------------
 // pass 1
 // ---------------------------------------------------------------------------
+// one camera ray per pixel of every scene still taking part; the live rays
+// are compacted into the queue
 __global__ void __launch_bounds__(256) k_camera(RenderArgs A, PathQ q) {
+    const int iter = A.cnt->iter;
+    unsigned started = 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < A.npix; i += gridDim.x * blockDim.x) {
-        int px = i % A.cam.w, py = i / A.cam.w;
-        U4 u = uniforms(A.k0, A.k1, (uint32_t)i, (uint32_t)A.iter, 0u, kTagCamera);
-        f3 d = cam_ray(A.cam, px, py, u.u[0], u.u[1]);
-        q.q0[i] = f4(load3(A.cam.eye), ibits(i));
-        q.q1[i] = f4(d, ibits(1));
-        q.q2[i] = make_float4(1.f, 1.f, 1.f, 0.f);
-        q.q3[i] = make_float4(0.f, 0.f, 0.f, ibits(-1));
+        int s = scene_of_pixel(A.pix_base, A.n_scenes, i);
+        const SceneInfo& I = A.sc[s];
+        bool act = scene_active(I, iter);
+        int slot = wave_reserve(&A.cnt->qcount[0], act);
+        if (act) {
+            int local = i - I.pix_base;
+            int px = local % I.cam.w, py = local / I.cam.w;
+            U4 u = uniforms(I.k0, I.k1, (uint32_t)local, (uint32_t)iter, 0u, kTagCamera);
+            f3 d = cam_ray(I.cam, px, py, u.u[0], u.u[1]);
+            q.q0[slot] = f4(load3(I.cam.eye), ibits(i));
+            q.q1[slot] = f4(d, ibits(make_tag(1, s)));
+            q.q2[slot] = make_float4(1.f, 1.f, 1.f, 0.f);
+            q.q3[slot] = make_float4(0.f, 0.f, 0.f, ibits(-1));
+            ++started;
+        }
     }
+    wave_add_u64(&A.cnt->paths, started);
 }
 
-// closest hit for a queue of rays given as (origin, direction) float4 arrays;
-// also clears the counter of the queue the next kernel appends to
-__global__ void __launch_bounds__(kTraceBlock) k_extend(SceneView S, const float4* __restrict__ org,
+// closest hit for a queue of rays given as (origin, direction) float4 arrays
+// (the direction's w is a tag word naming the scene); also clears the
+// counter of the queue the next kernel appends to
+template <int kStack>
+__global__ void __launch_bounds__(kTraceBlock) k_extend(SceneView S, const SceneInfo* sc,
+                                                        const float4* __restrict__ org,
                                                         const float4* __restrict__ dir, const int32_t* count,
                                                         int32_t* next_count, int2* __restrict__ hits,
                                                         unsigned long long* rays, Counters* cnt) {
-    __shared__ int stack[kBvhStack * kTraceBlock];
+    __shared__ int stack[kStack * kTraceBlock];
     int n = *count;
     if (blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
     unsigned traced = 0, nodes = 0, tris = 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         float t;
-        int prim = trace<false>(S, xyz(org[i]), xyz(dir[i]), INFINITY, t, stack + threadIdx.x, nodes, tris);
+        float4 d = dir[i];
+        int root = sc[tag_scene(fbits(d.w))].bvh_root;
+        int prim = trace<false, kStack>(S, root, xyz(org[i]), xyz(d), INFINITY, t, stack + threadIdx.x, nodes, tris);
         hits[i] = make_int2(fbits(t), prim);
         ++traced;
     }
@@ -186,10 +269,13 @@ __global__ void __launch_bounds__(256) k_shade(RenderArgs A, PathQ in, const int
                                                neb_path_record* rec) {
     int n = *count_in;
     const SceneView& S = A.S;
+    const int iter = A.cnt->iter;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         float4 a0 = in.q0[i], a1 = in.q1[i], a2 = in.q2[i], a3 = in.q3[i];
         int2 h = hits[i];
-        int pixel = fbits(a0.w), k = fbits(a1.w);
+        int pixel = fbits(a0.w), tg = fbits(a1.w);
+        int k = tag_depth(tg), sid = tag_scene(tg);
+        const SceneInfo& I = A.sc[sid];
         neb_path_record* rc = rec ? rec + (size_t)pixel * A.L + (k - 1) : nullptr;
         bool alive = h.y >= 0;
         if (!alive && rc) {
@@ -227,15 +313,15 @@ __global__ void __launch_bounds__(256) k_shade(RenderArgs A, PathQ in, const int
                 q = p_light / f_prev;
             }
             ev0[eslot] = f4(tau * load3(m.emission), q);
-            ev1[eslot] = make_float4(a3.x, a3.z, a3.w, ibits(pixel));
+            ev1[eslot] = make_float4(a3.x * I.r2pi, a3.z, a3.w, ibits(pixel));
         }
-        bool store = alive && !mat_black(m) && k <= A.L - 1;
+        bool store = alive && !mat_black(m) && k <= I.L - 1;
         float g = (k >= 2) ? a3.y / fabsf(cin) : 0.f;
         float B = (k >= 2) ? a3.x + a3.z : 0.f;
         int vid = wave_reserve(n_vertices, store);
         if (store) {
             V.v0[vid] = f4(x, ibits(pixel));
-            V.v1[vid] = f4(nrm, ibits(k | (mid << 8)));
+            V.v1[vid] = f4(nrm, ibits(make_vtag(k, sid, mid)));
             V.v2[vid] = f4(wo, B);
             V.v3[vid] = f4(tau, g);
             if (slots) slots[(size_t)(k - 1) * A.npix + pixel] = vid;
@@ -243,7 +329,7 @@ __global__ void __launch_bounds__(256) k_shade(RenderArgs A, PathQ in, const int
         Sample s;
         s.ev = 0;
         if (store) {
-            U4 u = uniforms(A.k0, A.k1, (uint32_t)pixel, (uint32_t)A.iter, (uint32_t)k, kTagBsdf);
+            U4 u = uniforms(I.k0, I.k1, (uint32_t)(pixel - I.pix_base), (uint32_t)iter, (uint32_t)k, kTagBsdf);
             s = bsdf_sample(m, nrm, wo, u);
         }
         bool go = s.ev != 0;
@@ -253,8 +339,8 @@ __global__ void __launch_bounds__(256) k_shade(RenderArgs A, PathQ in, const int
             float Acur = (k >= 2) ? bsdf_pdf(m, nrm, s.dir, wo) * g * B : 0.f;
             float gp = fabsf(dot3(nrm, s.dir)) / s.pdf;
             float dnon = mat_delta(m.type) ? 0.f : 1.f;
-            out.q0[slot] = f4(offset_origin(x, nrm, s.dir, S.eps), ibits(pixel));
-            out.q1[slot] = f4(s.dir, ibits(k + 1));
+            out.q0[slot] = f4(offset_origin(x, nrm, s.dir, I.eps), ibits(pixel));
+            out.q1[slot] = f4(s.dir, ibits(make_tag(k + 1, sid)));
             out.q2[slot] = f4(tau * s.w, s.pdf);
             out.q3[slot] = make_float4(Acur, gp, dnon, ibits(vid));
         }
@@ -266,18 +352,23 @@ __global__ void __launch_bounds__(256) k_shade(RenderArgs A, PathQ in, const int
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_density(RenderArgs A, VertexStore V, const int32_t* n_vertices,
                                                  const int32_t* __restrict__ nodes, const OctState* ost,
-                                                 OctParams P) {
+                                                 const OctParams* prm, const OctDyn* dyn) {
     int n = *n_vertices;
-    int depth = ost->depth;
+    const float scale = dyn->density_scale;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        f3 x = xyz(V.v0[i]), nn = xyz(V.v1[i]);
+        f3 x = xyz(V.v0[i]);
+        float4 a1 = V.v1[i];
+        f3 nn = xyz(a1);
+        int s = tag_scene(fbits(a1.w));
         float rho;
-        if (A.density_mode == NEB_DENSITY_ANALYTIC)
-            rho = A.rho0 + A.cam_w * cam_hit_density(A.cam, x, nn);
-        else if (A.density_mode == NEB_DENSITY_OCTREE)
-            rho = oct_query(nodes, P, depth, x, nn, false, nullptr);
-        else
-            rho = oct_query_robust(nodes, P, depth, x, nn);
+        if (A.density_mode == NEB_DENSITY_ANALYTIC) {
+            const SceneInfo& I = A.sc[s];
+            rho = I.rho0 + I.cam_w * cam_hit_density(I.cam, x, nn);
+        } else if (A.density_mode == NEB_DENSITY_OCTREE) {
+            rho = oct_query(nodes, prm[s], scale, ost[s].depth, x, nn, false, nullptr);
+        } else {
+            rho = oct_query_robust(nodes, prm[s], scale, ost[s].depth, x, nn);
+        }
         V.rho[i] = rho;
     }
 }
@@ -291,19 +382,23 @@ struct LightSample {
     bool hittable;
 };
 
-__device__ __forceinline__ LightSample sample_light(const SceneView& S, f3 x, f3 nx, const U4& u) {
+// lights of one scene: [base, base + count) of the light pool, selected by
+// the scene's cumulative power table
+__device__ __forceinline__ LightSample sample_light(const SceneView& S, int base, int count, f3 x, f3 nx,
+                                                    const U4& u) {
     LightSample ls;
     ls.dE = mk3(0.f, 0.f, 0.f);
     ls.hittable = false;
     ls.p_light = 0.f;
     ls.cos_l = 0.f;
-    int lo = 0, hi = S.n_lights - 1;
+    int lo = 0, hi = count - 1;
+    const float* cdf = S.light_cdf + base;
     while (lo < hi) {
         int mid = (lo + hi) >> 1;
-        if (u.u[0] < S.light_cdf[mid]) hi = mid;
+        if (u.u[0] < cdf[mid]) hi = mid;
         else lo = mid + 1;
     }
-    const float4* L = S.lights + 5 * lo;
+    const float4* L = S.lights + 5 * (size_t)(base + lo);
     float4 l0 = L[0], l1 = L[1], l2 = L[2], l3 = L[3];
     float psel = l0.w;
     if (l1.w > 0.f) {  // emissive triangle
@@ -341,30 +436,36 @@ __device__ __forceinline__ LightSample sample_light(const SceneView& S, f3 x, f3
     return ls;
 }
 
+template <int kStack>
 __global__ void __launch_bounds__(kTraceBlock) k_nee(RenderArgs A, VertexStore V, const int32_t* n_vertices,
-                                                     Images img, PhotonQ pq, int32_t* pcount, Counters* cnt) {
-    __shared__ int stack[kBvhStack * kTraceBlock];
+                                                     Images img, PhotonQ pq, int32_t* pcount) {
+    __shared__ int stack[kStack * kTraceBlock];
     int n = *n_vertices;
     const SceneView& S = A.S;
+    Counters* cnt = A.cnt;
+    const int iter = cnt->iter;
     unsigned vis = 0, emitted = 0, rays = 0, nodes = 0, tris = 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         float4 a0 = V.v0[i], a1 = V.v1[i], a2 = V.v2[i], a3 = V.v3[i];
         float rho = V.rho[i];
         f3 x = xyz(a0), nrm = xyz(a1), wo = xyz(a2), tau = xyz(a3);
         int pixel = fbits(a0.w);
-        int packed = fbits(a1.w);
-        int k = packed & 0xFF, mid = packed >> 8;
+        int tg = fbits(a1.w);
+        int k = tag_depth(tg), sid = tag_scene(tg), mid = tag_mat(tg);
+        const SceneInfo& I = A.sc[sid];
+        const uint32_t lpix = (uint32_t)(pixel - I.pix_base);
         const neb_material& m = S.mats[mid];
-        U4 u = uniforms(A.k0, A.k1, (uint32_t)pixel, (uint32_t)A.iter, (uint32_t)k, kTagNee);
-        LightSample ls = sample_light(S, x, nrm, u);
+        U4 u = uniforms(I.k0, I.k1, lpix, (uint32_t)iter, (uint32_t)k, kTagNee);
+        LightSample ls = sample_light(S, I.light_base, I.n_lights, x, nrm, u);
         bool ok = !is_zero3(ls.dE);
         if (ok) {
-            f3 so = offset_origin(x, nrm, ls.w, S.eps);
+            f3 so = offset_origin(x, nrm, ls.w, I.eps);
             f3 sd = ls.x - so;
             float sl = sqrtf(dot3(sd, sd));
             float tt;
             ++rays;
-            ok = trace<true>(S, so, sd * (1.0f / sl), (1.0f - 1e-5f) * sl, tt, stack + threadIdx.x, nodes, tris) < 0;
+            ok = trace<true, kStack>(S, I.bvh_root, so, sd * (1.0f / sl), (1.0f - 1e-5f) * sl, tt, stack + threadIdx.x,
+                                     nodes, tris) < 0;
         }
         bool photon = false;
         Sample s;
@@ -378,12 +479,12 @@ __global__ void __launch_bounds__(kTraceBlock) k_nee(RenderArgs A, VertexStore V
                     float Am1 = (k >= 2) ? bsdf_pdf(m, nrm, ls.w, wo) * a3.w * a2.w : 0.f;
                     float ratio = 1.0f;
                     if (ls.hittable) ratio += bsdf_pdf(m, nrm, wo, ls.w) * ls.cos_l / (ls.d2 * ls.p_light);
-                    if (A.photons) ratio += rho * A.r2pi * Am1;
+                    if (A.photons) ratio += rho * I.r2pi * Am1;
                     atomic_add3(img.E, pixel, tau * f * ls.dE * (1.0f / ratio));
                 }
             }
             if (A.photons && rho > 0.f) {
-                U4 up = uniforms(A.k0, A.k1, (uint32_t)pixel, (uint32_t)A.iter, (uint32_t)(16 * k), kTagPhoton);
+                U4 up = uniforms(I.k0, I.k1, lpix, (uint32_t)iter, (uint32_t)(16 * k), kTagPhoton);
                 s = bsdf_sample(m, nrm, ls.w, up);
                 photon = s.ev != 0;
             }
@@ -393,11 +494,11 @@ __global__ void __launch_bounds__(kTraceBlock) k_nee(RenderArgs A, VertexStore V
             ++emitted;
             float fo = ls.hittable ? bsdf_pdf(m, nrm, s.dir, ls.w) * ls.cos_l / (ls.d2 * ls.p_light) : 0.f;
             float dnon = mat_delta(m.type) ? 0.f : 1.f;
-            float U1 = (fo + dnon) / (rho * A.r2pi);
+            float U1 = (fo + dnon) / (rho * I.r2pi);
             float hp = fabsf(dot3(nrm, s.dir)) / s.pdf;
             f3 phi = ls.dE * (1.0f / rho) * s.w;
-            pq.p0[slot] = f4(offset_origin(x, nrm, s.dir, S.eps), ibits(pixel));
-            pq.p1[slot] = f4(s.dir, ibits(16 * k + 1));
+            pq.p0[slot] = f4(offset_origin(x, nrm, s.dir, I.eps), ibits(pixel));
+            pq.p1[slot] = f4(s.dir, ibits(make_tag(16 * k + 1, sid)));
             pq.p2[slot] = f4(phi, hp);
             pq.pu[slot] = U1;
         }
@@ -413,42 +514,48 @@ __global__ void __launch_bounds__(kTraceBlock) k_nee(RenderArgs A, VertexStore V
 // merge structure: hash grid of cell size 2r over the non-delta view vertices
 // (count -> exclusive scan -> scatter); count[] returns to zero after scatter
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t cell_hash(int cx, int cy, int cz, int32_t T) {
-    return (((uint32_t)cx * 73856093u) ^ ((uint32_t)cy * 19349663u) ^ ((uint32_t)cz * 83492791u)) & (uint32_t)(T - 1);
+__device__ __forceinline__ uint32_t cell_hash(int cx, int cy, int cz, int scene, int32_t T) {
+    return (((uint32_t)cx * 73856093u) ^ ((uint32_t)cy * 19349663u) ^ ((uint32_t)cz * 83492791u) ^
+            ((uint32_t)scene * 2654435761u)) &
+           (uint32_t)(T - 1);
 }
-__device__ __forceinline__ uint32_t point_hash(f3 p, float inv_cell, int32_t T) {
-    return cell_hash((int)floorf(p.x * inv_cell), (int)floorf(p.y * inv_cell), (int)floorf(p.z * inv_cell), T);
+__device__ __forceinline__ uint32_t point_hash(f3 p, float inv_cell, int scene, int32_t T) {
+    return cell_hash((int)floorf(p.x * inv_cell), (int)floorf(p.y * inv_cell), (int)floorf(p.z * inv_cell), scene, T);
 }
 
 __device__ __forceinline__ int64_t grid_key(const Grid& G, uint32_t h, int depth) {
     return (int64_t)h * G.D + (depth - 1);
 }
 
-__global__ void __launch_bounds__(256) k_grid_count(const neb_material* mats, VertexStore V, const int32_t* n_vertices,
-                                                    Grid G) {
+__global__ void __launch_bounds__(256) k_grid_count(const neb_material* mats, const SceneInfo* sc, VertexStore V,
+                                                    const int32_t* n_vertices, Grid G) {
     int n = *n_vertices;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        int packed = fbits(V.v1[i].w);
-        if (mat_delta(mats[packed >> 8].type)) continue;
-        atomicAdd(&G.count[grid_key(G, point_hash(xyz(V.v0[i]), G.inv_cell, G.T), packed & 0xFF)], 1);
+        int tg = fbits(V.v1[i].w);
+        if (mat_delta(mats[tag_mat(tg)].type)) continue;
+        int s = tag_scene(tg);
+        atomicAdd(&G.count[grid_key(G, point_hash(xyz(V.v0[i]), sc[s].inv_cell, s, G.T), tag_depth(tg))], 1);
     }
 }
 
-__global__ void __launch_bounds__(256) k_grid_scatter(const neb_material* mats, VertexStore V,
+__global__ void __launch_bounds__(256) k_grid_scatter(const neb_material* mats, const SceneInfo* sc, VertexStore V,
                                                       const int32_t* n_vertices, Grid G) {
     int n = *n_vertices;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        int packed = fbits(V.v1[i].w);
-        if (mat_delta(mats[packed >> 8].type)) continue;
-        f3 p = xyz(V.v0[i]);
-        int64_t key = grid_key(G, point_hash(p, G.inv_cell, G.T), packed & 0xFF);
+        float4 a1 = V.v1[i];
+        int tg = fbits(a1.w);
+        if (mat_delta(mats[tag_mat(tg)].type)) continue;
+        int s = tag_scene(tg);
+        float4 a0 = V.v0[i];
+        f3 p = xyz(a0);
+        int64_t key = grid_key(G, point_hash(p, sc[s].inv_cell, s, G.T), tag_depth(tg));
         int pos = G.start[key] + atomicSub(&G.count[key], 1) - 1;
-        G.sorted[pos] = f4(p, ibits(i));
+        G.sorted[pos] = f4(p, ibits(s));
         float4* m = G.mrec + 4 * (size_t)pos;
-        m[0] = V.v1[i];
+        m[0] = a1;
         m[1] = V.v2[i];
         m[2] = V.v3[i];
-        m[3] = make_float4(V.v0[i].w, 0.f, 0.f, 0.f);
+        m[3] = make_float4(a0.w, 0.f, 0.f, 0.f);
     }
 }
 
@@ -554,18 +661,16 @@ static void scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* 
 // One wave per block.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const int32_t* count_in, const int2* hits,
-                                               PhotonQ out, int32_t* count_out, VertexStore V, Grid G, Images img,
-                                               Counters* cnt) {
+                                               PhotonQ out, int32_t* count_out, Grid G, Images img) {
     __shared__ int2 queue[128];
-    __shared__ float4 tp[64][2];  // per lane's photon: (-d, h*U), (Phi / (pi r^2), bounce)
+    __shared__ float4 tp[64][2];  // per lane's photon: (-d, h*U), (Phi / (pi r^2), deepest mergeable depth)
     const int lane = threadIdx.x;
     const unsigned long long below = (1ull << lane) - 1ull;
     const int n = *count_in;
     const SceneView& S = A.S;
+    Counters* cnt = A.cnt;
+    const int iter = cnt->iter;
     unsigned segs = 0, merges = 0, items = 0, cont = 0, cells = 0, cands = 0;
-    const float r2 = A.r * A.r;
-    const float kern = 1.0f / A.r2pi;
-    const float cell = 1.0f / G.inv_cell;
     int qn = 0;  // queue length, identical in every lane
 
     auto flush = [&](int count) {
@@ -574,10 +679,10 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
             float4 t0 = tp[pr.x][0], t1 = tp[pr.x][1];
             const float4* mr = G.mrec + 4 * (size_t)pr.y;  // one 64-byte record
             float4 v1 = mr[0];
-            int packed = fbits(v1.w);
-            int k = packed & 0xFF;
-            if (k + fbits(t1.w) + 1 <= A.L) {
-                const neb_material& mv = S.mats[packed >> 8];
+            int tg = fbits(v1.w);
+            int k = tag_depth(tg);
+            if (k <= fbits(t1.w)) {
+                const neb_material& mv = S.mats[tag_mat(tg)];
                 float4 v2 = mr[1];
                 f3 nv = xyz(v1), wv = xyz(v2), wd = xyz(t0);
                 f3 f = bsdf_f(mv, nv, wv, wd);
@@ -607,8 +712,11 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
             ++items;
         }
         bool hit = h.y >= 0;
-        int code = fbits(b1.w);
+        int tg = fbits(b1.w);
+        int code = tag_depth(tg), sid = tag_scene(tg);
         int j = code & 15, odepth = code >> 4, opix = fbits(b0.w);
+        const SceneInfo& I = A.sc[sid];
+        const float r = I.r, r2 = r * r, inv_cell = I.inv_cell, cell = 1.0f / inv_cell;
         f3 d = xyz(b1);
         f3 y = mk3(0.f, 0.f, 0.f), ny = mk3(0.f, 0.f, 1.f);
         float hh = 0.f;
@@ -623,28 +731,28 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
         }
         const neb_material& my = S.mats[mid];
         bool mergeable = hit && !mat_delta(my.type);
+        const int kmax = I.L - 1 - j;  // deepest view vertex this photon may merge with
         tp[lane][0] = f4(-d, hh * U);
-        tp[lane][1] = f4(xyz(b2) * kern, ibits(j));
+        tp[lane][1] = f4(xyz(b2) * (1.0f / I.r2pi), ibits(kmax));
         // candidate ranges of the (at most 8) cells the ball touches
         int lo[8], pre[9];
         pre[0] = 0;
-        const int kmax = A.L - 1 - j;  // deepest view vertex this photon may merge with
         {
-            float rr = A.r * 1.00001f;
-            int lx = (int)floorf((y.x - rr) * G.inv_cell), hx = min((int)floorf((y.x + rr) * G.inv_cell), lx + 1);
-            int ly = (int)floorf((y.y - rr) * G.inv_cell), hy = min((int)floorf((y.y + rr) * G.inv_cell), ly + 1);
-            int lz = (int)floorf((y.z - rr) * G.inv_cell), hz = min((int)floorf((y.z + rr) * G.inv_cell), lz + 1);
+            float rr = r * 1.00001f;
+            int lx = (int)floorf((y.x - rr) * inv_cell), hx = min((int)floorf((y.x + rr) * inv_cell), lx + 1);
+            int ly = (int)floorf((y.y - rr) * inv_cell), hy = min((int)floorf((y.y + rr) * inv_cell), ly + 1);
+            int lz = (int)floorf((y.z - rr) * inv_cell), hz = min((int)floorf((y.z + rr) * inv_cell), lz + 1);
             uint32_t seen[8];
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
                 int cx = lx + (c & 1), cy = ly + ((c >> 1) & 1), cz = lz + ((c >> 2) & 1);
-                bool use = mergeable && cx <= hx && cy <= hy && cz <= hz;
+                bool use = mergeable && kmax >= 1 && cx <= hx && cy <= hy && cz <= hz;
                 // skip cells whose box is farther than r from the hit
                 float dx = fmaxf(fmaxf(cx * cell - y.x, y.x - (cx + 1) * cell), 0.f);
                 float dy = fmaxf(fmaxf(cy * cell - y.y, y.y - (cy + 1) * cell), 0.f);
                 float dz = fmaxf(fmaxf(cz * cell - y.z, y.z - (cz + 1) * cell), 0.f);
                 use = use && dx * dx + dy * dy + dz * dz <= r2 * 1.0001f;
-                uint32_t hc = cell_hash(cx, cy, cz, G.T);
+                uint32_t hc = cell_hash(cx, cy, cz, sid, G.T);
                 seen[c] = use ? hc : 0xFFFFFFFFu;
 #pragma unroll
                 for (int q = 0; q < c; ++q) use = use && seen[q] != hc;
@@ -674,7 +782,8 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
                     if (k >= pre[c] && k < pre[c + 1]) e = lo[c] + (k - pre[c]);
                 float4 cd = G.sorted[e];
                 f3 dv = xyz(cd) - y;
-                acc = dot3(dv, dv) < r2;
+                // a bucket may also hold another scene's cell
+                acc = dot3(dv, dv) < r2 && fbits(cd.w) == sid;
                 vid = e;  // the record index: its merge data sits at G.mrec[4 e]
             }
             unsigned long long m = __ballot(acc);
@@ -702,8 +811,9 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
         bool go = false;
         Sample s;
         s.ev = 0;
-        if (hit && j < A.L - 2 && !mat_black(my)) {
-            U4 u = uniforms(A.k0, A.k1, (uint32_t)opix, (uint32_t)A.iter, (uint32_t)(16 * odepth + j), kTagPhoton);
+        if (hit && j < I.L - 2 && !mat_black(my)) {
+            U4 u = uniforms(I.k0, I.k1, (uint32_t)(opix - I.pix_base), (uint32_t)iter, (uint32_t)(16 * odepth + j),
+                            kTagPhoton);
             s = bsdf_sample(my, ny, -d, u);
             go = s.ev != 0;
         }
@@ -714,8 +824,8 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
             float prev = bsdf_pdf(my, ny, s.dir, wd);
             float Un = (mat_delta(my.type) ? 0.f : 1.f) + prev * hh * U;
             float hp = fabsf(dot3(ny, s.dir)) / s.pdf;
-            out.p0[slot] = f4(offset_origin(y, ny, s.dir, S.eps), ibits(opix));
-            out.p1[slot] = f4(s.dir, ibits(16 * odepth + j + 1));
+            out.p0[slot] = f4(offset_origin(y, ny, s.dir, I.eps), ibits(opix));
+            out.p1[slot] = f4(s.dir, ibits(make_tag(16 * odepth + j + 1, sid)));
             out.p2[slot] = f4(xyz(b2) * s.w, hp);
             out.pu[slot] = Un;
         }
@@ -741,7 +851,7 @@ __global__ void __launch_bounds__(256) k_finalize(RenderArgs A, const float4* ev
         if (a.w > 0.f) {
             int pv = fbits(b.z);
             float ratio = b.y;
-            if (A.photons) ratio += rho[pv] * A.r2pi * b.x;
+            if (A.photons) ratio += rho[pv] * b.x;
             w = 1.0f / (1.0f + a.w * ratio);
         }
         atomic_add3(img.e, fbits(b.w), xyz(a) * w);
@@ -777,20 +887,55 @@ struct neb_octree_s {
     Octree o;
 };
 
-struct neb_ctx_s {
-    neb_params prm{};
-    int npix = 0, L = 0;
-    int64_t vcap = 0, ecap = 0;
-    // scene
-    bool has_scene = false;
-    float4 *bvh = nullptr, *tri = nullptr, *prim_n = nullptr, *lights = nullptr;
-    int32_t* prim_light = nullptr;
-    float* light_cdf = nullptr;
-    neb_material* mats = nullptr;
-    SceneView view{};
+// validated host copy of one scene of the batch
+struct HostScene {
+    bool set = false;
+    BvhHost bvh;
+    int32_t nt = 0;
+    std::vector<float> prim_n;        // 4 per prim: unit normal, w = scene-local material id bits
+    std::vector<int32_t> prim_light;  // scene-local light id or -1
+    std::vector<float> lights;        // 20 floats per light
+    std::vector<float> cdf;           // cumulative selection probabilities
+    std::vector<neb_material> mats;
+    float bmin[3] = {0, 0, 0}, bmax[3] = {0, 0, 0};
     CamParams cam{};
-    Octree oct;
-    // pools
+    float eps = 0.f;
+};
+
+// launch shapes picked by neb_autotune (or set by the caller)
+struct LaunchCfg {
+    int stack = 48;      // LDS traversal stack entries per lane: 32, 48 or 64
+    int trace_bpc = 0;   // traversal blocks (one wave each) per CU; 0 = one block per 64 queue slots
+    int photon_bpc = 0;  // photon-merge blocks (one wave each) per CU; 0 = one block per 256 queue slots
+};
+
+struct neb_ctx_s {
+    int n_scenes = 0;
+    std::vector<neb_params> prm;
+    std::vector<HostScene> hs;
+    std::vector<int32_t> pix_base;  // n_scenes + 1
+    int npix = 0, L = 0;
+    int64_t vcap = 0, ecap = 0, slot_cap = 0;
+    int density_mode = 0, flags = 0, photons = 1;
+    int cus = 256;
+    // per-scene device tables and the shared geometry pools
+    bool ready = false;  // forest uploaded and octrees initialised since the last scene change
+    int forest_depth = 0;
+    SceneInfo* sc_dev = nullptr;
+    int32_t* pix_base_dev = nullptr;
+    std::vector<SceneInfo> sc_host;
+    SceneView view{};
+    std::vector<void*> scene_allocs;
+    // octree pool: scene s owns [oct_prm[s].root, oct_prm[s].end)
+    int32_t* oct_nodes = nullptr;
+    OctState* oct_states = nullptr;
+    OctParams* oct_prm_dev = nullptr;
+    OctDyn* oct_dyn = nullptr;
+    std::vector<OctParams> oct_prm;
+    int64_t oct_total = 0;
+    int32_t* defer[2] = {nullptr, nullptr};
+    int32_t* defer_cnt = nullptr;
+    // per-iteration pools
     PathQ q[2]{};
     PhotonQ pq[2]{};
     int2* hits = nullptr;
@@ -799,14 +944,18 @@ struct neb_ctx_s {
     int32_t* slots = nullptr;
     neb_path_record* recs = nullptr;
     Grid G{};
-    float* img = nullptr;  // e, E, P accumulators
+    float* img = nullptr;  // e, E, P accumulators, 3 * npix floats each
     Counters* cnt = nullptr;
     int32_t iter = 0;
     int32_t first_iter_recorded = 0;
-    int32_t trace_grid = 4096;  // resident traversal blocks on this device
     hipStream_t last_stream = nullptr;
     std::vector<void*> allocs;
-    std::vector<void*> scene_allocs;
+    LaunchCfg cfg;
+    // captured iteration
+    bool use_graph = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t cap_stream = nullptr;
     // kernel profiling
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;
@@ -834,6 +983,25 @@ static void prof_harvest(neb_ctx c) {
         }
     }
     c->prof_used = 0;
+}
+
+static void prof_clear(neb_ctx c) {
+    prof_harvest(c);
+    for (int k = 0; k < 32; ++k) {
+        c->prof_ms[k] = 0.0;
+        c->prof_launches[k] = 0;
+    }
+}
+
+static hipError_t prof_alloc(neb_ctx c) {
+    if (!c->prof_ev.empty()) return hipSuccess;
+    c->prof_ev.resize(4096);
+    c->prof_kid.resize(2048);
+    for (auto& e : c->prof_ev) {
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+    }
+    return hipSuccess;
 }
 
 static void prof_begin(neb_ctx c, int kid, hipStream_t s) {
@@ -897,9 +1065,31 @@ static uint32_t next_pow2(uint64_t v) {
     return (uint32_t)p;
 }
 
-extern "C" neb_status neb_create(const neb_params* p, neb_ctx* out) {
-    if (!p || !out) return fail(NEB_ERR_INVALID_ARG, "null pointer");
-    *out = nullptr;
+static int lds_blocks_per_cu(int stack) { return (160 * 1024) / (stack * kTraceBlock * 4); }
+
+// blocks of a traversal launch over a queue of at most cap rays
+static int trace_grid(neb_ctx c, int64_t cap) {
+    if (c->cfg.trace_bpc > 0) return std::max(1, c->cus * c->cfg.trace_bpc);
+    return grid_of(cap, kTraceBlock, 1 << 20);
+}
+
+static void drop_graph(neb_ctx c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+}
+
+static void destroy_ctx(neb_ctx c) {
+    drop_graph(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    free_list(c->scene_allocs);
+    free_list(c->allocs);
+    for (auto& e : c->prof_ev) (void)hipEventDestroy(e);
+    delete c;
+}
+
+static neb_status check_params(const neb_params* p) {
     if (p->width < 1 || p->height < 1 || p->width > 8192 || p->height > 8192)
         return fail(NEB_ERR_INVALID_ARG, "image size out of range");
     if (p->max_path_len < 1 || p->max_path_len > kMaxPathLen) return fail(NEB_ERR_INVALID_ARG, "max_path_len out of range");
@@ -910,21 +1100,71 @@ extern "C" neb_status neb_create(const neb_params* p, neb_ctx* out) {
         return fail(NEB_ERR_INVALID_ARG, "unknown density mode");
     if (!std::isfinite(p->analytic_rho0) || !std::isfinite(p->analytic_cam_weight))
         return fail(NEB_ERR_INVALID_ARG, "analytic density parameters must be finite");
-    int64_t npix = (int64_t)p->width * p->height;
-    int64_t vcap = npix * std::max(1, p->max_path_len - 1);
-    if (vcap * 4 > (int64_t)INT32_MAX) return fail(NEB_ERR_CAPACITY, "image too large for the vertex pool");
+    if (p->spp < 0) return fail(NEB_ERR_INVALID_ARG, "spp must be >= 0");
+    return NEB_OK;
+}
+
+extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scenes, neb_ctx* out) {
+    if (!params || !out) return fail(NEB_ERR_INVALID_ARG, "null pointer");
+    *out = nullptr;
+    if (n_scenes < 1 || n_scenes > kMaxScenes) return fail(NEB_ERR_INVALID_ARG, "scene count out of range (1..256)");
+    int64_t npix = 0, vcap = 0, ecap = 0, oct_total = 0;
+    int L = 0;
+    for (int s = 0; s < n_scenes; ++s) {
+        neb_status st = check_params(params + s);
+        if (st != NEB_OK) return st;
+        const neb_params& p = params[s];
+        if (p.density_mode != params[0].density_mode || p.flags != params[0].flags)
+            return fail(NEB_ERR_INVALID_ARG, "every scene of a batch needs the same density mode and flags");
+        int64_t np = (int64_t)p.width * p.height;
+        npix += np;
+        vcap += np * std::max(1, p.max_path_len - 1);
+        ecap += np * p.max_path_len;
+        oct_total += octree_capacity_rounded(p.octree_capacity);
+        L = std::max(L, p.max_path_len);
+    }
+    if (npix > (int64_t)INT32_MAX / 16 || vcap * 4 > (int64_t)INT32_MAX || ecap > (int64_t)INT32_MAX)
+        return fail(NEB_ERR_CAPACITY, "images too large for the vertex pool");
+    if (oct_total >= (int64_t)INT32_MAX - 16) return fail(NEB_ERR_CAPACITY, "octree pool over 2^31 nodes");
+    int64_t slot_cap = npix * std::max(1, L - 1);
+    if ((params[0].flags & NEB_FLAG_SINGLE_THREAD_OCTREE) && slot_cap > (int64_t)INT32_MAX)
+        return fail(NEB_ERR_CAPACITY, "too many pixels for single-thread deposits");
+
     neb_ctx c = new neb_ctx_s();
-    c->prm = *p;
+    c->n_scenes = n_scenes;
+    c->prm.assign(params, params + n_scenes);
+    c->hs.resize(n_scenes);
+    c->pix_base.resize(n_scenes + 1);
+    c->oct_prm.resize(n_scenes);
+    c->sc_host.resize(n_scenes);
+    {
+        int64_t pb = 0, root = 0;
+        for (int s = 0; s < n_scenes; ++s) {
+            c->pix_base[s] = (int32_t)pb;
+            pb += (int64_t)params[s].width * params[s].height;
+            OctParams& P = c->oct_prm[s];
+            std::memset(&P, 0, sizeof(P));
+            P.root = (int32_t)root;
+            P.end = (int32_t)(root + octree_capacity_rounded(params[s].octree_capacity));
+            root = P.end;
+        }
+        c->pix_base[n_scenes] = (int32_t)pb;
+    }
+    c->npix = (int)npix;
+    c->L = L;
+    c->vcap = vcap;
+    c->ecap = ecap;
+    c->slot_cap = slot_cap;
+    c->oct_total = oct_total;
+    c->density_mode = params[0].density_mode;
+    c->flags = params[0].flags;
+    c->photons = (c->flags & NEB_FLAG_NO_PHOTONS) ? 0 : 1;
     {
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-            c->trace_grid = cus * kTraceBlocksPerCU;
+            c->cus = cus;
     }
-    c->npix = (int)npix;
-    c->L = p->max_path_len;
-    c->vcap = vcap;
-    c->ecap = npix * p->max_path_len;
     hipError_t e = hipSuccess;
 #define ALLOC(ptr, n)                                   \
     if (e == hipSuccess) e = dalloc(c->allocs, &(ptr), (size_t)(n));
@@ -944,13 +1184,12 @@ extern "C" neb_status neb_create(const neb_params* p, neb_ctx* out) {
     ALLOC(c->V.v2, vcap);
     ALLOC(c->V.v3, vcap);
     ALLOC(c->V.rho, vcap);
-    ALLOC(c->ev0, c->ecap);
-    ALLOC(c->ev1, c->ecap);
-    if (p->flags & NEB_FLAG_SINGLE_THREAD_OCTREE) ALLOC(c->slots, vcap);
-    if (p->flags & NEB_FLAG_RECORD_PATHS) ALLOC(c->recs, npix * p->max_path_len);
-    c->G.D = std::max(1, p->max_path_len - 1);
+    ALLOC(c->ev0, ecap);
+    ALLOC(c->ev1, ecap);
+    if (c->flags & NEB_FLAG_SINGLE_THREAD_OCTREE) ALLOC(c->slots, slot_cap);
+    if (c->flags & NEB_FLAG_RECORD_PATHS) ALLOC(c->recs, npix * L);
+    c->G.D = std::max(1, L - 1);
     c->G.T = (int32_t)std::max<uint64_t>(1024, std::min<uint64_t>(next_pow2((uint64_t)vcap) / 2, 1u << 23));
-    c->G.inv_cell = 1.0f / (2.0001f * p->merge_radius);  // a little wider than the ball's diameter
     int64_t gkeys = (int64_t)c->G.T * c->G.D + 1;
     ALLOC(c->G.count, gkeys);
     ALLOC(c->G.start, gkeys);
@@ -959,45 +1198,46 @@ extern "C" neb_status neb_create(const neb_params* p, neb_ctx* out) {
     ALLOC(c->G.sums, scan_scratch(gkeys));
     ALLOC(c->img, 9 * npix);
     ALLOC(c->cnt, 1);
-    ALLOC(c->oct.nodes, 1 + ((p->octree_capacity + 7) & ~7));
-    ALLOC(c->oct.state, 1);
+    ALLOC(c->oct_nodes, oct_total);
+    ALLOC(c->oct_states, n_scenes);
+    ALLOC(c->oct_prm_dev, n_scenes);
+    ALLOC(c->oct_dyn, 1);
+    ALLOC(c->defer[0], vcap);
+    ALLOC(c->defer[1], vcap);
+    ALLOC(c->defer_cnt, 3);
+    ALLOC(c->sc_dev, n_scenes);
+    ALLOC(c->pix_base_dev, n_scenes + 1);
 #undef ALLOC
-    if (e == hipSuccess) e = octree_reserve(c->oct, vcap);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(gkeys, 256)), dim3(256), 0, nullptr, c->G.count, 0, gkeys);
+        hipLaunchKernelGGL(k_fill_f32, dim3(grid_of(9 * npix, 256)), dim3(256), 0, nullptr, c->img, 0.f, 9 * npix);
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, nullptr, (int32_t*)c->cnt, 0,
+                           (int64_t)(sizeof(Counters) / 4));
+        e = hipMemcpy(c->pix_base_dev, c->pix_base.data(), 4 * c->pix_base.size(), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         neb_status s = oom_or_device(e, "neb_create");
-        free_list(c->allocs);
-        c->oct.nodes = nullptr;
-        c->oct.state = nullptr;
-        octree_release(c->oct);
-        delete c;
-        return s;
-    }
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(gkeys, 256)), dim3(256), 0, nullptr, c->G.count, 0, gkeys);
-    hipLaunchKernelGGL(k_fill_f32, dim3(grid_of(9 * npix, 256)), dim3(256), 0, nullptr, c->img, 0.f, 9 * npix);
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, nullptr, (int32_t*)c->cnt, 0,
-                       (int64_t)(sizeof(Counters) / 4));
-    e = hipDeviceSynchronize();
-    if (e != hipSuccess) {
-        neb_status s = oom_or_device(e, "neb_create init");
-        free_list(c->allocs);
-        c->oct.nodes = nullptr;
-        c->oct.state = nullptr;
-        octree_release(c->oct);
-        delete c;
+        destroy_ctx(c);
         return s;
     }
     *out = c;
     return NEB_OK;
 }
 
+extern "C" neb_status neb_create(const neb_params* p, neb_ctx* out) { return neb_create_batch(p, 1, out); }
+
 static bool finite3(const float* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
 
-extern "C" neb_status neb_set_scene(neb_ctx c, const float* vertices, int32_t nv, const int32_t* tris,
-                                    const int32_t* tri_material, int32_t nt, const neb_material* materials, int32_t nm,
-                                    const neb_point_light* point_lights, int32_t npl, const neb_camera* camera) {
-    if (!c || !vertices || !tris || !tri_material || !materials || !camera) return fail(NEB_ERR_INVALID_ARG, "null pointer");
+// validates one scene and builds its BVH and light table on the host
+static neb_status build_host_scene(const neb_params& prm, const float* vertices, int32_t nv, const int32_t* tris,
+                                   const int32_t* tri_material, int32_t nt, const neb_material* materials, int32_t nm,
+                                   const neb_point_light* point_lights, int32_t npl, const neb_camera* camera,
+                                   HostScene& H) {
+    if (!vertices || !tris || !tri_material || !materials || !camera) return fail(NEB_ERR_INVALID_ARG, "null pointer");
     if (nv < 3 || nt < 1 || nm < 1 || npl < 0 || (npl > 0 && !point_lights))
         return fail(NEB_ERR_INVALID_ARG, "bad scene sizes");
+    if (nm > kMaxMaterials) return fail(NEB_ERR_CAPACITY, "more than 65536 materials");
     float bmin[3] = {INFINITY, INFINITY, INFINITY}, bmax[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int64_t i = 0; i < nv; ++i) {
         if (!finite3(vertices + 3 * i)) return fail(NEB_ERR_INVALID_ARG, "non-finite vertex");
@@ -1027,101 +1267,8 @@ extern "C" neb_status neb_set_scene(neb_ctx c, const float* vertices, int32_t nv
     if (!finite3(camera->eye) || !finite3(camera->look_at) || !finite3(camera->up) ||
         !(camera->vfov_deg > 0.f && camera->vfov_deg < 180.f))
         return fail(NEB_ERR_INVALID_ARG, "bad camera");
-
-    // BVH
-    BvhHost bvh;
-    if (!build_bvh(vertices, nv, tris, nt, bvh)) return fail(NEB_ERR_INVALID_ARG, "BVH build failed");
-    if (bvh.max_depth >= kBvhStack) return fail(NEB_ERR_CAPACITY, "BVH deeper than the traversal stack");
-    // per-prim normals and light table (emissive triangles, then point lights)
-    std::vector<float> prim_n(4 * (size_t)nt);
-    std::vector<int32_t> prim_light(nt, -1);
-    std::vector<double> w;
-    std::vector<float> lights;
-    auto emis = [&](const neb_material& m) { return ((double)m.emission[0] + m.emission[1] + m.emission[2]) / 3.0; };
-    for (int64_t t = 0; t < nt; ++t) {
-        const float* a = vertices + 3 * (size_t)tris[3 * t];
-        const float* b = vertices + 3 * (size_t)tris[3 * t + 1];
-        const float* cc = vertices + 3 * (size_t)tris[3 * t + 2];
-        double e1[3], e2[3], cr[3];
-        for (int k = 0; k < 3; ++k) {
-            e1[k] = (double)b[k] - a[k];
-            e2[k] = (double)cc[k] - a[k];
-        }
-        cr[0] = e1[1] * e2[2] - e1[2] * e2[1];
-        cr[1] = e1[2] * e2[0] - e1[0] * e2[2];
-        cr[2] = e1[0] * e2[1] - e1[1] * e2[0];
-        double len = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
-        for (int k = 0; k < 3; ++k) prim_n[4 * t + k] = len > 0 ? (float)(cr[k] / len) : (k == 2 ? 1.f : 0.f);
-        int32_t mid = tri_material[t];
-        std::memcpy(&prim_n[4 * t + 3], &mid, 4);
-        const neb_material& m = materials[mid];
-        if (emis(m) > 0.0 && len > 0) {
-            prim_light[t] = (int32_t)w.size();
-            double area = 0.5 * len;
-            w.push_back(M_PI * area * emis(m));
-            float L0[20] = {a[0], a[1], a[2], 0.f,
-                            (float)e1[0], (float)e1[1], (float)e1[2], (float)area,
-                            (float)e2[0], (float)e2[1], (float)e2[2], 0.f,
-                            m.emission[0], m.emission[1], m.emission[2], 0.f,
-                            prim_n[4 * t], prim_n[4 * t + 1], prim_n[4 * t + 2], 0.f};
-            lights.insert(lights.end(), L0, L0 + 20);
-        }
-    }
-    for (int i = 0; i < npl; ++i) {
-        const neb_point_light& l = point_lights[i];
-        w.push_back(((double)l.power[0] + l.power[1] + l.power[2]) / 3.0);
-        const double inv4pi = 1.0 / (4.0 * M_PI);
-        float L0[20] = {l.pos[0], l.pos[1], l.pos[2], 0.f,
-                        0.f, 0.f, 0.f, 0.f,
-                        0.f, 0.f, 0.f, 1.f,
-                        (float)(l.power[0] * inv4pi), (float)(l.power[1] * inv4pi), (float)(l.power[2] * inv4pi), 0.f,
-                        0.f, 0.f, 0.f, 0.f};
-        lights.insert(lights.end(), L0, L0 + 20);
-    }
-    int nl = (int)w.size();
-    if (nl == 0) return fail(NEB_ERR_INVALID_ARG, "scene has no lights");
-    double tot = 0.0;
-    for (double x : w) tot += x;
-    if (!(tot > 0.0)) return fail(NEB_ERR_INVALID_ARG, "scene lights carry no power");
-    std::vector<float> cdf(nl);
-    double acc = 0.0;
-    for (int i = 0; i < nl; ++i) {
-        acc += w[i];
-        cdf[i] = (float)(acc / tot);
-        lights[20 * (size_t)i + 3] = (float)(w[i] / tot);
-    }
-    cdf[nl - 1] = 1.0f;
-
-    // upload
-    free_list(c->scene_allocs);
-    hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = dalloc(c->scene_allocs, &c->bvh, 4 * (size_t)bvh.n_nodes);
-    if (e == hipSuccess) e = dalloc(c->scene_allocs, &c->tri, 3 * (size_t)nt);
-    if (e == hipSuccess) e = dalloc(c->scene_allocs, &c->prim_n, (size_t)nt);
-    if (e == hipSuccess) e = dalloc(c->scene_allocs, &c->prim_light, (size_t)nt);
-    if (e == hipSuccess) e = dalloc(c->scene_allocs, &c->mats, (size_t)nm);
-    if (e == hipSuccess) e = dalloc(c->scene_allocs, &c->lights, 5 * (size_t)nl);
-    if (e == hipSuccess) e = dalloc(c->scene_allocs, &c->light_cdf, (size_t)nl);
-    if (e != hipSuccess) return oom_or_device(e, "scene upload");
-    HIP_TRY(hipMemcpy(c->bvh, bvh.nodes.data(), bvh.nodes.size() * 4, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(c->tri, bvh.tris.data(), bvh.tris.size() * 4, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(c->prim_n, prim_n.data(), prim_n.size() * 4, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(c->prim_light, prim_light.data(), prim_light.size() * 4, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(c->mats, materials, sizeof(neb_material) * (size_t)nm, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(c->lights, lights.data(), lights.size() * 4, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(c->light_cdf, cdf.data(), cdf.size() * 4, hipMemcpyHostToDevice));
-    c->view.bvh = c->bvh;
-    c->view.tri = c->tri;
-    c->view.prim_n = c->prim_n;
-    c->view.prim_light = c->prim_light;
-    c->view.mats = c->mats;
-    c->view.lights = c->lights;
-    c->view.light_cdf = c->light_cdf;
-    c->view.n_lights = nl;
-    float dg[3] = {bmax[0] - bmin[0], bmax[1] - bmin[1], bmax[2] - bmin[2]};
-    c->view.eps = 1e-5f * std::sqrt(dg[0] * dg[0] + dg[1] * dg[1] + dg[2] * dg[2]);
-    // camera
-    CamParams& C = c->cam;
+    // camera basis
+    CamParams& C = H.cam;
     double f[3], up[3], r[3], u[3];
     for (int k = 0; k < 3; ++k) {
         C.eye[k] = camera->eye[k];
@@ -1146,51 +1293,307 @@ extern "C" neb_status neb_set_scene(neb_ctx c, const float* vertices, int32_t nv
         C.u[k] = (float)u[k];
     }
     C.tan_half = (float)std::tan(0.5 * camera->vfov_deg * M_PI / 180.0);
-    C.aspect = (float)c->prm.width / (float)c->prm.height;
-    C.w = c->prm.width;
-    C.h = c->prm.height;
-    // octree over the scene bounds
-    octree_params_init(c->oct.prm, bmin, bmax, c->prm.octree_capacity);
-    HIP_TRY(octree_init_nodes(c->oct, nullptr));
-    hipLaunchKernelGGL(k_fill_f32, dim3(grid_of(9 * (int64_t)c->npix, 256)), dim3(256), 0, nullptr, c->img, 0.f,
+    C.aspect = (float)prm.width / (float)prm.height;
+    C.w = prm.width;
+    C.h = prm.height;
+
+    // BVH
+    if (!build_bvh(vertices, nv, tris, nt, H.bvh)) return fail(NEB_ERR_INVALID_ARG, "BVH build failed");
+    if (H.bvh.max_depth >= kBvhStackMax) return fail(NEB_ERR_CAPACITY, "BVH deeper than the traversal stack");
+    // per-prim normals and light table (emissive triangles, then point lights)
+    H.nt = nt;
+    H.prim_n.assign(4 * (size_t)nt, 0.f);
+    H.prim_light.assign(nt, -1);
+    H.lights.clear();
+    std::vector<double> w;
+    auto emis = [&](const neb_material& m) { return ((double)m.emission[0] + m.emission[1] + m.emission[2]) / 3.0; };
+    for (int64_t t = 0; t < nt; ++t) {
+        const float* a = vertices + 3 * (size_t)tris[3 * t];
+        const float* b = vertices + 3 * (size_t)tris[3 * t + 1];
+        const float* cc = vertices + 3 * (size_t)tris[3 * t + 2];
+        double e1[3], e2[3], cr[3];
+        for (int k = 0; k < 3; ++k) {
+            e1[k] = (double)b[k] - a[k];
+            e2[k] = (double)cc[k] - a[k];
+        }
+        cr[0] = e1[1] * e2[2] - e1[2] * e2[1];
+        cr[1] = e1[2] * e2[0] - e1[0] * e2[2];
+        cr[2] = e1[0] * e2[1] - e1[1] * e2[0];
+        double len = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+        for (int k = 0; k < 3; ++k) H.prim_n[4 * t + k] = len > 0 ? (float)(cr[k] / len) : (k == 2 ? 1.f : 0.f);
+        int32_t mid = tri_material[t];
+        std::memcpy(&H.prim_n[4 * t + 3], &mid, 4);
+        const neb_material& m = materials[mid];
+        if (emis(m) > 0.0 && len > 0) {
+            H.prim_light[t] = (int32_t)w.size();
+            double area = 0.5 * len;
+            w.push_back(M_PI * area * emis(m));
+            float L0[20] = {a[0], a[1], a[2], 0.f,
+                            (float)e1[0], (float)e1[1], (float)e1[2], (float)area,
+                            (float)e2[0], (float)e2[1], (float)e2[2], 0.f,
+                            m.emission[0], m.emission[1], m.emission[2], 0.f,
+                            H.prim_n[4 * t], H.prim_n[4 * t + 1], H.prim_n[4 * t + 2], 0.f};
+            H.lights.insert(H.lights.end(), L0, L0 + 20);
+        }
+    }
+    for (int i = 0; i < npl; ++i) {
+        const neb_point_light& l = point_lights[i];
+        w.push_back(((double)l.power[0] + l.power[1] + l.power[2]) / 3.0);
+        const double inv4pi = 1.0 / (4.0 * M_PI);
+        float L0[20] = {l.pos[0], l.pos[1], l.pos[2], 0.f,
+                        0.f, 0.f, 0.f, 0.f,
+                        0.f, 0.f, 0.f, 1.f,
+                        (float)(l.power[0] * inv4pi), (float)(l.power[1] * inv4pi), (float)(l.power[2] * inv4pi), 0.f,
+                        0.f, 0.f, 0.f, 0.f};
+        H.lights.insert(H.lights.end(), L0, L0 + 20);
+    }
+    int nl = (int)w.size();
+    if (nl == 0) return fail(NEB_ERR_INVALID_ARG, "scene has no lights");
+    double tot = 0.0;
+    for (double x : w) tot += x;
+    if (!(tot > 0.0)) return fail(NEB_ERR_INVALID_ARG, "scene lights carry no power");
+    H.cdf.assign(nl, 0.f);
+    double acc = 0.0;
+    for (int i = 0; i < nl; ++i) {
+        acc += w[i];
+        H.cdf[i] = (float)(acc / tot);
+        H.lights[20 * (size_t)i + 3] = (float)(w[i] / tot);
+    }
+    H.cdf[nl - 1] = 1.0f;
+    H.mats.assign(materials, materials + nm);
+    for (int k = 0; k < 3; ++k) {
+        H.bmin[k] = bmin[k];
+        H.bmax[k] = bmax[k];
+    }
+    float dg[3] = {bmax[0] - bmin[0], bmax[1] - bmin[1], bmax[2] - bmin[2]};
+    H.eps = 1e-5f * std::sqrt(dg[0] * dg[0] + dg[1] * dg[1] + dg[2] * dg[2]);
+    H.set = true;
+    return NEB_OK;
+}
+
+// clears images, counters and every octree of the batch; iteration 0
+static neb_status restart(neb_ctx c, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_f32, dim3(grid_of(9 * (int64_t)c->npix, 256)), dim3(256), 0, s, c->img, 0.f,
                        9 * (int64_t)c->npix);
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, nullptr, (int32_t*)c->cnt, 0, (int64_t)(sizeof(Counters) / 4));
-    HIP_TRY(hipDeviceSynchronize());
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int32_t*)c->cnt, 0, (int64_t)(sizeof(Counters) / 4));
+    for (int i = 0; i < c->n_scenes; ++i)
+        HIP_TRY(octree_init_range(c->oct_nodes, c->oct_states + i, c->oct_prm[i].root,
+                                  c->oct_prm[i].end - c->oct_prm[i].root, s));
+    OctDyn d0;
+    octree_dyn_for(d0, 1);
+    HIP_TRY(octree_set_dyn(c->oct_dyn, d0, s));
+    HIP_TRY(hipGetLastError());
     c->iter = 0;
     c->first_iter_recorded = 0;
-    c->has_scene = true;
     return NEB_OK;
+}
+
+// Concatenates the scenes into the shared pools (BVH forest with per-scene
+// roots, triangles, prim tables, materials, lights), writes the per-scene
+// tables and initialises the octrees.  Runs once after the scenes change.
+static neb_status prepare(neb_ctx c) {
+    if (c->ready) return NEB_OK;
+    for (int s = 0; s < c->n_scenes; ++s)
+        if (!c->hs[s].set) return fail(NEB_ERR_STATE, "scene " + std::to_string(s) + " not set");
+    drop_graph(c);
+    int64_t n_nodes = 0, n_tris = 0, n_mats = 0, n_lights = 0;
+    int depth = 0;
+    for (const HostScene& H : c->hs) {
+        n_nodes += H.bvh.n_nodes;
+        n_tris += H.nt;
+        n_mats += (int64_t)H.mats.size();
+        n_lights += (int64_t)H.cdf.size();
+        depth = std::max(depth, H.bvh.max_depth);
+    }
+    if (n_mats > kMaxMaterials) return fail(NEB_ERR_CAPACITY, "more than 65536 materials over the batch");
+    if (n_nodes * 4 > (int64_t)INT32_MAX || n_tris * 3 > (int64_t)INT32_MAX || n_lights * 5 > (int64_t)INT32_MAX)
+        return fail(NEB_ERR_CAPACITY, "geometry pools over 2^31 entries");
+    std::vector<float> nodes(16 * (size_t)n_nodes), tri(12 * (size_t)n_tris), prim_n(4 * (size_t)n_tris),
+        lights(20 * (size_t)n_lights), cdf((size_t)n_lights);
+    std::vector<int32_t> prim_light((size_t)n_tris);
+    std::vector<neb_material> mats((size_t)n_mats);
+    int64_t nb = 0, tb = 0, mb = 0, lb = 0;
+    for (int s = 0; s < c->n_scenes; ++s) {
+        const HostScene& H = c->hs[s];
+        const neb_params& P = c->prm[s];
+        // nodes: child links are node indices (inner) or triangle indices (leaves)
+        for (int i = 0; i < H.bvh.n_nodes; ++i) {
+            const float* src = &H.bvh.nodes[16 * (size_t)i];
+            float* dst = &nodes[16 * (size_t)(nb + i)];
+            std::memcpy(dst, src, 12 * 4);
+            int32_t lk[4];
+            std::memcpy(lk, src + 12, 16);
+            for (int ch = 0; ch < 2; ++ch) {
+                if (lk[2 + ch] > 0) lk[ch] += (int32_t)tb;
+                else if (lk[ch] >= 0) lk[ch] += (int32_t)nb;
+            }
+            std::memcpy(dst + 12, lk, 16);
+        }
+        for (int t = 0; t < H.nt; ++t) {
+            const float* src = &H.bvh.tris[12 * (size_t)t];
+            float* dst = &tri[12 * (size_t)(tb + t)];
+            std::memcpy(dst, src, 48);
+            int32_t pid;
+            std::memcpy(&pid, src + 3, 4);
+            pid += (int32_t)tb;
+            std::memcpy(dst + 3, &pid, 4);
+            float* pn = &prim_n[4 * (size_t)(tb + t)];
+            std::memcpy(pn, &H.prim_n[4 * (size_t)t], 16);
+            int32_t mid;
+            std::memcpy(&mid, pn + 3, 4);
+            mid += (int32_t)mb;
+            std::memcpy(pn + 3, &mid, 4);
+            prim_light[tb + t] = H.prim_light[t] >= 0 ? H.prim_light[t] + (int32_t)lb : -1;
+        }
+        std::copy(H.mats.begin(), H.mats.end(), mats.begin() + mb);
+        std::copy(H.lights.begin(), H.lights.end(), lights.begin() + 20 * lb);
+        std::copy(H.cdf.begin(), H.cdf.end(), cdf.begin() + lb);
+        SceneInfo& I = c->sc_host[s];
+        std::memset(&I, 0, sizeof(I));
+        I.cam = H.cam;
+        I.pix_base = c->pix_base[s];
+        I.npix = P.width * P.height;
+        I.L = P.max_path_len;
+        I.spp = P.spp;
+        I.bvh_root = (int32_t)nb;
+        I.light_base = (int32_t)lb;
+        I.n_lights = (int32_t)H.cdf.size();
+        I.k0 = P.seed;
+        I.k1 = P.scene_id;
+        I.eps = H.eps;
+        I.r = P.merge_radius;
+        I.r2pi = (float)(M_PI * (double)P.merge_radius * (double)P.merge_radius);
+        I.inv_cell = 1.0f / (2.0001f * P.merge_radius);  // a little wider than the ball's diameter
+        I.rho0 = P.analytic_rho0;
+        I.cam_w = P.analytic_cam_weight;
+        OctParams& O = c->oct_prm[s];
+        octree_params_init(O, H.bmin, H.bmax, O.root, P.octree_capacity);
+        nb += H.bvh.n_nodes;
+        tb += H.nt;
+        mb += (int64_t)H.mats.size();
+        lb += (int64_t)H.cdf.size();
+    }
+    free_list(c->scene_allocs);
+    float4 *d_nodes = nullptr, *d_tri = nullptr, *d_pn = nullptr, *d_lights = nullptr;
+    int32_t* d_pl = nullptr;
+    float* d_cdf = nullptr;
+    neb_material* d_mats = nullptr;
+    hipError_t e = dalloc(c->scene_allocs, &d_nodes, 4 * (size_t)n_nodes);
+    if (e == hipSuccess) e = dalloc(c->scene_allocs, &d_tri, 3 * (size_t)n_tris);
+    if (e == hipSuccess) e = dalloc(c->scene_allocs, &d_pn, (size_t)n_tris);
+    if (e == hipSuccess) e = dalloc(c->scene_allocs, &d_pl, (size_t)n_tris);
+    if (e == hipSuccess) e = dalloc(c->scene_allocs, &d_mats, (size_t)n_mats);
+    if (e == hipSuccess) e = dalloc(c->scene_allocs, &d_lights, 5 * (size_t)n_lights);
+    if (e == hipSuccess) e = dalloc(c->scene_allocs, &d_cdf, (size_t)n_lights);
+    if (e != hipSuccess) return oom_or_device(e, "scene upload");
+    HIP_TRY(hipMemcpy(d_nodes, nodes.data(), nodes.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d_tri, tri.data(), tri.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d_pn, prim_n.data(), prim_n.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d_pl, prim_light.data(), prim_light.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d_mats, mats.data(), mats.size() * sizeof(neb_material), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d_lights, lights.data(), lights.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d_cdf, cdf.data(), cdf.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->sc_dev, c->sc_host.data(), sizeof(SceneInfo) * c->sc_host.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->oct_prm_dev, c->oct_prm.data(), sizeof(OctParams) * c->oct_prm.size(), hipMemcpyHostToDevice));
+    c->view.bvh = d_nodes;
+    c->view.tri = d_tri;
+    c->view.prim_n = d_pn;
+    c->view.prim_light = d_pl;
+    c->view.mats = d_mats;
+    c->view.lights = d_lights;
+    c->view.light_cdf = d_cdf;
+    c->forest_depth = depth;
+    // the shallowest stack that holds the deepest tree
+    if (c->cfg.stack <= depth) c->cfg.stack = depth < 32 ? 32 : (depth < 48 ? 48 : 64);
+    neb_status st = restart(c, nullptr);
+    if (st != NEB_OK) return st;
+    HIP_TRY(hipDeviceSynchronize());
+    c->ready = true;
+    return NEB_OK;
+}
+
+extern "C" neb_status neb_set_batch_scene(neb_ctx c, int32_t scene, const float* vertices, int32_t nv,
+                                          const int32_t* tris, const int32_t* tri_material, int32_t nt,
+                                          const neb_material* materials, int32_t nm,
+                                          const neb_point_light* point_lights, int32_t npl, const neb_camera* camera) {
+    if (!c) return fail(NEB_ERR_INVALID_ARG, "null context");
+    if (scene < 0 || scene >= c->n_scenes) return fail(NEB_ERR_INVALID_ARG, "scene index out of range");
+    HostScene H;
+    neb_status st = build_host_scene(c->prm[scene], vertices, nv, tris, tri_material, nt, materials, nm, point_lights,
+                                     npl, camera, H);
+    if (st != NEB_OK) return st;
+    HIP_TRY(hipDeviceSynchronize());
+    c->hs[scene] = std::move(H);
+    c->ready = false;
+    drop_graph(c);
+    // a batch of one uploads at once, so that scene errors surface here
+    bool all = true;
+    for (const HostScene& h : c->hs) all = all && h.set;
+    if (all && c->n_scenes == 1) return prepare(c);
+    return NEB_OK;
+}
+
+extern "C" neb_status neb_set_scene(neb_ctx c, const float* vertices, int32_t nv, const int32_t* tris,
+                                    const int32_t* tri_material, int32_t nt, const neb_material* materials, int32_t nm,
+                                    const neb_point_light* point_lights, int32_t npl, const neb_camera* camera) {
+    if (!c) return fail(NEB_ERR_INVALID_ARG, "null context");
+    if (c->n_scenes != 1) return fail(NEB_ERR_STATE, "neb_set_scene needs a context of one scene");
+    return neb_set_batch_scene(c, 0, vertices, nv, tris, tri_material, nt, materials, nm, point_lights, npl, camera);
 }
 
 static RenderArgs make_args(neb_ctx c) {
     RenderArgs A;
     A.S = c->view;
-    A.cam = c->cam;
-    A.k0 = c->prm.seed;
-    A.k1 = c->prm.scene_id;
-    A.iter = c->iter;
+    A.sc = c->sc_dev;
+    A.pix_base = c->pix_base_dev;
+    A.cnt = c->cnt;
+    A.n_scenes = c->n_scenes;
     A.L = c->L;
     A.npix = c->npix;
-    A.photons = (c->prm.flags & NEB_FLAG_NO_PHOTONS) ? 0 : 1;
-    A.r = c->prm.merge_radius;
-    A.r2pi = (float)(M_PI * (double)c->prm.merge_radius * (double)c->prm.merge_radius);
-    A.density_mode = c->prm.density_mode;
-    A.rho0 = c->prm.analytic_rho0;
-    A.cam_w = c->prm.analytic_cam_weight;
+    A.photons = c->photons;
+    A.density_mode = c->density_mode;
     return A;
 }
 
-static neb_status render_iteration(neb_ctx c, hipStream_t s) {
-    c->iter += 1;
-    octree_params_set_iteration(c->oct.prm, c->iter);
+template <int kStack>
+static void launch_extend(neb_ctx c, int64_t cap, const float4* org, const float4* dir, int32_t* count, int32_t* next,
+                          unsigned long long* rays, hipStream_t s) {
+    hipLaunchKernelGGL(k_extend<kStack>, dim3(trace_grid(c, cap)), dim3(kTraceBlock), 0, s, c->view,
+                       (const SceneInfo*)c->sc_dev, org, dir, (const int32_t*)count, next, c->hits, rays, c->cnt);
+}
+
+static void extend(neb_ctx c, int64_t cap, const float4* org, const float4* dir, int32_t* count, int32_t* next,
+                   unsigned long long* rays, hipStream_t s) {
+    if (c->cfg.stack == 32) launch_extend<32>(c, cap, org, dir, count, next, rays, s);
+    else if (c->cfg.stack == 48) launch_extend<48>(c, cap, org, dir, count, next, rays, s);
+    else launch_extend<64>(c, cap, org, dir, count, next, rays, s);
+}
+
+static void nee(neb_ctx c, const RenderArgs& A, Images im, hipStream_t s) {
+    dim3 g(trace_grid(c, c->vcap)), b(kTraceBlock);
+    if (c->cfg.stack == 32)
+        hipLaunchKernelGGL(k_nee<32>, g, b, 0, s, A, c->V, (const int32_t*)&c->cnt->n_vertices, im, c->pq[0],
+                           &c->cnt->pcount[0]);
+    else if (c->cfg.stack == 48)
+        hipLaunchKernelGGL(k_nee<48>, g, b, 0, s, A, c->V, (const int32_t*)&c->cnt->n_vertices, im, c->pq[0],
+                           &c->cnt->pcount[0]);
+    else
+        hipLaunchKernelGGL(k_nee<64>, g, b, 0, s, A, c->V, (const int32_t*)&c->cnt->n_vertices, im, c->pq[0],
+                           &c->cnt->pcount[0]);
+}
+
+// Enqueues one iteration.  Every argument is fixed for the context (the
+// iteration number is read from device memory), so the same sequence can be
+// captured once and replayed.
+static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
     RenderArgs A = make_args(c);
     const int npix = c->npix, L = c->L;
     const int64_t vcap = c->vcap;
     Counters* cnt = c->cnt;
-    bool record = c->recs && c->first_iter_recorded == 0;
-    hipLaunchKernelGGL(k_iter_begin, dim3(1), dim3(1), 0, s, cnt, npix);
+    Images im{c->img, c->img + 3 * (size_t)npix, c->img + 6 * (size_t)npix};
+    hipLaunchKernelGGL(k_iter_begin, dim3(1), dim3(1), 0, s, cnt, c->oct_dyn);
     if (c->slots)
-        hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(vcap, 256)), dim3(256), 0, s, c->slots, -1, vcap);
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(c->slot_cap, 256)), dim3(256), 0, s, c->slots, -1, c->slot_cap);
     if (record)
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_of((int64_t)npix * L * 6, 256)), dim3(256), 0, s, (int32_t*)c->recs, 0,
                            (int64_t)npix * L * 6);
@@ -1199,78 +1602,128 @@ static neb_status render_iteration(neb_ctx c, hipStream_t s) {
     for (int k = 1; k <= L; ++k) {
         int in = (k - 1) & 1, out = k & 1;
         TIMED(K_EXTEND_CAMERA,
-              hipLaunchKernelGGL(k_extend, dim3(grid_of(npix, kTraceBlock, 1 << 20)), dim3(kTraceBlock), 0, s, c->view,
-                                 c->q[in].q0, c->q[in].q1, &cnt->qcount[in], &cnt->qcount[out], c->hits,
-                                 &cnt->camera_rays, cnt));
+              extend(c, npix, c->q[in].q0, c->q[in].q1, &cnt->qcount[in], &cnt->qcount[out], &cnt->camera_rays, s));
         TIMED(K_SHADE, hipLaunchKernelGGL(k_shade, dim3(grid_of(npix, 256)), dim3(256), 0, s, A, c->q[in],
                                           &cnt->qcount[in], c->hits, c->q[out], &cnt->qcount[out], c->V,
                                           &cnt->n_vertices, c->ev0, c->ev1, &cnt->n_events, c->slots,
                                           record ? c->recs : (neb_path_record*)nullptr));
     }
-    // deposits
-    if (c->prm.density_mode != NEB_DENSITY_ANALYTIC) {
+    // deposits of this iteration's NEE vertices into their scenes' octrees
+    if (c->density_mode != NEB_DENSITY_ANALYTIC) {
         hipError_t e;
+        const float* pos = (const float*)c->V.v0;
+        const int32_t* tagw = (const int32_t*)c->V.v1 + 3;
         prof_begin(c, K_OCTREE_INSERT, s);
         if (c->slots)
-            e = octree_increment_slots(c->oct, c->V.v0, c->slots, (int32_t)vcap, s);
+            e = octree_insert_single(c->oct_nodes, c->oct_states, c->oct_prm_dev, c->oct_dyn, pos, 4, tagw, 8, c->slots,
+                                     (int32_t)c->slot_cap, s);
         else
-            e = octree_increment_vertices(c->oct, c->V.v0, &cnt->n_vertices, (int32_t)vcap, s);
+            e = octree_insert_rounds(c->oct_nodes, c->oct_states, c->oct_prm_dev, c->oct_dyn, pos, 4, tagw, 8,
+                                     &cnt->n_vertices, (int32_t)vcap, c->defer, c->defer_cnt, s);
         prof_end(c, s);
         HIP_TRY(e);
     }
     // pass 2
     TIMED(K_DENSITY, hipLaunchKernelGGL(k_density, dim3(grid_of(vcap, 256)), dim3(256), 0, s, A, c->V,
-                                        &cnt->n_vertices, c->oct.nodes, c->oct.state, c->oct.prm));
-    TIMED(K_NEE, hipLaunchKernelGGL(k_nee, dim3(grid_of(vcap, kTraceBlock, 1 << 20)), dim3(kTraceBlock), 0, s, A, c->V,
-                                    &cnt->n_vertices,
-                                    Images{c->img, c->img + 3 * (size_t)npix, c->img + 6 * (size_t)npix}, c->pq[0],
-                                    &cnt->pcount[0], cnt));
-    if (A.photons && L >= 3) {
+                                        (const int32_t*)&cnt->n_vertices, (const int32_t*)c->oct_nodes,
+                                        (const OctState*)c->oct_states, (const OctParams*)c->oct_prm_dev,
+                                        (const OctDyn*)c->oct_dyn));
+    TIMED(K_NEE, nee(c, A, im, s));
+    if (c->photons && L >= 3) {
         // merge grid over this iteration's view vertices
         int64_t n = (int64_t)c->G.T * c->G.D + 1;
         prof_begin(c, K_GRID_BUILD, s);
-        hipLaunchKernelGGL(k_grid_count, dim3(grid_of(vcap, 256)), dim3(256), 0, s, c->mats, c->V, &cnt->n_vertices, c->G);
+        hipLaunchKernelGGL(k_grid_count, dim3(grid_of(vcap, 256)), dim3(256), 0, s, (const neb_material*)c->view.mats,
+                           (const SceneInfo*)c->sc_dev, c->V, (const int32_t*)&cnt->n_vertices, c->G);
         scan_exclusive(c->G.count, c->G.start, n, c->G.sums, s);
-        hipLaunchKernelGGL(k_grid_scatter, dim3(grid_of(vcap, 256)), dim3(256), 0, s, c->mats, c->V, &cnt->n_vertices,
-                           c->G);
+        hipLaunchKernelGGL(k_grid_scatter, dim3(grid_of(vcap, 256)), dim3(256), 0, s,
+                           (const neb_material*)c->view.mats, (const SceneInfo*)c->sc_dev, c->V,
+                           (const int32_t*)&cnt->n_vertices, c->G);
         prof_end(c, s);
+        const int pgrid = c->cfg.photon_bpc > 0 ? std::max(1, std::min(grid_of(vcap, 64, 1 << 20), c->cus * c->cfg.photon_bpc))
+                                                : grid_of(vcap, 256);
         for (int j = 1; j <= L - 2; ++j) {
             int in = (j - 1) & 1, out = j & 1;
-            TIMED(K_EXTEND_PHOTON,
-                  hipLaunchKernelGGL(k_extend, dim3(grid_of(vcap, kTraceBlock, 1 << 20)), dim3(kTraceBlock), 0, s, c->view,
-                                     c->pq[in].p0, c->pq[in].p1, &cnt->pcount[in], &cnt->pcount[out], c->hits,
-                                     &cnt->photon_rays, cnt));
-            TIMED(K_PHOTON, hipLaunchKernelGGL(k_photon, dim3(grid_of(vcap, 256)), dim3(64), 0, s, A, c->pq[in],
-                                               &cnt->pcount[in], c->hits, c->pq[out], &cnt->pcount[out], c->V, c->G,
-                                               Images{c->img, c->img + 3 * (size_t)npix, c->img + 6 * (size_t)npix},
-                                               cnt));
+            TIMED(K_EXTEND_PHOTON, extend(c, vcap, c->pq[in].p0, c->pq[in].p1, &cnt->pcount[in], &cnt->pcount[out],
+                                          &cnt->photon_rays, s));
+            TIMED(K_PHOTON, hipLaunchKernelGGL(k_photon, dim3(pgrid), dim3(64), 0, s, A, c->pq[in],
+                                               (const int32_t*)&cnt->pcount[in], (const int2*)c->hits, c->pq[out],
+                                               &cnt->pcount[out], c->G, im));
         }
     }
     // pass 3
-    TIMED(K_FINALIZE, hipLaunchKernelGGL(k_finalize, dim3(grid_of(c->ecap, 256)), dim3(256), 0, s, A, c->ev0, c->ev1,
-                                         &cnt->n_events, c->V.rho,
-                                         Images{c->img, c->img + 3 * (size_t)npix, c->img + 6 * (size_t)npix}));
+    TIMED(K_FINALIZE, hipLaunchKernelGGL(k_finalize, dim3(grid_of(c->ecap, 256)), dim3(256), 0, s, A,
+                                         (const float4*)c->ev0, (const float4*)c->ev1,
+                                         (const int32_t*)&cnt->n_events, (const float*)c->V.rho, im));
     hipLaunchKernelGGL(k_iter_end, dim3(1), dim3(1), 0, s, cnt);
     HIP_TRY(hipGetLastError());
-    if (record) c->first_iter_recorded = c->iter;
+    return NEB_OK;
+}
+
+// captures one iteration on a private stream into an executable graph
+static neb_status capture(neb_ctx c) {
+    if (c->gexec) return NEB_OK;
+    if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+    bool was = c->prof_on;
+    c->prof_on = false;
+    neb_status st = enqueue_iteration(c, c->cap_stream, false);
+    c->prof_on = was;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (st != NEB_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(NEB_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(NEB_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    c->graph = g;
+    c->gexec = x;
+    return NEB_OK;
+}
+
+static neb_status render_n(neb_ctx c, int32_t n_iterations, hipStream_t s) {
+    for (int i = 0; i < n_iterations; ++i) {
+        bool record = c->recs && c->first_iter_recorded == 0;
+        if (c->use_graph && !c->prof_on && !record) {
+            neb_status st = capture(c);
+            if (st != NEB_OK) return st;
+            HIP_TRY(hipGraphLaunch(c->gexec, s));
+        } else {
+            neb_status st = enqueue_iteration(c, s, record);
+            if (st != NEB_OK) return st;
+        }
+        c->iter += 1;
+        if (record) c->first_iter_recorded = c->iter;
+    }
     return NEB_OK;
 }
 
 extern "C" neb_status neb_render(neb_ctx c, int32_t n_iterations, void* stream) {
     if (!c) return fail(NEB_ERR_INVALID_ARG, "null context");
-    if (!c->has_scene) return fail(NEB_ERR_STATE, "no scene set");
     if (n_iterations < 0) return fail(NEB_ERR_INVALID_ARG, "negative iteration count");
+    neb_status st = prepare(c);
+    if (st != NEB_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     c->last_stream = s;
-    for (int i = 0; i < n_iterations; ++i) {
-        neb_status st = render_iteration(c, s);
-        if (st != NEB_OK) return st;
-    }
-    return NEB_OK;
+    return render_n(c, n_iterations, s);
 }
 
-static neb_status copy_out(neb_ctx c, const float* src_dev, float* dst, int32_t is_dev, float scale, hipStream_t s,
-                           int64_t n) {
+// iterations scene s has taken part in
+static int scene_iters(neb_ctx c, int s) {
+    int spp = c->prm[s].spp;
+    return spp > 0 ? std::min(c->iter, spp) : c->iter;
+}
+
+static neb_status copy_out(const float* src_dev, float* dst, int32_t is_dev, float scale, hipStream_t s, int64_t n) {
     if (is_dev) {
         hipLaunchKernelGGL(k_scale_image, dim3(grid_of(n, 256)), dim3(256), 0, s, src_dev, dst, n, scale);
         HIP_TRY(hipGetLastError());
@@ -1280,51 +1733,76 @@ static neb_status copy_out(neb_ctx c, const float* src_dev, float* dst, int32_t 
     HIP_TRY(hipStreamSynchronize(s));
     HIP_TRY(hipMemcpy(h.data(), src_dev, n * 4, hipMemcpyDeviceToHost));
     for (int64_t i = 0; i < n; ++i) dst[i] = h[i] * scale;
-    (void)c;
     return NEB_OK;
 }
 
-extern "C" neb_status neb_get_image(neb_ctx c, float* rgb, int32_t is_dev, void* stream) {
-    if (!c || !rgb) return fail(NEB_ERR_INVALID_ARG, "null pointer");
+static neb_status check_scene_ready(neb_ctx c, int32_t scene) {
+    if (!c) return fail(NEB_ERR_INVALID_ARG, "null context");
+    if (scene < 0 || scene >= c->n_scenes) return fail(NEB_ERR_INVALID_ARG, "scene index out of range");
+    if (!c->ready) return fail(NEB_ERR_STATE, "scenes not set or not rendered since they changed");
+    return NEB_OK;
+}
+
+extern "C" neb_status neb_get_scene_image(neb_ctx c, int32_t scene, float* rgb, int32_t is_dev, void* stream) {
+    if (!rgb) return fail(NEB_ERR_INVALID_ARG, "null pointer");
+    neb_status st = check_scene_ready(c, scene);
+    if (st != NEB_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    int64_t n = 3 * (int64_t)c->npix;
-    float scale = c->iter > 0 ? 1.0f / (float)c->iter : 0.f;
+    const int64_t n = 3 * (int64_t)c->prm[scene].width * c->prm[scene].height;
+    const int64_t N = 3 * (int64_t)c->npix, off = 3 * (int64_t)c->pix_base[scene];
+    int it = scene_iters(c, scene);
+    float scale = it > 0 ? 1.0f / (float)it : 0.f;
     if (is_dev) {
-        hipLaunchKernelGGL(k_mean_image, dim3(grid_of(n, 256)), dim3(256), 0, s, c->img, c->img + n, c->img + 2 * n, rgb,
-                           n, scale);
+        hipLaunchKernelGGL(k_mean_image, dim3(grid_of(n, 256)), dim3(256), 0, s, c->img + off, c->img + N + off,
+                           c->img + 2 * N + off, rgb, n, scale);
         HIP_TRY(hipGetLastError());
         return NEB_OK;
     }
     std::vector<float> h(3 * (size_t)n);
     HIP_TRY(hipStreamSynchronize(s));
-    HIP_TRY(hipMemcpy(h.data(), c->img, 3 * n * 4, hipMemcpyDeviceToHost));
+    for (int t = 0; t < 3; ++t)
+        HIP_TRY(hipMemcpy(h.data() + t * n, c->img + t * N + off, n * 4, hipMemcpyDeviceToHost));
     for (int64_t i = 0; i < n; ++i) rgb[i] = (h[i] + h[n + i] + h[2 * n + i]) * scale;
     return NEB_OK;
 }
 
-extern "C" neb_status neb_get_technique_images(neb_ctx c, float* e, float* E, float* P, int32_t is_dev, void* stream) {
-    if (!c) return fail(NEB_ERR_INVALID_ARG, "null context");
+extern "C" neb_status neb_get_image(neb_ctx c, float* rgb, int32_t is_dev, void* stream) {
+    return neb_get_scene_image(c, 0, rgb, is_dev, stream);
+}
+
+extern "C" neb_status neb_get_scene_technique_images(neb_ctx c, int32_t scene, float* e, float* E, float* P,
+                                                     int32_t is_dev, void* stream) {
+    neb_status st = check_scene_ready(c, scene);
+    if (st != NEB_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    int64_t n = 3 * (int64_t)c->npix;
-    float scale = c->iter > 0 ? 1.0f / (float)c->iter : 0.f;
+    const int64_t n = 3 * (int64_t)c->prm[scene].width * c->prm[scene].height;
+    const int64_t N = 3 * (int64_t)c->npix, off = 3 * (int64_t)c->pix_base[scene];
+    int it = scene_iters(c, scene);
+    float scale = it > 0 ? 1.0f / (float)it : 0.f;
     float* dst[3] = {e, E, P};
     for (int t = 0; t < 3; ++t)
         if (dst[t]) {
-            neb_status st = copy_out(c, c->img + t * n, dst[t], is_dev, scale, s, n);
+            st = copy_out(c->img + t * N + off, dst[t], is_dev, scale, s, n);
             if (st != NEB_OK) return st;
         }
     return NEB_OK;
+}
+
+extern "C" neb_status neb_get_technique_images(neb_ctx c, float* e, float* E, float* P, int32_t is_dev, void* stream) {
+    return neb_get_scene_technique_images(c, 0, e, E, P, is_dev, stream);
 }
 
 extern "C" neb_status neb_query_density(neb_ctx c, const float* pos, const float* nrm, int32_t n, float* out,
                                         int32_t is_dev, void* stream) {
     if (!c || !pos || !nrm || !out) return fail(NEB_ERR_INVALID_ARG, "null pointer");
     if (n < 0) return fail(NEB_ERR_INVALID_ARG, "negative count");
-    if (!c->has_scene) return fail(NEB_ERR_STATE, "no scene set");
+    neb_status st0 = check_scene_ready(c, 0);
+    if (st0 != NEB_OK) return st0;
     if (n == 0) return NEB_OK;
     hipStream_t s = (hipStream_t)stream;
+    const OctParams& P = c->oct_prm[0];
     if (is_dev) {
-        HIP_TRY(octree_density_xyz(c->oct, pos, nrm, n, 1, out, s));
+        HIP_TRY(octree_density_raw(c->oct_nodes, c->oct_states, P, c->oct_dyn, pos, nrm, n, 1, out, s));
         return NEB_OK;
     }
     float *dp = nullptr, *dn = nullptr, *dout = nullptr;
@@ -1339,24 +1817,27 @@ extern "C" neb_status neb_query_density(neb_ctx c, const float* pos, const float
     neb_status st = NEB_OK;
     if (hipMemcpy(dp, pos, 12 * (size_t)n, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(dn, nrm, 12 * (size_t)n, hipMemcpyHostToDevice) != hipSuccess ||
-        octree_density_xyz(c->oct, dp, dn, n, 1, dout, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess ||
+        octree_density_raw(c->oct_nodes, c->oct_states, P, c->oct_dyn, dp, dn, n, 1, dout, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess ||
         hipMemcpy(out, dout, 4 * (size_t)n, hipMemcpyDeviceToHost) != hipSuccess)
         st = fail(NEB_ERR_DEVICE, "neb_query_density transfer failed");
     free_list(tmp);
     return st;
 }
 
-static neb_status octree_info(const Octree& o, hipStream_t s, int64_t info[8]) {
+// info of the octree that owns [root, end) of a pool
+static neb_status octree_info(const int32_t* pool, const OctState* state, int32_t root, int32_t end, hipStream_t s,
+                              int64_t info[8]) {
     OctState st;
     HIP_TRY(hipStreamSynchronize(s));
-    HIP_TRY(hipMemcpy(&st, o.state, sizeof(st), hipMemcpyDeviceToHost));
-    int32_t used = std::min(st.alloc, o.prm.capacity);
-    std::vector<int32_t> nodes((size_t)used);
-    HIP_TRY(hipMemcpy(nodes.data(), o.nodes, 4 * (size_t)used, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&st, state, sizeof(st), hipMemcpyDeviceToHost));
+    int32_t used = std::min(st.alloc, end) - root;
+    std::vector<int32_t> nodes((size_t)std::max(used, 0));
+    if (used > 0) HIP_TRY(hipMemcpy(nodes.data(), pool + root, 4 * (size_t)used, hipMemcpyDeviceToHost));
     int64_t leaf = 0;
     for (int32_t v : nodes)
         if (v >= 0) leaf += v & kOctCountMask;
-    info[0] = o.prm.capacity;
+    info[0] = end - root;
     info[1] = used;
     info[2] = st.depth;
     info[3] = leaf - (int64_t)kOctSplitFactor * (int64_t)st.block_iter_sum;
@@ -1390,18 +1871,22 @@ extern "C" neb_status neb_get_stats(neb_ctx c, neb_stats* out) {
     out->photon_continued = (int64_t)h.photon_continued;
     out->grid_cells = (int64_t)h.grid_cells;
     out->candidates = (int64_t)h.candidates;
-    if (c->has_scene) {
-        int64_t info[8];
-        neb_status st = octree_info(c->oct, c->last_stream, info);
-        if (st != NEB_OK) return st;
-        out->oct_capacity = info[0];
-        out->oct_allocated = info[1];
-        out->oct_depth = info[2];
-        out->oct_ledger = info[3];
-        out->oct_deposits = info[4];
-        out->oct_overflow = info[5];
-        out->oct_rejected = info[6];
-        out->oct_lost = info[7];
+    if (c->ready) {
+        // octree fields: summed over the scenes of the batch (depth: the deepest)
+        for (int s = 0; s < c->n_scenes; ++s) {
+            int64_t info[8];
+            neb_status st = octree_info(c->oct_nodes, c->oct_states + s, c->oct_prm[s].root, c->oct_prm[s].end,
+                                        c->last_stream, info);
+            if (st != NEB_OK) return st;
+            out->oct_capacity += info[0];
+            out->oct_allocated += info[1];
+            out->oct_depth = std::max<int64_t>(out->oct_depth, info[2]);
+            out->oct_ledger += info[3];
+            out->oct_deposits += info[4];
+            out->oct_overflow += info[5];
+            out->oct_rejected += info[6];
+            out->oct_lost += info[7];
+        }
     }
     return NEB_OK;
 }
@@ -1416,29 +1901,28 @@ extern "C" neb_status neb_get_path_records(neb_ctx c, neb_path_record* out, int6
     return NEB_OK;
 }
 
-extern "C" neb_status neb_get_octree(neb_ctx c, int32_t* nodes, int32_t cap, int64_t info[8]) {
-    if (!c || !info) return fail(NEB_ERR_INVALID_ARG, "null pointer");
-    if (!c->has_scene) return fail(NEB_ERR_STATE, "no scene set");
-    neb_status st = octree_info(c->oct, c->last_stream, info);
+extern "C" neb_status neb_get_scene_octree(neb_ctx c, int32_t scene, int32_t* nodes, int32_t cap, int64_t info[8]) {
+    if (!info) return fail(NEB_ERR_INVALID_ARG, "null pointer");
+    neb_status st = check_scene_ready(c, scene);
+    if (st != NEB_OK) return st;
+    const OctParams& P = c->oct_prm[scene];
+    st = octree_info(c->oct_nodes, c->oct_states + scene, P.root, P.end, c->last_stream, info);
     if (st != NEB_OK) return st;
     if (nodes && cap > 0)
-        HIP_TRY(hipMemcpy(nodes, c->oct.nodes, 4 * (size_t)std::min(cap, c->oct.prm.capacity), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(nodes, c->oct_nodes + P.root, 4 * (size_t)std::min(cap, P.end - P.root),
+                          hipMemcpyDeviceToHost));
     return NEB_OK;
+}
+
+extern "C" neb_status neb_get_octree(neb_ctx c, int32_t* nodes, int32_t cap, int64_t info[8]) {
+    return neb_get_scene_octree(c, 0, nodes, cap, info);
 }
 
 extern "C" neb_status neb_profile_kernels(neb_ctx c, int32_t enable) {
     if (!c) return fail(NEB_ERR_INVALID_ARG, "null context");
     if (enable) {
-        if (c->prof_ev.empty()) {
-            c->prof_ev.resize(4096);
-            c->prof_kid.resize(2048);
-            for (auto& e : c->prof_ev) HIP_TRY(hipEventCreate(&e));
-        }
-        prof_harvest(c);
-        for (int k = 0; k < 32; ++k) {
-            c->prof_ms[k] = 0.0;
-            c->prof_launches[k] = 0;
-        }
+        HIP_TRY(prof_alloc(c));
+        prof_clear(c);
     }
     c->prof_on = enable != 0;
     return NEB_OK;
@@ -1463,26 +1947,131 @@ extern "C" neb_status neb_get_kernel_profile(neb_ctx c, neb_kernel_time* out, in
 extern "C" neb_status neb_reset(neb_ctx c) {
     if (!c) return fail(NEB_ERR_INVALID_ARG, "null context");
     HIP_TRY(hipDeviceSynchronize());
-    hipLaunchKernelGGL(k_fill_f32, dim3(grid_of(9 * (int64_t)c->npix, 256)), dim3(256), 0, nullptr, c->img, 0.f,
-                       9 * (int64_t)c->npix);
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, nullptr, (int32_t*)c->cnt, 0, (int64_t)(sizeof(Counters) / 4));
-    if (c->has_scene) HIP_TRY(octree_init_nodes(c->oct, nullptr));
+    if (!c->ready) {
+        neb_status st = prepare(c);
+        if (st != NEB_OK) return st;
+    } else {
+        neb_status st = restart(c, nullptr);
+        if (st != NEB_OK) return st;
+    }
     HIP_TRY(hipDeviceSynchronize());
-    c->iter = 0;
-    c->first_iter_recorded = 0;
     return NEB_OK;
+}
+
+extern "C" neb_status neb_use_graph(neb_ctx c, int32_t enable) {
+    if (!c) return fail(NEB_ERR_INVALID_ARG, "null context");
+    c->use_graph = enable != 0;
+    return NEB_OK;
+}
+
+static neb_status apply_config(neb_ctx c, const neb_launch_config& cfg) {
+    if (cfg.bvh_stack != 32 && cfg.bvh_stack != 48 && cfg.bvh_stack != 64)
+        return fail(NEB_ERR_INVALID_ARG, "bvh_stack must be 32, 48 or 64");
+    if (c->ready && cfg.bvh_stack <= c->forest_depth)
+        return fail(NEB_ERR_CAPACITY, "bvh_stack must exceed the deepest BVH");
+    if (cfg.trace_blocks_per_cu < 0 || cfg.trace_blocks_per_cu > lds_blocks_per_cu(cfg.bvh_stack))
+        return fail(NEB_ERR_INVALID_ARG, "trace_blocks_per_cu out of range for this stack");
+    if (cfg.photon_blocks_per_cu < 0 || cfg.photon_blocks_per_cu > 64)
+        return fail(NEB_ERR_INVALID_ARG, "photon_blocks_per_cu out of range (0..64)");
+    c->cfg.stack = cfg.bvh_stack;
+    c->cfg.trace_bpc = cfg.trace_blocks_per_cu;
+    c->cfg.photon_bpc = cfg.photon_blocks_per_cu;
+    drop_graph(c);
+    return NEB_OK;
+}
+
+extern "C" neb_status neb_set_launch_config(neb_ctx c, const neb_launch_config* cfg) {
+    if (!c || !cfg) return fail(NEB_ERR_INVALID_ARG, "null pointer");
+    return apply_config(c, *cfg);
+}
+
+extern "C" neb_status neb_get_launch_config(neb_ctx c, neb_launch_config* cfg) {
+    if (!c || !cfg) return fail(NEB_ERR_INVALID_ARG, "null pointer");
+    cfg->bvh_stack = c->cfg.stack;
+    cfg->trace_blocks_per_cu = c->cfg.trace_bpc;
+    cfg->photon_blocks_per_cu = c->cfg.photon_bpc;
+    return NEB_OK;
+}
+
+// device time of the listed kernels over n iterations with configuration cfg
+static neb_status time_config(neb_ctx c, const neb_launch_config& cfg, int n, const int* kids, int nk, hipStream_t s,
+                              double& ms) {
+    neb_status st = apply_config(c, cfg);
+    if (st != NEB_OK) return st;
+    prof_clear(c);
+    st = render_n(c, n, s);
+    if (st != NEB_OK) return st;
+    prof_harvest(c);
+    ms = 0.0;
+    for (int k = 0; k < nk; ++k) ms += c->prof_ms[kids[k]];
+    return NEB_OK;
+}
+
+// Picks the launch shapes by timing real iterations of this context:
+// first the traversal stack depth and resident traversal blocks per CU
+// (closest-hit and shadow rays), then the photon-merge grid.  The context
+// is reset afterwards (images, statistics, octrees, iteration counter).
+extern "C" neb_status neb_autotune(neb_ctx c, int32_t trial_iterations, void* stream, neb_launch_config* chosen) {
+    if (!c) return fail(NEB_ERR_INVALID_ARG, "null context");
+    if (trial_iterations < 1 || trial_iterations > 64) return fail(NEB_ERR_INVALID_ARG, "trial_iterations out of range (1..64)");
+    neb_status st = prepare(c);
+    if (st != NEB_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    c->last_stream = s;
+    HIP_TRY(prof_alloc(c));
+    bool was_on = c->prof_on;
+    c->prof_on = true;
+    LaunchCfg keep = c->cfg;
+    neb_launch_config best{c->cfg.stack, c->cfg.trace_bpc, c->cfg.photon_bpc};
+    st = render_n(c, 1, s);  // warm-up: octree and caches
+    double best_ms = 1e300;
+    const int trace_k[3] = {K_EXTEND_CAMERA, K_EXTEND_PHOTON, K_NEE};
+    for (int stack : {32, 48, 64}) {
+        if (st != NEB_OK) break;
+        if (stack <= c->forest_depth) continue;
+        int maxb = lds_blocks_per_cu(stack);
+        for (int b : {0, 4, 8, maxb}) {
+            neb_launch_config cfg{stack, b, best.photon_blocks_per_cu};
+            double ms = 0.0;
+            st = time_config(c, cfg, trial_iterations, trace_k, 3, s, ms);
+            if (st != NEB_OK) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best.bvh_stack = stack;
+                best.trace_blocks_per_cu = b;
+            }
+        }
+    }
+    best_ms = 1e300;
+    const int photon_k[1] = {K_PHOTON};
+    for (int pb : {0, 8, 16, 32, 64}) {
+        if (st != NEB_OK) break;
+        neb_launch_config cfg{best.bvh_stack, best.trace_blocks_per_cu, pb};
+        double ms = 0.0;
+        st = time_config(c, cfg, trial_iterations, photon_k, 1, s, ms);
+        if (st != NEB_OK) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best.photon_blocks_per_cu = pb;
+        }
+    }
+    prof_clear(c);
+    c->prof_on = was_on;
+    if (st != NEB_OK) {
+        c->cfg = keep;
+        drop_graph(c);
+        return st;
+    }
+    st = apply_config(c, best);
+    if (st != NEB_OK) return st;
+    if (chosen) *chosen = best;
+    return neb_reset(c);
 }
 
 extern "C" void neb_destroy(neb_ctx c) {
     if (!c) return;
     (void)hipDeviceSynchronize();
-    free_list(c->scene_allocs);
-    free_list(c->allocs);
-    c->oct.nodes = nullptr;   // owned by allocs
-    c->oct.state = nullptr;
-    octree_release(c->oct);
-    for (auto& e : c->prof_ev) (void)hipEventDestroy(e);
-    delete c;
+    destroy_ctx(c);
 }
 
 // ---------------------------------------------------------------------------
@@ -1497,14 +2086,19 @@ extern "C" neb_status neb_octree_create(const float scene_min[3], const float sc
         if (!std::isfinite(scene_min[k]) || !std::isfinite(scene_max[k]) || !(scene_max[k] > scene_min[k]))
             return fail(NEB_ERR_INVALID_ARG, "bounds must be finite with max > min");
     neb_octree o = new neb_octree_s();
-    octree_params_init(o->o.prm, scene_min, scene_max, capacity);
-    o->o.last_iter = 1;
-    hipError_t e = hipMalloc(&o->o.nodes, 4 * (size_t)o->o.prm.capacity);
-    if (e == hipSuccess) e = hipMalloc(&o->o.state, sizeof(OctState));
-    if (e == hipSuccess) e = octree_init_nodes(o->o, nullptr);
+    Octree& t = o->o;
+    octree_params_init(t.prm, scene_min, scene_max, 0, capacity);
+    t.capacity = t.prm.end;
+    t.last_iter = 1;
+    hipError_t e = hipMalloc(&t.nodes, 4 * (size_t)t.capacity);
+    if (e == hipSuccess) e = hipMalloc(&t.state, sizeof(OctState));
+    if (e == hipSuccess) e = hipMalloc(&t.dyn, sizeof(OctDyn));
+    if (e == hipSuccess) e = hipMalloc(&t.prm_dev, sizeof(OctParams));
+    if (e == hipSuccess) e = hipMemcpy(t.prm_dev, &t.prm, sizeof(OctParams), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = octree_reset(t, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
-        octree_release(o->o);
+        octree_release(t);
         delete o;
         return oom_or_device(e, "neb_octree_create");
     }
@@ -1516,7 +2110,12 @@ extern "C" neb_status neb_octree_set_iteration(neb_octree o, int32_t iter) {
     if (!o) return fail(NEB_ERR_INVALID_ARG, "null octree");
     if (iter < 1) return fail(NEB_ERR_INVALID_ARG, "iteration must be >= 1");
     if (iter < o->o.last_iter) return fail(NEB_ERR_STATE, "iterations must not decrease");
-    octree_params_set_iteration(o->o.prm, iter);
+    OctDyn d;
+    octree_dyn_for(d, iter);
+    // the scalars live in device memory: wait for every launch that may read
+    // them, then write them synchronously
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(o->o.dyn, &d, sizeof(d), hipMemcpyHostToDevice));
     o->o.last_iter = iter;
     return NEB_OK;
 }
@@ -1545,10 +2144,10 @@ extern "C" neb_status neb_octree_clear_counters(neb_octree o, void* stream) {
 
 extern "C" neb_status neb_octree_export(neb_octree o, int32_t* nodes, int32_t cap, int64_t info[8], void* stream) {
     if (!o || !info) return fail(NEB_ERR_INVALID_ARG, "null pointer");
-    neb_status st = octree_info(o->o, (hipStream_t)stream, info);
+    neb_status st = octree_info(o->o.nodes, o->o.state, 0, o->o.capacity, (hipStream_t)stream, info);
     if (st != NEB_OK) return st;
     if (nodes && cap > 0)
-        HIP_TRY(hipMemcpy(nodes, o->o.nodes, 4 * (size_t)std::min(cap, o->o.prm.capacity), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(nodes, o->o.nodes, 4 * (size_t)std::min(cap, o->o.capacity), hipMemcpyDeviceToHost));
     return NEB_OK;
 }
 

@@ -19,9 +19,11 @@ FLAG_SINGLE_THREAD_OCTREE, FLAG_RECORD_PATHS, FLAG_NO_PHOTONS = 1, 2, 4
 
 # every symbol the header declares
 EXPORTS = [
-    "neb_create", "neb_set_scene", "neb_render", "neb_get_image", "neb_get_technique_images",
-    "neb_query_density", "neb_get_stats", "neb_get_path_records", "neb_get_octree", "neb_profile_kernels",
-    "neb_get_kernel_profile", "neb_reset",
+    "neb_create", "neb_create_batch", "neb_set_scene", "neb_set_batch_scene", "neb_render", "neb_use_graph",
+    "neb_autotune", "neb_set_launch_config", "neb_get_launch_config", "neb_get_image", "neb_get_scene_image",
+    "neb_get_technique_images", "neb_get_scene_technique_images",
+    "neb_query_density", "neb_get_stats", "neb_get_path_records", "neb_get_octree", "neb_get_scene_octree",
+    "neb_profile_kernels", "neb_get_kernel_profile", "neb_reset",
     "neb_destroy", "neb_status_string", "neb_last_error",
     "neb_octree_create", "neb_octree_set_iteration", "neb_octree_increment", "neb_octree_density",
     "neb_octree_clear_counters", "neb_octree_export", "neb_octree_destroy",
@@ -37,7 +39,15 @@ class Params(ctypes.Structure):
                 ("octree_capacity", ctypes.c_int32), ("merge_radius", ctypes.c_float),
                 ("seed", ctypes.c_uint32), ("scene_id", ctypes.c_uint32), ("density_mode", ctypes.c_int32),
                 ("analytic_rho0", ctypes.c_float), ("analytic_cam_weight", ctypes.c_float),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("spp", ctypes.c_int32)]
+
+
+class LaunchConfig(ctypes.Structure):
+    _fields_ = [("bvh_stack", ctypes.c_int32), ("trace_blocks_per_cu", ctypes.c_int32),
+                ("photon_blocks_per_cu", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 class Stats(ctypes.Structure):
@@ -71,14 +81,23 @@ def lib():
         i32, i64 = ctypes.c_int32, ctypes.c_int64
         sig = {
             "neb_create": ([ctypes.POINTER(Params), ctypes.POINTER(_P)], i32),
+            "neb_create_batch": ([ctypes.POINTER(Params), i32, ctypes.POINTER(_P)], i32),
             "neb_set_scene": ([_P, _P, i32, _P, _P, i32, _P, i32, _P, i32, _P], i32),
+            "neb_set_batch_scene": ([_P, i32, _P, i32, _P, _P, i32, _P, i32, _P, i32, _P], i32),
             "neb_render": ([_P, i32, _P], i32),
+            "neb_use_graph": ([_P, i32], i32),
+            "neb_autotune": ([_P, i32, _P, ctypes.POINTER(LaunchConfig)], i32),
+            "neb_set_launch_config": ([_P, ctypes.POINTER(LaunchConfig)], i32),
+            "neb_get_launch_config": ([_P, ctypes.POINTER(LaunchConfig)], i32),
             "neb_get_image": ([_P, _P, i32, _P], i32),
+            "neb_get_scene_image": ([_P, i32, _P, i32, _P], i32),
             "neb_get_technique_images": ([_P, _P, _P, _P, i32, _P], i32),
+            "neb_get_scene_technique_images": ([_P, i32, _P, _P, _P, i32, _P], i32),
             "neb_query_density": ([_P, _P, _P, i32, _P, i32, _P], i32),
             "neb_get_stats": ([_P, ctypes.POINTER(Stats)], i32),
             "neb_get_path_records": ([_P, _P, i64], i32),
             "neb_get_octree": ([_P, _P, i32, _P], i32),
+            "neb_get_scene_octree": ([_P, i32, _P, i32, _P], i32),
             "neb_profile_kernels": ([_P, i32], i32),
             "neb_get_kernel_profile": ([_P, ctypes.POINTER(KernelTime), i32, ctypes.POINTER(i32)], i32),
             "neb_reset": ([_P], i32),
@@ -138,25 +157,45 @@ def make_params(scene, density_mode=DENSITY_OCTREE_ROBUST, flags=0, rho0=0.0, ca
     p.analytic_rho0 = rho0
     p.analytic_cam_weight = cam_weight
     p.flags = flags
+    p.spp = over.get("spp", 0)
     return p
 
 
-class Renderer:
-    """One rendering context on the current device."""
+def _scene_arrays(scene):
+    return [np.ascontiguousarray(scene.vertices, np.float32), np.ascontiguousarray(scene.tris, np.int32),
+            np.ascontiguousarray(scene.tri_mat, np.int32), np.ascontiguousarray(scene.materials),
+            np.ascontiguousarray(scene.point_lights), np.ascontiguousarray(scene.camera)]
 
-    def __init__(self, scene, density_mode=DENSITY_OCTREE_ROBUST, flags=0, rho0=0.0, cam_weight=0.0, **over):
-        self.params = make_params(scene, density_mode, flags, rho0, cam_weight, **over)
+
+class BatchRenderer:
+    """A context rendering several scenes together (neb_create_batch); every
+    launch covers all of them.  Per-scene settings come from each scene
+    object (its image size, path length, octree capacity, merge radius, seed,
+    scene id and spp) unless overridden by `per_scene` dicts."""
+
+    def __init__(self, scenes, density_mode=DENSITY_OCTREE_ROBUST, flags=0, rho0=0.0, cam_weight=0.0,
+                 per_scene=None, spp=None):
+        self.scenes = list(scenes)
+        n = len(self.scenes)
+        per_scene = per_scene or [{} for _ in range(n)]
+        arr = (Params * n)()
+        for i, sc in enumerate(self.scenes):
+            over = dict(per_scene[i])
+            if spp is not None:
+                over.setdefault("spp", spp[i] if hasattr(spp, "__len__") else spp)
+            arr[i] = make_params(sc, density_mode, flags, rho0, cam_weight, **over)
+        self.params_list = [arr[i] for i in range(n)]
         h = _P()
-        _check(lib().neb_create(ctypes.byref(self.params), ctypes.byref(h)))
+        _check(lib().neb_create_batch(arr, n, ctypes.byref(h)))
         self.h = h
-        self.scene = scene
-        arrs = [np.ascontiguousarray(scene.vertices, np.float32), np.ascontiguousarray(scene.tris, np.int32),
-                np.ascontiguousarray(scene.tri_mat, np.int32), np.ascontiguousarray(scene.materials),
-                np.ascontiguousarray(scene.point_lights), np.ascontiguousarray(scene.camera)]
-        v, t, m, mats, pl, cam = arrs
-        _check(lib().neb_set_scene(self.h, _np_ptr(v), v.shape[0], _np_ptr(t), _np_ptr(m), t.shape[0],
-                                   _np_ptr(mats), mats.shape[0], _np_ptr(pl) if len(pl) else None, pl.shape[0],
-                                   _np_ptr(cam)))
+        for i, sc in enumerate(self.scenes):
+            self._set(i, sc)
+
+    def _set(self, i, scene):
+        v, t, m, mats, pl, cam = _scene_arrays(scene)
+        _check(lib().neb_set_batch_scene(self.h, i, _np_ptr(v), v.shape[0], _np_ptr(t), _np_ptr(m), t.shape[0],
+                                         _np_ptr(mats), mats.shape[0], _np_ptr(pl) if len(pl) else None,
+                                         pl.shape[0], _np_ptr(cam)))
 
     def close(self):
         if getattr(self, "h", None):
@@ -172,27 +211,45 @@ class Renderer:
     def render(self, n_iterations, stream=None):
         _check(lib().neb_render(self.h, int(n_iterations), _stream(stream)))
 
-    def image(self, out=None, stream=None):
-        """Mean radiance: a (H, W, 3) float32 device tensor (written into
-        `out` if given)."""
+    def use_graph(self, enable=True):
+        _check(lib().neb_use_graph(self.h, int(enable)))
+
+    def autotune(self, trial_iterations=2, stream=None):
+        cfg = LaunchConfig()
+        _check(lib().neb_autotune(self.h, int(trial_iterations), _stream(stream), ctypes.byref(cfg)))
+        return cfg.as_dict()
+
+    def set_launch_config(self, bvh_stack, trace_blocks_per_cu, photon_blocks_per_cu):
+        cfg = LaunchConfig(bvh_stack, trace_blocks_per_cu, photon_blocks_per_cu)
+        _check(lib().neb_set_launch_config(self.h, ctypes.byref(cfg)))
+
+    def launch_config(self):
+        cfg = LaunchConfig()
+        _check(lib().neb_get_launch_config(self.h, ctypes.byref(cfg)))
+        return cfg.as_dict()
+
+    def image(self, scene=0, out=None, stream=None):
+        """Mean radiance of one scene: a (H, W, 3) float32 device tensor
+        (written into `out` if given)."""
         import torch
-        H, W = self.params.height, self.params.width
+        P = self.params_list[scene]
         if out is None:
-            out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
-        _check(lib().neb_get_image(self.h, _dev_ptr(out), 1, _stream(stream)))
+            out = torch.empty((P.height, P.width, 3), dtype=torch.float32, device="cuda")
+        _check(lib().neb_get_scene_image(self.h, int(scene), _dev_ptr(out), 1, _stream(stream)))
         return out
 
-    def image_host(self):
-        H, W = self.params.height, self.params.width
-        out = np.zeros((H, W, 3), np.float32)
-        _check(lib().neb_get_image(self.h, _np_ptr(out), 0, None))
+    def image_host(self, scene=0):
+        P = self.params_list[scene]
+        out = np.zeros((P.height, P.width, 3), np.float32)
+        _check(lib().neb_get_scene_image(self.h, int(scene), _np_ptr(out), 0, None))
         return out
 
-    def technique_images_host(self):
-        H, W = self.params.height, self.params.width
-        e, E, P = (np.zeros((H, W, 3), np.float32) for _ in range(3))
-        _check(lib().neb_get_technique_images(self.h, _np_ptr(e), _np_ptr(E), _np_ptr(P), 0, None))
-        return {"e": e, "E": E, "P": P}
+    def technique_images_host(self, scene=0):
+        P = self.params_list[scene]
+        e, E, Pi = (np.zeros((P.height, P.width, 3), np.float32) for _ in range(3))
+        _check(lib().neb_get_scene_technique_images(self.h, int(scene), _np_ptr(e), _np_ptr(E), _np_ptr(Pi), 0,
+                                                    None))
+        return {"e": e, "E": E, "P": Pi}
 
     def stats(self):
         s = Stats()
@@ -200,20 +257,24 @@ class Renderer:
         return s.as_dict()
 
     def records(self):
-        n = self.params.width * self.params.height * self.params.max_path_len
-        out = np.zeros(n, RECORD_DTYPE)
-        _check(lib().neb_get_path_records(self.h, _np_ptr(out), n))
-        return out.reshape(self.params.width * self.params.height, self.params.max_path_len)
+        """Path records of the first iteration: (pixels over all scenes,
+        longest path length)."""
+        npix = sum(P.width * P.height for P in self.params_list)
+        L = max(P.max_path_len for P in self.params_list)
+        out = np.zeros(npix * L, RECORD_DTYPE)
+        _check(lib().neb_get_path_records(self.h, _np_ptr(out), out.size))
+        return out.reshape(npix, L)
 
-    def octree(self):
+    def octree(self, scene=0):
         info = np.zeros(8, np.int64)
-        _check(lib().neb_get_octree(self.h, None, 0, _np_ptr(info)))
+        _check(lib().neb_get_scene_octree(self.h, int(scene), None, 0, _np_ptr(info)))
         nodes = np.zeros(int(info[0]), np.int32)
-        _check(lib().neb_get_octree(self.h, _np_ptr(nodes), nodes.size, _np_ptr(info)))
+        _check(lib().neb_get_scene_octree(self.h, int(scene), _np_ptr(nodes), nodes.size, _np_ptr(info)))
         return nodes, dict(zip(OCT_INFO_KEYS, (int(x) for x in info)))
 
     def query_density(self, pos, nrm, stream=None):
-        """pos, nrm: (n, 3) float32 device tensors -> (n,) densities."""
+        """Scene 0's octree.  pos, nrm: (n, 3) float32 device tensors -> (n,)
+        densities."""
         import torch
         out = torch.empty(pos.shape[0], dtype=torch.float32, device=pos.device)
         _check(lib().neb_query_density(self.h, _dev_ptr(pos), _dev_ptr(nrm), pos.shape[0], _dev_ptr(out), 1,
@@ -232,6 +293,30 @@ class Renderer:
 
     def reset(self):
         _check(lib().neb_reset(self.h))
+
+
+class Renderer(BatchRenderer):
+    """One rendering context of one scene on the current device (a batch of
+    one; progressive: every iteration counts unless spp is given)."""
+
+    def __init__(self, scene, density_mode=DENSITY_OCTREE_ROBUST, flags=0, rho0=0.0, cam_weight=0.0, **over):
+        self.params = make_params(scene, density_mode, flags, rho0, cam_weight, **over)
+        self.params_list = [self.params]
+        self.scenes = [scene]
+        self.scene = scene
+        h = _P()
+        _check(lib().neb_create(ctypes.byref(self.params), ctypes.byref(h)))
+        self.h = h
+        v, t, m, mats, pl, cam = _scene_arrays(scene)
+        _check(lib().neb_set_scene(self.h, _np_ptr(v), v.shape[0], _np_ptr(t), _np_ptr(m), t.shape[0],
+                                   _np_ptr(mats), mats.shape[0], _np_ptr(pl) if len(pl) else None, pl.shape[0],
+                                   _np_ptr(cam)))
+
+    def records(self):
+        n = self.params.width * self.params.height * self.params.max_path_len
+        out = np.zeros(n, RECORD_DTYPE)
+        _check(lib().neb_get_path_records(self.h, _np_ptr(out), n))
+        return out.reshape(self.params.width * self.params.height, self.params.max_path_len)
 
 
 class DeviceOctree:

@@ -50,3 +50,19 @@ def test_invalid_arguments_are_rejected_without_a_device():
     assert L.neb_render(None, 1, None) == -1
     lo = (ctypes.c_float * 3)(0, 0, 0)
     assert L.neb_octree_create(lo, lo, 16, ctypes.byref(h)) == -1     # flat bounds
+    # batch, graph and tuning entry points check their arguments first
+    one = (neb.Params * 2)()
+    for q in one:
+        q.width, q.height, q.max_path_len, q.octree_capacity, q.merge_radius = 8, 8, 4, 64, 0.01
+    assert L.neb_create_batch(one, 0, ctypes.byref(h)) == -1
+    assert L.neb_create_batch(one, 257, ctypes.byref(h)) == -1
+    one[1].density_mode = 3
+    assert L.neb_create_batch(one, 2, ctypes.byref(h)) == -1          # mixed density modes
+    one[1].density_mode = 0
+    one[1].spp = -1
+    assert L.neb_create_batch(one, 2, ctypes.byref(h)) == -1
+    assert L.neb_use_graph(None, 1) == -1
+    assert L.neb_autotune(None, 1, None, None) == -1
+    assert L.neb_set_launch_config(None, None) == -1
+    assert L.neb_get_scene_image(None, 0, None, 0, None) == -1
+    assert L.neb_set_batch_scene(None, 0, None, 0, None, None, 0, None, 0, None, 0, None) == -1
