@@ -8,11 +8,18 @@ a 20k-triangle glass sphere (IOR 1.5) on a table and four emissive spheres,
 512 x 512 pixels, path length 8, octree of 2^20 nodes, merge radius 0.02.
 The 16 steps after the warm-up reproduce the workload's 16 spp.
 
+Launch shapes are picked first by the library's autotuner (they change
+the speed, not the result).
+
 Prints one JSON line with camera paths/s (value), photons/s, the roofline
 of the dominant kernel (HIP-event durations on the launch stream, the
-library's work counters for algorithmic bytes) and the FP64 oracle timed on
-the host cores over a bounded pixel window of the same workload.
+library's work counters for algorithmic bytes, HBM traffic from the
+committed counter summary while the kernel source is unchanged), the FP64
+oracle timed on the host cores over a bounded pixel window of the same
+workload, and the batched form: 64 box rooms rendered in one context
+against the same 64 scenes rendered one after another.
 """
+import hashlib
 import argparse
 import json
 import os
@@ -54,8 +61,9 @@ def algorithmic_bytes(stats, name, npix, vertices):
     return None
 
 
-def cpu_baseline(target_s=12.0):
-    """The oracle, untouched, on a window of the same workload (1 iteration)."""
+def cpu_baseline(target_s=11.0):
+    """The oracle, untouched, on a window of the same workload (1 iteration):
+    a 16x16 probe sizes a square window expected to take target_s."""
     from neb_inputs import room
     from oracle import oracle as O
     O.build()
@@ -65,20 +73,106 @@ def cpu_baseline(target_s=12.0):
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count() or 1
-    side = 16
-    while True:
+
+    def run(side):
         x0, y0 = 256 - side // 2, 256 - side // 2
         t0 = time.perf_counter()
         r = O.render(sc, n_iter=1, window=(x0, y0, x0 + side, y0 + side), n_threads=cores, oscene=osc)
-        dt = time.perf_counter() - t0
-        if dt >= target_s / 4 or side >= 256:
-            break
-        side = min(256, int(side * max(1.5, min(4.0, (target_s / max(dt, 1e-3)) ** 0.5))))
+        return r, time.perf_counter() - t0
+
+    _, dt = run(16)
+    side = int(max(16, min(256, 16 * (target_s / max(dt, 1e-3)) ** 0.5)))
+    r, dt = run(side)
     paths = side * side
     return {"value": paths / dt, "unit": "camera paths/s", "cores": cores, "kind": "oracle",
             "sample": f"{side}x{side} pixel window at the centre of the 512x512 room, 1 iteration, full NEB "
                       f"(photons {int(r['stats']['photons'])}, merges {int(r['stats']['merges'])}) in {dt:.2f} s",
             "photons_per_s": r["stats"]["photons"] / dt}
+
+
+def source_digest():
+    """Digest of the sources that define the merge kernel's code."""
+    h = hashlib.sha256()
+    for f in ("neb_render.hip", "neb_device.h", "neb_internal.h"):
+        with open(os.path.join(ROOT, "paper_1909_00573_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/<kernel>_room_counters.txt: 'key: value' lines), or None when
+    the summary is missing or was taken from other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_room_counters.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_digest") != source_digest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def batch_comparison(stream, cfg_trials=1):
+    """64 box rooms (batch recipe, seed 4) rendered to their own spp in one
+    batched context, against the same scenes rendered one after another in
+    single-scene contexts with the same launch shapes.  A batched scene
+    renders the same estimator as alone (same paths and photons), so equal
+    spp is equal RMSE and the time ratio is the time-to-equal-RMSE ratio."""
+    import torch
+    from neb_inputs import batch_rooms
+    from paper_1909_00573_amd import neb
+    t0 = time.perf_counter()
+    scenes = batch_rooms()
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    B = neb.BatchRenderer(scenes, spp=[s.spp for s in scenes])
+    t_build = time.perf_counter() - t0
+    cfg = B.autotune(cfg_trials, stream=stream)
+    n_iter = max(s.spp for s in scenes)
+    paths = sum(s.width * s.height * s.spp for s in scenes)
+
+    def timed(render):
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        render()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / 1e3
+
+    B.reset()
+    t_batch = timed(lambda: B.render(n_iter, stream=stream))
+    st = B.stats()
+    B.reset()
+    B.use_graph(True)
+    t_graph = timed(lambda: B.render(n_iter, stream=stream))
+    B.close()
+    del B
+    # the same scenes one after another (contexts built beforehand, not timed)
+    ctxs = []
+    t_seq = 0.0
+    for sc in scenes:
+        R = neb.Renderer(sc, spp=sc.spp)
+        # the batch's stack is deeper than every scene's BVH
+        R.set_launch_config(cfg["bvh_stack"], cfg["trace_blocks_per_cu"], cfg["photon_blocks_per_cu"])
+        t_seq += timed(lambda: R.render(sc.spp, stream=stream))
+        R.close()
+    return {"scenes": len(scenes), "triangles": int(sum(s.n_tris for s in scenes)),
+            "pixels": int(sum(s.width * s.height for s in scenes)), "camera_paths": int(paths),
+            "photons": int(st["photons"]), "launch_config": cfg,
+            "batched_s": round(t_batch, 4), "batched_graph_s": round(t_graph, 4), "sequential_s": round(t_seq, 4),
+            "batched_paths_per_s": round(paths / t_batch, 1), "sequential_paths_per_s": round(paths / t_seq, 1),
+            "speedup": round(t_seq / min(t_batch, t_graph), 3),
+            "host_setup_s": {"generate": round(t_gen, 1), "bvh_and_pools": round(t_build, 1)}}
 
 
 def main():
@@ -88,6 +182,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event pass")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-scene batching comparison")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB device copy first (for counter calibration)")
     args = ap.parse_args()
@@ -111,6 +207,7 @@ def main():
     npix = sc.width * sc.height
     R = neb.Renderer(sc)
     stream = torch.cuda.current_stream()
+    launch_cfg = R.launch_config() if args.no_autotune else R.autotune(2, stream=stream)
     # warm-up on a throw-away progression, then start the 16-spp render afresh
     R.render(args.warmup, stream=stream)
     torch.cuda.synchronize()
@@ -159,8 +256,10 @@ def main():
             v = prof[best]
             per_launch = nb / v["launches"]
             achieved = per_launch / (v["total_ms"] * 1e-3 / v["launches"]) / 1e9
+            traffic = committed_traffic(best)
             roof = {"kernel": best, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": None if traffic is None else int(traffic),
                     "algorithmic_bytes_per_launch": int(per_launch),
                     "avg_launch_us": round(1e3 * v["total_ms"] / v["launches"], 2)}
 
@@ -180,8 +279,11 @@ def main():
         "work_per_step": {k: round((st[k] - s0[k]) / args.steps) for k in
                           ("vertices", "photons", "photon_segments", "merges", "candidates", "grid_cells",
                            "camera_rays", "shadow_rays", "bvh_nodes", "bvh_tris")},
-        "roofline": roof, "kernels": kernels,
+        "roofline": roof, "kernels": kernels, "launch_config": launch_cfg,
     }
+    R.close()
+    if not args.no_batch:
+        out["batch"] = batch_comparison(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

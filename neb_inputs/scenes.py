@@ -68,12 +68,15 @@ class _Mesh:
         self.v = []
         self.t = []
         self.m = []
+        self.nv = 0
 
     def add(self, verts, tris, mat):
-        base = sum(len(a) for a in self.v)
-        self.v.append(np.asarray(verts, np.float64))
-        self.t.append(np.asarray(tris, np.int64) + base)
-        self.m.append(np.full(len(tris), mat, np.int32))
+        verts = np.asarray(verts, np.float64)
+        tris = np.asarray(tris, np.int64)
+        self.v.append(verts)
+        self.t.append(tris + self.nv)
+        self.m.append(np.broadcast_to(np.asarray(mat, np.int32), (len(tris),)).copy())
+        self.nv += len(verts)
 
     def quad(self, a, b, c, d, mat):
         """Quad a-b-c-d, counter-clockwise seen from the normal side."""
@@ -93,21 +96,33 @@ class _Mesh:
                 tris += [[a, b, c], [a, c, d]]
         self.add(verts, tris, mat)
 
-    def box(self, lo, hi, mat, inward=False):
-        lo, hi = np.asarray(lo, np.float64), np.asarray(hi, np.float64)
-        x0, y0, z0 = lo
-        x1, y1, z1 = hi
-        p = [[x0, y0, z0], [x1, y0, z0], [x1, y1, z0], [x0, y1, z0],
-             [x0, y0, z1], [x1, y0, z1], [x1, y1, z1], [x0, y1, z1]]
-        # outward-facing quads
-        faces = [[0, 3, 2, 1], [4, 5, 6, 7], [0, 1, 5, 4],
-                 [3, 7, 6, 2], [0, 4, 7, 3], [1, 2, 6, 5]]
+    _CORNERS = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0],
+                         [0, 0, 1], [1, 0, 1], [1, 1, 1], [0, 1, 1]], np.float64)
+    # outward-facing quads over the corners above
+    _FACES = [[0, 3, 2, 1], [4, 5, 6, 7], [0, 1, 5, 4], [3, 7, 6, 2], [0, 4, 7, 3], [1, 2, 6, 5]]
+
+    @classmethod
+    def _box_tris(cls, inward):
         tris = []
-        for f in faces:
+        for f in cls._FACES:
             if inward:
                 f = f[::-1]
             tris += [[f[0], f[1], f[2]], [f[0], f[2], f[3]]]
-        self.add(p, tris, mat)
+        return np.asarray(tris, np.int64)
+
+    def box(self, lo, hi, mat, inward=False):
+        lo, hi = np.asarray(lo, np.float64), np.asarray(hi, np.float64)
+        self.add(lo + self._CORNERS * (hi - lo), self._box_tris(inward), mat)
+
+    def boxes(self, lo, hi, mats):
+        """Many outward-facing boxes at once: lo, hi (n, 3), mats (n,)."""
+        lo, hi = np.asarray(lo, np.float64), np.asarray(hi, np.float64)
+        n = len(lo)
+        if n == 0:
+            return
+        verts = (lo[:, None, :] + self._CORNERS[None] * (hi - lo)[:, None, :]).reshape(-1, 3)
+        tris = (self._box_tris(False)[None] + 8 * np.arange(n)[:, None, None]).reshape(-1, 3)
+        self.add(verts, tris, np.repeat(np.asarray(mats, np.int32), 12))
 
     def icosphere(self, center, radius, subdiv, mat):
         v, t = icosphere(subdiv)
@@ -363,10 +378,15 @@ def _box_room_scene(rng, n_target, n_lights, res, spp, seed, scene_id):
     M.box([0, 0, 0], [L, 2.5, L], 0, inward=True)
     # interior random boxes up to the triangle budget
     n_boxes = max(0, (n_target - 12 - n_lights * 80) // 12)
-    for _ in range(int(n_boxes)):
+    lo = np.empty((int(n_boxes), 3))
+    hi = np.empty((int(n_boxes), 3))
+    bm = np.empty(int(n_boxes), np.int32)
+    for i in range(int(n_boxes)):
         s = rng.uniform(0.02, 0.3, 3)
         c = rng.uniform([0.2, 0.0, 0.2], [L - 0.2, 1.5, L - 0.2])
-        M.box(c, c + s, int(rng.integers(0, 5)) if rng.uniform() < 0.1 else int(rng.integers(0, 2)))
+        lo[i], hi[i] = c, c + s
+        bm[i] = int(rng.integers(0, 5)) if rng.uniform() < 0.1 else int(rng.integers(0, 2))
+    M.boxes(lo, hi, bm)
     for _ in range(int(n_lights)):
         c = rng.uniform([0.3, 1.9, 0.3], [L - 0.3, 2.3, L - 0.3])
         M.icosphere(c, 0.02, 1, 2)
