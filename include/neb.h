@@ -50,6 +50,8 @@ typedef struct neb_octree_s* neb_octree;
 enum {
     NEB_DENSITY_OCTREE = 0,        /* one octree probe (Appendix B get_density) */
     NEB_DENSITY_OCTREE_ROBUST = 1, /* median of five probes (Appendix B, default) */
+    NEB_DENSITY_MLP = 2,           /* learned density fitted to the robust octree, with octree
+                                      fallback per region (see neb_configure_mlp) */
     NEB_DENSITY_ANALYTIC = 3       /* test hook: rho0 + w * primary-hit density of the camera */
 };
 
@@ -273,6 +275,85 @@ neb_status neb_reset(neb_ctx ctx);
 void neb_destroy(neb_ctx ctx);
 const char* neb_status_string(neb_status s);
 const char* neb_last_error(void);
+
+/* ---------------------------------------------------------------------- */
+/* learned density (stands in for the octree query of Sec. 5 / eq.         */
+/* octdensity; the model is not in the paper)                              */
+/* ---------------------------------------------------------------------- */
+
+/* Model: 80 encoded inputs (the point normalised to the octree box, q in
+ * [0,1)^3, the unit normal n, then sin and cos of 2^f pi c for the six
+ * coordinates c = q0,q1,q2,n0,n1,n2 and octaves f = 0..5, feature
+ * 6 + 12 c + 2 f, then two zeros) -> 64 -> 64 -> 64 (ReLU) -> 1 output y;
+ * log rho = mu + sigma * y.  Hidden layers run on the matrix cores with
+ * bf16 operands and FP32 accumulation; the parameters are FP32 master
+ * copies trained with Adam on the mean squared error of y against
+ * (log rho_target - mu) / sigma.  Flat parameter layout (host and device):
+ * W1 (80 x 64, row k = input feature k), b1 (64), W2 (64 x 64), b2,
+ * W3 (64 x 64), b3, w4 (64), b4 (1). */
+#define NEB_MLP_PARAMS 13569
+
+typedef struct neb_mlp_s* neb_mlp;
+
+/* Settings of NEB_DENSITY_MLP.  The first train_iterations iterations use
+ * the robust octree; after each, the NEE vertices with rho > 0 become the
+ * training pool (position, normal, log rho) and steps_per_iteration Adam
+ * steps are taken on batches of `batch` draws from it (mu, sigma are the
+ * first pool's mean and standard deviation).  Later iterations take rho
+ * from the model; the octree stops counting (it keeps the density of the
+ * training iterations) and judges the model: all vertices of the first
+ * model iteration, then `probes` random vertices every probe_every
+ * iterations, are compared with the robust octree query; each of the 32^3
+ * regions of the octree box keeps the model while the median of its probes'
+ * relative errors is at most max_rel_error, else it falls back to the
+ * octree query. */
+typedef struct {
+    int32_t train_iterations;    /* default 4 */
+    int32_t steps_per_iteration; /* default 250 */
+    int32_t batch;               /* default 65536, 16 .. 1048576 */
+    float lr, beta1, beta2, eps; /* default 2e-3, 0.9, 0.999, 1e-8 */
+    int32_t probe_every;         /* default 8 */
+    int32_t probes;              /* default 4096 */
+    float max_rel_error;         /* default 0.1 */
+    uint32_t seed;               /* initial weights (He uniform) and batch draws */
+} neb_mlp_params;
+
+typedef struct {
+    int32_t phase;               /* 0 training on the octree, 1 model in use */
+    int64_t adam_steps;
+    double last_loss;            /* mean loss over the last training iteration's steps */
+    float mu, sigma;
+    int64_t probes, probes_bad;  /* probe comparisons so far, and those over the bound */
+    int64_t regions_probed, regions_disabled;
+    int64_t fallback_queries;    /* vertex densities taken from the octree in model iterations */
+} neb_mlp_status;
+
+/* Sets the model settings of a context created with NEB_DENSITY_MLP (one
+ * scene) and restarts it (NULL = defaults).  NEB_ERR_STATE for other
+ * contexts, NEB_ERR_INVALID_ARG for values out of range. */
+neb_status neb_configure_mlp(neb_ctx ctx, const neb_mlp_params* params);
+neb_status neb_get_mlp_status(neb_ctx ctx, neb_mlp_status* out);
+/* The context's model parameters (host, NEB_MLP_PARAMS floats). */
+neb_status neb_get_mlp_weights(neb_ctx ctx, float* params);
+
+/* A standalone model for batches of up to max_batch samples.  init: host,
+ * NEB_MLP_PARAMS floats, or NULL for He-uniform weights from `seed` and
+ * zero biases; mu = 0, sigma = 1. */
+neb_status neb_mlp_create(const float* init, uint32_t seed, int32_t max_batch, neb_mlp* out);
+neb_status neb_mlp_set_normalization(neb_mlp mlp, float mu, float sigma, void* stream);
+/* log rho at n points: q, nrm device (n*3 floats; q normalised to
+ * [0,1)^3), out device (n floats). */
+neb_status neb_mlp_infer(neb_mlp mlp, const float* q, const float* nrm, int32_t n, float* out, void* stream);
+/* Gradient of the batch's mean loss (device q, nrm: n*3 floats; log_rho:
+ * n floats; 1 <= n <= max_batch) into grad (device, NEB_MLP_PARAMS floats)
+ * and the loss into *loss (host; the call synchronises `stream`). */
+neb_status neb_mlp_gradient(neb_mlp mlp, const float* q, const float* nrm, const float* log_rho, int32_t n,
+                            float* grad, float* loss, void* stream);
+/* One Adam step on the batch's gradient. */
+neb_status neb_mlp_train_step(neb_mlp mlp, const float* q, const float* nrm, const float* log_rho, int32_t n,
+                              float lr, float beta1, float beta2, float eps, void* stream);
+neb_status neb_mlp_get_params(neb_mlp mlp, float* params);
+void neb_mlp_destroy(neb_mlp mlp);
 
 /* ---------------------------------------------------------------------- */
 /* density octree (Sec. 5, Appendix B), batched and stream-ordered         */

@@ -16,7 +16,7 @@ constexpr int kMaxPathLen = 16;
 constexpr int kBvhStackMax = 64;           // deepest LDS traversal stack (entries per lane)
 constexpr int kTraceBlock = 64;            // threads per traversal block (one wave)
 
-constexpr uint32_t kTagCamera = 1, kTagBsdf = 2, kTagNee = 3, kTagPhoton = 4;
+constexpr uint32_t kTagCamera = 1, kTagBsdf = 2, kTagNee = 3, kTagPhoton = 4, kTagMlp = 5, kTagProbe = 6;
 
 // Static scalars of one octree (the members of the class of Appendix B that
 // do not change with the iteration), passed by value.  Several octrees can

@@ -26,6 +26,7 @@
 // replays for every iteration.
 #include <algorithm>
 #include <chrono>
+#include <random>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -34,6 +35,7 @@
 
 #include "neb_bvh.h"
 #include "neb_device.h"
+#include "neb_mlp.h"
 
 namespace neb {
 
@@ -178,8 +180,9 @@ __global__ void k_fill_f32(float* p, float v, int64_t n) {
 }
 // Starts an iteration: advances the device iteration counter, sets the
 // octree's iteration scalars (Appendix B set_iteration) and empties the
-// queues.
-__global__ void k_iter_begin(Counters* c, OctDyn* dyn) {
+// queues.  The octree counts iterations 1..freeze only (freeze is the
+// number of training iterations of the learned density, else unbounded).
+__global__ void k_iter_begin(Counters* c, OctDyn* dyn, int32_t freeze) {
     int it = c->iter + 1;
     c->iter = it;
     c->qcount[0] = 0;
@@ -188,12 +191,13 @@ __global__ void k_iter_begin(Counters* c, OctDyn* dyn) {
     c->pcount[1] = 0;
     c->n_vertices = 0;
     c->n_events = 0;
-    int ic = it < kOctFillIterations ? it : kOctFillIterations;
+    int oit = it < freeze ? it : freeze;
+    int ic = oit < kOctFillIterations ? oit : kOctFillIterations;
     OctDyn d;
-    d.iter = it;
+    d.iter = oit;
     d.split_count = kOctSplitFactor * ic;
     d.density_scale = 1.0f / (float)ic;
-    d.stop_filling = it > kOctFillIterations;
+    d.stop_filling = it > kOctFillIterations || it > freeze;
     *dyn = d;
 }
 __global__ void k_iter_end(Counters* c) {
@@ -859,6 +863,115 @@ __global__ void __launch_bounds__(256) k_finalize(RenderArgs A, const float4* ev
 }
 
 // ---------------------------------------------------------------------------
+// learned density: training pool, probes against the octree, region gates
+// and the octree fallback (one scene per context)
+// ---------------------------------------------------------------------------
+constexpr int kRegionRes = 32;  // regions of the octree box per axis (octree depth 5)
+constexpr int kRegions = kRegionRes * kRegionRes * kRegionRes;
+enum { kMlpCntProbes = 0, kMlpCntBad = 1, kMlpCntFallback = 2, kMlpCntDisabled = 3, kMlpCntProbed = 4, kMlpCnt = 8 };
+
+__device__ __forceinline__ int region_of(const OctParams& P, f3 p) {
+    float v[3] = {p.x, p.y, p.z};
+    int r[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float q = __fmul_rn(__fsub_rn(v[c], P.min_bound[c]), P.size_inv[c]);
+        r[c] = min(kRegionRes - 1, max(0, (int)(q * (float)kRegionRes)));
+    }
+    return r[0] + kRegionRes * (r[1] + kRegionRes * r[2]);
+}
+
+// the vertices with rho > 0 become the pool: position, normal, log rho
+__global__ void __launch_bounds__(256) k_mlp_collect(VertexStore V, const int32_t* n_vertices, float* pos, float* nrm,
+                                                     float* tgt, int32_t* count) {
+    int n = *n_vertices;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        float rho = V.rho[i];
+        bool take = rho > 0.f;
+        int slot = wave_reserve(count, take);
+        if (take) {
+            float4 a = V.v0[i], b = V.v1[i];
+            pos[3 * (size_t)slot] = a.x;
+            pos[3 * (size_t)slot + 1] = a.y;
+            pos[3 * (size_t)slot + 2] = a.z;
+            nrm[3 * (size_t)slot] = b.x;
+            nrm[3 * (size_t)slot + 1] = b.y;
+            nrm[3 * (size_t)slot + 2] = b.z;
+            tgt[slot] = logf(rho);
+        }
+    }
+}
+
+// Compares the model's density (already in V.rho) with the robust octree
+// query at every vertex (all != 0) or at n_probe random vertices, and adds
+// the comparisons to the per-region tallies.
+__global__ void __launch_bounds__(256) k_mlp_probe(VertexStore V, const int32_t* n_vertices,
+                                                   const int32_t* __restrict__ nodes, const OctState* ost,
+                                                   OctParams P, const OctDyn* dyn, int all, int n_probe, uint32_t k0,
+                                                   uint32_t k1, const Counters* cnt, int32_t* total, int32_t* bad,
+                                                   float max_rel, unsigned long long* mc) {
+    const int nv = *n_vertices;
+    const int count = all ? nv : (nv > 0 ? n_probe : 0);
+    const int depth = ost->depth;
+    const float scale = dyn->density_scale;
+    const uint32_t it = (uint32_t)cnt->iter;
+    unsigned probes = 0, nbad = 0;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
+        int i = t;
+        if (!all) i = (int)(((uint64_t)philox10(make_uint4((uint32_t)t, it, 0u, kTagProbe), k0, k1).x * (uint64_t)nv) >> 32);
+        f3 x = xyz(V.v0[i]), nn = xyz(V.v1[i]);
+        float rm = V.rho[i];
+        float ro = oct_query_robust(nodes, P, scale, depth, x, nn);
+        bool b = ro > 0.f ? fabsf(rm - ro) > max_rel * ro : rm > 0.f;
+        int r = region_of(P, x);
+        atomicAdd(total + r, 1);
+        if (b) atomicAdd(bad + r, 1);
+        ++probes;
+        nbad += b;
+    }
+    wave_add_u64(mc + kMlpCntProbes, probes);
+    wave_add_u64(mc + kMlpCntBad, nbad);
+}
+
+// a region keeps the model while the median of its probes' relative
+// errors is within the bound: at most half of them exceed it
+__global__ void k_mlp_gate(const int32_t* total, const int32_t* bad, int32_t* gate, unsigned long long* mc) {
+    unsigned off = 0, probed = 0;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < kRegions; r += gridDim.x * blockDim.x) {
+        int t = total[r];
+        bool on = t == 0 || 2 * bad[r] <= t;
+        gate[r] = on ? 1 : 0;
+        off += !on;
+        probed += t > 0;
+    }
+    wave_add_u64(mc + kMlpCntDisabled, off);
+    wave_add_u64(mc + kMlpCntProbed, probed);
+}
+
+__global__ void k_mlp_clear_gate_counts(unsigned long long* mc) {
+    mc[kMlpCntDisabled] = 0;
+    mc[kMlpCntProbed] = 0;
+}
+
+// vertices in disabled regions take the robust octree query instead
+__global__ void __launch_bounds__(256) k_density_fallback(VertexStore V, const int32_t* n_vertices,
+                                                          const int32_t* __restrict__ gate,
+                                                          const int32_t* __restrict__ nodes, const OctState* ost,
+                                                          OctParams P, const OctDyn* dyn, unsigned long long* mc) {
+    const int n = *n_vertices;
+    const int depth = ost->depth;
+    const float scale = dyn->density_scale;
+    unsigned fb = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        f3 x = xyz(V.v0[i]);
+        if (gate[region_of(P, x)]) continue;
+        V.rho[i] = oct_query_robust(nodes, P, scale, depth, x, xyz(V.v1[i]));
+        ++fb;
+    }
+    wave_add_u64(mc + kMlpCntFallback, fb);
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 static int grid_of(int64_t n, int block, int cap = 8192) {
@@ -956,6 +1069,15 @@ struct neb_ctx_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap_stream = nullptr;
+    // learned density (NEB_DENSITY_MLP)
+    bool mlp_mode = false;
+    neb_mlp_params mcfg{};
+    Mlp mlp;
+    float *tpos = nullptr, *tnrm = nullptr, *ttgt = nullptr;  // training pool
+    int32_t* tcount = nullptr;
+    int32_t *reg_total = nullptr, *reg_bad = nullptr, *reg_gate = nullptr;
+    unsigned long long* mlp_cnt = nullptr;
+    int32_t last_train_steps = 0;
     // kernel profiling
     bool prof_on = false;
     std::vector<hipEvent_t> prof_ev;
@@ -967,10 +1089,11 @@ struct neb_ctx_s {
 
 enum KernelId {
     K_CAMERA, K_EXTEND_CAMERA, K_SHADE, K_OCTREE_INSERT, K_DENSITY, K_NEE, K_GRID_BUILD, K_EXTEND_PHOTON, K_PHOTON,
-    K_FINALIZE, K_MISC, K_COUNT
+    K_FINALIZE, K_MLP_TRAIN, K_MISC, K_COUNT
 };
 static const char* kKernelNames[K_COUNT] = {"camera", "extend_camera", "shade", "octree_insert", "density", "nee",
-                                            "grid_build", "extend_photon", "photon_merge", "finalize", "misc"};
+                                            "grid_build", "extend_photon", "photon_merge", "finalize", "mlp_train",
+                                            "misc"};
 
 static void prof_harvest(neb_ctx c) {
     if (c->prof_used == 0) return;
@@ -1082,11 +1205,41 @@ static void drop_graph(neb_ctx c) {
 
 static void destroy_ctx(neb_ctx c) {
     drop_graph(c);
+    mlp_free(c->mlp);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     free_list(c->scene_allocs);
     free_list(c->allocs);
     for (auto& e : c->prof_ev) (void)hipEventDestroy(e);
     delete c;
+}
+
+static void mlp_defaults(neb_mlp_params& m) {
+    m.train_iterations = 4;
+    m.steps_per_iteration = 250;
+    m.batch = 65536;
+    m.lr = 2e-3f;
+    m.beta1 = 0.9f;
+    m.beta2 = 0.999f;
+    m.eps = 1e-8f;
+    m.probe_every = 8;
+    m.probes = 4096;
+    m.max_rel_error = 0.1f;
+    m.seed = 1;
+}
+
+// He-uniform weights (bound sqrt(6 / fan_in)) and zero biases
+static std::vector<float> mlp_he_init(uint32_t seed) {
+    std::vector<float> w(kMlpParams, 0.f);
+    std::mt19937_64 rng(seed);
+    auto fill = [&](int off, int n, int fan_in) {
+        std::uniform_real_distribution<double> u(-std::sqrt(6.0 / fan_in), std::sqrt(6.0 / fan_in));
+        for (int i = 0; i < n; ++i) w[off + i] = (float)u(rng);
+    };
+    fill(kMlpW1, kMlpIn * kMlpWidth, kMlpIn);
+    fill(kMlpW2, kMlpWidth * kMlpWidth, kMlpWidth);
+    fill(kMlpW3, kMlpWidth * kMlpWidth, kMlpWidth);
+    fill(kMlpW4, kMlpWidth, kMlpWidth);
+    return w;
 }
 
 static neb_status check_params(const neb_params* p) {
@@ -1096,7 +1249,7 @@ static neb_status check_params(const neb_params* p) {
     if (p->octree_capacity < 1 || p->octree_capacity > (1 << 29)) return fail(NEB_ERR_INVALID_ARG, "octree capacity out of range");
     if (!(p->merge_radius > 0.f) || !std::isfinite(p->merge_radius)) return fail(NEB_ERR_INVALID_ARG, "merge radius must be > 0");
     if (p->density_mode != NEB_DENSITY_OCTREE && p->density_mode != NEB_DENSITY_OCTREE_ROBUST &&
-        p->density_mode != NEB_DENSITY_ANALYTIC)
+        p->density_mode != NEB_DENSITY_ANALYTIC && p->density_mode != NEB_DENSITY_MLP)
         return fail(NEB_ERR_INVALID_ARG, "unknown density mode");
     if (!std::isfinite(p->analytic_rho0) || !std::isfinite(p->analytic_cam_weight))
         return fail(NEB_ERR_INVALID_ARG, "analytic density parameters must be finite");
@@ -1126,6 +1279,8 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
     if (npix > (int64_t)INT32_MAX / 16 || vcap * 4 > (int64_t)INT32_MAX || ecap > (int64_t)INT32_MAX)
         return fail(NEB_ERR_CAPACITY, "images too large for the vertex pool");
     if (oct_total >= (int64_t)INT32_MAX - 16) return fail(NEB_ERR_CAPACITY, "octree pool over 2^31 nodes");
+    if (params[0].density_mode == NEB_DENSITY_MLP && n_scenes != 1)
+        return fail(NEB_ERR_INVALID_ARG, "the learned density needs a context of one scene");
     int64_t slot_cap = npix * std::max(1, L - 1);
     if ((params[0].flags & NEB_FLAG_SINGLE_THREAD_OCTREE) && slot_cap > (int64_t)INT32_MAX)
         return fail(NEB_ERR_CAPACITY, "too many pixels for single-thread deposits");
@@ -1207,6 +1362,19 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
     ALLOC(c->defer_cnt, 3);
     ALLOC(c->sc_dev, n_scenes);
     ALLOC(c->pix_base_dev, n_scenes + 1);
+    if (c->density_mode == NEB_DENSITY_MLP) {
+        c->mlp_mode = true;
+        mlp_defaults(c->mcfg);
+        ALLOC(c->tpos, 3 * vcap);
+        ALLOC(c->tnrm, 3 * vcap);
+        ALLOC(c->ttgt, vcap);
+        ALLOC(c->tcount, 1);
+        ALLOC(c->reg_total, kRegions);
+        ALLOC(c->reg_bad, kRegions);
+        ALLOC(c->reg_gate, kRegions);
+        ALLOC(c->mlp_cnt, kMlpCnt);
+        if (e == hipSuccess) e = mlp_alloc(c->mlp, c->mcfg.batch);
+    }
 #undef ALLOC
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(gkeys, 256)), dim3(256), 0, nullptr, c->G.count, 0, gkeys);
@@ -1382,6 +1550,18 @@ static neb_status restart(neb_ctx c, hipStream_t s) {
     OctDyn d0;
     octree_dyn_for(d0, 1);
     HIP_TRY(octree_set_dyn(c->oct_dyn, d0, s));
+    if (c->mlp_mode) {
+        std::vector<float> w = mlp_he_init(c->mcfg.seed);
+        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(mlp_set_weights(c->mlp, w.data(), s));
+        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(mlp_set_norm(c->mlp, 0.f, 1.f, s));
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(kRegions, 256)), dim3(256), 0, s, c->reg_total, 0, (int64_t)kRegions);
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(kRegions, 256)), dim3(256), 0, s, c->reg_bad, 0, (int64_t)kRegions);
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(kRegions, 256)), dim3(256), 0, s, c->reg_gate, 1, (int64_t)kRegions);
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int32_t*)c->mlp_cnt, 0, (int64_t)(2 * kMlpCnt));
+        c->last_train_steps = 0;
+    }
     HIP_TRY(hipGetLastError());
     c->iter = 0;
     c->first_iter_recorded = 0;
@@ -1591,7 +1771,11 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
     const int64_t vcap = c->vcap;
     Counters* cnt = c->cnt;
     Images im{c->img, c->img + 3 * (size_t)npix, c->img + 6 * (size_t)npix};
-    hipLaunchKernelGGL(k_iter_begin, dim3(1), dim3(1), 0, s, cnt, c->oct_dyn);
+    // learned density: train on the octree in iterations 1..T, then use the model
+    const int it = c->iter + 1;
+    const int T = c->mlp_mode ? c->mcfg.train_iterations : 0;
+    const bool model = c->mlp_mode && it > T;
+    hipLaunchKernelGGL(k_iter_begin, dim3(1), dim3(1), 0, s, cnt, c->oct_dyn, c->mlp_mode ? T : INT32_MAX);
     if (c->slots)
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(c->slot_cap, 256)), dim3(256), 0, s, c->slots, -1, c->slot_cap);
     if (record)
@@ -1609,7 +1793,7 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
                                           record ? c->recs : (neb_path_record*)nullptr));
     }
     // deposits of this iteration's NEE vertices into their scenes' octrees
-    if (c->density_mode != NEB_DENSITY_ANALYTIC) {
+    if (c->density_mode != NEB_DENSITY_ANALYTIC && !model) {
         hipError_t e;
         const float* pos = (const float*)c->V.v0;
         const int32_t* tagw = (const int32_t*)c->V.v1 + 3;
@@ -1624,10 +1808,34 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
         HIP_TRY(e);
     }
     // pass 2
-    TIMED(K_DENSITY, hipLaunchKernelGGL(k_density, dim3(grid_of(vcap, 256)), dim3(256), 0, s, A, c->V,
-                                        (const int32_t*)&cnt->n_vertices, (const int32_t*)c->oct_nodes,
-                                        (const OctState*)c->oct_states, (const OctParams*)c->oct_prm_dev,
-                                        (const OctDyn*)c->oct_dyn));
+    if (model) {
+        const OctParams& P0 = c->oct_prm[0];
+        prof_begin(c, K_DENSITY, s);
+        HIP_TRY(mlp_infer(c->mlp, (const float*)c->V.v0, 4, (const float*)c->V.v1, 4, &cnt->n_vertices,
+                          (int32_t)vcap, &P0, c->V.rho, 1, s));
+        const int j = it - T;
+        if (j == 1 || (j - 1) % c->mcfg.probe_every == 0) {
+            const int n_probe = j == 1 ? (int)vcap : c->mcfg.probes;
+            hipLaunchKernelGGL(k_mlp_probe, dim3(grid_of(n_probe, 256, 4096)), dim3(256), 0, s, c->V,
+                               (const int32_t*)&cnt->n_vertices, (const int32_t*)c->oct_nodes,
+                               (const OctState*)c->oct_states, P0, (const OctDyn*)c->oct_dyn, j == 1 ? 1 : 0,
+                               c->mcfg.probes, c->mcfg.seed, 0x50524F42u, (const Counters*)cnt, c->reg_total,
+                               c->reg_bad, c->mcfg.max_rel_error, c->mlp_cnt);
+            hipLaunchKernelGGL(k_mlp_clear_gate_counts, dim3(1), dim3(1), 0, s, c->mlp_cnt);
+            hipLaunchKernelGGL(k_mlp_gate, dim3(grid_of(kRegions, 256)), dim3(256), 0, s, (const int32_t*)c->reg_total,
+                               (const int32_t*)c->reg_bad, c->reg_gate, c->mlp_cnt);
+        }
+        hipLaunchKernelGGL(k_density_fallback, dim3(grid_of(vcap, 256)), dim3(256), 0, s, c->V,
+                           (const int32_t*)&cnt->n_vertices, (const int32_t*)c->reg_gate,
+                           (const int32_t*)c->oct_nodes, (const OctState*)c->oct_states, P0,
+                           (const OctDyn*)c->oct_dyn, c->mlp_cnt);
+        prof_end(c, s);
+    } else {
+        TIMED(K_DENSITY, hipLaunchKernelGGL(k_density, dim3(grid_of(vcap, 256)), dim3(256), 0, s, A, c->V,
+                                            (const int32_t*)&cnt->n_vertices, (const int32_t*)c->oct_nodes,
+                                            (const OctState*)c->oct_states, (const OctParams*)c->oct_prm_dev,
+                                            (const OctDyn*)c->oct_dyn));
+    }
     TIMED(K_NEE, nee(c, A, im, s));
     if (c->photons && L >= 3) {
         // merge grid over this iteration's view vertices
@@ -1656,6 +1864,25 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
                                          (const float4*)c->ev0, (const float4*)c->ev1,
                                          (const int32_t*)&cnt->n_events, (const float*)c->V.rho, im));
     hipLaunchKernelGGL(k_iter_end, dim3(1), dim3(1), 0, s, cnt);
+    // learned density, training iterations: this iteration's vertices with
+    // rho > 0 form the pool, then Adam steps on batches drawn from it
+    if (c->mlp_mode && !model) {
+        const OctParams& P0 = c->oct_prm[0];
+        const neb_mlp_params& M = c->mcfg;
+        prof_begin(c, K_MLP_TRAIN, s);
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, c->tcount, 0, (int64_t)1);
+        hipLaunchKernelGGL(k_mlp_collect, dim3(grid_of(vcap, 256)), dim3(256), 0, s, c->V,
+                           (const int32_t*)&cnt->n_vertices, c->tpos, c->tnrm, c->ttgt, c->tcount);
+        if (it == 1) HIP_TRY(mlp_norm_from_pool(c->mlp, c->ttgt, c->tcount, (int32_t)vcap, s));
+        hipLaunchKernelGGL(k_fill_f32, dim3(1), dim3(64), 0, s, c->mlp.loss, 0.f, (int64_t)1);
+        for (int k = 0; k < M.steps_per_iteration; ++k) {
+            HIP_TRY(mlp_gradient(c->mlp, c->tpos, 3, c->tnrm, 3, c->ttgt, c->tcount, (int32_t)vcap, M.batch, 1, M.seed,
+                                 0x4D4C5031u, &P0, s));
+            HIP_TRY(mlp_adam(c->mlp, M.lr, M.beta1, M.beta2, M.eps, s));
+        }
+        prof_end(c, s);
+        c->last_train_steps = M.steps_per_iteration;
+    }
     HIP_TRY(hipGetLastError());
     return NEB_OK;
 }
@@ -1693,7 +1920,7 @@ static neb_status capture(neb_ctx c) {
 static neb_status render_n(neb_ctx c, int32_t n_iterations, hipStream_t s) {
     for (int i = 0; i < n_iterations; ++i) {
         bool record = c->recs && c->first_iter_recorded == 0;
-        if (c->use_graph && !c->prof_on && !record) {
+        if (c->use_graph && !c->prof_on && !record && !c->mlp_mode) {
             neb_status st = capture(c);
             if (st != NEB_OK) return st;
             HIP_TRY(hipGraphLaunch(c->gexec, s));
@@ -2072,6 +2299,175 @@ extern "C" void neb_destroy(neb_ctx c) {
     if (!c) return;
     (void)hipDeviceSynchronize();
     destroy_ctx(c);
+}
+
+// ---------------------------------------------------------------------------
+// learned density C ABI
+// ---------------------------------------------------------------------------
+static neb_status check_mlp_params(const neb_mlp_params& m) {
+    if (m.train_iterations < 1 || m.train_iterations > 1000)
+        return fail(NEB_ERR_INVALID_ARG, "train_iterations out of range (1..1000)");
+    if (m.steps_per_iteration < 0 || m.steps_per_iteration > 100000)
+        return fail(NEB_ERR_INVALID_ARG, "steps_per_iteration out of range (0..100000)");
+    if (m.batch < 16 || m.batch > (1 << 20)) return fail(NEB_ERR_INVALID_ARG, "batch out of range (16..2^20)");
+    if (!(m.lr > 0.f) || !(m.beta1 >= 0.f && m.beta1 < 1.f) || !(m.beta2 >= 0.f && m.beta2 < 1.f) || !(m.eps > 0.f) ||
+        !std::isfinite(m.lr) || !std::isfinite(m.eps))
+        return fail(NEB_ERR_INVALID_ARG, "Adam settings out of range");
+    if (m.probe_every < 1 || m.probes < 1 || m.probes > (1 << 24))
+        return fail(NEB_ERR_INVALID_ARG, "probe settings out of range");
+    if (!(m.max_rel_error > 0.f) || !std::isfinite(m.max_rel_error))
+        return fail(NEB_ERR_INVALID_ARG, "max_rel_error must be > 0");
+    return NEB_OK;
+}
+
+extern "C" neb_status neb_configure_mlp(neb_ctx c, const neb_mlp_params* params) {
+    if (!c) return fail(NEB_ERR_INVALID_ARG, "null context");
+    if (!c->mlp_mode) return fail(NEB_ERR_STATE, "context was not created with NEB_DENSITY_MLP");
+    neb_mlp_params m;
+    if (params) m = *params;
+    else mlp_defaults(m);
+    neb_status st = check_mlp_params(m);
+    if (st != NEB_OK) return st;
+    HIP_TRY(hipDeviceSynchronize());
+    if (m.batch > c->mlp.max_batch) {
+        mlp_free(c->mlp);
+        hipError_t e = mlp_alloc(c->mlp, m.batch);
+        if (e != hipSuccess) {
+            mlp_free(c->mlp);
+            (void)mlp_alloc(c->mlp, c->mcfg.batch);
+            return oom_or_device(e, "neb_configure_mlp");
+        }
+    }
+    c->mcfg = m;
+    if (c->ready) return neb_reset(c);
+    return NEB_OK;
+}
+
+extern "C" neb_status neb_get_mlp_status(neb_ctx c, neb_mlp_status* out) {
+    if (!c || !out) return fail(NEB_ERR_INVALID_ARG, "null pointer");
+    if (!c->mlp_mode) return fail(NEB_ERR_STATE, "context was not created with NEB_DENSITY_MLP");
+    HIP_TRY(hipStreamSynchronize(c->last_stream));
+    unsigned long long mc[kMlpCnt];
+    MlpNorm nm;
+    float loss = 0.f;
+    HIP_TRY(hipMemcpy(mc, c->mlp_cnt, sizeof(mc), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&nm, c->mlp.norm, sizeof(nm), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&loss, c->mlp.loss, sizeof(loss), hipMemcpyDeviceToHost));
+    std::memset(out, 0, sizeof(*out));
+    out->phase = c->iter > c->mcfg.train_iterations ? 1 : 0;
+    out->adam_steps = c->mlp.step;
+    double denom = (double)c->last_train_steps * (double)c->mcfg.batch;
+    out->last_loss = denom > 0 ? (double)loss / denom : 0.0;
+    out->mu = nm.mu;
+    out->sigma = nm.sigma;
+    out->probes = (int64_t)mc[kMlpCntProbes];
+    out->probes_bad = (int64_t)mc[kMlpCntBad];
+    out->regions_probed = (int64_t)mc[kMlpCntProbed];
+    out->regions_disabled = (int64_t)mc[kMlpCntDisabled];
+    out->fallback_queries = (int64_t)mc[kMlpCntFallback];
+    return NEB_OK;
+}
+
+extern "C" neb_status neb_get_mlp_weights(neb_ctx c, float* params) {
+    if (!c || !params) return fail(NEB_ERR_INVALID_ARG, "null pointer");
+    if (!c->mlp_mode) return fail(NEB_ERR_STATE, "context was not created with NEB_DENSITY_MLP");
+    HIP_TRY(hipStreamSynchronize(c->last_stream));
+    HIP_TRY(hipMemcpy(params, c->mlp.theta, 4 * (size_t)kMlpParams, hipMemcpyDeviceToHost));
+    return NEB_OK;
+}
+
+struct neb_mlp_s {
+    Mlp m;
+};
+
+extern "C" neb_status neb_mlp_create(const float* init, uint32_t seed, int32_t max_batch, neb_mlp* out) {
+    if (!out) return fail(NEB_ERR_INVALID_ARG, "null pointer");
+    *out = nullptr;
+    if (max_batch < 1 || max_batch > (1 << 20)) return fail(NEB_ERR_INVALID_ARG, "max_batch out of range (1..2^20)");
+    std::vector<float> w;
+    if (init) {
+        w.assign(init, init + kMlpParams);
+        for (float x : w)
+            if (!std::isfinite(x)) return fail(NEB_ERR_INVALID_ARG, "non-finite initial parameter");
+    } else {
+        w = mlp_he_init(seed);
+    }
+    neb_mlp h = new neb_mlp_s();
+    hipError_t e = mlp_alloc(h->m, max_batch);
+    if (e == hipSuccess) e = mlp_set_weights(h->m, w.data(), nullptr);
+    if (e == hipSuccess) e = mlp_set_norm(h->m, 0.f, 1.f, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        mlp_free(h->m);
+        delete h;
+        return oom_or_device(e, "neb_mlp_create");
+    }
+    *out = h;
+    return NEB_OK;
+}
+
+extern "C" neb_status neb_mlp_set_normalization(neb_mlp h, float mu, float sigma, void* stream) {
+    if (!h) return fail(NEB_ERR_INVALID_ARG, "null model");
+    if (!std::isfinite(mu) || !(sigma > 0.f) || !std::isfinite(sigma))
+        return fail(NEB_ERR_INVALID_ARG, "mu must be finite and sigma > 0");
+    HIP_TRY(mlp_set_norm(h->m, mu, sigma, (hipStream_t)stream));
+    return NEB_OK;
+}
+
+extern "C" neb_status neb_mlp_infer(neb_mlp h, const float* q, const float* nrm, int32_t n, float* out, void* stream) {
+    if (!h || ((!q || !nrm || !out) && n > 0)) return fail(NEB_ERR_INVALID_ARG, "null pointer");
+    if (n < 0) return fail(NEB_ERR_INVALID_ARG, "negative count");
+    HIP_TRY(mlp_infer(h->m, q, 3, nrm, 3, nullptr, n, nullptr, out, 0, (hipStream_t)stream));
+    return NEB_OK;
+}
+
+static neb_status mlp_batch_grad(neb_mlp h, const float* q, const float* nrm, const float* t, int32_t n,
+                                 hipStream_t s) {
+    if (!h || !q || !nrm || !t) return fail(NEB_ERR_INVALID_ARG, "null pointer");
+    if (n < 1 || n > h->m.max_batch) return fail(NEB_ERR_INVALID_ARG, "batch size out of range (1..max_batch)");
+    HIP_TRY(hipMemsetAsync(h->m.loss, 0, sizeof(float), s));
+    HIP_TRY(mlp_gradient(h->m, q, 3, nrm, 3, t, nullptr, n, n, 0, 0u, 0u, nullptr, s));
+    return NEB_OK;
+}
+
+extern "C" neb_status neb_mlp_gradient(neb_mlp h, const float* q, const float* nrm, const float* log_rho, int32_t n,
+                                       float* grad, float* loss, void* stream) {
+    if (!grad || !loss) return fail(NEB_ERR_INVALID_ARG, "null pointer");
+    hipStream_t s = (hipStream_t)stream;
+    neb_status st = mlp_batch_grad(h, q, nrm, log_rho, n, s);
+    if (st != NEB_OK) return st;
+    HIP_TRY(hipMemcpyAsync(grad, h->m.grad, 4 * (size_t)kMlpParams, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemsetAsync(h->m.grad, 0, 4 * (size_t)kMlpParams, s));
+    float sum = 0.f;
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipMemcpy(&sum, h->m.loss, sizeof(float), hipMemcpyDeviceToHost));
+    *loss = sum / (float)n;
+    return NEB_OK;
+}
+
+extern "C" neb_status neb_mlp_train_step(neb_mlp h, const float* q, const float* nrm, const float* log_rho, int32_t n,
+                                         float lr, float beta1, float beta2, float eps, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (!(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return fail(NEB_ERR_INVALID_ARG, "Adam settings out of range");
+    neb_status st = mlp_batch_grad(h, q, nrm, log_rho, n, s);
+    if (st != NEB_OK) return st;
+    HIP_TRY(mlp_adam(h->m, lr, beta1, beta2, eps, s));
+    return NEB_OK;
+}
+
+extern "C" neb_status neb_mlp_get_params(neb_mlp h, float* params) {
+    if (!h || !params) return fail(NEB_ERR_INVALID_ARG, "null pointer");
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(params, h->m.theta, 4 * (size_t)kMlpParams, hipMemcpyDeviceToHost));
+    return NEB_OK;
+}
+
+extern "C" void neb_mlp_destroy(neb_mlp h) {
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    mlp_free(h->m);
+    delete h;
 }
 
 // ---------------------------------------------------------------------------

@@ -14,7 +14,8 @@ LIB_PATH = os.path.join(_HERE, "libneb.so")
 _lib = None
 
 NEB_OK = 0
-DENSITY_OCTREE, DENSITY_OCTREE_ROBUST, DENSITY_ANALYTIC = 0, 1, 3
+DENSITY_OCTREE, DENSITY_OCTREE_ROBUST, DENSITY_MLP, DENSITY_ANALYTIC = 0, 1, 2, 3
+MLP_PARAMS = 13569
 FLAG_SINGLE_THREAD_OCTREE, FLAG_RECORD_PATHS, FLAG_NO_PHOTONS = 1, 2, 4
 
 # every symbol the header declares
@@ -25,6 +26,8 @@ EXPORTS = [
     "neb_query_density", "neb_get_stats", "neb_get_path_records", "neb_get_octree", "neb_get_scene_octree",
     "neb_profile_kernels", "neb_get_kernel_profile", "neb_reset",
     "neb_destroy", "neb_status_string", "neb_last_error",
+    "neb_configure_mlp", "neb_get_mlp_status", "neb_get_mlp_weights", "neb_mlp_create", "neb_mlp_set_normalization",
+    "neb_mlp_infer", "neb_mlp_gradient", "neb_mlp_train_step", "neb_mlp_get_params", "neb_mlp_destroy",
     "neb_octree_create", "neb_octree_set_iteration", "neb_octree_increment", "neb_octree_density",
     "neb_octree_clear_counters", "neb_octree_export", "neb_octree_destroy",
 ]
@@ -59,6 +62,28 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class MlpParams(ctypes.Structure):
+    _fields_ = [("train_iterations", ctypes.c_int32), ("steps_per_iteration", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("probe_every", ctypes.c_int32),
+                ("probes", ctypes.c_int32), ("max_rel_error", ctypes.c_float), ("seed", ctypes.c_uint32)]
+
+
+MLP_DEFAULTS = dict(train_iterations=4, steps_per_iteration=250, batch=65536, lr=2e-3, beta1=0.9, beta2=0.999,
+                    eps=1e-8, probe_every=8, probes=4096, max_rel_error=0.1, seed=1)
+
+
+class MlpStatus(ctypes.Structure):
+    _fields_ = [("phase", ctypes.c_int32), ("adam_steps", ctypes.c_int64), ("last_loss", ctypes.c_double),
+                ("mu", ctypes.c_float), ("sigma", ctypes.c_float), ("probes", ctypes.c_int64),
+                ("probes_bad", ctypes.c_int64), ("regions_probed", ctypes.c_int64),
+                ("regions_disabled", ctypes.c_int64), ("fallback_queries", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: (float(getattr(self, k)) if t in (ctypes.c_double, ctypes.c_float) else int(getattr(self, k)))
+                for k, t in self._fields_}
 
 
 class KernelTime(ctypes.Structure):
@@ -104,6 +129,17 @@ def lib():
             "neb_destroy": ([_P], None),
             "neb_status_string": ([i32], ctypes.c_char_p),
             "neb_last_error": ([], ctypes.c_char_p),
+            "neb_configure_mlp": ([_P, ctypes.POINTER(MlpParams)], i32),
+            "neb_get_mlp_status": ([_P, ctypes.POINTER(MlpStatus)], i32),
+            "neb_get_mlp_weights": ([_P, _P], i32),
+            "neb_mlp_create": ([_P, ctypes.c_uint32, i32, ctypes.POINTER(_P)], i32),
+            "neb_mlp_set_normalization": ([_P, ctypes.c_float, ctypes.c_float, _P], i32),
+            "neb_mlp_infer": ([_P, _P, _P, i32, _P, _P], i32),
+            "neb_mlp_gradient": ([_P, _P, _P, _P, i32, _P, ctypes.POINTER(ctypes.c_float), _P], i32),
+            "neb_mlp_train_step": ([_P, _P, _P, _P, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float, _P], i32),
+            "neb_mlp_get_params": ([_P, _P], i32),
+            "neb_mlp_destroy": ([_P], None),
             "neb_octree_create": ([_P, _P, i32, ctypes.POINTER(_P)], i32),
             "neb_octree_set_iteration": ([_P, i32], i32),
             "neb_octree_increment": ([_P, _P, i32, i32, _P], i32),
@@ -294,6 +330,23 @@ class BatchRenderer:
     def reset(self):
         _check(lib().neb_reset(self.h))
 
+    def configure_mlp(self, **kw):
+        """Learned-density settings (NEB_DENSITY_MLP contexts); restarts."""
+        d = dict(MLP_DEFAULTS)
+        d.update(kw)
+        p = MlpParams(**d)
+        _check(lib().neb_configure_mlp(self.h, ctypes.byref(p)))
+
+    def mlp_status(self):
+        st = MlpStatus()
+        _check(lib().neb_get_mlp_status(self.h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def mlp_weights(self):
+        out = np.zeros(MLP_PARAMS, np.float32)
+        _check(lib().neb_get_mlp_weights(self.h, _np_ptr(out)))
+        return out
+
 
 class Renderer(BatchRenderer):
     """One rendering context of one scene on the current device (a batch of
@@ -317,6 +370,56 @@ class Renderer(BatchRenderer):
         out = np.zeros(n, RECORD_DTYPE)
         _check(lib().neb_get_path_records(self.h, _np_ptr(out), n))
         return out.reshape(self.params.width * self.params.height, self.params.max_path_len)
+
+
+class Mlp:
+    """Standalone learned-density model on the current device."""
+
+    def __init__(self, init=None, seed=1, max_batch=65536):
+        h = _P()
+        w = None if init is None else np.ascontiguousarray(init, np.float32)
+        if w is not None and w.size != MLP_PARAMS:
+            raise NebError("init must hold MLP_PARAMS values")
+        _check(lib().neb_mlp_create(_np_ptr(w) if w is not None else None, int(seed), int(max_batch),
+                                    ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().neb_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_normalization(self, mu, sigma, stream=None):
+        _check(lib().neb_mlp_set_normalization(self.h, float(mu), float(sigma), _stream(stream)))
+
+    def infer(self, q, nrm, stream=None):
+        import torch
+        out = torch.empty(q.shape[0], dtype=torch.float32, device=q.device)
+        _check(lib().neb_mlp_infer(self.h, _dev_ptr(q), _dev_ptr(nrm), q.shape[0], _dev_ptr(out), _stream(stream)))
+        return out
+
+    def gradient(self, q, nrm, log_rho, stream=None):
+        import torch
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=q.device)
+        loss = ctypes.c_float()
+        _check(lib().neb_mlp_gradient(self.h, _dev_ptr(q), _dev_ptr(nrm), _dev_ptr(log_rho), q.shape[0],
+                                      _dev_ptr(g), ctypes.byref(loss), _stream(stream)))
+        return g, float(loss.value)
+
+    def train_step(self, q, nrm, log_rho, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(lib().neb_mlp_train_step(self.h, _dev_ptr(q), _dev_ptr(nrm), _dev_ptr(log_rho), q.shape[0],
+                                        float(lr), float(beta1), float(beta2), float(eps), _stream(stream)))
+
+    def params(self):
+        out = np.zeros(MLP_PARAMS, np.float32)
+        _check(lib().neb_mlp_get_params(self.h, _np_ptr(out)))
+        return out
 
 
 class DeviceOctree:

@@ -66,3 +66,10 @@ def test_invalid_arguments_are_rejected_without_a_device():
     assert L.neb_set_launch_config(None, None) == -1
     assert L.neb_get_scene_image(None, 0, None, 0, None) == -1
     assert L.neb_set_batch_scene(None, 0, None, 0, None, None, 0, None, 0, None, 0, None) == -1
+    mh = ctypes.c_void_p()
+    assert L.neb_mlp_create(None, 1, 0, ctypes.byref(mh)) == -1          # max_batch < 1
+    assert L.neb_mlp_infer(None, None, None, 1, None, None) == -1
+    assert L.neb_configure_mlp(None, None) == -1
+    one[1].spp = 0
+    one[0].density_mode = one[1].density_mode = 2
+    assert L.neb_create_batch(one, 2, ctypes.byref(h)) == -1          # learned density: one scene only
