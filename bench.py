@@ -163,7 +163,8 @@ def batch_comparison(stream, cfg_trials=1):
     for sc in scenes:
         R = neb.Renderer(sc, spp=sc.spp)
         # the batch's stack is deeper than every scene's BVH
-        R.set_launch_config(cfg["bvh_stack"], cfg["trace_blocks_per_cu"], cfg["photon_blocks_per_cu"])
+        R.set_launch_config(cfg["bvh_stack"], cfg["trace_blocks_per_cu"], cfg["photon_blocks_per_cu"],
+                            cfg["photon_order"])
         t_seq += timed(lambda: R.render(sc.spp, stream=stream))
         R.close()
     return {"scenes": len(scenes), "triangles": int(sum(s.n_tris for s in scenes)),
@@ -184,6 +185,8 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event pass")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-scene batching comparison")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--launch-config", default=None,
+                    help="bvh_stack,trace_blocks_per_cu,photon_blocks_per_cu,photon_order instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB device copy first (for counter calibration)")
     args = ap.parse_args()
@@ -198,16 +201,23 @@ def main():
 
     torch.cuda.set_device(0)
     if args.copy_calibration:
+        # one elementwise kernel that reads 256 MiB and writes 256 MiB
         a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.mul(a, 2.0, out=b)
         torch.cuda.synchronize()
         del a, b
     sc = room()
     npix = sc.width * sc.height
     R = neb.Renderer(sc)
     stream = torch.cuda.current_stream()
-    launch_cfg = R.launch_config() if args.no_autotune else R.autotune(2, stream=stream)
+    if args.launch_config:
+        R.set_launch_config(*[int(x) for x in args.launch_config.split(",")])
+        launch_cfg = R.launch_config()
+    elif args.no_autotune:
+        launch_cfg = R.launch_config()
+    else:
+        launch_cfg = R.autotune(2, stream=stream)
     # warm-up on a throw-away progression, then start the 16-spp render afresh
     R.render(args.warmup, stream=stream)
     torch.cuda.synchronize()

@@ -88,6 +88,8 @@ typedef struct {
                                      0 = one block per 64 queue slots */
     int32_t photon_blocks_per_cu; /* photon-merge blocks (one wave each) per compute unit, 0..64;
                                      0 = one block per 256 queue slots */
+    int32_t photon_order;         /* 1: merge photons in the spatial (Morton) order of their hits,
+                                     each XCD taking a contiguous share; 0: queue order */
 } neb_launch_config;
 
 /* One material per entry; emission is radiance leaving the front side of

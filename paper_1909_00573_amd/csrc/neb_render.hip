@@ -241,15 +241,49 @@ __global__ void __launch_bounds__(256) k_camera(RenderArgs A, PathQ q) {
     wave_add_u64(&A.cnt->paths, started);
 }
 
+// Spatial bins of photon hits: a 2^bits-per-axis grid over each scene's
+// octree box in Morton order (neighbouring bins are neighbouring boxes),
+// scenes one after another, and one last bin for the rays that missed.
+struct HitBins {
+    int32_t* bin;          // per ray: its bin (null: no binning)
+    int32_t* count;        // per bin: rays (returns to zero after the scatter)
+    const OctParams* prm;  // per scene: the box
+    int32_t bits;          // per axis
+    int32_t n_bins;        // bins of all scenes; the miss bin is n_bins
+};
+
+__device__ __forceinline__ uint32_t spread3(uint32_t v) {  // bits b -> 3b
+    v &= 0x3FF;
+    v = (v | (v << 16)) & 0x030000FF;
+    v = (v | (v << 8)) & 0x0300F00F;
+    v = (v | (v << 4)) & 0x030C30C3;
+    v = (v | (v << 2)) & 0x09249249;
+    return v;
+}
+
+__device__ __forceinline__ int hit_bin(const HitBins& B, int scene, f3 y) {
+    const OctParams& P = B.prm[scene];
+    const float res = (float)(1 << B.bits);
+    float v[3] = {y.x, y.y, y.z};
+    uint32_t c[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float q = (v[k] - P.min_bound[k]) * P.size_inv[k];
+        c[k] = (uint32_t)min((int)res - 1, max(0, (int)(q * res)));
+    }
+    return (scene << (3 * B.bits)) + (int)(spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2));
+}
+
 // closest hit for a queue of rays given as (origin, direction) float4 arrays
 // (the direction's w is a tag word naming the scene); also clears the
-// counter of the queue the next kernel appends to
+// counter of the queue the next kernel appends to, and optionally counts
+// the hits per spatial bin
 template <int kStack>
 __global__ void __launch_bounds__(kTraceBlock) k_extend(SceneView S, const SceneInfo* sc,
                                                         const float4* __restrict__ org,
                                                         const float4* __restrict__ dir, const int32_t* count,
                                                         int32_t* next_count, int2* __restrict__ hits,
-                                                        unsigned long long* rays, Counters* cnt) {
+                                                        unsigned long long* rays, Counters* cnt, HitBins B) {
     __shared__ int stack[kStack * kTraceBlock];
     int n = *count;
     if (blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
@@ -257,9 +291,16 @@ __global__ void __launch_bounds__(kTraceBlock) k_extend(SceneView S, const Scene
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         float t;
         float4 d = dir[i];
-        int root = sc[tag_scene(fbits(d.w))].bvh_root;
-        int prim = trace<false, kStack>(S, root, xyz(org[i]), xyz(d), INFINITY, t, stack + threadIdx.x, nodes, tris);
+        const int sid = tag_scene(fbits(d.w));
+        int root = sc[sid].bvh_root;
+        f3 o = xyz(org[i]);
+        int prim = trace<false, kStack>(S, root, o, xyz(d), INFINITY, t, stack + threadIdx.x, nodes, tris);
         hits[i] = make_int2(fbits(t), prim);
+        if (B.bin) {
+            int b = prim >= 0 ? hit_bin(B, sid, o + xyz(d) * t) : B.n_bins;
+            B.bin[i] = b;
+            atomicAdd(&B.count[b], 1);
+        }
         ++traced;
     }
     wave_add_u64(rays, traced);
@@ -654,6 +695,18 @@ static void scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* 
     hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nb), dim3(kScanBlock), 0, s, out, scratch, n);
 }
 
+// photon order by bin (count -> exclusive scan -> this scatter); the bin
+// counts return to zero
+__global__ void __launch_bounds__(256) k_bin_scatter(const int32_t* __restrict__ bin, const int32_t* n_dev,
+                                                     int32_t* count, const int32_t* __restrict__ start,
+                                                     int32_t* __restrict__ order) {
+    int n = *n_dev;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int b = bin[i];
+        order[start[b] + atomicSub(&count[b], 1) - 1] = i;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // photon bounce: merge with view vertices around the hit, then scatter.
 // One photon per lane (many independent candidate streams in flight, which
@@ -664,8 +717,13 @@ static void scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* 
 // with every lane busy instead of with the ~10 % of lanes that accepted.
 // One wave per block.
 // ---------------------------------------------------------------------------
+// Photons are taken in the spatial order `order` (null: queue order).  Blocks
+// b, b + 8, b + 16, ... run on one XCD (round-robin dispatch), so each XCD
+// takes one contiguous eighth of the ordered photons: neighbouring photons
+// then share that XCD's L2 for their cells and candidates.
 __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const int32_t* count_in, const int2* hits,
-                                               PhotonQ out, int32_t* count_out, Grid G, Images img) {
+                                               PhotonQ out, int32_t* count_out, Grid G, Images img,
+                                               const int32_t* __restrict__ order) {
     __shared__ int2 queue[128];
     __shared__ float4 tp[64][2];  // per lane's photon: (-d, h*U), (Phi / (pi r^2), deepest mergeable depth)
     const int lane = threadIdx.x;
@@ -702,9 +760,20 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
         }
     };
 
-    for (int base = blockIdx.x * 64; base < n; base += gridDim.x * 64) {
+    const int nchunk = (n + 63) >> 6;
+    const int nblk = gridDim.x;
+    int c_begin = blockIdx.x, c_end = nchunk, c_step = nblk;
+    if (nblk >= 8) {
+        const int x = blockIdx.x & 7, seg = (nchunk + 7) >> 3;
+        c_begin = x * seg + (blockIdx.x >> 3);
+        c_end = min(nchunk, (x + 1) * seg);
+        c_step = (nblk - x + 7) >> 3;  // blocks on this XCD
+    }
+    for (int chunk = c_begin; chunk < c_end; chunk += c_step) {
+        const int base = chunk * 64;
         int i = base + lane;
         bool valid = i < n;
+        if (valid && order) i = order[i];
         int2 h = valid ? hits[i] : make_int2(0, -1);
         float4 b0 = make_float4(0.f, 0.f, 0.f, 0.f), b1 = b0, b2 = b0;
         float U = 0.f;
@@ -774,35 +843,43 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
         int total = pre[8];
         cands += (unsigned)total;
         __syncthreads();
-        for (int k = 0;; ++k) {
-            bool act = k < total;
-            if (!__any(act)) break;
-            bool acc = false;
-            int vid = 0;
-            if (act) {
-                int e = 0;
+        // four candidates per lane per step: their loads are independent
+        constexpr int kU = 4;
+        for (int k = 0;; k += kU) {
+            if (!__any(k < total)) break;
+            int ev[kU];
+            float4 cd[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int kk = k + u;
+                int e = -1;
 #pragma unroll
                 for (int c = 0; c < 8; ++c)
-                    if (k >= pre[c] && k < pre[c + 1]) e = lo[c] + (k - pre[c]);
-                float4 cd = G.sorted[e];
-                f3 dv = xyz(cd) - y;
-                // a bucket may also hold another scene's cell
-                acc = dot3(dv, dv) < r2 && fbits(cd.w) == sid;
-                vid = e;  // the record index: its merge data sits at G.mrec[4 e]
+                    if (kk >= pre[c] && kk < pre[c + 1]) e = lo[c] + (kk - pre[c]);
+                ev[u] = kk < total ? e : -1;
             }
-            unsigned long long m = __ballot(acc);
-            if (m) {
-                if (acc) queue[qn + __popcll(m & below)] = make_int2(lane, vid);
-                qn += __popcll(m);
-                if (qn >= 64) {
-                    __syncthreads();
-                    flush(64);
-                    __syncthreads();
-                    int2 rest = lane < qn - 64 ? queue[64 + lane] : make_int2(0, 0);
-                    __syncthreads();
-                    if (lane < qn - 64) queue[lane] = rest;
-                    qn -= 64;
-                    __syncthreads();
+#pragma unroll
+            for (int u = 0; u < kU; ++u) cd[u] = ev[u] >= 0 ? G.sorted[ev[u]] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                f3 dv = xyz(cd[u]) - y;
+                // a bucket may also hold another scene's cell
+                bool acc = ev[u] >= 0 && dot3(dv, dv) < r2 && fbits(cd[u].w) == sid;
+                // the record index: its merge data sits at G.mrec[4 e]
+                unsigned long long m = __ballot(acc);
+                if (m) {
+                    if (acc) queue[qn + __popcll(m & below)] = make_int2(lane, ev[u]);
+                    qn += __popcll(m);
+                    if (qn >= 64) {
+                        __syncthreads();
+                        flush(64);
+                        __syncthreads();
+                        int2 rest = lane < qn - 64 ? queue[64 + lane] : make_int2(0, 0);
+                        __syncthreads();
+                        if (lane < qn - 64) queue[lane] = rest;
+                        qn -= 64;
+                        __syncthreads();
+                    }
                 }
             }
         }
@@ -1017,9 +1094,10 @@ struct HostScene {
 
 // launch shapes picked by neb_autotune (or set by the caller)
 struct LaunchCfg {
-    int stack = 48;      // LDS traversal stack entries per lane: 32, 48 or 64
-    int trace_bpc = 0;   // traversal blocks (one wave each) per CU; 0 = one block per 64 queue slots
-    int photon_bpc = 0;  // photon-merge blocks (one wave each) per CU; 0 = one block per 256 queue slots
+    int stack = 48;        // LDS traversal stack entries per lane: 32, 48 or 64
+    int trace_bpc = 0;     // traversal blocks (one wave each) per CU; 0 = one block per 64 queue slots
+    int photon_bpc = 0;    // photon-merge blocks (one wave each) per CU; 0 = one block per 256 queue slots
+    int photon_order = 1;  // merge photons in the spatial order of their hits
 };
 
 struct neb_ctx_s {
@@ -1057,6 +1135,9 @@ struct neb_ctx_s {
     int32_t* slots = nullptr;
     neb_path_record* recs = nullptr;
     Grid G{};
+    // spatial order of photon hits
+    int32_t *pbin = nullptr, *porder = nullptr, *bcount = nullptr, *bstart = nullptr, *bsums = nullptr;
+    int32_t bin_bits = 0, n_bins = 0;
     float* img = nullptr;  // e, E, P accumulators, 3 * npix floats each
     Counters* cnt = nullptr;
     int32_t iter = 0;
@@ -1089,11 +1170,11 @@ struct neb_ctx_s {
 
 enum KernelId {
     K_CAMERA, K_EXTEND_CAMERA, K_SHADE, K_OCTREE_INSERT, K_DENSITY, K_NEE, K_GRID_BUILD, K_EXTEND_PHOTON, K_PHOTON,
-    K_FINALIZE, K_MLP_TRAIN, K_MISC, K_COUNT
+    K_FINALIZE, K_MLP_TRAIN, K_PHOTON_ORDER, K_MISC, K_COUNT
 };
 static const char* kKernelNames[K_COUNT] = {"camera", "extend_camera", "shade", "octree_insert", "density", "nee",
                                             "grid_build", "extend_photon", "photon_merge", "finalize", "mlp_train",
-                                            "misc"};
+                                            "photon_order", "misc"};
 
 static void prof_harvest(neb_ctx c) {
     if (c->prof_used == 0) return;
@@ -1362,6 +1443,18 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
     ALLOC(c->defer_cnt, 3);
     ALLOC(c->sc_dev, n_scenes);
     ALLOC(c->pix_base_dev, n_scenes + 1);
+    {
+        // about 2^18 bins over all scenes, 2..6 bits per axis
+        int bits = 6;
+        while (bits > 2 && ((int64_t)n_scenes << (3 * bits)) > (1 << 18)) --bits;
+        c->bin_bits = bits;
+        c->n_bins = n_scenes << (3 * bits);
+    }
+    ALLOC(c->pbin, vcap);
+    ALLOC(c->porder, vcap);
+    ALLOC(c->bcount, c->n_bins + 2);
+    ALLOC(c->bstart, c->n_bins + 2);
+    ALLOC(c->bsums, scan_scratch(c->n_bins + 2));
     if (c->density_mode == NEB_DENSITY_MLP) {
         c->mlp_mode = true;
         mlp_defaults(c->mcfg);
@@ -1378,6 +1471,8 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
 #undef ALLOC
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(gkeys, 256)), dim3(256), 0, nullptr, c->G.count, 0, gkeys);
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(c->n_bins + 2, 256)), dim3(256), 0, nullptr, c->bcount, 0,
+                           (int64_t)c->n_bins + 2);
         hipLaunchKernelGGL(k_fill_f32, dim3(grid_of(9 * npix, 256)), dim3(256), 0, nullptr, c->img, 0.f, 9 * npix);
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, nullptr, (int32_t*)c->cnt, 0,
                            (int64_t)(sizeof(Counters) / 4));
@@ -1737,16 +1832,24 @@ static RenderArgs make_args(neb_ctx c) {
 
 template <int kStack>
 static void launch_extend(neb_ctx c, int64_t cap, const float4* org, const float4* dir, int32_t* count, int32_t* next,
-                          unsigned long long* rays, hipStream_t s) {
+                          unsigned long long* rays, const HitBins& B, hipStream_t s) {
     hipLaunchKernelGGL(k_extend<kStack>, dim3(trace_grid(c, cap)), dim3(kTraceBlock), 0, s, c->view,
-                       (const SceneInfo*)c->sc_dev, org, dir, (const int32_t*)count, next, c->hits, rays, c->cnt);
+                       (const SceneInfo*)c->sc_dev, org, dir, (const int32_t*)count, next, c->hits, rays, c->cnt, B);
 }
 
 static void extend(neb_ctx c, int64_t cap, const float4* org, const float4* dir, int32_t* count, int32_t* next,
-                   unsigned long long* rays, hipStream_t s) {
-    if (c->cfg.stack == 32) launch_extend<32>(c, cap, org, dir, count, next, rays, s);
-    else if (c->cfg.stack == 48) launch_extend<48>(c, cap, org, dir, count, next, rays, s);
-    else launch_extend<64>(c, cap, org, dir, count, next, rays, s);
+                   unsigned long long* rays, hipStream_t s, bool bin = false) {
+    HitBins B{};
+    if (bin) {
+        B.bin = c->pbin;
+        B.count = c->bcount;
+        B.prm = c->oct_prm_dev;
+        B.bits = c->bin_bits;
+        B.n_bins = c->n_bins;
+    }
+    if (c->cfg.stack == 32) launch_extend<32>(c, cap, org, dir, count, next, rays, B, s);
+    else if (c->cfg.stack == 48) launch_extend<48>(c, cap, org, dir, count, next, rays, B, s);
+    else launch_extend<64>(c, cap, org, dir, count, next, rays, B, s);
 }
 
 static void nee(neb_ctx c, const RenderArgs& A, Images im, hipStream_t s) {
@@ -1852,11 +1955,21 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
                                                 : grid_of(vcap, 256);
         for (int j = 1; j <= L - 2; ++j) {
             int in = (j - 1) & 1, out = j & 1;
+            const bool ordered = c->cfg.photon_order != 0;
             TIMED(K_EXTEND_PHOTON, extend(c, vcap, c->pq[in].p0, c->pq[in].p1, &cnt->pcount[in], &cnt->pcount[out],
-                                          &cnt->photon_rays, s));
+                                          &cnt->photon_rays, s, ordered));
+            if (ordered) {
+                // photons in the spatial order of their hits
+                prof_begin(c, K_PHOTON_ORDER, s);
+                scan_exclusive(c->bcount, c->bstart, c->n_bins + 1, c->bsums, s);
+                hipLaunchKernelGGL(k_bin_scatter, dim3(grid_of(vcap, 256)), dim3(256), 0, s, (const int32_t*)c->pbin,
+                                   (const int32_t*)&cnt->pcount[in], c->bcount, (const int32_t*)c->bstart, c->porder);
+                prof_end(c, s);
+            }
             TIMED(K_PHOTON, hipLaunchKernelGGL(k_photon, dim3(pgrid), dim3(64), 0, s, A, c->pq[in],
                                                (const int32_t*)&cnt->pcount[in], (const int2*)c->hits, c->pq[out],
-                                               &cnt->pcount[out], c->G, im));
+                                               &cnt->pcount[out], c->G, im,
+                                               ordered ? (const int32_t*)c->porder : (const int32_t*)nullptr));
         }
     }
     // pass 3
@@ -2200,9 +2313,11 @@ static neb_status apply_config(neb_ctx c, const neb_launch_config& cfg) {
         return fail(NEB_ERR_INVALID_ARG, "trace_blocks_per_cu out of range for this stack");
     if (cfg.photon_blocks_per_cu < 0 || cfg.photon_blocks_per_cu > 64)
         return fail(NEB_ERR_INVALID_ARG, "photon_blocks_per_cu out of range (0..64)");
+    if (cfg.photon_order != 0 && cfg.photon_order != 1) return fail(NEB_ERR_INVALID_ARG, "photon_order must be 0 or 1");
     c->cfg.stack = cfg.bvh_stack;
     c->cfg.trace_bpc = cfg.trace_blocks_per_cu;
     c->cfg.photon_bpc = cfg.photon_blocks_per_cu;
+    c->cfg.photon_order = cfg.photon_order;
     drop_graph(c);
     return NEB_OK;
 }
@@ -2217,6 +2332,7 @@ extern "C" neb_status neb_get_launch_config(neb_ctx c, neb_launch_config* cfg) {
     cfg->bvh_stack = c->cfg.stack;
     cfg->trace_blocks_per_cu = c->cfg.trace_bpc;
     cfg->photon_blocks_per_cu = c->cfg.photon_bpc;
+    cfg->photon_order = c->cfg.photon_order;
     return NEB_OK;
 }
 
@@ -2249,7 +2365,7 @@ extern "C" neb_status neb_autotune(neb_ctx c, int32_t trial_iterations, void* st
     bool was_on = c->prof_on;
     c->prof_on = true;
     LaunchCfg keep = c->cfg;
-    neb_launch_config best{c->cfg.stack, c->cfg.trace_bpc, c->cfg.photon_bpc};
+    neb_launch_config best{c->cfg.stack, c->cfg.trace_bpc, c->cfg.photon_bpc, c->cfg.photon_order};
     st = render_n(c, 1, s);  // warm-up: octree and caches
     double best_ms = 1e300;
     const int trace_k[3] = {K_EXTEND_CAMERA, K_EXTEND_PHOTON, K_NEE};
@@ -2258,7 +2374,7 @@ extern "C" neb_status neb_autotune(neb_ctx c, int32_t trial_iterations, void* st
         if (stack <= c->forest_depth) continue;
         int maxb = lds_blocks_per_cu(stack);
         for (int b : {0, 4, 8, maxb}) {
-            neb_launch_config cfg{stack, b, best.photon_blocks_per_cu};
+            neb_launch_config cfg{stack, b, best.photon_blocks_per_cu, best.photon_order};
             double ms = 0.0;
             st = time_config(c, cfg, trial_iterations, trace_k, 3, s, ms);
             if (st != NEB_OK) break;
@@ -2270,16 +2386,20 @@ extern "C" neb_status neb_autotune(neb_ctx c, int32_t trial_iterations, void* st
         }
     }
     best_ms = 1e300;
-    const int photon_k[1] = {K_PHOTON};
-    for (int pb : {0, 8, 16, 32, 64}) {
-        if (st != NEB_OK) break;
-        neb_launch_config cfg{best.bvh_stack, best.trace_blocks_per_cu, pb};
-        double ms = 0.0;
-        st = time_config(c, cfg, trial_iterations, photon_k, 1, s, ms);
-        if (st != NEB_OK) break;
-        if (ms < best_ms) {
-            best_ms = ms;
-            best.photon_blocks_per_cu = pb;
+    // the photon stage: ordering (which also adds to the photon traversal) and the merge grid
+    const int photon_k[3] = {K_PHOTON, K_PHOTON_ORDER, K_EXTEND_PHOTON};
+    for (int order : {1, 0}) {
+        for (int pb : {0, 8, 16, 32, 64}) {
+            if (st != NEB_OK) break;
+            neb_launch_config cfg{best.bvh_stack, best.trace_blocks_per_cu, pb, order};
+            double ms = 0.0;
+            st = time_config(c, cfg, trial_iterations, photon_k, 3, s, ms);
+            if (st != NEB_OK) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best.photon_blocks_per_cu = pb;
+                best.photon_order = order;
+            }
         }
     }
     prof_clear(c);

@@ -181,10 +181,11 @@ def test_autotune_changes_speed_not_results(neb, batch_scenes):
     assert cfg["bvh_stack"] in (32, 48, 64)
     assert 0 <= cfg["trace_blocks_per_cu"] <= 20
     assert 0 <= cfg["photon_blocks_per_cu"] <= 64
+    assert cfg["photon_order"] in (0, 1)
     assert T.launch_config() == cfg
     assert T.stats()["iterations"] == 0  # reset after tuning
     F = neb.BatchRenderer(scenes, flags=neb.FLAG_SINGLE_THREAD_OCTREE, spp=spp)
-    F.set_launch_config(64, 4, 8)
+    F.set_launch_config(64, 4, 8, 1 - cfg["photon_order"])  # the other photon order
     T.render(3)
     F.render(3)
     for s in range(len(scenes)):
