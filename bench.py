@@ -8,8 +8,8 @@ a 20k-triangle glass sphere (IOR 1.5) on a table and four emissive spheres,
 512 x 512 pixels, path length 8, octree of 2^20 nodes, merge radius 0.02.
 The 16 steps after the warm-up reproduce the workload's 16 spp.
 
-Launch shapes are picked first by the library's autotuner (they change
-the speed, not the result).
+Launch shapes are the library's defaults (tuned for this workload), or
+tuned afresh with --autotune (they change the speed, not the result).
 
 Prints one JSON line with camera paths/s (value), photons/s, the roofline
 of the dominant kernel (HIP-event durations on the launch stream, the
@@ -184,7 +184,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event pass")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-scene batching comparison")
-    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the launch shapes on this workload first (default: the library's defaults)")
     ap.add_argument("--launch-config", default=None,
                     help="bvh_stack,trace_blocks_per_cu,photon_blocks_per_cu,photon_order instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -214,10 +215,10 @@ def main():
     if args.launch_config:
         R.set_launch_config(*[int(x) for x in args.launch_config.split(",")])
         launch_cfg = R.launch_config()
-    elif args.no_autotune:
-        launch_cfg = R.launch_config()
-    else:
+    elif args.autotune:
         launch_cfg = R.autotune(2, stream=stream)
+    else:
+        launch_cfg = R.launch_config()
     # warm-up on a throw-away progression, then start the 16-spp render afresh
     R.render(args.warmup, stream=stream)
     torch.cuda.synchronize()

@@ -80,7 +80,9 @@ typedef struct {
 } neb_params;
 
 /* Launch shapes of the traversal and photon kernels (neb_autotune picks
- * them; results do not depend on them). */
+ * them; results do not depend on them).  Defaults: the shallowest stack
+ * that holds every BVH, as many resident traversal blocks as the LDS holds,
+ * 8 photon-merge blocks per CU, queue order. */
 typedef struct {
     int32_t bvh_stack;            /* LDS traversal stack entries per lane: 32, 48 or 64; must
                                      exceed the depth of every scene's BVH */

@@ -13,14 +13,16 @@
 //    child pointer spin until the pointer appears.  On a 64-wide wavefront
 //    the splitter may sit in the same wave as the spinner, and the
 //    compiler places the split (which follows the loop-exiting CAS) after
-//    the loop's reconvergence point: the wave deadlocks.  Here such a
-//    deposit is deferred to a queue and retried by the next launch; the
-//    kernel boundary guarantees the split has been published.  A deposit
-//    is deferred at most once per level, so kOctMaxDepth + 1 retry rounds
-//    bound the work;
-//  - lanes of a wave that reach the same node word add their count with one
-//    CAS (capped at the split threshold; the rest defer), so a burst of
-//    deposits into one cell costs one atomic per wave;
+//    the loop's reconvergence point: the wave deadlocks.  Here the lanes of
+//    a wave that reach the same node word add their count with one CAS
+//    (capped at the split threshold), the lane whose addition fills the
+//    leaf splits it on the spot, and the lanes beyond the cap follow the
+//    pointer their own wave has just published; so a full leaf without a
+//    pointer was always filled by another, resident wave.  Such a lane
+//    re-reads the word from L2 a bounded number of times, then defers the
+//    deposit to a queue retried by the next launch (the kernel boundary
+//    guarantees the split has been published).  A deposit is deferred at
+//    most once per level, so kOctMaxDepth + 1 retry rounds bound the work;
 //  - no increment is overwritten by the pointer store (deposits never
 //    count past the threshold), so the ledger
 //        S = sum(leaf counts) - 4 * sum(iteration of each allocated block)
@@ -32,6 +34,8 @@
 //    changes again and every other decision is validated by the CAS;
 //  - nodes at depth 20 never split (FP32 positions cannot resolve finer
 //    cells).
+#include <algorithm>
+
 #include "neb_device.h"
 
 namespace neb {
@@ -41,23 +45,32 @@ __device__ __forceinline__ int32_t ld_node(const int32_t* p) {
 }
 
 enum { kInsRejected = 0, kInsCounted = 1, kInsDeferred = 2 };
+constexpr int kOctSpins = 64;  // L2 re-reads of a leaf whose split is in flight, per deposit
 
 __device__ __forceinline__ int child_index(const float q[3], int level) {
     float sc = (float)(1 << level);
     return (((int32_t)(q[0] * sc)) & 1) | ((((int32_t)(q[1] * sc)) & 1) << 1) | ((((int32_t)(q[2] * sc)) & 1) << 2);
 }
 
-// The split of a full leaf: allocate 8 children, start them at the current
-// iteration (parent / 4), publish the pointer.  Called by exactly one lane,
-// the one whose CAS brought the count to the threshold.
-__device__ __forceinline__ void oct_split(int32_t* nodes, OctState* st, const OctParams& P, const OctDyn& D,
-                                          int32_t idx, int level) {
-    int32_t child = atomicAdd(&st->alloc, 8);
+// what a lane's splits add to its octree's state; flushed once per wave
+struct SplitTally {
+    unsigned long long iter_sum = 0;  // iteration of each block it allocated
+    int depth = 0;                    // deepest level it created
+    int failed = 0;                   // splits refused by a full pool
+};
+
+// Children of a full leaf whose word holds `full`, in the block `child`
+// (allocated by the caller; >= P.end means the pool is exhausted): start
+// the eight children at the current iteration (parent / 4), then publish
+// the pointer.  Returns the node word afterwards: the child pointer, or
+// `full` marked as a failed split.
+__device__ __forceinline__ int32_t oct_make_children(int32_t* nodes, const OctParams& P, const OctDyn& D,
+                                                     int32_t idx, int level, int32_t full, int32_t child,
+                                                     SplitTally& T) {
     if (child >= P.end) {
-        atomicExch(&st->alloc, P.end + 1);
         __hip_atomic_fetch_or(nodes + idx, kOctFailed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        atomicAdd(&st->overflow, 1);
-        return;
+        T.failed += 1;
+        return full | kOctFailed;
     }
     // the wait retires the eight atomic writes (CDNA tracks them in vmcnt)
     // before the pointer is published, so a lane that follows the pointer
@@ -67,8 +80,22 @@ __device__ __forceinline__ void oct_split(int32_t* nodes, OctState* st, const Oc
         __hip_atomic_exchange(nodes + child + c, D.iter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __hip_atomic_exchange(nodes + idx, -child, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    atomicAdd(&st->block_iter_sum, (unsigned long long)D.iter);
-    atomicMax(&st->depth, level + 1);
+    T.iter_sum += (unsigned long long)D.iter;
+    T.depth = max(T.depth, level + 1);
+    return -child;
+}
+
+// next free block of n blocks of 8 in an octree, or P.end if the pool is
+// full (a full pool is seen with a plain read, without an atomic)
+__device__ __forceinline__ int32_t oct_alloc(OctState* st, const OctParams& P, int n) {
+    if (__hip_atomic_load(&st->alloc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= P.end) return P.end;
+    return atomicAdd(&st->alloc, 8 * n);
+}
+
+__device__ __forceinline__ void flush_tally(OctState* st, const SplitTally& T) {
+    if (T.iter_sum) atomicAdd(&st->block_iter_sum, T.iter_sum);
+    if (T.depth) atomicMax(&st->depth, T.depth);
+    if (T.failed) atomicAdd(&st->overflow, T.failed);
 }
 
 // one deposit by one thread alone (sequential insertion, the oracle's order)
@@ -94,28 +121,40 @@ __device__ __forceinline__ int oct_insert(int32_t* nodes, OctState* st, const Oc
             v = expected;
             continue;
         }
-        if (can_split && cnt + 1 == D.split_count) oct_split(nodes, st, P, D, idx, level);
+        if (can_split && cnt + 1 == D.split_count) {
+            SplitTally T;
+            oct_make_children(nodes, P, D, idx, level, v + 1, oct_alloc(st, P, 1), T);
+            flush_tally(st, T);
+        }
         return kInsCounted;
     }
     return kInsDeferred;
 }
 
 // Wave-cooperative deposit of one point per lane (lanes may belong to
-// different octrees of the pool).  Lanes that reach the same node word with
-// the same observed value form a group; its first lane adds the group's
-// size (capped at the split threshold) with one CAS, the lanes beyond the
-// cap defer, and the lane whose addition reaches the threshold splits.
-// Must be called by all lanes of the wave.
+// different octrees of the pool).  Each pass: lanes that reach the same
+// node word with the same observed value form a group, and the group's
+// first lane adds the group's size (capped at the split threshold) with one
+// CAS; then every group whose addition filled its leaf splits, with one
+// block allocation per octree for all of the wave's splits of the pass.
+// The lanes beyond a cap follow the pointer their own wave has just
+// published (nobody waits for anybody).  Lanes that find a leaf filled by
+// another wave, whose split may still be in flight, re-read the word from
+// L2 a bounded number of times (the split is a short fixed sequence of
+// atomics by a resident wave) and defer to the next launch if it has not
+// appeared.  Must be called by all lanes of the wave.
 __device__ __forceinline__ int oct_insert_wave(int32_t* nodes, OctState* st, const OctParams& P, const OctDyn& D,
-                                               bool has, f3 p) {
+                                               bool has, f3 p, SplitTally& tally) {
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (1ull << lane) - 1ull;
+    const unsigned long long stkey = (unsigned long long)(uintptr_t)st;
     float q[3] = {0.f, 0.f, 0.f};
     bool active = has && oct_norm(P, p, q);
     int result = (has && !active) ? kInsRejected : kInsDeferred;
     int32_t idx = P.root;
     int level = 0;
     int32_t v = active ? ld_node(nodes + idx) : 0;
+    int spins = 0;
     for (int step = 0; step < 4096; ++step) {
         if (!__any(active)) break;
         if (active && v < 0) {
@@ -123,44 +162,76 @@ __device__ __forceinline__ int oct_insert_wave(int32_t* nodes, OctState* st, con
             idx = child_index(q, level) - v;
             v = ld_node(nodes + idx);
         }
-        bool want = active && v >= 0;
+        const bool grouped = active && v >= 0;
+        bool want = grouped;
         unsigned long long pend = __ballot(want);
+        // phase 1: one CAS per group
+        int my_leader = lane, my_rank = 0, my_m = 0;
+        int l_ok = 0, l_split = 0;
+        int32_t l_cur = v, l_full = v;
         while (pend) {
             int leader = __ffsll((long long)pend) - 1;
             int32_t lidx = __shfl(idx, leader, 64);
             int32_t lv = __shfl(v, leader, 64);
             int llevel = __shfl(level, leader, 64);
-            int32_t lsplit = __shfl(D.split_count, leader, 64);
             bool in = want && idx == lidx && v == lv;
             unsigned long long gm = __ballot(in);
             int k = __popcll(gm);
             int32_t cnt = lv & kOctCountMask;
             bool can_split = !(lv & kOctFailed) && llevel < kOctMaxDepth;
-            int m = can_split ? min(k, max(0, lsplit - cnt)) : k;
-            int ok = 0;
-            int32_t cur = lv;
+            int m = can_split ? min(k, max(0, D.split_count - cnt)) : k;
+            if (in) {
+                my_leader = leader;
+                my_rank = __popcll(gm & below);
+                my_m = m;
+            }
             if (lane == leader && m > 0) {
                 int32_t e = lv;
-                ok = __hip_atomic_compare_exchange_strong(nodes + lidx, &e, lv + m, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_AGENT);
-                cur = e;
-                if (ok && can_split && cnt + m == lsplit) oct_split(nodes, st, P, D, lidx, llevel);
-            }
-            ok = __shfl(ok, leader, 64);
-            cur = __shfl(cur, leader, 64);
-            if (in) {
-                if (m == 0) {  // full leaf, split in flight: retry after the launch
-                    result = kInsDeferred;
-                    active = false;
-                } else if (ok) {
-                    result = __popcll(gm & below) < m ? kInsCounted : kInsDeferred;
-                    active = false;
-                } else {
-                    v = cur;  // the word changed: retry with its current value
-                }
+                l_ok = __hip_atomic_compare_exchange_strong(nodes + lidx, &e, lv + m, __ATOMIC_RELAXED,
+                                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                l_cur = e;
+                l_full = lv + m;
+                l_split = l_ok && can_split && cnt + m == D.split_count;
             }
             want = want && !in;
             pend &= ~gm;
+        }
+        // phase 2: the pass's splits, one allocation per octree
+        int32_t l_after = l_full;
+        unsigned long long spl = __ballot(l_split);
+        while (spl) {
+            int first = __ffsll((long long)spl) - 1;
+            unsigned long long key = __shfl(stkey, first, 64);
+            bool mine = l_split && stkey == key;
+            unsigned long long sm = __ballot(mine);
+            int32_t base = 0;
+            if (lane == first) base = oct_alloc(st, P, __popcll(sm));
+            base = __shfl(base, first, 64);
+            if (mine) l_after = oct_make_children(nodes, P, D, idx, level, l_full, base + 8 * __popcll(sm & below), tally);
+            spl &= ~sm;
+        }
+        // phase 3: every grouped lane learns its group's outcome
+        int ok = __shfl(l_ok, my_leader, 64);
+        int32_t cur = __shfl(l_cur, my_leader, 64);
+        int32_t after = __shfl(l_after, my_leader, 64);
+        if (grouped) {
+            if (my_m == 0) {  // full leaf, split in flight: re-read, or retry after the launch
+                if (++spins <= kOctSpins) {
+                    v = __hip_atomic_load(nodes + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                } else {
+                    result = kInsDeferred;
+                    active = false;
+                }
+            } else if (ok) {
+                if (my_rank < my_m) {
+                    result = kInsCounted;
+                    active = false;
+                } else {
+                    v = after;  // this wave split the leaf: go on from its new word
+                }
+            } else {
+                v = cur;  // the word changed: retry with its current value
+            }
         }
     }
     return result;
@@ -168,22 +239,30 @@ __device__ __forceinline__ int oct_insert_wave(int32_t* nodes, OctState* st, con
 
 // one atomic per wave and state for each tally; lanes of a wave may belong
 // to different octree states
-__device__ __forceinline__ void oct_account(OctState* states, int scene, int counted, int rejected) {
+__device__ __forceinline__ void oct_account(OctState* states, int scene, int counted, int rejected,
+                                            const SplitTally& T) {
     const int lane = threadIdx.x & 63;
-    unsigned long long pend = __ballot(counted != 0 || rejected != 0);
+    unsigned long long pend =
+        __ballot(counted != 0 || rejected != 0 || T.iter_sum != 0 || T.depth != 0 || T.failed != 0);
     while (pend) {
         int leader = __ffsll((long long)pend) - 1;
         int ls = __shfl(scene, leader, 64);
         bool in = ((pend >> lane) & 1ull) && scene == ls;
         unsigned long long c = in ? (unsigned long long)counted : 0ull;
         int r = in ? rejected : 0;
+        SplitTally S;
+        if (in) S = T;
         for (int off = 32; off > 0; off >>= 1) {
             c += __shfl_xor(c, off, 64);
             r += __shfl_xor(r, off, 64);
+            S.iter_sum += __shfl_xor(S.iter_sum, off, 64);
+            S.failed += __shfl_xor(S.failed, off, 64);
+            S.depth = max(S.depth, __shfl_xor(S.depth, off, 64));
         }
         if (lane == leader) {
             if (c) atomicAdd(&states[ls].deposits, c);
             if (r) atomicAdd(&states[ls].rejected, r);
+            flush_tally(states + ls, S);
         }
         pend &= ~__ballot(in);
     }
@@ -222,9 +301,10 @@ __global__ void __launch_bounds__(256) k_oct_insert(int32_t* nodes, OctState* st
             s = item_scene(scene_word, stride, shift, item);
         }
         const OctParams P = prm[s];
-        int r = oct_insert_wave(nodes, states + s, P, D, has, pt);
+        SplitTally tally;
+        int r = oct_insert_wave(nodes, states + s, P, D, has, pt, tally);
         bool defer = has && r == kInsDeferred;
-        oct_account(states, s, has && r == kInsCounted, has && r == kInsRejected);
+        oct_account(states, s, has && r == kInsCounted, has && r == kInsRejected, tally);
         int slot = wave_reserve(defer_count, defer);
         if (defer) defer_out[slot] = item;
     }
@@ -345,7 +425,8 @@ hipError_t octree_insert_rounds(int32_t* nodes, OctState* states, const OctParam
     hipLaunchKernelGGL(k_oct_insert, dim3(grid_for(n_host, 256)), dim3(256), 0, s, nodes, states, prm, dyn, pos, stride,
                        scene_word, shift, (const int32_t*)nullptr, n_dev, n_host, defer[0], cnt + 1, cnt + 2);
     for (int r = 1; r <= kOctMaxDepth + 1; ++r) {
-        hipLaunchKernelGGL(k_oct_insert, dim3(64), dim3(256), 0, s, nodes, states, prm, dyn, pos, stride, scene_word,
+        hipLaunchKernelGGL(k_oct_insert, dim3(std::min(grid_for(n_host, 256), 1024)), dim3(256), 0, s, nodes, states,
+                           prm, dyn, pos, stride, scene_word,
                            shift, (const int32_t*)defer[(r - 1) & 1], (const int32_t*)(cnt + (r % 3)), n_host,
                            defer[r & 1], cnt + ((r + 1) % 3), cnt + ((r + 2) % 3));
     }

@@ -1093,11 +1093,14 @@ struct HostScene {
 };
 
 // launch shapes picked by neb_autotune (or set by the caller)
+// (defaults: the shapes the autotuner picks for the room workload; the
+// stack is raised to the shallowest that holds the deepest tree)
 struct LaunchCfg {
-    int stack = 48;        // LDS traversal stack entries per lane: 32, 48 or 64
-    int trace_bpc = 0;     // traversal blocks (one wave each) per CU; 0 = one block per 64 queue slots
-    int photon_bpc = 0;    // photon-merge blocks (one wave each) per CU; 0 = one block per 256 queue slots
-    int photon_order = 1;  // merge photons in the spatial order of their hits
+    int stack = 32;        // LDS traversal stack entries per lane: 32, 48 or 64
+    int trace_bpc = -1;    // traversal blocks (one wave each) per CU; 0 = one block per 64 queue slots,
+                           // -1 = as many as the LDS holds
+    int photon_bpc = 8;    // photon-merge blocks (one wave each) per CU; 0 = one block per 256 queue slots
+    int photon_order = 0;  // merge photons in the spatial order of their hits
 };
 
 struct neb_ctx_s {
@@ -1273,7 +1276,8 @@ static int lds_blocks_per_cu(int stack) { return (160 * 1024) / (stack * kTraceB
 
 // blocks of a traversal launch over a queue of at most cap rays
 static int trace_grid(neb_ctx c, int64_t cap) {
-    if (c->cfg.trace_bpc > 0) return std::max(1, c->cus * c->cfg.trace_bpc);
+    int bpc = c->cfg.trace_bpc < 0 ? lds_blocks_per_cu(c->cfg.stack) : c->cfg.trace_bpc;
+    if (bpc > 0) return std::max(1, c->cus * bpc);
     return grid_of(cap, kTraceBlock, 1 << 20);
 }
 
@@ -2330,7 +2334,7 @@ extern "C" neb_status neb_set_launch_config(neb_ctx c, const neb_launch_config* 
 extern "C" neb_status neb_get_launch_config(neb_ctx c, neb_launch_config* cfg) {
     if (!c || !cfg) return fail(NEB_ERR_INVALID_ARG, "null pointer");
     cfg->bvh_stack = c->cfg.stack;
-    cfg->trace_blocks_per_cu = c->cfg.trace_bpc;
+    cfg->trace_blocks_per_cu = c->cfg.trace_bpc < 0 ? lds_blocks_per_cu(c->cfg.stack) : c->cfg.trace_bpc;
     cfg->photon_blocks_per_cu = c->cfg.photon_bpc;
     cfg->photon_order = c->cfg.photon_order;
     return NEB_OK;
