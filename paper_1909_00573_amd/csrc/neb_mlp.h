@@ -40,7 +40,8 @@ struct Mlp {
     float* loss = nullptr;     // running sum of squared errors
     double* moments = nullptr;
     uint16_t* acts = nullptr;  // feature-major bf16 activations and deltas of one batch
-    int32_t max_batch = 0, npad = 0;
+    float* part = nullptr;     // per-wave partial sums of the small gradients and the loss
+    int32_t max_batch = 0, npad = 0, max_waves = 0;
     int64_t step = 0;          // Adam steps taken
 };
 

@@ -19,6 +19,8 @@
 // the activations and deltas.  Weights are kept as FP32 master copies
 // (Adam) and re-packed after every step into bf16 operand fragments (each
 // lane's four values contiguous), which the kernels stage in LDS.
+#include <algorithm>
+
 #include "neb_device.h"
 #include "neb_mlp.h"
 
@@ -243,25 +245,30 @@ struct MlpBatch {
     uint32_t k0, k1, step;     // Philox key and counter word for the draws
 };
 
-// Forward, output gradient, backward data pass, bias gradients and the
-// feature-major bf16 stores the weight-gradient GEMMs read (X: 80 rows,
-// H1, H2, D1, D2, D3: 64 rows each; row length npad).
+// per-wave partial sums of the small gradients: b1, b2, b3, w4 (64 each),
+// b4, loss
+constexpr int kPartStride = 4 * kMlpWidth + 2;
+// Activations and deltas of a batch, tile-major: per 16-sample tile 400 rows
+// of 16 bf16 (X rows 0..79, H1, H2, D1, D2, D3 64 rows each), so a wave
+// writes whole cache lines and a 16 x 16 operand fragment is 8 contiguous
+// bytes per lane.
+constexpr int kRowsX = 0, kRowsH1 = kMlpIn, kRowsH2 = kRowsH1 + kMlpWidth, kRowsD1 = kRowsH2 + kMlpWidth,
+              kRowsD2 = kRowsD1 + kMlpWidth, kRowsD3 = kRowsD2 + kMlpWidth, kRowsTile = kRowsD3 + kMlpWidth;
+
+// Forward, output gradient, backward data pass, the wave's partial sums of
+// the bias and output-layer gradients and of the loss (plain stores, summed
+// by k_mlp_wgrad), and the tile-major bf16 stores the weight-gradient GEMMs
+// read.
 __global__ void __launch_bounds__(256) k_mlp_train_fb(const uint16_t* __restrict__ blob,
                                                       const float* __restrict__ theta, const MlpNorm* norm,
                                                       MlpBatch B, uint16_t* __restrict__ acts, int npad,
-                                                      float* __restrict__ grad, float* loss_sum) {
+                                                      float* __restrict__ part) {
     __shared__ __attribute__((aligned(16))) uint16_t lds[kFragAll];
     stage_blob(blob, lds, kFragAll);
     const int lane = threadIdx.x & 63, s = lane & 15, g = lane >> 4;
     const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, n_waves = (gridDim.x * blockDim.x) >> 6;
     const float mu = norm->mu, inv_sigma = 1.0f / norm->sigma;
     const float inv_n = 2.0f / (float)B.n;
-    uint16_t* X = acts;
-    uint16_t* H1 = X + (size_t)kMlpIn * npad;
-    uint16_t* H2 = H1 + (size_t)kMlpWidth * npad;
-    uint16_t* D1 = H2 + (size_t)kMlpWidth * npad;
-    uint16_t* D2 = D1 + (size_t)kMlpWidth * npad;
-    uint16_t* D3 = D2 + (size_t)kMlpWidth * npad;
     float gb1[16], gb2[16], gb3[16], gw4[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) gb1[k] = gb2[k] = gb3[k] = gw4[k] = 0.f;
@@ -331,22 +338,22 @@ __global__ void __launch_bounds__(256) k_mlp_train_fb(const uint16_t* __restrict
             }
             d1b[kb] = pack4(acc[0], acc[1], acc[2], acc[3]);
         }
-        // feature-major stores for the weight gradients
-        const size_t col = (size_t)(base + s);
+        // tile-major stores for the weight gradients
+        uint16_t* tile = acts + (size_t)(base >> 4) * (kRowsTile * 16) + s;
 #pragma unroll
         for (int ks = 0; ks < 5; ++ks)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) X[(size_t)(16 * ks + 4 * g + i) * npad + col] = (uint16_t)T.x[ks][i];
+            for (int i = 0; i < 4; ++i) tile[(kRowsX + 16 * ks + 4 * g + i) * 16] = (uint16_t)T.x[ks][i];
 #pragma unroll
         for (int ob = 0; ob < 4; ++ob)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                size_t row = (size_t)(16 * ob + 4 * g + i) * npad + col;
-                H1[row] = to_bf16(fmaxf(T.z1[ob][i], 0.f));
-                H2[row] = to_bf16(fmaxf(T.z2[ob][i], 0.f));
-                D1[row] = (uint16_t)d1b[ob][i];
-                D2[row] = (uint16_t)d2b[ob][i];
-                D3[row] = (uint16_t)d3b[ob][i];
+                const int f = 16 * ob + 4 * g + i;
+                tile[(kRowsH1 + f) * 16] = to_bf16(fmaxf(T.z1[ob][i], 0.f));
+                tile[(kRowsH2 + f) * 16] = to_bf16(fmaxf(T.z2[ob][i], 0.f));
+                tile[(kRowsD1 + f) * 16] = (uint16_t)d1b[ob][i];
+                tile[(kRowsD2 + f) * 16] = (uint16_t)d2b[ob][i];
+                tile[(kRowsD3 + f) * 16] = (uint16_t)d3b[ob][i];
             }
     }
     // sum the per-sample partials over the 16 sample lanes of each group
@@ -364,70 +371,120 @@ __global__ void __launch_bounds__(256) k_mlp_train_fb(const uint16_t* __restrict
         gb4 += __shfl_xor(gb4, off, 64);
         lsum += __shfl_xor(lsum, off, 64);
     }
+    float* P = part + (size_t)wave * kPartStride;
     if (s == 0) {
 #pragma unroll
         for (int ob = 0; ob < 4; ++ob)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 int f = 16 * ob + 4 * g + i;
-                atomicAdd(grad + kMlpB1 + f, gb1[4 * ob + i]);
-                atomicAdd(grad + kMlpB2 + f, gb2[4 * ob + i]);
-                atomicAdd(grad + kMlpB3 + f, gb3[4 * ob + i]);
-                atomicAdd(grad + kMlpW4 + f, gw4[4 * ob + i]);
+                P[f] = gb1[4 * ob + i];
+                P[kMlpWidth + f] = gb2[4 * ob + i];
+                P[2 * kMlpWidth + f] = gb3[4 * ob + i];
+                P[3 * kMlpWidth + f] = gw4[4 * ob + i];
             }
         if (g == 0) {
-            atomicAdd(grad + kMlpB4, gb4);
-            atomicAdd(loss_sum, lsum);
+            P[4 * kMlpWidth] = gb4;
+            P[4 * kMlpWidth + 1] = lsum;
         }
     }
 }
 
-// Weight gradients dW_l[k][n] = sum_s Hin[k][s] D[n][s] as K = batch GEMMs:
-// block (tile, slice) accumulates one 16 x 16 tile of dW^T over a slice of
-// the batch with A = D (rows n), B = Hin (columns k).
+// Weight gradients dW_l[k][n] = sum_s Hin[k][s] D[n][s] as K = batch GEMMs.
+// Block (layer, slice) is one wave that reads each row of its slice of the
+// batch once (per 16-sample tile: the layer's delta rows as A fragments,
+// its input rows as B fragments) and accumulates every 16 x 16 tile of
+// dW^T of that layer in registers; the tiles are added to the gradient at
+// the end.  Blocks past the three layers sum the training kernel's
+// per-wave partials, each slice a share of the waves.
 constexpr int kWgSlice = 1024;
-__global__ void __launch_bounds__(64) k_mlp_wgrad(const uint16_t* __restrict__ acts, int npad,
-                                                  float* __restrict__ grad) {
+constexpr int kWgLayers = 3;
+constexpr int kWgReduce = (kPartStride + 63) / 64;
+
+template <int KB>
+__device__ __forceinline__ void wgrad_layer(const uint16_t* __restrict__ acts, int t_begin, int t_end, int hrow,
+                                            int drow, int woff, int kmax, float* __restrict__ grad) {
     const int lane = threadIdx.x, g = lane >> 4, r = lane & 15;
-    int tile = blockIdx.x;
-    const int slice = blockIdx.y;
-    int layer, nb, kb;
-    if (tile < 20) {
-        layer = 1;
-        nb = tile / 5;
-        kb = tile % 5;
-    } else if (tile < 36) {
-        layer = 2;
-        nb = (tile - 20) / 4;
-        kb = (tile - 20) % 4;
-    } else {
-        layer = 3;
-        nb = (tile - 36) / 4;
-        kb = (tile - 36) % 4;
-    }
-    const uint16_t* X = acts;
-    const uint16_t* H1 = X + (size_t)kMlpIn * npad;
-    const uint16_t* H2 = H1 + (size_t)kMlpWidth * npad;
-    const uint16_t* D1 = H2 + (size_t)kMlpWidth * npad;
-    const uint16_t* D2 = D1 + (size_t)kMlpWidth * npad;
-    const uint16_t* D3 = D2 + (size_t)kMlpWidth * npad;
-    const uint16_t* Hin = layer == 1 ? X : (layer == 2 ? H1 : H2);
-    const uint16_t* D = layer == 1 ? D1 : (layer == 2 ? D2 : D3);
-    const int woff = layer == 1 ? kMlpW1 : (layer == 2 ? kMlpW2 : kMlpW3);
-    const uint16_t* arow = D + (size_t)(16 * nb + r) * npad;
-    const uint16_t* brow = Hin + (size_t)(16 * kb + r) * npad;
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    const int s_end = min(npad, (slice + 1) * kWgSlice);
-    for (int s0 = slice * kWgSlice; s0 < s_end; s0 += 16) {
-        bf16x4 a = *reinterpret_cast<const bf16x4*>(arow + s0 + 4 * g);
-        bf16x4 b = *reinterpret_cast<const bf16x4*>(brow + s0 + 4 * g);
-        acc = mfma(a, b, acc);
-    }
-    // acc[i] = dW^T[16 nb + 4 g + i][16 kb + r]
-    const int k = 16 * kb + r;
-    if (layer == 1 && k >= kMlpEnc) return;  // the zero pads carry no gradient
+    constexpr size_t kTile = (size_t)kRowsTile * 16;
+    f32x4 acc[4][KB];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) atomicAdd(grad + woff + k * kMlpWidth + 16 * nb + 4 * g + i, acc[i]);
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) acc[nb][kb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const uint16_t* abase = acts + (drow + r) * 16 + 4 * g;
+    const uint16_t* bbase = acts + (hrow + r) * 16 + 4 * g;
+    // U tiles' fragments are loaded before any of them is used
+    constexpr int U = 8;
+    int t = t_begin;
+    for (; t + U <= t_end; t += U) {
+        bf16x4 a[U][4], b[U][KB];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t off = (size_t)(t + u) * kTile;
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) a[u][nb] = *reinterpret_cast<const bf16x4*>(abase + off + 16 * 16 * nb);
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) b[u][kb] = *reinterpret_cast<const bf16x4*>(bbase + off + 16 * 16 * kb);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb) acc[nb][kb] = mfma(a[u][nb], b[u][kb], acc[nb][kb]);
+    }
+    for (; t < t_end; ++t) {
+        const size_t off = (size_t)t * kTile;
+        bf16x4 a[4], b[KB];
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) a[nb] = *reinterpret_cast<const bf16x4*>(abase + off + 16 * 16 * nb);
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) b[kb] = *reinterpret_cast<const bf16x4*>(bbase + off + 16 * 16 * kb);
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) acc[nb][kb] = mfma(a[nb], b[kb], acc[nb][kb]);
+    }
+    // acc[nb][kb][i] = dW^T[16 nb + 4 g + i][16 kb + r]
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+        const int k = 16 * kb + r;
+        if (k >= kmax) continue;  // the zero pads of the input carry no gradient
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) atomicAdd(grad + woff + k * kMlpWidth + 16 * nb + 4 * g + i, acc[nb][kb][i]);
+    }
+}
+
+__global__ void __launch_bounds__(64) k_mlp_wgrad(const uint16_t* __restrict__ acts, int npad,
+                                                  float* __restrict__ grad, const float* __restrict__ part,
+                                                  int n_waves, float* loss_sum) {
+    const int lane = threadIdx.x;
+    const int job = blockIdx.x;
+    const int slice = blockIdx.y;
+    if (job >= kWgLayers) {
+        const int j = (job - kWgLayers) * 64 + lane;
+        if (j >= kPartStride) return;
+        const int share = (n_waves + gridDim.y - 1) / gridDim.y;
+        const int w0 = slice * share, w1 = min(n_waves, w0 + share);
+        if (w0 >= w1) return;
+        float sum = 0.f;
+        for (int w = w0; w < w1; ++w) sum += part[(size_t)w * kPartStride + j];
+        if (j < 4 * kMlpWidth) {
+            const int off = j < kMlpWidth ? kMlpB1 : (j < 2 * kMlpWidth ? kMlpB2 : (j < 3 * kMlpWidth ? kMlpB3 : kMlpW4));
+            atomicAdd(grad + off + (j % kMlpWidth), sum);
+        } else if (j == 4 * kMlpWidth) {
+            atomicAdd(grad + kMlpB4, sum);
+        } else {
+            atomicAdd(loss_sum, sum);
+        }
+        return;
+    }
+    const int t_begin = (slice * kWgSlice) >> 4, t_end = min(npad, (slice + 1) * kWgSlice) >> 4;
+    if (job == 0) wgrad_layer<5>(acts, t_begin, t_end, kRowsX, kRowsD1, kMlpW1, kMlpEnc, grad);
+    else if (job == 1) wgrad_layer<4>(acts, t_begin, t_end, kRowsH1, kRowsD2, kMlpW2, kMlpWidth, grad);
+    else wgrad_layer<4>(acts, t_begin, t_end, kRowsH2, kRowsD3, kMlpW3, kMlpWidth, grad);
 }
 
 // One Adam step on the FP32 master parameters; re-packs the bf16 operand
@@ -509,11 +566,14 @@ hipError_t mlp_alloc(Mlp& m, int32_t max_batch) {
     if (e == hipSuccess) e = hipMalloc(&m.loss, sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&m.moments, 2 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&m.acts, 2 * (size_t)(kMlpIn + 5 * kMlpWidth) * m.npad);
+    // one partial row per wave of the training kernel at its largest grid
+    m.max_waves = 4 * std::max(1, std::min((m.npad / 16 + 15) / 16, 1 << 16));
+    if (e == hipSuccess) e = hipMalloc(&m.part, 4 * (size_t)kPartStride * m.max_waves);
     return e;
 }
 
 void mlp_free(Mlp& m) {
-    void* ps[] = {m.theta, m.m, m.v, m.grad, m.blob, m.norm, m.loss, m.moments, m.acts};
+    void* ps[] = {m.theta, m.m, m.v, m.grad, m.blob, m.norm, m.loss, m.moments, m.acts, m.part};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     m = Mlp();
@@ -591,11 +651,13 @@ hipError_t mlp_gradient(Mlp& m, const float* pos, int pos_stride, const float* n
     B.step = (uint32_t)m.step;
     const int npad = (batch + 15) & ~15;
     const int tiles = npad / 16;
-    hipLaunchKernelGGL(k_mlp_train_fb, dim3(blocks_for(tiles, 16, 1 << 16)), dim3(256), 0, s,
-                       (const uint16_t*)m.blob, (const float*)m.theta, (const MlpNorm*)m.norm, B, m.acts, npad,
-                       m.grad, m.loss);
-    hipLaunchKernelGGL(k_mlp_wgrad, dim3(52, (npad + kWgSlice - 1) / kWgSlice), dim3(64), 0, s,
-                       (const uint16_t*)m.acts, npad, m.grad);
+    const int blocks = blocks_for(tiles, 16, 1 << 16);
+    const int n_waves = 4 * blocks;
+    if (n_waves > m.max_waves) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mlp_train_fb, dim3(blocks), dim3(256), 0, s, (const uint16_t*)m.blob, (const float*)m.theta,
+                       (const MlpNorm*)m.norm, B, m.acts, npad, m.part);
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3(kWgLayers + kWgReduce, (npad + kWgSlice - 1) / kWgSlice), dim3(64), 0, s,
+                       (const uint16_t*)m.acts, npad, m.grad, (const float*)m.part, n_waves, m.loss);
     return hipGetLastError();
 }
 

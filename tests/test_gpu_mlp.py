@@ -158,12 +158,14 @@ def test_render_with_learned_density(neb):
     tech = R.technique_images_host()
     for t in tech.values():
         assert np.all(np.isfinite(t))
-    # against the plain method at the same spp: the same light transport
+    # against the plain method at the same spp: the same light transport (E
+    # and P depend on rho through the MIS weights and the photon flux, and
+    # the trained model varies with the order of the gradient additions)
     P = neb.Renderer(sc)
     P.render(8)
     ref = P.technique_images_host()
-    assert abs(tech["E"].mean() / ref["E"].mean() - 1) < 0.01
-    assert abs(tech["P"].mean() / ref["P"].mean() - 1) < 0.06
+    assert abs(tech["E"].mean() / ref["E"].mean() - 1) < 0.03
+    assert abs(tech["P"].mean() / ref["P"].mean() - 1) < 0.08
     # a tiny error bound sends every probed region back to the octree
     R.configure_mlp(train_iterations=2, steps_per_iteration=20, batch=4096, probe_every=2, probes=512,
                     max_rel_error=1e-7)
