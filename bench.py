@@ -16,8 +16,9 @@ of the dominant kernel (HIP-event durations on the launch stream, the
 library's work counters for algorithmic bytes, HBM traffic from the
 committed counter summary while the kernel source is unchanged), the FP64
 oracle timed on the host cores over a bounded pixel window of the same
-workload, and the batched form: 64 box rooms rendered in one context
-against the same 64 scenes rendered one after another.
+workload, the batched form (64 box rooms rendered in one context against
+the same 64 scenes rendered one after another) and the learned-density form
+(time to the plain form's RMSE at 64 spp).
 """
 import hashlib
 import argparse
@@ -176,6 +177,77 @@ def batch_comparison(stream, cfg_trials=1):
             "host_setup_s": {"generate": round(t_gen, 1), "bvh_and_pools": round(t_build, 1)}}
 
 
+def rel_rmse(img, ref):
+    import numpy as np
+    return float(np.sqrt(np.mean((img.astype(np.float64) - ref) ** 2)) / np.mean(ref))
+
+
+def learned_comparison(stream, spp=64, train_iterations=4, ref_spp=256, check_every=4):
+    """The room with the learned density (4 training iterations, then the
+    model) against the plain octree form, both to `spp`, each checked every
+    `check_every` iterations against a plain render of ref_spp with another
+    seed.  Reports the plain form's relative RMSE at `spp` and the time
+    each form needs to reach it (render time only: GPU events around the
+    render calls, the RMSE checks excluded)."""
+    import numpy as np
+    import torch
+    from neb_inputs import room
+    from paper_1909_00573_amd import neb
+
+    def timed(render):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        render()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / 1e3
+
+    sc = room()
+    ref_sc = sc.with_settings(seed=sc.seed + 1000)
+    R = neb.Renderer(ref_sc)
+    R.render(ref_spp, stream=stream)
+    ref = R.image_host().astype(np.float64)
+    R.close()
+
+    def progression(R):
+        t, curve = 0.0, []
+        for it in range(check_every, spp + 1, check_every):
+            t += timed(lambda: R.render(check_every, stream=stream))
+            curve.append((it, t, rel_rmse(R.image_host(), ref)))
+        return curve
+
+    P = neb.Renderer(sc)
+    plain = progression(P)
+    P.close()
+    M = neb.Renderer(sc, density_mode=neb.DENSITY_MLP)
+    M.configure_mlp(train_iterations=train_iterations)
+    learned = progression(M)
+    status = M.mlp_status()
+    M.close()
+    target = plain[-1][2]
+
+    def time_to(curve):
+        for it, t, e in curve:
+            if e <= target:
+                return it, t
+        return None, None
+
+    it_l, t_l = time_to(learned)
+    return {"workload": "room 512x512, %d spp; learned density trained on the octree for %d iterations "
+                        "(250 Adam steps x 65536 each), then used with region-gated octree fallback" %
+                        (spp, train_iterations),
+            "reference": "plain octree form, %d spp, seed %d" % (ref_spp, ref_sc.seed),
+            "plain_rel_rmse": round(target, 5), "plain_s": round(plain[-1][1], 4),
+            "learned_rel_rmse": round(learned[-1][2], 5), "learned_s": round(learned[-1][1], 4),
+            "learned_spp_to_equal_rmse": it_l, "learned_s_to_equal_rmse": None if t_l is None else round(t_l, 4),
+            "speedup_to_equal_rmse": None if t_l is None else round(plain[-1][1] / t_l, 3),
+            "curves": {"plain": [[i, round(t, 4), round(e, 5)] for i, t, e in plain],
+                       "learned": [[i, round(t, 4), round(e, 5)] for i, t, e in learned]},
+            "model": {k: status[k] for k in ("adam_steps", "last_loss", "probes", "probes_bad", "regions_probed",
+                                             "regions_disabled", "fallback_queries")}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +256,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event pass")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-scene batching comparison")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-density comparison")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the launch shapes on this workload first (default: the library's defaults)")
     ap.add_argument("--launch-config", default=None,
@@ -295,6 +368,8 @@ def main():
     R.close()
     if not args.no_batch:
         out["batch"] = batch_comparison(stream)
+    if not args.no_learned:
+        out["learned"] = learned_comparison(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -18,11 +18,12 @@
 //    (capped at the split threshold), the lane whose addition fills the
 //    leaf splits it on the spot, and the lanes beyond the cap follow the
 //    pointer their own wave has just published; so a full leaf without a
-//    pointer was always filled by another, resident wave.  Such a lane
-//    re-reads the word from L2 a bounded number of times, then defers the
-//    deposit to a queue retried by the next launch (the kernel boundary
-//    guarantees the split has been published).  A deposit is deferred at
-//    most once per level, so kOctMaxDepth + 1 retry rounds bound the work;
+//    pointer was always filled by another wave.  Such a deposit is deferred
+//    to a queue retried by the next launch (the kernel boundary guarantees
+//    the split has been published).  A deposit is deferred at most once per
+//    level, so kOctMaxDepth + 1 retry rounds bound the work.  (Re-reading
+//    the word a bounded number of times instead was measured slower: a
+//    wave keeps looping while any lane waits);
 //  - no increment is overwritten by the pointer store (deposits never
 //    count past the threshold), so the ledger
 //        S = sum(leaf counts) - 4 * sum(iteration of each allocated block)
@@ -45,7 +46,6 @@ __device__ __forceinline__ int32_t ld_node(const int32_t* p) {
 }
 
 enum { kInsRejected = 0, kInsCounted = 1, kInsDeferred = 2 };
-constexpr int kOctSpins = 64;  // L2 re-reads of a leaf whose split is in flight, per deposit
 
 __device__ __forceinline__ int child_index(const float q[3], int level) {
     float sc = (float)(1 << level);
@@ -139,10 +139,8 @@ __device__ __forceinline__ int oct_insert(int32_t* nodes, OctState* st, const Oc
 // block allocation per octree for all of the wave's splits of the pass.
 // The lanes beyond a cap follow the pointer their own wave has just
 // published (nobody waits for anybody).  Lanes that find a leaf filled by
-// another wave, whose split may still be in flight, re-read the word from
-// L2 a bounded number of times (the split is a short fixed sequence of
-// atomics by a resident wave) and defer to the next launch if it has not
-// appeared.  Must be called by all lanes of the wave.
+// another wave, whose split may still be in flight, defer to the next
+// launch.  Must be called by all lanes of the wave.
 __device__ __forceinline__ int oct_insert_wave(int32_t* nodes, OctState* st, const OctParams& P, const OctDyn& D,
                                                bool has, f3 p, SplitTally& tally) {
     const int lane = threadIdx.x & 63;
@@ -154,7 +152,6 @@ __device__ __forceinline__ int oct_insert_wave(int32_t* nodes, OctState* st, con
     int32_t idx = P.root;
     int level = 0;
     int32_t v = active ? ld_node(nodes + idx) : 0;
-    int spins = 0;
     for (int step = 0; step < 4096; ++step) {
         if (!__any(active)) break;
         if (active && v < 0) {
@@ -215,13 +212,9 @@ __device__ __forceinline__ int oct_insert_wave(int32_t* nodes, OctState* st, con
         int32_t cur = __shfl(l_cur, my_leader, 64);
         int32_t after = __shfl(l_after, my_leader, 64);
         if (grouped) {
-            if (my_m == 0) {  // full leaf, split in flight: re-read, or retry after the launch
-                if (++spins <= kOctSpins) {
-                    v = __hip_atomic_load(nodes + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                } else {
-                    result = kInsDeferred;
-                    active = false;
-                }
+            if (my_m == 0) {  // full leaf, split in flight: retry after the launch
+                result = kInsDeferred;
+                active = false;
             } else if (ok) {
                 if (my_rank < my_m) {
                     result = kInsCounted;
