@@ -175,3 +175,39 @@ def test_render_with_learned_density(neb):
     assert s["fallback_queries"] > 0
     R.close()
     P.close()
+
+
+def test_room_full_size_model_matches_reference(neb):
+    """Room at its full size with the default model settings (4 training
+    iterations of 250 Adam steps on 65 536 draws): the trained model's
+    log density at sampled surface points equals the FP64 reference's
+    evaluation of the same weights (bf16 operand rounding emulated)."""
+    import torch
+    from neb_inputs import room
+    sc = room()
+    R = neb.Renderer(sc, density_mode=neb.DENSITY_MLP, flags=neb.FLAG_RECORD_PATHS)
+    R.render(5)
+    s = R.mlp_status()
+    assert s["phase"] == 1 and s["adam_steps"] == 1000
+    assert s["last_loss"] < 0.2
+    w = R.mlp_weights()
+    rec = R.records()
+    R.close()
+    # sampled first-hit points of the recorded paths, normalised to the octree box
+    hits = rec[:, 0][(rec[:, 0]["type"] >= 1) & (rec[:, 0]["type"] <= 4)]
+    rng = np.random.default_rng(1)
+    pos = hits["pos"][rng.choice(len(hits), 2000, replace=False)].astype(np.float64)
+    lo, hi = sc.bbox()
+    size = (hi.astype(np.float64) - lo) * 1.002
+    q = np.clip((pos - (lo - size * (0.001 / 1.002))) / size, 0, 1 - 1e-7).astype(np.float32)
+    nn = rng.normal(size=(len(q), 3))
+    nn = (nn / np.linalg.norm(nn, axis=1, keepdims=True)).astype(np.float32)
+    m = neb.Mlp(init=w, max_batch=2048)
+    m.set_normalization(s["mu"], s["sigma"])
+    got = m.infer(_dev(q), _dev(nn)).cpu().numpy().astype(np.float64)
+    y, _ = M.forward(w.astype(np.float64), M.encode(q.astype(np.float64), nn.astype(np.float64)), bf16=True)
+    want = s["mu"] + s["sigma"] * y
+    d = np.abs(got - want)
+    assert np.median(d) <= 1e-4 and np.percentile(d, 99) <= 5e-3 and d.max() <= 5e-2, (np.median(d), d.max())
+    m.close()
+    torch.cuda.synchronize()

@@ -156,3 +156,60 @@ def test_room_full_size_sampled_paths(neb, oracle):
     pix = np.array([y * 512 + x for y in range(y0, y0 + 16) for x in range(x0, x0 + 16)])
     frac, _ = path_agreement(rg[pix], ro, _diag(sc))
     assert frac >= 0.99, frac
+
+
+def test_city_block_full_size_sampled_paths(neb, oracle):
+    """City block at its full size (1 M triangles, 1024 point lights, 5 %
+    GGX, 1024 x 1024, path length 10, octree 2^24): the paths of an 8 x 8
+    window equal the paths the oracle traces for exactly those pixels."""
+    from neb_inputs import city_block
+    sc = city_block()
+    g = neb.Renderer(sc, flags=neb.FLAG_RECORD_PATHS)
+    g.render(1)
+    rg = g.records()
+    st = g.stats()
+    assert st["oct_ledger"] == st["oct_deposits"]
+    assert st["oct_deposits"] + st["oct_rejected"] == st["vertices"]
+    W = sc.width
+    rng = np.random.default_rng(3)
+    x0, y0 = int(rng.integers(0, W - 8)), int(rng.integers(W // 4, W - 8))
+    win = (x0, y0, x0 + 8, y0 + 8)
+    ro = oracle.render(sc, n_iter=1, window=win, record=True, enable_photons=False)["records"]
+    pix = np.array([y * W + x for y in range(y0, y0 + 8) for x in range(x0, x0 + 8)])
+    frac, _ = path_agreement(rg[pix], ro, _diag(sc))
+    assert frac >= 0.98, frac
+    # the window holds surface hits, not only sky
+    assert (rg[pix]["type"][:, 0] != 5).sum() >= 16
+    g.close()
+
+
+def test_batch_full_size_sampled_paths(neb, oracle):
+    """The 64-room batch at its full size in one context, with the launch
+    shapes the bench's tuner picks for it (results do not depend on the
+    shapes; tests/test_gpu_batch.py checks that): sampled pixels of two
+    scenes follow the paths the oracle traces for them alone."""
+    from neb_inputs import batch_rooms
+    scenes = batch_rooms()
+    B = neb.BatchRenderer(scenes, flags=neb.FLAG_RECORD_PATHS, spp=[s.spp for s in scenes])
+    B.set_launch_config(32, 0, 16, 0)
+    B.render(1)
+    rb = B.records()
+    st = B.stats()
+    assert st["oct_ledger"] == st["oct_deposits"]
+    base = np.cumsum([0] + [s.width * s.height for s in scenes])
+    tri = np.cumsum([0] + [s.n_tris for s in scenes])
+    mat = np.cumsum([0] + [len(s.materials) for s in scenes])
+    for k in (5, 41):
+        sc = scenes[k]
+        W = sc.width
+        x0, y0 = W // 2 - 4, sc.height // 2 - 4
+        win = (x0, y0, x0 + 8, y0 + 8)
+        ro = oracle.render(sc, n_iter=1, window=win, record=True, enable_photons=False)["records"]
+        pix = np.array([base[k] + y * W + x for y in range(y0, y0 + 8) for x in range(x0, x0 + 8)])
+        part = rb[pix, :sc.max_path_len].copy()
+        live = (part["type"] >= 1) & (part["type"] <= 4)
+        part["mat"] = np.where(live, part["mat"] - mat[k], part["mat"])
+        part["prim"] = np.where(live, part["prim"] - tri[k], part["prim"])
+        frac, _ = path_agreement(part, ro, _diag(sc))
+        assert frac >= 0.98, (k, frac)
+    B.close()
