@@ -165,7 +165,7 @@ def batch_comparison(stream, cfg_trials=1):
         R = neb.Renderer(sc, spp=sc.spp)
         # the batch's stack is deeper than every scene's BVH
         R.set_launch_config(cfg["bvh_stack"], cfg["trace_blocks_per_cu"], cfg["photon_blocks_per_cu"],
-                            cfg["photon_order"])
+                            cfg["photon_order"], cfg["nee_blocks_per_cu"])
         t_seq += timed(lambda: R.render(sc.spp, stream=stream))
         R.close()
     return {"scenes": len(scenes), "triangles": int(sum(s.n_tris for s in scenes)),
@@ -260,7 +260,8 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="tune the launch shapes on this workload first (default: the library's defaults)")
     ap.add_argument("--launch-config", default=None,
-                    help="bvh_stack,trace_blocks_per_cu,photon_blocks_per_cu,photon_order instead of autotuning")
+                    help="bvh_stack,trace_blocks_per_cu,photon_blocks_per_cu,photon_order[,nee_blocks_per_cu] "
+                         "instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 256 MiB device copy first (for counter calibration)")
     args = ap.parse_args()

@@ -81,13 +81,15 @@ typedef struct {
 
 /* Launch shapes of the traversal and photon kernels (neb_autotune picks
  * them; results do not depend on them).  Defaults: the shallowest stack
- * that holds every BVH, as many resident traversal blocks as the LDS holds,
- * 8 photon-merge blocks per CU, queue order. */
+ * that holds every BVH, 8 resident closest-hit blocks per CU, as many
+ * NEE blocks as the LDS holds, 8 photon-merge blocks per CU, queue order. */
 typedef struct {
     int32_t bvh_stack;            /* LDS traversal stack entries per lane: 32, 48 or 64; must
                                      exceed the depth of every scene's BVH */
-    int32_t trace_blocks_per_cu;  /* resident traversal blocks (one wave each) per compute unit;
-                                     0 = one block per 64 queue slots */
+    int32_t trace_blocks_per_cu;  /* resident closest-hit blocks (one wave each) per compute unit;
+                                     0 = one block per 64 queue slots, -1 = as many as the LDS holds */
+    int32_t nee_blocks_per_cu;    /* resident NEE (shadow-ray) blocks per compute unit, same
+                                     conventions */
     int32_t photon_blocks_per_cu; /* photon-merge blocks (one wave each) per compute unit, 0..64;
                                      0 = one block per 256 queue slots */
     int32_t photon_order;         /* 1: merge photons in the spatial (Morton) order of their hits,

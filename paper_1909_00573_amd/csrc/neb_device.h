@@ -462,6 +462,86 @@ __device__ __forceinline__ int trace(const SceneView& S, int root, f3 o, f3 d, f
     return prim;
 }
 
+// Resumable closest-hit traversal (same steps and tie rule as trace): the
+// state of one ray, advanced by up to max_steps node visits per call, so a
+// lane whose ray ends can take a new one while the rest of its wave is
+// still traversing.
+struct TraceState {
+    RayPre r;
+    float best;
+    int prim;
+    int node;
+    int sp;
+};
+
+__device__ __forceinline__ void trace_begin(TraceState& T, int root, f3 o, f3 d) {
+    T.r = ray_pre(o, d);
+    T.best = INFINITY;
+    T.prim = -1;
+    T.node = root;
+    T.sp = 0;
+}
+
+// returns true when the ray is done (T.best, T.prim hold the closest hit)
+template <int kStack>
+__device__ __forceinline__ bool trace_steps(const SceneView& S, TraceState& T, int* stack, int max_steps,
+                                            unsigned& nodes, unsigned& tris) {
+    const RayPre& r = T.r;
+    for (int step = 0; step < max_steps; ++step) {
+        const float4* nd = S.bvh + 4 * T.node;
+        ++nodes;
+        float4 a = nd[0], b = nd[1], c = nd[2];
+        int4 lk = *reinterpret_cast<const int4*>(nd + 3);
+        float tn0, tn1;
+        bool h0 = box_hit(r, a.x, a.y, a.z, a.w, b.x, b.y, T.best, tn0);
+        bool h1 = box_hit(r, b.z, b.w, c.x, c.y, c.z, c.w, T.best, tn1);
+        if (h0 && lk.z > 0) {
+            tris += lk.z;
+            for (int k = lk.x; k < lk.x + lk.z; ++k) {
+                const float4* tp = S.tri + 3 * k;
+                float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
+                float t = tri_hit(r, xyz(p0), xyz(p1), xyz(p2), T.best * 1.0000001f);
+                int id = __float_as_int(p0.w);
+                if (t > 0.f && (t < T.best || (t == T.best && id < T.prim))) {
+                    T.best = t;
+                    T.prim = id;
+                }
+            }
+            h0 = false;
+        }
+        if (h1 && lk.w > 0) {
+            tris += lk.w;
+            for (int k = lk.y; k < lk.y + lk.w; ++k) {
+                const float4* tp = S.tri + 3 * k;
+                float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
+                float t = tri_hit(r, xyz(p0), xyz(p1), xyz(p2), T.best * 1.0000001f);
+                int id = __float_as_int(p0.w);
+                if (t > 0.f && (t < T.best || (t == T.best && id < T.prim))) {
+                    T.best = t;
+                    T.prim = id;
+                }
+            }
+            h1 = false;
+        }
+        h0 = h0 && lk.x >= 0 && tn0 < T.best;
+        h1 = h1 && lk.y >= 0 && tn1 < T.best;
+        if (h0 && h1) {
+            int nearc = tn0 <= tn1 ? lk.x : lk.y;
+            int farc = tn0 <= tn1 ? lk.y : lk.x;
+            if (T.sp < kStack) stack[(T.sp++) * kTraceBlock] = farc;
+            T.node = nearc;
+        } else if (h0) {
+            T.node = lk.x;
+        } else if (h1) {
+            T.node = lk.y;
+        } else {
+            if (T.sp == 0) return true;
+            T.node = stack[(--T.sp) * kTraceBlock];
+        }
+    }
+    return false;
+}
+
 // device-wide counter add with one atomic per wave
 __device__ __forceinline__ void wave_add_u64(unsigned long long* dst, unsigned v) {
     unsigned long long s = v;

@@ -88,6 +88,8 @@ struct Counters {
     int32_t n_events;
     int32_t iter;            // current iteration (incremented at the start of each one)
     int32_t pad;
+    int32_t trace_next;      // next ray of a closest-hit launch (reset by its last block)
+    int32_t trace_done;      // blocks of that launch that finished
     unsigned long long paths, vertices, photons, photon_segments, merges, nee_visible, events;
     unsigned long long camera_rays, shadow_rays, photon_rays;
     unsigned long long photon_items, photon_continued, grid_cells, candidates;

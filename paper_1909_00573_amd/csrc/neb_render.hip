@@ -285,23 +285,48 @@ __global__ void __launch_bounds__(kTraceBlock) k_extend(SceneView S, const Scene
                                                         int32_t* next_count, int2* __restrict__ hits,
                                                         unsigned long long* rays, Counters* cnt, HitBins B) {
     __shared__ int stack[kStack * kTraceBlock];
-    int n = *count;
+    const int n = *count;
     if (blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
     unsigned traced = 0, nodes = 0, tris = 0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        float t;
-        float4 d = dir[i];
-        const int sid = tag_scene(fbits(d.w));
-        int root = sc[sid].bvh_root;
-        f3 o = xyz(org[i]);
-        int prim = trace<false, kStack>(S, root, o, xyz(d), INFINITY, t, stack + threadIdx.x, nodes, tris);
-        hits[i] = make_int2(fbits(t), prim);
-        if (B.bin) {
-            int b = prim >= 0 ? hit_bin(B, sid, o + xyz(d) * t) : B.n_bins;
-            B.bin[i] = b;
-            atomicAdd(&B.count[b], 1);
+    // Each lane holds one ray; a lane whose ray ends takes the next one from
+    // the launch's work counter (one atomic per wave), so short rays do not
+    // leave lanes idle behind long ones.
+    constexpr int kSteps = 16;
+    int i = -1;  // this lane's ray; >= n once the queue is exhausted
+    TraceState T;
+    f3 o = mk3(0.f, 0.f, 0.f), dd = mk3(0.f, 0.f, 1.f);
+    int sid = 0;
+    for (;;) {
+        const bool need = i < 0;
+        const int got = wave_reserve(&cnt->trace_next, need);
+        if (need) {
+            i = got < n ? got : n;
+            if (i < n) {
+                float4 d4 = dir[i];
+                sid = tag_scene(fbits(d4.w));
+                o = xyz(org[i]);
+                dd = xyz(d4);
+                trace_begin(T, sc[sid].bvh_root, o, dd);
+            }
         }
-        ++traced;
+        const bool act = i < n;
+        if (!__any(act)) break;
+        if (act && trace_steps<kStack>(S, T, stack + threadIdx.x, kSteps, nodes, tris)) {
+            hits[i] = make_int2(fbits(T.best), T.prim);
+            if (B.bin) {
+                int b = T.prim >= 0 ? hit_bin(B, sid, o + dd * T.best) : B.n_bins;
+                B.bin[i] = b;
+                atomicAdd(&B.count[b], 1);
+            }
+            ++traced;
+            i = -1;
+        }
+    }
+    // the last block to finish resets the work counter for the next launch
+    __syncthreads();
+    if (threadIdx.x == 0 && atomicAdd(&cnt->trace_done, 1) == (int)gridDim.x - 1) {
+        cnt->trace_next = 0;
+        cnt->trace_done = 0;
     }
     wave_add_u64(rays, traced);
     wave_add_u64(&cnt->bvh_nodes, nodes);
@@ -1097,8 +1122,9 @@ struct HostScene {
 // stack is raised to the shallowest that holds the deepest tree)
 struct LaunchCfg {
     int stack = 32;        // LDS traversal stack entries per lane: 32, 48 or 64
-    int trace_bpc = -1;    // traversal blocks (one wave each) per CU; 0 = one block per 64 queue slots,
+    int trace_bpc = 8;     // closest-hit blocks (one wave each) per CU; 0 = one block per 64 queue slots,
                            // -1 = as many as the LDS holds
+    int nee_bpc = -1;      // NEE (shadow-ray) blocks per CU, same conventions
     int photon_bpc = 8;    // photon-merge blocks (one wave each) per CU; 0 = one block per 256 queue slots
     int photon_order = 0;  // merge photons in the spatial order of their hits
 };
@@ -1274,9 +1300,10 @@ static uint32_t next_pow2(uint64_t v) {
 
 static int lds_blocks_per_cu(int stack) { return (160 * 1024) / (stack * kTraceBlock * 4); }
 
-// blocks of a traversal launch over a queue of at most cap rays
-static int trace_grid(neb_ctx c, int64_t cap) {
-    int bpc = c->cfg.trace_bpc < 0 ? lds_blocks_per_cu(c->cfg.stack) : c->cfg.trace_bpc;
+// blocks of a traversal launch over a queue of at most cap rays, with bpc
+// blocks per CU (0: one block per 64 queue slots, -1: as many as the LDS holds)
+static int trace_grid(neb_ctx c, int64_t cap, int bpc) {
+    if (bpc < 0) bpc = lds_blocks_per_cu(c->cfg.stack);
     if (bpc > 0) return std::max(1, c->cus * bpc);
     return grid_of(cap, kTraceBlock, 1 << 20);
 }
@@ -1837,7 +1864,7 @@ static RenderArgs make_args(neb_ctx c) {
 template <int kStack>
 static void launch_extend(neb_ctx c, int64_t cap, const float4* org, const float4* dir, int32_t* count, int32_t* next,
                           unsigned long long* rays, const HitBins& B, hipStream_t s) {
-    hipLaunchKernelGGL(k_extend<kStack>, dim3(trace_grid(c, cap)), dim3(kTraceBlock), 0, s, c->view,
+    hipLaunchKernelGGL(k_extend<kStack>, dim3(trace_grid(c, cap, c->cfg.trace_bpc)), dim3(kTraceBlock), 0, s, c->view,
                        (const SceneInfo*)c->sc_dev, org, dir, (const int32_t*)count, next, c->hits, rays, c->cnt, B);
 }
 
@@ -1857,7 +1884,7 @@ static void extend(neb_ctx c, int64_t cap, const float4* org, const float4* dir,
 }
 
 static void nee(neb_ctx c, const RenderArgs& A, Images im, hipStream_t s) {
-    dim3 g(trace_grid(c, c->vcap)), b(kTraceBlock);
+    dim3 g(trace_grid(c, c->vcap, c->cfg.nee_bpc)), b(kTraceBlock);
     if (c->cfg.stack == 32)
         hipLaunchKernelGGL(k_nee<32>, g, b, 0, s, A, c->V, (const int32_t*)&c->cnt->n_vertices, im, c->pq[0],
                            &c->cnt->pcount[0]);
@@ -2313,13 +2340,16 @@ static neb_status apply_config(neb_ctx c, const neb_launch_config& cfg) {
         return fail(NEB_ERR_INVALID_ARG, "bvh_stack must be 32, 48 or 64");
     if (c->ready && cfg.bvh_stack <= c->forest_depth)
         return fail(NEB_ERR_CAPACITY, "bvh_stack must exceed the deepest BVH");
-    if (cfg.trace_blocks_per_cu < 0 || cfg.trace_blocks_per_cu > lds_blocks_per_cu(cfg.bvh_stack))
+    if (cfg.trace_blocks_per_cu < -1 || cfg.trace_blocks_per_cu > lds_blocks_per_cu(cfg.bvh_stack))
         return fail(NEB_ERR_INVALID_ARG, "trace_blocks_per_cu out of range for this stack");
+    if (cfg.nee_blocks_per_cu < -1 || cfg.nee_blocks_per_cu > lds_blocks_per_cu(cfg.bvh_stack))
+        return fail(NEB_ERR_INVALID_ARG, "nee_blocks_per_cu out of range for this stack");
     if (cfg.photon_blocks_per_cu < 0 || cfg.photon_blocks_per_cu > 64)
         return fail(NEB_ERR_INVALID_ARG, "photon_blocks_per_cu out of range (0..64)");
     if (cfg.photon_order != 0 && cfg.photon_order != 1) return fail(NEB_ERR_INVALID_ARG, "photon_order must be 0 or 1");
     c->cfg.stack = cfg.bvh_stack;
     c->cfg.trace_bpc = cfg.trace_blocks_per_cu;
+    c->cfg.nee_bpc = cfg.nee_blocks_per_cu;
     c->cfg.photon_bpc = cfg.photon_blocks_per_cu;
     c->cfg.photon_order = cfg.photon_order;
     drop_graph(c);
@@ -2335,6 +2365,7 @@ extern "C" neb_status neb_get_launch_config(neb_ctx c, neb_launch_config* cfg) {
     if (!c || !cfg) return fail(NEB_ERR_INVALID_ARG, "null pointer");
     cfg->bvh_stack = c->cfg.stack;
     cfg->trace_blocks_per_cu = c->cfg.trace_bpc < 0 ? lds_blocks_per_cu(c->cfg.stack) : c->cfg.trace_bpc;
+    cfg->nee_blocks_per_cu = c->cfg.nee_bpc < 0 ? lds_blocks_per_cu(c->cfg.stack) : c->cfg.nee_bpc;
     cfg->photon_blocks_per_cu = c->cfg.photon_bpc;
     cfg->photon_order = c->cfg.photon_order;
     return NEB_OK;
@@ -2355,9 +2386,10 @@ static neb_status time_config(neb_ctx c, const neb_launch_config& cfg, int n, co
 }
 
 // Picks the launch shapes by timing real iterations of this context:
-// first the traversal stack depth and resident traversal blocks per CU
-// (closest-hit and shadow rays), then the photon-merge grid.  The context
-// is reset afterwards (images, statistics, octrees, iteration counter).
+// first the traversal stack depth and resident closest-hit blocks per CU,
+// then the NEE (shadow-ray) blocks per CU, then the photon stage (order
+// and merge grid).  The context is reset afterwards (images, statistics,
+// octrees, iteration counter).
 extern "C" neb_status neb_autotune(neb_ctx c, int32_t trial_iterations, void* stream, neb_launch_config* chosen) {
     if (!c) return fail(NEB_ERR_INVALID_ARG, "null context");
     if (trial_iterations < 1 || trial_iterations > 64) return fail(NEB_ERR_INVALID_ARG, "trial_iterations out of range (1..64)");
@@ -2369,18 +2401,18 @@ extern "C" neb_status neb_autotune(neb_ctx c, int32_t trial_iterations, void* st
     bool was_on = c->prof_on;
     c->prof_on = true;
     LaunchCfg keep = c->cfg;
-    neb_launch_config best{c->cfg.stack, c->cfg.trace_bpc, c->cfg.photon_bpc, c->cfg.photon_order};
+    neb_launch_config best{c->cfg.stack, -1, -1, c->cfg.photon_bpc, c->cfg.photon_order};
     st = render_n(c, 1, s);  // warm-up: octree and caches
     double best_ms = 1e300;
-    const int trace_k[3] = {K_EXTEND_CAMERA, K_EXTEND_PHOTON, K_NEE};
+    const int trace_k[2] = {K_EXTEND_CAMERA, K_EXTEND_PHOTON};
     for (int stack : {32, 48, 64}) {
         if (st != NEB_OK) break;
         if (stack <= c->forest_depth) continue;
         int maxb = lds_blocks_per_cu(stack);
         for (int b : {0, 4, 8, maxb}) {
-            neb_launch_config cfg{stack, b, best.photon_blocks_per_cu, best.photon_order};
+            neb_launch_config cfg{stack, b, -1, best.photon_blocks_per_cu, best.photon_order};
             double ms = 0.0;
-            st = time_config(c, cfg, trial_iterations, trace_k, 3, s, ms);
+            st = time_config(c, cfg, trial_iterations, trace_k, 2, s, ms);
             if (st != NEB_OK) break;
             if (ms < best_ms) {
                 best_ms = ms;
@@ -2390,12 +2422,26 @@ extern "C" neb_status neb_autotune(neb_ctx c, int32_t trial_iterations, void* st
         }
     }
     best_ms = 1e300;
+    const int nee_k[1] = {K_NEE};
+    for (int b : {0, 4, 8, lds_blocks_per_cu(best.bvh_stack)}) {
+        if (st != NEB_OK) break;
+        neb_launch_config cfg{best.bvh_stack, best.trace_blocks_per_cu, b, best.photon_blocks_per_cu,
+                              best.photon_order};
+        double ms = 0.0;
+        st = time_config(c, cfg, trial_iterations, nee_k, 1, s, ms);
+        if (st != NEB_OK) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best.nee_blocks_per_cu = b;
+        }
+    }
+    best_ms = 1e300;
     // the photon stage: ordering (which also adds to the photon traversal) and the merge grid
     const int photon_k[3] = {K_PHOTON, K_PHOTON_ORDER, K_EXTEND_PHOTON};
     for (int order : {1, 0}) {
         for (int pb : {0, 8, 16, 32, 64}) {
             if (st != NEB_OK) break;
-            neb_launch_config cfg{best.bvh_stack, best.trace_blocks_per_cu, pb, order};
+            neb_launch_config cfg{best.bvh_stack, best.trace_blocks_per_cu, best.nee_blocks_per_cu, pb, order};
             double ms = 0.0;
             st = time_config(c, cfg, trial_iterations, photon_k, 3, s, ms);
             if (st != NEB_OK) break;

@@ -179,7 +179,7 @@ def test_autotune_changes_speed_not_results(neb, batch_scenes):
     T = neb.BatchRenderer(scenes, flags=neb.FLAG_SINGLE_THREAD_OCTREE, spp=spp)
     cfg = T.autotune(1)
     assert cfg["bvh_stack"] in (32, 48, 64)
-    assert 0 <= cfg["trace_blocks_per_cu"] <= 20
+    assert 0 <= cfg["trace_blocks_per_cu"] <= 20 and 0 <= cfg["nee_blocks_per_cu"] <= 20
     assert 0 <= cfg["photon_blocks_per_cu"] <= 64
     assert cfg["photon_order"] in (0, 1)
     assert T.launch_config() == cfg
