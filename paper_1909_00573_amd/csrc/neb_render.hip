@@ -584,10 +584,16 @@ __global__ void __launch_bounds__(kTraceBlock) k_nee(RenderArgs A, VertexStore V
 // merge structure: hash grid of cell size 2r over the non-delta view vertices
 // (count -> exclusive scan -> scatter); count[] returns to zero after scatter
 // ---------------------------------------------------------------------------
+// Bucket of a cell: the cells of one 4 x 4 x 4 block take 64 consecutive
+// buckets (Morton order inside the block), the blocks are hashed with the
+// scene.  The <= 8 cells around a photon hit, and the cells of neighbouring
+// hits, then share a few cache lines of the count/start tables.
 __device__ __forceinline__ uint32_t cell_hash(int cx, int cy, int cz, int scene, int32_t T) {
-    return (((uint32_t)cx * 73856093u) ^ ((uint32_t)cy * 19349663u) ^ ((uint32_t)cz * 83492791u) ^
-            ((uint32_t)scene * 2654435761u)) &
-           (uint32_t)(T - 1);
+    const uint32_t lo = (uint32_t)((cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2) | ((cx & 2) << 2) | ((cy & 2) << 3) |
+                                   ((cz & 2) << 4));
+    const uint32_t hi = ((uint32_t)(cx >> 2) * 73856093u) ^ ((uint32_t)(cy >> 2) * 19349663u) ^
+                        ((uint32_t)(cz >> 2) * 83492791u) ^ ((uint32_t)scene * 2654435761u);
+    return ((hi << 6) | lo) & (uint32_t)(T - 1);
 }
 __device__ __forceinline__ uint32_t point_hash(f3 p, float inv_cell, int scene, int32_t T) {
     return cell_hash((int)floorf(p.x * inv_cell), (int)floorf(p.y * inv_cell), (int)floorf(p.z * inv_cell), scene, T);
