@@ -9,6 +9,7 @@ from .scenes import (  # noqa: F401
     MAT_DTYPE, LIGHT_DTYPE, CAM_DTYPE, Scene,
     MAT_LAMBERT, MAT_MIRROR, MAT_DIELECTRIC, MAT_GGX,
     tiny_box, room, city_block, batch_rooms, box_room, furnace_sphere, disk_light_plane,
+    point_light_plane,
     random_triangle_soup, deposit_stream, plane_deposits, query_points,
     scene_by_name,
 )

@@ -466,6 +466,26 @@ def disk_light_plane(disk_radius=0.5, height=1.0, radiance=2.0, albedo=0.6, n_se
                  octree_capacity=1 << 14, merge_radius=0.01, seed=seed, scene_id=0)
 
 
+def point_light_plane(height=1.0, power=40.0, albedo=0.6, width=8, height_px=8, spp=16, seed=13,
+                      plane_half=4.0, merge_radius=0.05):
+    """An isotropic point light of `power` watts at `height` above a grey
+    Lambertian plane; the camera sits halfway between them on the axis and
+    looks straight down with a narrow field of view.  Path length 2
+    (direct light only)."""
+    mats = _materials([{"albedo": (albedo,) * 3}])
+    M = _Mesh()
+    M.quad([-plane_half, 0, -plane_half], [-plane_half, 0, plane_half],
+           [plane_half, 0, plane_half], [plane_half, 0, -plane_half], 0)   # n=+y
+    v, t, m = M.build()
+    lights = np.zeros(1, LIGHT_DTYPE)
+    lights["pos"][0] = (0.0, height, 0.0)
+    lights["power"][0] = (power,) * 3
+    return Scene("point_light", v, t, m, mats, lights,
+                 _camera([0.0, height * 0.5, 0.0], [0.0, 0.0, 0.0], (0, 0, 1), 20.0),
+                 width=width, height=height_px, spp=spp, max_path_len=2,
+                 octree_capacity=1 << 14, merge_radius=merge_radius, seed=seed, scene_id=0)
+
+
 def random_triangle_soup(n_tris, seed, extent=1.0):
     """Random triangles in [0, extent]^3 (for intersection tests)."""
     rng = np.random.default_rng(seed)

@@ -21,6 +21,11 @@
  *   - MIS: balance heuristic eq. (misweight) with the path densities of
  *     eq. (rhpdf), (neepdf), (photonpdf) summed as in eq. (misw); here
  *     evaluated as EXPLICIT products over the whole path (no recursion).
+ *   - optional conventional light photons (Sec. 4, eq. stdphotonpdf and
+ *     the n_LP sum of eq. misw): n_LP photons per iteration, emitted from
+ *     a light picked by power, merged at every non-delta hit with the view
+ *     vertices within r (paths of length k + j for a view vertex of depth
+ *     k and a photon of j segments).
  *   - density octree: Sec. 5.1 (counting), 5.2 (split, children start at
  *     parent/4), 5.3 (rho = c / |B cap P|, eq. octdensity), time
  *     integration (threshold and scale follow the iteration count), 5.4
@@ -50,10 +55,18 @@
  *     there, but they emit photons); occluded NEEs emit no photon.
  *   - delta BSDF pdfs are the discrete lobe probabilities.
  *   - no Russian roulette; geometric normals only; no eta^2 scaling.
+ *   - light photons: area lights emit with the cosine lobe around their
+ *     normal, point lights uniformly over the sphere; the light vertex of
+ *     their paths is the sampled light point; the density rho_{L-1} that
+ *     their paths' NEB technique needs is queried at the photon's first
+ *     hit (with that hit's normal), also when the merge happens there.
  *   - uniform random numbers are (x >> 8) * 2^-24 of Philox-4x32-10
  *     outputs, counter (pixel, iteration, depth, stream), key (seed,
  *     scene id); photon streams use counter (origin pixel, iteration,
- *     16 * origin depth + photon bounce, PHOTON).
+ *     16 * origin depth + photon bounce, PHOTON); light photon i draws
+ *     its light point with (i, iteration, 0, LIGHT), its direction with
+ *     (i, iteration, 1, LIGHT) and its scattering after hit j with
+ *     (i, iteration, j - 1, PHOTON).
  *
  * Precision: FP64 everywhere except the octree's cell addressing, which
  * follows the FP32 arithmetic of the class in Appendix B exactly (build
@@ -94,7 +107,7 @@ static inline double comp(v3 a, int i) { return i == 0 ? a.x : (i == 1 ? a.y : a
 /* ------------------------------------------------------------------ */
 /* Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11)                   */
 /* ------------------------------------------------------------------ */
-enum { TAG_CAMERA = 1, TAG_BSDF = 2, TAG_NEE = 3, TAG_PHOTON = 4 };
+enum { TAG_CAMERA = 1, TAG_BSDF = 2, TAG_NEE = 3, TAG_PHOTON = 4, TAG_LIGHT = 7 };
 
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
     uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
@@ -140,11 +153,13 @@ typedef struct {
     int32_t win_x0, win_y0, win_x1, win_y1;   /* pixel window, exclusive end; 0,0,0,0 = all */
     int32_t n_threads;
     int32_t record_paths;          /* record vertex sequences of the first iteration */
+    int32_t light_photons;         /* n_LP: conventional light photons per iteration (0 = none) */
 } o_params;
 
 typedef struct {
     double paths, vertices, photons, photon_segments, merges, nee_visible, events, rays;
     int64_t oct_nodes, oct_depth, oct_overflow, oct_ledger, oct_deposits, oct_capacity, oct_rejected;
+    double light_photons;          /* light photons emitted */
 } o_stats;
 
 /* path record entry (first iteration only): one per (path, depth) */
@@ -824,9 +839,15 @@ typedef struct {
     double rho;            /* density of NEE vertices at x_{L-1} */
     double r2pi;           /* pi r^2 */
     int photons;           /* n_P > 0 */
+    double n_lp;           /* n_LP, light photons per iteration (0 = none) */
 } o_path;
 
-/* returns all technique densities: out[0] = e, out[1] = E, out[1+k] = P_k */
+/* index of the conventional-photon technique LP_k in the technique list */
+static int lp_tech(int L, int k) { return 1 + (L >= 2 ? L - 2 : 0) + k; }
+static int n_techniques(int L) { return 2 + (L >= 2 ? L - 2 : 0) + (L >= 1 ? L - 1 : 0); }
+
+/* returns all technique densities: out[0] = e, out[1] = E, out[1+k] = P_k
+ * (k = 1 .. L-2), out[lp_tech(L, k)] = LP_k (k = 1 .. L-1) */
 static void path_densities(const o_path* P, double* out) {
     int L = P->L;
     double f[MAXL], r[MAXL];
@@ -866,13 +887,35 @@ static void path_densities(const o_path* P, double* out) {
         }
         out[1 + k] = pp;
     }
+    /* conventional light photons, eq. (stdphotonpdf): the light point (p_light),
+     * the emission toward x_{L-1} (p_{L -> L-1}: cosine lobe of an area light,
+     * uniform sphere of a point light, converted to area at x_{L-1}), the
+     * backward walk down to x_k, the camera walk up to x_k and the merge
+     * disc pi r^2; n_LP photons per iteration */
+    double rl = 0.0;
+    if (L >= 1) {
+        v3 d = sub(P->seg_b[L - 1], P->seg_a[L - 1]);
+        double d2 = dot(d, d);
+        v3 w = scl(d, 1.0 / sqrt(d2));
+        double emit = P->hittable ? fmax(0.0, -dot(P->nb[L - 1], w)) / PI : 1.0 / (4.0 * PI);
+        rl = emit * fabs(dot(P->na[L - 1], w)) / d2;
+    }
+    for (int k = 1; k <= L - 1; ++k) {
+        double q = 0.0;
+        if (P->n_lp > 0.0 && !mat_is_delta(P->mat[k])) {
+            q = P->n_lp * P->p_light * P->r2pi * rl;
+            for (int i = k; i <= L - 2; ++i) q *= r[i];
+            for (int i = 1; i <= k - 1; ++i) q *= f[i];
+        }
+        out[lp_tech(L, k)] = q;
+    }
 }
 
-/* tech: 0 = e, 1 = E, 1 + k = P_k */
+/* tech: 0 = e, 1 = E, 1 + k = P_k, lp_tech(L, k) = LP_k */
 static double mis_weight(const o_path* P, int tech) {
-    double pd[MAXL + 2];
+    double pd[2 * MAXL + 2];
     path_densities(P, pd);
-    int nt = 2 + (P->L >= 2 ? P->L - 2 : 0);
+    int nt = n_techniques(P->L);
     double sum = 0.0;
     for (int i = 0; i < nt; ++i) sum += pd[i];
     if (!(sum > 0.0)) return 0.0;
@@ -1032,7 +1075,7 @@ static double query_density(const o_iter* it, v3 x, v3 n) {
     return 0.0;
 }
 
-typedef struct { double *e, *E, *P; o_stats st; } o_accum;
+typedef struct { double *e, *E, *P, *LP; o_stats st; } o_accum;
 
 static void add_px(double* img, int pix, v3 c) {
     img[3 * pix] += c.x; img[3 * pix + 1] += c.y; img[3 * pix + 2] += c.z;
@@ -1068,6 +1111,7 @@ static void nee_and_photon(const o_iter* it, int vi, int iter, o_accum* acc) {
             P.seg_a[m] = x; P.seg_b[m] = ls.x; P.na[m] = n; P.nb[m] = ls.n;
             P.p_light = ls.p_light; P.hittable = ls.hittable; P.rho = rho; P.r2pi = r2pi;
             P.photons = prm->enable_photons;
+            P.n_lp = prm->light_photons;
             double w = mis_weight(&P, 1);
             add_px(acc->E, pix, scl(hmul(hmul(tau, f), ls.dE), w));
         }
@@ -1123,6 +1167,7 @@ static void nee_and_photon(const o_iter* it, int vi, int iter, o_accum* acc) {
                 P.seg_a[k + j] = ypos[0]; P.seg_b[k + j] = ls.x; P.na[k + j] = yn[0]; P.nb[k + j] = ls.n;
                 P.p_light = ls.p_light; P.hittable = ls.hittable; P.rho = rho; P.r2pi = r2pi;
                 P.photons = 1;
+                P.n_lp = prm->light_photons;
                 double w = mis_weight(&P, 1 + k);
                 v3 c = scl(hmul(hmul(it->tau[qid], f), phi), w / r2pi);
                 add_px(acc->P, it->pixel[it->v_path[q]], c);
@@ -1154,8 +1199,113 @@ static void emission_event(const o_iter* it, int e, o_accum* acc) {
     }
     P.r2pi = PI * it->prm->merge_radius * it->prm->merge_radius;
     P.photons = it->prm->enable_photons;
+    P.n_lp = it->prm->light_photons;
     double w = mis_weight(&P, 0);
     add_px(acc->e, it->pixel[p], scl(it->ev_val[e], w));
+}
+
+/* pass 2 (d), optional conventional photons (Sec. 4, eq. stdphotonpdf):
+ * light photon i of this iteration.  A light is picked by power and a
+ * point on it as for NEE (stream LIGHT, word 0); the direction (word 1)
+ * follows the cosine lobe of an area light or the uniform sphere of a
+ * point light, so the emitted flux is L_e pi / p_light (area) or
+ * power / P_sel (point), shared by the n_LP photons.  At every non-delta
+ * hit y_j the view vertices within r of depth k with k + j <= maxlen
+ * receive w_LP tau f Phi / (pi r^2).  The density rho at the first hit
+ * (the start of the NEB technique for these paths) is queried once. */
+static void light_photon(const o_iter* it, int i, int iter, o_accum* acc) {
+    const o_scene* s = it->s;
+    const o_params* prm = it->prm;
+    if (s->nlights == 0) return;
+    double u[4], u2[4];
+    uniforms(it->key, (uint32_t)i, (uint32_t)iter, 0u, TAG_LIGHT, u);
+    uniforms(it->key, (uint32_t)i, (uint32_t)iter, 1u, TAG_LIGHT, u2);
+    int li = 0;
+    while (li < s->nlights - 1 && !(u[0] < s->light_cdf[li])) ++li;
+    double psel = s->light_psel[li];
+    double nlp = (double)prm->light_photons;
+    int L = prm->max_path_len;
+    v3 ypos[MAXL], yn[MAXL];
+    const o_material* ymat[MAXL];
+    v3 o, d, phi;
+    double p_light;
+    int hittable;
+    if (s->light_tri[li] >= 0) {
+        int t = s->light_tri[li];
+        double su = sqrt(u[1]);
+        double b0 = 1.0 - su, b1 = u[2] * su;
+        v3 y0 = add(add(scl(s->p0[t], b0), scl(s->p1[t], b1)), scl(s->p2[t], 1.0 - b0 - b1));
+        v3 ln = s->ng[t], t1, t2;
+        onb(ln, &t1, &t2);
+        double rr = sqrt(u2[0]), ph = 2.0 * PI * u2[1], z = sqrt(fmax(0.0, 1.0 - u2[0]));
+        d = nrm(add(add(scl(t1, rr * cos(ph)), scl(t2, rr * sin(ph))), scl(ln, z)));
+        if (dot(d, ln) <= 0.0) return;
+        p_light = psel / s->area[t];
+        phi = scl(from_f(s->mats[s->mat[t]].emission), PI / (p_light * nlp));
+        o = offset_origin(s, y0, ln, d);
+        ypos[0] = y0; yn[0] = ln;
+        hittable = 1;
+    } else {
+        const o_point_light* l = &s->pl[s->light_pl[li]];
+        double z = 1.0 - 2.0 * u2[0], rr = sqrt(fmax(0.0, 1.0 - z * z)), ph = 2.0 * PI * u2[1];
+        d = mk(rr * cos(ph), rr * sin(ph), z);
+        p_light = psel;
+        phi = scl(from_f(l->power), 1.0 / (psel * nlp));
+        o = from_f(l->pos);
+        ypos[0] = o; yn[0] = d;
+        hittable = 0;
+    }
+    acc->st.light_photons += 1;
+    double r = prm->merge_radius, r2pi = PI * r * r, rho1 = 0.0;
+    for (int j = 1; j <= L - 1; ++j) {
+        double t;
+        int prim = closest_hit(s, o, d, &t);
+        acc->st.rays += 1;
+        if (prim < 0) break;
+        acc->st.photon_segments += 1;
+        v3 y = add(o, scl(d, t));
+        v3 ny = s->ng[prim];
+        const o_material* my = &s->mats[s->mat[prim]];
+        ypos[j] = y; yn[j] = ny; ymat[j] = my;
+        if (j == 1 && prm->enable_photons) rho1 = query_density(it, y, ny);
+        if (!mat_is_delta(my)) {
+            v3 wd = scl(d, -1.0);
+            for (int q = 0; q < it->nvert; ++q) {
+                int k = it->v_depth[q];
+                if (k + j > L) continue;
+                size_t qid = IDX(it, it->v_path[q], k);
+                v3 dq = sub(it->pos[qid], y);
+                if (dot(dq, dq) >= r * r) continue;
+                const o_material* mq = &s->mats[it->mat[qid]];
+                if (mat_is_delta(mq)) continue;
+                v3 f = bsdf_f(mq, it->nrml[qid], it->wo[qid], wd);
+                if (is_zero(f)) continue;
+                o_path P;
+                P.L = k + j;
+                path_from_camera(it, it->v_path[q], k, &P);
+                /* from the merge point (photon hit geometry) back along the photon to the light */
+                P.seg_a[k] = y; P.seg_b[k] = ypos[j - 1]; P.na[k] = ny; P.nb[k] = yn[j - 1];
+                for (int ii = 1; ii <= j - 1; ++ii) {
+                    P.seg_a[k + ii] = ypos[j - ii]; P.seg_b[k + ii] = ypos[j - ii - 1];
+                    P.na[k + ii] = yn[j - ii]; P.nb[k + ii] = yn[j - ii - 1];
+                    P.mat[k + ii] = ymat[j - ii]; P.vn[k + ii] = yn[j - ii];
+                }
+                P.p_light = p_light; P.hittable = hittable; P.rho = rho1; P.r2pi = r2pi;
+                P.photons = prm->enable_photons;
+                P.n_lp = nlp;
+                double w = mis_weight(&P, lp_tech(P.L, k));
+                add_px(acc->LP, it->pixel[it->v_path[q]], scl(hmul(hmul(it->tau[qid], f), phi), w / r2pi));
+                acc->st.merges += 1;
+            }
+        }
+        if (j == L - 1 || mat_is_black(my)) break;
+        uniforms(it->key, (uint32_t)i, (uint32_t)iter, (uint32_t)(j - 1), TAG_PHOTON, u);
+        bsdf_sample bs = sample_bsdf(my, ny, scl(d, -1.0), u);
+        if (!bs.ok) break;
+        phi = hmul(phi, bs.weight);
+        o = offset_origin(s, y, ny, bs.dir);
+        d = bs.dir;
+    }
 }
 
 static int nthreads_of(const o_params* prm) {
@@ -1168,12 +1318,14 @@ static int nthreads_of(const o_params* prm) {
 }
 
 int32_t orc_render(const o_scene* s, const o_params* prm, int32_t n_iter, int32_t first_iter,
-                   o_octree* oct, double* img_e, double* img_E, double* img_P, o_stats* st,
+                   o_octree* oct, double* img_e, double* img_E, double* img_P, double* img_LP, o_stats* st,
                    o_record* rec) {
     if (!s || !prm || prm->width <= 0 || prm->height <= 0 || prm->max_path_len < 1 ||
         prm->max_path_len > MAXL - 2 || n_iter < 0)
         return -1;
     if ((prm->density_mode == 0 || prm->density_mode == 1) && !oct) return -1;
+    if (prm->light_photons < 0) return -1;
+    const int L_lp = prm->max_path_len >= 2 ? prm->light_photons : 0;
     o_iter it;
     memset(&it, 0, sizeof(it));
     it.s = s; it.prm = prm; it.oct = oct;
@@ -1203,6 +1355,7 @@ int32_t orc_render(const o_scene* s, const o_params* prm, int32_t n_iter, int32_
         acc[t].e = calloc(npix, sizeof(double));
         acc[t].E = calloc(npix, sizeof(double));
         acc[t].P = calloc(npix, sizeof(double));
+        acc[t].LP = calloc(npix, sizeof(double));
     }
     memset(st, 0, sizeof(*st));
     for (int32_t ii = 0; ii < n_iter; ++ii) {
@@ -1258,6 +1411,20 @@ int32_t orc_render(const o_scene* s, const o_params* prm, int32_t n_iter, int32_
 #endif
             nee_and_photon(&it, q, iter, &acc[t]);
         }
+        /* pass 2 (d): conventional light photons */
+        if (L_lp > 0) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 8) num_threads(nth)
+#endif
+            for (int i = 0; i < L_lp; ++i) {
+#ifdef _OPENMP
+                int t = omp_get_thread_num();
+#else
+                int t = 0;
+#endif
+                light_photon(&it, i, iter, &acc[t]);
+            }
+        }
         /* pass 3 */
         for (int e = 0; e < it.nev; ++e) emission_event(&it, e, &acc[0]);
         st->paths += it.npath;
@@ -1270,13 +1437,15 @@ int32_t orc_render(const o_scene* s, const o_params* prm, int32_t n_iter, int32_
             if (img_e) img_e[i] += acc[t].e[i];
             if (img_E) img_E[i] += acc[t].E[i];
             if (img_P) img_P[i] += acc[t].P[i];
+            if (img_LP) img_LP[i] += acc[t].LP[i];
         }
         st->photons += acc[t].st.photons;
         st->photon_segments += acc[t].st.photon_segments;
         st->merges += acc[t].st.merges;
         st->nee_visible += acc[t].st.nee_visible;
         st->rays += acc[t].st.rays;
-        free(acc[t].e); free(acc[t].E); free(acc[t].P);
+        st->light_photons += acc[t].st.light_photons;
+        free(acc[t].e); free(acc[t].E); free(acc[t].P); free(acc[t].LP);
     }
     free(acc);
     if (oct) {
@@ -1296,11 +1465,15 @@ int32_t orc_render(const o_scene* s, const o_params* prm, int32_t n_iter, int32_
 /* MIS test hook: densities of all techniques of an explicit path       */
 /* ------------------------------------------------------------------ */
 /* pos: (L+1) x 3 vertex positions (camera first, light last); nrmv: the
- * same for normals (camera normal unused); mats: materials of vertices
- * 1..L-1.  Returns the number of techniques written to out. */
+ * same for normals (camera normal unused; at the light, its normal, used
+ * for an area light's emission cosine); mats: materials of vertices
+ * 1..L-1; n_lp: light photons per iteration.  out holds 2 L entries:
+ * e, E, P_1 .. P_{L-2}, LP_1 .. LP_{L-1}.  Returns the number of
+ * techniques written (2 + max(0, L-2) + max(0, L-1)). */
 int32_t orc_path_technique_densities(int32_t L, const double* pos, const double* nrmv,
                                      const o_material* mats, double p_light, int32_t hittable,
-                                     double rho, double radius, int32_t photons, double* out) {
+                                     double rho, double radius, int32_t photons, double n_lp,
+                                     double* out) {
     if (L < 1 || L > MAXL - 2) return 0;
     o_path P;
     memset(&P, 0, sizeof(P));
@@ -1316,7 +1489,7 @@ int32_t orc_path_technique_densities(int32_t L, const double* pos, const double*
         P.vn[i] = mk(nrmv[3 * i], nrmv[3 * i + 1], nrmv[3 * i + 2]);
     }
     P.p_light = p_light; P.hittable = hittable; P.rho = rho;
-    P.r2pi = PI * radius * radius; P.photons = photons;
+    P.r2pi = PI * radius * radius; P.photons = photons; P.n_lp = n_lp;
     path_densities(&P, out);
-    return 2 + (L >= 2 ? L - 2 : 0);
+    return n_techniques(L);
 }

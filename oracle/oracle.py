@@ -43,7 +43,8 @@ class Params(ctypes.Structure):
                 ("enable_photons", ctypes.c_int32),
                 ("win_x0", ctypes.c_int32), ("win_y0", ctypes.c_int32),
                 ("win_x1", ctypes.c_int32), ("win_y1", ctypes.c_int32),
-                ("n_threads", ctypes.c_int32), ("record_paths", ctypes.c_int32)]
+                ("n_threads", ctypes.c_int32), ("record_paths", ctypes.c_int32),
+                ("light_photons", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -52,7 +53,8 @@ class Stats(ctypes.Structure):
                  "events", "rays")] + \
                [(k, ctypes.c_int64) for k in
                 ("oct_nodes", "oct_depth", "oct_overflow", "oct_ledger", "oct_deposits",
-                 "oct_capacity", "oct_rejected")]
+                 "oct_capacity", "oct_rejected")] + \
+               [("light_photons", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -93,14 +95,14 @@ def lib():
         L.orc_closest_hit.argtypes = [_P, _P, _P, _P]
         L.orc_closest_hit.restype = ctypes.c_int32
         L.orc_render.argtypes = [_P, ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_int32, _P,
-                                 _P, _P, _P, ctypes.POINTER(Stats), _P]
+                                 _P, _P, _P, _P, ctypes.POINTER(Stats), _P]
         L.orc_render.restype = ctypes.c_int32
         L.orc_bsdf_eval.argtypes = [ctypes.POINTER(Material), _P, _P, _P, _P, _P]
         L.orc_bsdf_sample.argtypes = [ctypes.POINTER(Material), _P, _P, _P, _P, _P, _P]
         L.orc_bsdf_sample.restype = ctypes.c_int32
         L.orc_path_technique_densities.argtypes = [ctypes.c_int32, _P, _P, _P, ctypes.c_double,
                                                    ctypes.c_int32, ctypes.c_double, ctypes.c_double,
-                                                   ctypes.c_int32, _P]
+                                                   ctypes.c_int32, ctypes.c_double, _P]
         L.orc_path_technique_densities.restype = ctypes.c_int32
         _lib = L
     return _lib
@@ -151,14 +153,19 @@ def bsdf_sample(mat, n, wi, u):
     return ev, d, w, float(pdf[0])
 
 
-def technique_densities(pos, nrm, mats, p_light, hittable, rho, radius, photons=True):
+def technique_densities(pos, nrm, mats, p_light, hittable, rho, radius, photons=True, n_lp=None):
+    """Densities of every technique that can form the explicit path `pos`
+    (camera first, light last): [e, E, P_1 .. P_{L-2}], followed by
+    [LP_1 .. LP_{L-1}] when `n_lp` (light photons per iteration) is given."""
     L = len(pos) - 1
     pos = np.ascontiguousarray(pos, np.float64)
     nrm = np.ascontiguousarray(nrm, np.float64)
     arr = (Material * max(1, L - 1))(*mats) if L > 1 else (Material * 1)()
-    out = np.zeros(L + 2)
+    out = np.zeros(2 * L + 2)
     n = lib().orc_path_technique_densities(L, _ptr(pos), _ptr(nrm), arr, p_light, int(hittable),
-                                           rho, radius, int(photons), _ptr(out))
+                                           rho, radius, int(photons), float(n_lp or 0.0), _ptr(out))
+    if n_lp is None:
+        n = 2 + max(0, L - 2)
     return out[:n]
 
 
@@ -244,7 +251,7 @@ class OracleScene:
 
 
 def make_params(scene, density_mode=DENSITY_ROBUST, enable_photons=True, window=None, n_threads=0,
-                record=False, rho0=0.0, cam_weight=0.0, **over):
+                record=False, rho0=0.0, cam_weight=0.0, light_photons=0, **over):
     p = Params()
     p.width = over.get("width", scene.width)
     p.height = over.get("height", scene.height)
@@ -261,25 +268,28 @@ def make_params(scene, density_mode=DENSITY_ROBUST, enable_photons=True, window=
         p.win_x0, p.win_y0, p.win_x1, p.win_y1 = window
     p.n_threads = n_threads
     p.record_paths = int(record)
+    p.light_photons = int(light_photons)
     return p
 
 
 def render(scene, n_iter=None, first_iter=1, density_mode=DENSITY_ROBUST, enable_photons=True,
            window=None, n_threads=0, record=False, rho0=0.0, cam_weight=0.0, oscene=None,
-           octree=None, **over):
+           octree=None, light_photons=0, **over):
     """Render `n_iter` progressive iterations (1 spp each).  Returns a dict
-    with per-technique image sums (H, W, 3), their sum, the mean image, the
-    stats and, if requested, the first iteration's path records."""
+    with per-technique image sums (H, W, 3): e, E, P and, with
+    `light_photons` > 0 conventional photons per iteration, LP; their sum,
+    the mean image, the stats and, if requested, the first iteration's path
+    records."""
     osc = oscene or OracleScene(scene)
     prm = make_params(scene, density_mode, enable_photons, window, n_threads, record, rho0,
-                      cam_weight, **over)
+                      cam_weight, light_photons, **over)
     n_iter = scene.spp if n_iter is None else n_iter
     oct_ = octree
     if oct_ is None and density_mode in (DENSITY_SINGLE, DENSITY_ROBUST):
         lo, hi = osc.bounds()
         oct_ = Octree(lo, hi, prm.octree_capacity)
     H, W = prm.height, prm.width
-    imgs = {k: np.zeros((H, W, 3)) for k in ("e", "E", "P")}
+    imgs = {k: np.zeros((H, W, 3)) for k in ("e", "E", "P", "LP")}
     st = Stats()
     rec = None
     if record:
@@ -287,10 +297,11 @@ def render(scene, n_iter=None, first_iter=1, density_mode=DENSITY_ROBUST, enable
         rec = np.zeros(((x1 - x0) * (y1 - y0), prm.max_path_len), RECORD_DTYPE)
     rc = lib().orc_render(osc.h, ctypes.byref(prm), int(n_iter), int(first_iter),
                           oct_.h if oct_ is not None else None,
-                          _ptr(imgs["e"]), _ptr(imgs["E"]), _ptr(imgs["P"]), ctypes.byref(st),
+                          _ptr(imgs["e"]), _ptr(imgs["E"]), _ptr(imgs["P"]), _ptr(imgs["LP"]),
+                          ctypes.byref(st),
                           _ptr(rec) if rec is not None else None)
     if rc != 0:
         raise RuntimeError("oracle render failed")
-    total = imgs["e"] + imgs["E"] + imgs["P"]
+    total = imgs["e"] + imgs["E"] + imgs["P"] + imgs["LP"]
     return {"sum": total, "mean": total / max(1, n_iter), "tech": imgs, "stats": st.as_dict(),
             "records": rec, "octree": oct_, "n_iter": n_iter}
