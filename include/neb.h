@@ -77,6 +77,10 @@ typedef struct {
     int32_t flags;             /* NEB_FLAG_* */
     int32_t spp;               /* iterations this scene takes part in, counted from the last
                                   reset; 0 = every iteration (progressive) */
+    int32_t light_photons;     /* n_LP: conventional light photons traced per iteration and merged
+                                  with the view vertices (the optional technique of Sec. 4,
+                                  eq. stdphotonpdf, weighted into eq. misw); 0 = none, at most
+                                  2^26; not with NEB_DENSITY_MLP */
 } neb_params;
 
 /* Launch shapes of the traversal and photon kernels (neb_autotune picks
@@ -132,6 +136,9 @@ typedef struct {
     int64_t camera_rays, shadow_rays;
     /* BVH nodes fetched and triangles tested by all traversals */
     int64_t bvh_nodes, bvh_tris;
+    /* conventional light photons emitted (their segments and merges are
+     * counted with the NEB photons') */
+    int64_t light_photons;
 } neb_stats;
 
 /* per-kernel device time, collected with HIP events on the launch stream */
@@ -238,6 +245,14 @@ neb_status neb_get_technique_images(neb_ctx ctx, float* e, float* E, float* P, i
                                     void* stream);
 neb_status neb_get_scene_technique_images(neb_ctx ctx, int32_t scene, float* e, float* E, float* P,
                                           int32_t is_device_ptr, void* stream);
+
+/* Mean radiance of the conventional light-photon merges (LP, Sec. 4,
+ * eq. stdphotonpdf) of scene `scene`: height*width*3 floats, zero when the
+ * scene traces no light photons.  The image of neb_get_scene_image is the
+ * sum of e, E, P and LP.  LP is device memory if is_device_ptr, else host
+ * memory (then the call synchronises). */
+neb_status neb_get_scene_light_photon_image(neb_ctx ctx, int32_t scene, float* LP, int32_t is_device_ptr,
+                                            void* stream);
 
 /* Density of NEE vertices at n surface points from the context's octree in
  * its current state (robust five-probe query; tangents from the normal).

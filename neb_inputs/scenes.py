@@ -471,11 +471,14 @@ def point_light_plane(height=1.0, power=40.0, albedo=0.6, width=8, height_px=8, 
     """An isotropic point light of `power` watts at `height` above a grey
     Lambertian plane; the camera sits halfway between them on the axis and
     looks straight down with a narrow field of view.  Path length 2
-    (direct light only)."""
-    mats = _materials([{"albedo": (albedo,) * 3}])
+    (direct light only).  A small black triangle above a far corner gives
+    the scene a non-flat bounding box; it shades nothing the camera sees."""
+    mats = _materials([{"albedo": (albedo,) * 3}, {"albedo": (0.0,) * 3}])
     M = _Mesh()
     M.quad([-plane_half, 0, -plane_half], [-plane_half, 0, plane_half],
            [plane_half, 0, plane_half], [plane_half, 0, -plane_half], 0)   # n=+y
+    c = plane_half * 0.9
+    M.add([[c, 2 * height, c], [c - 0.1, 2 * height, c], [c, 2 * height, c - 0.1]], [[0, 1, 2]], 1)
     v, t, m = M.build()
     lights = np.zeros(1, LIGHT_DTYPE)
     lights["pos"][0] = (0.0, height, 0.0)

@@ -16,7 +16,8 @@ constexpr int kMaxPathLen = 16;
 constexpr int kBvhStackMax = 64;           // deepest LDS traversal stack (entries per lane)
 constexpr int kTraceBlock = 64;            // threads per traversal block (one wave)
 
-constexpr uint32_t kTagCamera = 1, kTagBsdf = 2, kTagNee = 3, kTagPhoton = 4, kTagMlp = 5, kTagProbe = 6;
+constexpr uint32_t kTagCamera = 1, kTagBsdf = 2, kTagNee = 3, kTagPhoton = 4, kTagMlp = 5, kTagProbe = 6,
+                   kTagLight = 7;
 
 // Static scalars of one octree (the members of the class of Appendix B that
 // do not change with the iteration), passed by value.  Several octrees can
@@ -87,13 +88,14 @@ struct Counters {
     int32_t n_vertices;
     int32_t n_events;
     int32_t iter;            // current iteration (incremented at the start of each one)
-    int32_t pad;
+    int32_t lp_count;        // light photons emitted this iteration (the first entries of photon queue 0)
     int32_t trace_next;      // next ray of a closest-hit launch (reset by its last block)
     int32_t trace_done;      // blocks of that launch that finished
     unsigned long long paths, vertices, photons, photon_segments, merges, nee_visible, events;
     unsigned long long camera_rays, shadow_rays, photon_rays;
     unsigned long long photon_items, photon_continued, grid_cells, candidates;
     unsigned long long bvh_nodes, bvh_tris;   // traversal work of closest-hit and shadow rays
+    unsigned long long light_photons;
 };
 
 // octree (neb_octree.hip)

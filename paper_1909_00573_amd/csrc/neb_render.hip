@@ -8,12 +8,18 @@
 //           shadow ray, L_E, and the photon of flux dE / rho (eq. flux) with
 //           its first scatter at the vertex -> merge grid over the view
 //           vertices -> [extend -> merge + scatter] x (maxlen - 2)
+//           optional conventional light photons (Sec. 4): emitted from the
+//           lights before the NEB photons enter the same queue, their first
+//           hit gets its density, then they share the merge loop
 //   pass 3  emitter-hit events weighted with w_e (Sec. 3.3)
-// MIS weights (Sec. 4, balance heuristic over e, E and P_k) are evaluated
-// with running ratios carried by the view and photon states, so no event
-// needs the full path: each view vertex stores B = A_{m-2} + [x_{m-1} not
-// delta] and g = |cos out at x_{m-1}| / (pdf at x_{m-1} * |cos in at x_m|),
-// each photon carries U and h with the same meaning from the light side.
+// MIS weights (Sec. 4, balance heuristic over e, E, P_k and, with light
+// photons, LP_k) are evaluated with running ratios carried by the view and
+// photon states, so no event needs the full path: each view vertex stores
+// B = A_{m-2} + [x_{m-1} not delta] and g = |cos out at x_{m-1}| / (pdf at
+// x_{m-1} * |cos in at x_m|), each photon carries U and h with the same
+// meaning from the light side.  The light-photon terms of eq. misw sum to
+// n_LP pi r^2 p_{l -> l-1} (A_{l-2} + [x_{l-1} not delta]); a photon folds
+// the constant factor they add to its merges into its flux and its U.
 //
 // A context holds a batch of 1..256 scenes that share every pool: a BVH
 // forest (one root per scene in one node pool), one octree node pool split
@@ -51,9 +57,12 @@ constexpr int kMaxMaterials = 65536;
 //        q3 (A_{m-1}, |cos out|/pdf at the last vertex, last vertex non-delta, last vertex index)
 //   vertex v0 (pos, global pixel)  v1 (n, tag: depth | scene | material)  v2 (wo, B)  v3 (tau, g)
 //   event e0 (tau*Le, p_light/f or 0 for a direct hit)
-//         e1 (pi r^2 A, prev non-delta, prev vertex, global pixel)
+//         e1 (pi r^2 A, prev non-delta + light-photon term, prev vertex, global pixel)
 //   photon p0 (o, global origin pixel)  p1 (d, tag: 16*origin depth + bounce)
 //          p2 (Phi, |cos out|/pdf)  pu (U)
+//          a light photon has origin depth 0 and p0.w = its scene's first
+//          pixel + its index; before its first hit pu holds its light, at
+//          its first hit p2.w and pu hold its MIS terms (k_lp_first)
 // ---------------------------------------------------------------------------
 struct PathQ {
     float4 *q0, *q1, *q2, *q3;
@@ -67,7 +76,7 @@ struct VertexStore {
     float* rho;
 };
 struct Images {
-    float *e, *E, *P;
+    float *e, *E, *P, *LP;
 };
 
 // per-scene constants, one entry per scene of the batch (device array)
@@ -86,6 +95,10 @@ struct SceneInfo {
     float r, r2pi;      // merge radius and pi r^2
     float inv_cell;     // 1 / merge-grid cell size
     float rho0, cam_w;  // analytic density (test hook)
+    int32_t n_lp;       // light photons per iteration
+    int32_t lp_base;    // first global light-photon index of the scene
+    float nlp;          // n_LP as a float (0: no light photons)
+    float pad2;
 };
 
 // Merge grid keyed by (hash of scene and cell, depth - 1): the records of
@@ -113,6 +126,8 @@ struct RenderArgs {
     int32_t npix;             // pixels of all scenes
     int32_t photons;          // n_P > 0
     int32_t density_mode;
+    const int32_t* lp_base;   // n_scenes + 1 entries: light photons of the scenes before
+    int32_t n_lp;             // light photons of all scenes per iteration
 };
 
 __device__ __forceinline__ int fbits(float f) { return __float_as_int(f); }
@@ -156,7 +171,7 @@ __device__ __forceinline__ float cam_hit_density(const CamParams& C, f3 x, f3 n)
     return (float)C.w * (float)C.h / (film * c * c * c) * fabsf(dot3(n, w)) / d2;
 }
 
-// scene of a global pixel: the last s with pix_base[s] <= i
+// scene of a global pixel (or light photon): the last s with pix_base[s] <= i
 __device__ __forceinline__ int scene_of_pixel(const int32_t* pix_base, int n_scenes, int i) {
     int lo = 0, hi = n_scenes - 1;
     while (lo < hi) {
@@ -191,6 +206,7 @@ __global__ void k_iter_begin(Counters* c, OctDyn* dyn, int32_t freeze) {
     c->pcount[1] = 0;
     c->n_vertices = 0;
     c->n_events = 0;
+    c->lp_count = 0;
     int oit = it < freeze ? it : freeze;
     int ic = oit < kOctFillIterations ? oit : kOctFillIterations;
     OctDyn d;
@@ -204,9 +220,10 @@ __global__ void k_iter_end(Counters* c) {
     c->vertices += (unsigned long long)c->n_vertices;
     c->events += (unsigned long long)c->n_events;
 }
-__global__ void k_mean_image(const float* e, const float* E, const float* P, float* out, int64_t n, float scale) {
+__global__ void k_mean_image(const float* e, const float* E, const float* P, const float* LP, float* out, int64_t n,
+                             float scale) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = (e[i] + E[i] + P[i]) * scale;
+        out[i] = (e[i] + E[i] + P[i] + LP[i]) * scale;
 }
 __global__ void k_scale_image(const float* a, float* out, int64_t n, float scale) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -375,15 +392,18 @@ __global__ void __launch_bounds__(256) k_shade(RenderArgs A, PathQ in, const int
         bool emit = alive && mat_emits(m) && cin > 0.f && S.prim_light[prim] >= 0;
         int eslot = wave_reserve(n_events, emit);
         if (emit) {
-            float q = 0.f;
+            float q = 0.f, D = a3.z;
             if (k > 1) {
                 int lid = S.prim_light[prim];
                 float p_light = S.lights[5 * lid].w / S.lights[5 * lid + 1].w;
                 float f_prev = a2.w * cin / (t * t);
                 q = p_light / f_prev;
+                // light photons: n_LP pi r^2 p_{l -> l-1} (A_{l-2} + delta_{l-1}), where the
+                // emission density p_{l -> l-1} = (cin / pi) |cos out| / t^2 = (a3.y / pi) f_prev
+                D += I.nlp * I.r * I.r * a3.y * f_prev * (a3.x + a3.z);
             }
             ev0[eslot] = f4(tau * load3(m.emission), q);
-            ev1[eslot] = make_float4(a3.x * I.r2pi, a3.z, a3.w, ibits(pixel));
+            ev1[eslot] = make_float4(a3.x * I.r2pi, D, a3.w, ibits(pixel));
         }
         bool store = alive && !mat_black(m) && k <= I.L - 1;
         float g = (k >= 2) ? a3.y / fabsf(cin) : 0.f;
@@ -420,26 +440,26 @@ __global__ void __launch_bounds__(256) k_shade(RenderArgs A, PathQ in, const int
 // ---------------------------------------------------------------------------
 // pass 2 (a): density at every NEE vertex
 // ---------------------------------------------------------------------------
+// density of NEE vertices at x (geometric normal nn) in scene s, from the
+// octree or the analytic test density
+__device__ __forceinline__ float point_density(const RenderArgs& A, int s, f3 x, f3 nn, const int32_t* __restrict__ nodes,
+                                               const OctState* ost, const OctParams* prm, float scale) {
+    if (A.density_mode == NEB_DENSITY_ANALYTIC) {
+        const SceneInfo& I = A.sc[s];
+        return I.rho0 + I.cam_w * cam_hit_density(I.cam, x, nn);
+    }
+    if (A.density_mode == NEB_DENSITY_OCTREE) return oct_query(nodes, prm[s], scale, ost[s].depth, x, nn, false, nullptr);
+    return oct_query_robust(nodes, prm[s], scale, ost[s].depth, x, nn);
+}
+
 __global__ void __launch_bounds__(256) k_density(RenderArgs A, VertexStore V, const int32_t* n_vertices,
                                                  const int32_t* __restrict__ nodes, const OctState* ost,
                                                  const OctParams* prm, const OctDyn* dyn) {
     int n = *n_vertices;
     const float scale = dyn->density_scale;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        f3 x = xyz(V.v0[i]);
         float4 a1 = V.v1[i];
-        f3 nn = xyz(a1);
-        int s = tag_scene(fbits(a1.w));
-        float rho;
-        if (A.density_mode == NEB_DENSITY_ANALYTIC) {
-            const SceneInfo& I = A.sc[s];
-            rho = I.rho0 + I.cam_w * cam_hit_density(I.cam, x, nn);
-        } else if (A.density_mode == NEB_DENSITY_OCTREE) {
-            rho = oct_query(nodes, prm[s], scale, ost[s].depth, x, nn, false, nullptr);
-        } else {
-            rho = oct_query_robust(nodes, prm[s], scale, ost[s].depth, x, nn);
-        }
-        V.rho[i] = rho;
+        V.rho[i] = point_density(A, tag_scene(fbits(a1.w)), xyz(V.v0[i]), xyz(a1), nodes, ost, prm, scale);
     }
 }
 
@@ -453,7 +473,27 @@ struct LightSample {
 };
 
 // lights of one scene: [base, base + count) of the light pool, selected by
-// the scene's cumulative power table
+// the scene's cumulative power table (the first entry whose cdf exceeds u)
+__device__ __forceinline__ int pick_light(const SceneView& S, int base, int count, float u) {
+    int lo = 0, hi = count - 1;
+    const float* cdf = S.light_cdf + base;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (u < cdf[mid]) hi = mid;
+        else lo = mid + 1;
+    }
+    return base + lo;
+}
+
+// Light pool entry (5 float4): l0 (p0 or position, selection probability),
+// l1 (edge 1, area; 0 for a point light), l2 (edge 2), l3 (radiance or
+// intensity), l4 (normal).  Emission density toward a receiver at squared
+// distance d2 whose cosine is cx, in area measure at the receiver: cosine
+// lobe cos_l / pi of an area light, 1 / (4 pi) of a point light.
+__device__ __forceinline__ float emission_density(bool area, float cos_l, float cx, float d2) {
+    return (area ? fmaxf(cos_l, 0.f) * (1.0f / NEB_PI) : 1.0f / (4.0f * NEB_PI)) * cx / d2;
+}
+
 __device__ __forceinline__ LightSample sample_light(const SceneView& S, int base, int count, f3 x, f3 nx,
                                                     const U4& u) {
     LightSample ls;
@@ -461,14 +501,7 @@ __device__ __forceinline__ LightSample sample_light(const SceneView& S, int base
     ls.hittable = false;
     ls.p_light = 0.f;
     ls.cos_l = 0.f;
-    int lo = 0, hi = count - 1;
-    const float* cdf = S.light_cdf + base;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (u.u[0] < cdf[mid]) hi = mid;
-        else lo = mid + 1;
-    }
-    const float4* L = S.lights + 5 * (size_t)(base + lo);
+    const float4* L = S.lights + 5 * (size_t)pick_light(S, base, count, u.u[0]);
     float4 l0 = L[0], l1 = L[1], l2 = L[2], l3 = L[3];
     float psel = l0.w;
     if (l1.w > 0.f) {  // emissive triangle
@@ -540,8 +573,11 @@ __global__ void __launch_bounds__(kTraceBlock) k_nee(RenderArgs A, VertexStore V
         bool photon = false;
         Sample s;
         s.ev = 0;
+        // light photons: emission density p_{l -> l-1} from the light point toward x
+        float rem = 0.f;
         if (ok) {
             ++vis;
+            rem = emission_density(ls.hittable, ls.cos_l, fabsf(dot3(nrm, ls.w)), ls.d2);
             bool dnon = !mat_delta(m.type);
             if (dnon) {
                 f3 f = bsdf_f(m, nrm, wo, ls.w);
@@ -550,6 +586,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_nee(RenderArgs A, VertexStore V
                     float ratio = 1.0f;
                     if (ls.hittable) ratio += bsdf_pdf(m, nrm, wo, ls.w) * ls.cos_l / (ls.d2 * ls.p_light);
                     if (A.photons) ratio += rho * I.r2pi * Am1;
+                    ratio += I.nlp * I.r2pi * rem * (Am1 + 1.0f);
                     atomic_add3(img.E, pixel, tau * f * ls.dE * (1.0f / ratio));
                 }
             }
@@ -564,9 +601,12 @@ __global__ void __launch_bounds__(kTraceBlock) k_nee(RenderArgs A, VertexStore V
             ++emitted;
             float fo = ls.hittable ? bsdf_pdf(m, nrm, s.dir, ls.w) * ls.cos_l / (ls.d2 * ls.p_light) : 0.f;
             float dnon = mat_delta(m.type) ? 0.f : 1.f;
-            float U1 = (fo + dnon) / (rho * I.r2pi);
+            // with light photons every merge of this photon gains the factor 1 + c
+            // (c = n_LP p_{l -> l-1} / rho): folded into the flux and into U
+            float c1 = 1.0f + I.nlp * rem / rho;
+            float U1 = ((fo + dnon) / (rho * I.r2pi) + (c1 - 1.0f) * dnon) / c1;
             float hp = fabsf(dot3(nrm, s.dir)) / s.pdf;
-            f3 phi = ls.dE * (1.0f / rho) * s.w;
+            f3 phi = ls.dE * (1.0f / (rho * c1)) * s.w;
             pq.p0[slot] = f4(offset_origin(x, nrm, s.dir, I.eps), ibits(pixel));
             pq.p1[slot] = f4(s.dir, ibits(make_tag(16 * k + 1, sid)));
             pq.p2[slot] = f4(phi, hp);
@@ -578,6 +618,119 @@ __global__ void __launch_bounds__(kTraceBlock) k_nee(RenderArgs A, VertexStore V
     wave_add_u64(&cnt->shadow_rays, rays);
     wave_add_u64(&cnt->bvh_nodes, nodes);
     wave_add_u64(&cnt->bvh_tris, tris);
+}
+
+// ---------------------------------------------------------------------------
+// pass 2 (d): conventional light photons (Sec. 4, eq. stdphotonpdf)
+// ---------------------------------------------------------------------------
+// Light photon i of a scene picks a light by power and a point on it
+// (stream LIGHT, word 0) and a direction (word 1): the cosine lobe around an
+// area light's normal, the uniform sphere for a point light.  Its flux,
+// L_e pi / p_light (area) or 4 pi I / P_sel (point), is shared by the n_LP
+// photons.  The photons take the first entries of photon queue 0 (the NEB
+// photons follow), tagged origin depth 0, bounce 0; until the first hit the
+// U slot holds the light's pool index.
+__global__ void __launch_bounds__(256) k_lp_emit(RenderArgs A, PhotonQ pq, int32_t* pcount) {
+    const SceneView& S = A.S;
+    Counters* cnt = A.cnt;
+    const int iter = cnt->iter;
+    unsigned emitted = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < A.n_lp; i += gridDim.x * blockDim.x) {
+        const int sid = scene_of_pixel(A.lp_base, A.n_scenes, i);
+        const SceneInfo& I = A.sc[sid];
+        const int li = i - I.lp_base;
+        bool go = scene_active(I, iter);
+        f3 o = mk3(0.f, 0.f, 0.f), d = mk3(0.f, 0.f, 1.f), phi = o;
+        int lid = 0;
+        if (go) {
+            U4 u = uniforms(I.k0, I.k1, (uint32_t)li, (uint32_t)iter, 0u, kTagLight);
+            U4 v = uniforms(I.k0, I.k1, (uint32_t)li, (uint32_t)iter, 1u, kTagLight);
+            lid = pick_light(S, I.light_base, I.n_lights, u.u[0]);
+            const float4* L = S.lights + 5 * (size_t)lid;
+            float4 l0 = L[0], l1 = L[1];
+            f3 rad = xyz(L[3]);
+            float sp, cp;
+            sincosf(2.0f * NEB_PI * v.u[1], &sp, &cp);
+            if (l1.w > 0.f) {  // emissive triangle
+                float su = sqrtf(u.u[1]);
+                float b1 = u.u[2] * su;
+                float b2 = 1.0f - (1.0f - su) - b1;
+                f3 y = xyz(l0) + xyz(l1) * b1 + xyz(L[2]) * b2;
+                f3 ln = xyz(L[4]), t1, t2;
+                basis(ln, t1, t2);
+                float r = sqrtf(v.u[0]), z = sqrtf(fmaxf(0.f, 1.0f - v.u[0]));
+                d = normalize3(t1 * (r * cp) + t2 * (r * sp) + ln * z);
+                go = dot3(d, ln) > 0.f;
+                phi = rad * (NEB_PI * l1.w / (l0.w * I.nlp));  // L_e pi / p_light, p_light = P_sel / area
+                o = offset_origin(y, ln, d, I.eps);
+            } else {  // point light: l3 holds the intensity
+                float z = 1.0f - 2.0f * v.u[0], r = sqrtf(fmaxf(0.f, 1.0f - z * z));
+                d = mk3(r * cp, r * sp, z);
+                phi = rad * (4.0f * NEB_PI / (l0.w * I.nlp));
+                o = xyz(l0);
+            }
+        }
+        int slot = wave_reserve(pcount, go);
+        wave_reserve(&cnt->lp_count, go);
+        if (go) {
+            ++emitted;
+            pq.p0[slot] = f4(o, ibits(I.pix_base + li));
+            pq.p1[slot] = f4(d, ibits(make_tag(0, sid)));
+            pq.p2[slot] = f4(phi, 0.f);
+            pq.pu[slot] = ibits(lid);
+        }
+    }
+    wave_add_u64(&cnt->light_photons, emitted);
+}
+
+// First hit y of each light photon (after the first closest-hit pass).  The
+// paths these photons form have x_{l-1} = y; their NEB technique needs rho
+// there, so it is queried here.  With p_{l -> l-1} the emission density
+// toward y, n_LP p_{l -> l-1} sets the scale of the light-photon technique
+// and c' = rho / (n_LP p_{l -> l-1}) that of the NEB photons relative to it.
+// Every merge of the photon gains the factor 1 + c', which is folded into its
+// flux; the merge at y itself has the MIS denominator
+//   e + A_{k-1} + pdf_k(camera side -> light) X,
+// with e = (1 + 1 / (n_LP pi r^2 p_{l -> l-1})) / (1 + c') and
+// X = [area light] / (|cos at y| p_light n_LP r^2 (1 + c')), stored in p2.w
+// and U for k_photon.  A photon whose emission density vanishes (grazing
+// hit) carries no weight and is dropped.
+__global__ void __launch_bounds__(256) k_lp_first(RenderArgs A, PhotonQ pq, int2* hits,
+                                                  const int32_t* __restrict__ nodes, const OctState* ost,
+                                                  const OctParams* prm, const OctDyn* dyn) {
+    const int n = A.cnt->lp_count;
+    const SceneView& S = A.S;
+    const float scale = dyn->density_scale;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int2 h = hits[i];
+        if (h.y < 0) continue;
+        float4 b0 = pq.p0[i], b1 = pq.p1[i], b2 = pq.p2[i];
+        const int sid = tag_scene(fbits(b1.w));
+        const SceneInfo& I = A.sc[sid];
+        f3 o = xyz(b0), d = xyz(b1);
+        f3 y = o + d * ibits(h.x);
+        f3 ny = xyz(S.prim_n[h.y]);
+        const float4* L = S.lights + 5 * (size_t)fbits(pq.pu[i]);
+        float4 l0 = L[0], l1 = L[1];
+        const bool area = l1.w > 0.f;
+        f3 ln = xyz(L[4]);
+        f3 v = y - (area ? o - ln * I.eps : o);  // from the light point, before the ray offset
+        float d2 = dot3(v, v);
+        f3 w = v * rsqrtf(d2);
+        float cos_y = fabsf(dot3(ny, w));
+        float p_light = area ? l0.w / l1.w : l0.w;
+        float rl = emission_density(area, dot3(ln, w), cos_y, d2);
+        float rho = A.photons ? point_density(A, sid, y, ny, nodes, ost, prm, scale) : 0.f;
+        float c1 = 1.0f + rho / (I.nlp * rl);
+        float e = (1.0f + 1.0f / (I.nlp * I.r2pi * rl)) / c1;
+        float X = area ? 1.0f / (cos_y * p_light * I.nlp * I.r * I.r * c1) : 0.f;
+        if (!(rl > 0.f) || !isfinite(e) || !isfinite(X) || !isfinite(c1)) {
+            hits[i] = make_int2(h.x, -1);
+            continue;
+        }
+        pq.p2[i] = f4(xyz(b2) * (1.0f / c1), e);
+        pq.pu[i] = X;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -756,7 +909,8 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
                                                PhotonQ out, int32_t* count_out, Grid G, Images img,
                                                const int32_t* __restrict__ order) {
     __shared__ int2 queue[128];
-    __shared__ float4 tp[64][2];  // per lane's photon: (-d, h*U), (Phi / (pi r^2), deepest mergeable depth)
+    __shared__ float4 tp[64][2];  // per lane's photon: (-d, X), (Phi / (pi r^2), deepest mergeable depth | light bit)
+    __shared__ float te[64];      // per lane's photon: weight of its own technique in the MIS denominator
     const int lane = threadIdx.x;
     const unsigned long long below = (1ull << lane) - 1ull;
     const int n = *count_in;
@@ -774,7 +928,8 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
             float4 v1 = mr[0];
             int tg = fbits(v1.w);
             int k = tag_depth(tg);
-            if (k <= fbits(t1.w)) {
+            const int km = fbits(t1.w);
+            if (k <= (km & 255)) {
                 const neb_material& mv = S.mats[tag_mat(tg)];
                 float4 v2 = mr[1];
                 f3 nv = xyz(v1), wv = xyz(v2), wd = xyz(t0);
@@ -782,9 +937,9 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
                 if (!is_zero3(f)) {
                     float4 v3 = mr[2];
                     float T = bsdf_pdf(mv, nv, wv, wd) * t0.w;
-                    float C = 1.0f + ((k >= 2) ? bsdf_pdf(mv, nv, wd, wv) * v3.w * v2.w : 0.f);
+                    float C = te[pr.x] + ((k >= 2) ? bsdf_pdf(mv, nv, wd, wv) * v3.w * v2.w : 0.f);
                     int vpix = fbits(mr[3].x);
-                    atomic_add3(img.P, vpix, xyz(v3) * f * xyz(t1) * (1.0f / (C + T)));
+                    atomic_add3((km & 256) ? img.LP : img.P, vpix, xyz(v3) * f * xyz(t1) * (1.0f / (C + T)));
                     ++merges;
                 }
             }
@@ -835,9 +990,16 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
         }
         const neb_material& my = S.mats[mid];
         bool mergeable = hit && !mat_delta(my.type);
-        const int kmax = I.L - 1 - j;  // deepest view vertex this photon may merge with
-        tp[lane][0] = f4(-d, hh * U);
-        tp[lane][1] = f4(xyz(b2) * (1.0f / I.r2pi), ibits(kmax));
+        // deepest view vertex this photon may merge with (a light photon's bounce
+        // count is one less than its number of segments)
+        const int kmax = I.L - 1 - j;
+        // a light photon at its first hit brings the weight of its own technique
+        // in p2.w and X in U; every other photon has weight 1 and X = h U
+        const bool light = odepth == 0, lfirst = code == 0;
+        const float X = lfirst ? U : hh * U, ef = lfirst ? b2.w : 1.0f;
+        tp[lane][0] = f4(-d, X);
+        tp[lane][1] = f4(xyz(b2) * (1.0f / I.r2pi), ibits(kmax | (light ? 256 : 0)));
+        te[lane] = ef;
         // candidate ranges of the (at most 8) cells the ball touches
         int lo[8], pre[9];
         pre[0] = 0;
@@ -934,7 +1096,7 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
         if (go) {
             f3 wd = -d;
             float prev = bsdf_pdf(my, ny, s.dir, wd);
-            float Un = (mat_delta(my.type) ? 0.f : 1.f) + prev * hh * U;
+            float Un = (mat_delta(my.type) ? 0.f : ef) + prev * X;
             float hp = fabsf(dot3(ny, s.dir)) / s.pdf;
             out.p0[slot] = f4(offset_origin(y, ny, s.dir, I.eps), ibits(opix));
             out.p1[slot] = f4(s.dir, ibits(make_tag(16 * odepth + j + 1, sid)));
@@ -1140,8 +1302,10 @@ struct neb_ctx_s {
     std::vector<neb_params> prm;
     std::vector<HostScene> hs;
     std::vector<int32_t> pix_base;  // n_scenes + 1
-    int npix = 0, L = 0;
+    std::vector<int32_t> lp_base;   // n_scenes + 1: light photons per iteration of the scenes before
+    int npix = 0, L = 0, n_lp = 0;
     int64_t vcap = 0, ecap = 0, slot_cap = 0;
+    int64_t pcap = 0;               // photon queue entries: NEB photons (<= vertices) + light photons
     int density_mode = 0, flags = 0, photons = 1;
     int cus = 256;
     // per-scene device tables and the shared geometry pools
@@ -1149,6 +1313,7 @@ struct neb_ctx_s {
     int forest_depth = 0;
     SceneInfo* sc_dev = nullptr;
     int32_t* pix_base_dev = nullptr;
+    int32_t* lp_base_dev = nullptr;
     std::vector<SceneInfo> sc_host;
     SceneView view{};
     std::vector<void*> scene_allocs;
@@ -1173,7 +1338,7 @@ struct neb_ctx_s {
     // spatial order of photon hits
     int32_t *pbin = nullptr, *porder = nullptr, *bcount = nullptr, *bstart = nullptr, *bsums = nullptr;
     int32_t bin_bits = 0, n_bins = 0;
-    float* img = nullptr;  // e, E, P accumulators, 3 * npix floats each
+    float* img = nullptr;  // e, E, P, LP accumulators, 3 * npix floats each
     Counters* cnt = nullptr;
     int32_t iter = 0;
     int32_t first_iter_recorded = 0;
@@ -1205,11 +1370,11 @@ struct neb_ctx_s {
 
 enum KernelId {
     K_CAMERA, K_EXTEND_CAMERA, K_SHADE, K_OCTREE_INSERT, K_DENSITY, K_NEE, K_GRID_BUILD, K_EXTEND_PHOTON, K_PHOTON,
-    K_FINALIZE, K_MLP_TRAIN, K_PHOTON_ORDER, K_MISC, K_COUNT
+    K_FINALIZE, K_MLP_TRAIN, K_PHOTON_ORDER, K_MISC, K_LIGHT_PHOTON, K_COUNT
 };
 static const char* kKernelNames[K_COUNT] = {"camera", "extend_camera", "shade", "octree_insert", "density", "nee",
                                             "grid_build", "extend_photon", "photon_merge", "finalize", "mlp_train",
-                                            "photon_order", "misc"};
+                                            "photon_order", "misc", "light_photon"};
 
 static void prof_harvest(neb_ctx c) {
     if (c->prof_used == 0) return;
@@ -1372,6 +1537,8 @@ static neb_status check_params(const neb_params* p) {
     if (!std::isfinite(p->analytic_rho0) || !std::isfinite(p->analytic_cam_weight))
         return fail(NEB_ERR_INVALID_ARG, "analytic density parameters must be finite");
     if (p->spp < 0) return fail(NEB_ERR_INVALID_ARG, "spp must be >= 0");
+    if (p->light_photons < 0 || p->light_photons > (1 << 26))
+        return fail(NEB_ERR_INVALID_ARG, "light_photons out of range (0 .. 2^26)");
     return NEB_OK;
 }
 
@@ -1379,7 +1546,7 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
     if (!params || !out) return fail(NEB_ERR_INVALID_ARG, "null pointer");
     *out = nullptr;
     if (n_scenes < 1 || n_scenes > kMaxScenes) return fail(NEB_ERR_INVALID_ARG, "scene count out of range (1..256)");
-    int64_t npix = 0, vcap = 0, ecap = 0, oct_total = 0;
+    int64_t npix = 0, vcap = 0, ecap = 0, oct_total = 0, n_lp = 0;
     int L = 0;
     for (int s = 0; s < n_scenes; ++s) {
         neb_status st = check_params(params + s);
@@ -1393,12 +1560,16 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
         ecap += np * p.max_path_len;
         oct_total += octree_capacity_rounded(p.octree_capacity);
         L = std::max(L, p.max_path_len);
+        n_lp += p.max_path_len >= 2 ? p.light_photons : 0;
     }
     if (npix > (int64_t)INT32_MAX / 16 || vcap * 4 > (int64_t)INT32_MAX || ecap > (int64_t)INT32_MAX)
         return fail(NEB_ERR_CAPACITY, "images too large for the vertex pool");
     if (oct_total >= (int64_t)INT32_MAX - 16) return fail(NEB_ERR_CAPACITY, "octree pool over 2^31 nodes");
     if (params[0].density_mode == NEB_DENSITY_MLP && n_scenes != 1)
         return fail(NEB_ERR_INVALID_ARG, "the learned density needs a context of one scene");
+    if (params[0].density_mode == NEB_DENSITY_MLP && n_lp > 0)
+        return fail(NEB_ERR_INVALID_ARG, "light photons need the octree or the analytic density");
+    if (vcap + n_lp > (int64_t)INT32_MAX / 4) return fail(NEB_ERR_CAPACITY, "too many photons per iteration");
     int64_t slot_cap = npix * std::max(1, L - 1);
     if ((params[0].flags & NEB_FLAG_SINGLE_THREAD_OCTREE) && slot_cap > (int64_t)INT32_MAX)
         return fail(NEB_ERR_CAPACITY, "too many pixels for single-thread deposits");
@@ -1408,13 +1579,16 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
     c->prm.assign(params, params + n_scenes);
     c->hs.resize(n_scenes);
     c->pix_base.resize(n_scenes + 1);
+    c->lp_base.resize(n_scenes + 1);
     c->oct_prm.resize(n_scenes);
     c->sc_host.resize(n_scenes);
     {
-        int64_t pb = 0, root = 0;
+        int64_t pb = 0, root = 0, lb = 0;
         for (int s = 0; s < n_scenes; ++s) {
             c->pix_base[s] = (int32_t)pb;
             pb += (int64_t)params[s].width * params[s].height;
+            c->lp_base[s] = (int32_t)lb;
+            lb += params[s].max_path_len >= 2 ? params[s].light_photons : 0;
             OctParams& P = c->oct_prm[s];
             std::memset(&P, 0, sizeof(P));
             P.root = (int32_t)root;
@@ -1422,7 +1596,10 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
             root = P.end;
         }
         c->pix_base[n_scenes] = (int32_t)pb;
+        c->lp_base[n_scenes] = (int32_t)lb;
     }
+    c->n_lp = (int)n_lp;
+    c->pcap = vcap + n_lp;
     c->npix = (int)npix;
     c->L = L;
     c->vcap = vcap;
@@ -1446,12 +1623,12 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
         ALLOC(c->q[b].q1, npix);
         ALLOC(c->q[b].q2, npix);
         ALLOC(c->q[b].q3, npix);
-        ALLOC(c->pq[b].p0, vcap);
-        ALLOC(c->pq[b].p1, vcap);
-        ALLOC(c->pq[b].p2, vcap);
-        ALLOC(c->pq[b].pu, vcap);
+        ALLOC(c->pq[b].p0, c->pcap);
+        ALLOC(c->pq[b].p1, c->pcap);
+        ALLOC(c->pq[b].p2, c->pcap);
+        ALLOC(c->pq[b].pu, c->pcap);
     }
-    ALLOC(c->hits, std::max<int64_t>(npix, vcap));
+    ALLOC(c->hits, std::max<int64_t>(npix, c->pcap));
     ALLOC(c->V.v0, vcap);
     ALLOC(c->V.v1, vcap);
     ALLOC(c->V.v2, vcap);
@@ -1469,7 +1646,7 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
     ALLOC(c->G.sorted, vcap);
     ALLOC(c->G.mrec, 4 * vcap);
     ALLOC(c->G.sums, scan_scratch(gkeys));
-    ALLOC(c->img, 9 * npix);
+    ALLOC(c->img, 12 * npix);
     ALLOC(c->cnt, 1);
     ALLOC(c->oct_nodes, oct_total);
     ALLOC(c->oct_states, n_scenes);
@@ -1480,6 +1657,7 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
     ALLOC(c->defer_cnt, 3);
     ALLOC(c->sc_dev, n_scenes);
     ALLOC(c->pix_base_dev, n_scenes + 1);
+    ALLOC(c->lp_base_dev, n_scenes + 1);
     {
         // about 2^18 bins over all scenes, 2..6 bits per axis
         int bits = 6;
@@ -1487,8 +1665,8 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
         c->bin_bits = bits;
         c->n_bins = n_scenes << (3 * bits);
     }
-    ALLOC(c->pbin, vcap);
-    ALLOC(c->porder, vcap);
+    ALLOC(c->pbin, c->pcap);
+    ALLOC(c->porder, c->pcap);
     ALLOC(c->bcount, c->n_bins + 2);
     ALLOC(c->bstart, c->n_bins + 2);
     ALLOC(c->bsums, scan_scratch(c->n_bins + 2));
@@ -1510,10 +1688,12 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(gkeys, 256)), dim3(256), 0, nullptr, c->G.count, 0, gkeys);
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(c->n_bins + 2, 256)), dim3(256), 0, nullptr, c->bcount, 0,
                            (int64_t)c->n_bins + 2);
-        hipLaunchKernelGGL(k_fill_f32, dim3(grid_of(9 * npix, 256)), dim3(256), 0, nullptr, c->img, 0.f, 9 * npix);
+        hipLaunchKernelGGL(k_fill_f32, dim3(grid_of(12 * npix, 256)), dim3(256), 0, nullptr, c->img, 0.f, 12 * npix);
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, nullptr, (int32_t*)c->cnt, 0,
                            (int64_t)(sizeof(Counters) / 4));
         e = hipMemcpy(c->pix_base_dev, c->pix_base.data(), 4 * c->pix_base.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(c->lp_base_dev, c->lp_base.data(), 4 * c->lp_base.size(), hipMemcpyHostToDevice);
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -1673,8 +1853,8 @@ static neb_status build_host_scene(const neb_params& prm, const float* vertices,
 
 // clears images, counters and every octree of the batch; iteration 0
 static neb_status restart(neb_ctx c, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill_f32, dim3(grid_of(9 * (int64_t)c->npix, 256)), dim3(256), 0, s, c->img, 0.f,
-                       9 * (int64_t)c->npix);
+    hipLaunchKernelGGL(k_fill_f32, dim3(grid_of(12 * (int64_t)c->npix, 256)), dim3(256), 0, s, c->img, 0.f,
+                       12 * (int64_t)c->npix);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int32_t*)c->cnt, 0, (int64_t)(sizeof(Counters) / 4));
     for (int i = 0; i < c->n_scenes; ++i)
         HIP_TRY(octree_init_range(c->oct_nodes, c->oct_states + i, c->oct_prm[i].root,
@@ -1778,6 +1958,9 @@ static neb_status prepare(neb_ctx c) {
         I.inv_cell = 1.0f / (2.0001f * P.merge_radius);  // a little wider than the ball's diameter
         I.rho0 = P.analytic_rho0;
         I.cam_w = P.analytic_cam_weight;
+        I.n_lp = P.max_path_len >= 2 ? P.light_photons : 0;
+        I.lp_base = c->lp_base[s];
+        I.nlp = (float)I.n_lp;
         OctParams& O = c->oct_prm[s];
         octree_params_init(O, H.bmin, H.bmax, O.root, P.octree_capacity);
         nb += H.bvh.n_nodes;
@@ -1864,6 +2047,8 @@ static RenderArgs make_args(neb_ctx c) {
     A.npix = c->npix;
     A.photons = c->photons;
     A.density_mode = c->density_mode;
+    A.lp_base = c->lp_base_dev;
+    A.n_lp = c->n_lp;
     return A;
 }
 
@@ -1910,7 +2095,7 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
     const int npix = c->npix, L = c->L;
     const int64_t vcap = c->vcap;
     Counters* cnt = c->cnt;
-    Images im{c->img, c->img + 3 * (size_t)npix, c->img + 6 * (size_t)npix};
+    Images im{c->img, c->img + 3 * (size_t)npix, c->img + 6 * (size_t)npix, c->img + 9 * (size_t)npix};
     // learned density: train on the octree in iterations 1..T, then use the model
     const int it = c->iter + 1;
     const int T = c->mlp_mode ? c->mcfg.train_iterations : 0;
@@ -1976,8 +2161,16 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
                                             (const OctState*)c->oct_states, (const OctParams*)c->oct_prm_dev,
                                             (const OctDyn*)c->oct_dyn));
     }
+    // light photons take the first entries of photon queue 0, the NEB photons follow
+    const bool lp = c->n_lp > 0;
+    if (lp)
+        TIMED(K_LIGHT_PHOTON, hipLaunchKernelGGL(k_lp_emit, dim3(grid_of(c->n_lp, 256)), dim3(256), 0, s, A,
+                                                 c->pq[0], &cnt->pcount[0]));
     TIMED(K_NEE, nee(c, A, im, s));
-    if (c->photons && L >= 3) {
+    // bounces: NEB photons make at most maxlen - 2 segments, light photons maxlen - 1
+    const int rounds = std::max((c->photons && L >= 3) ? L - 2 : 0, lp ? L - 1 : 0);
+    const int64_t pcap = c->pcap;
+    if (rounds > 0) {
         // merge grid over this iteration's view vertices
         int64_t n = (int64_t)c->G.T * c->G.D + 1;
         prof_begin(c, K_GRID_BUILD, s);
@@ -1988,18 +2181,23 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
                            (const neb_material*)c->view.mats, (const SceneInfo*)c->sc_dev, c->V,
                            (const int32_t*)&cnt->n_vertices, c->G);
         prof_end(c, s);
-        const int pgrid = c->cfg.photon_bpc > 0 ? std::max(1, std::min(grid_of(vcap, 64, 1 << 20), c->cus * c->cfg.photon_bpc))
-                                                : grid_of(vcap, 256);
-        for (int j = 1; j <= L - 2; ++j) {
+        const int pgrid = c->cfg.photon_bpc > 0 ? std::max(1, std::min(grid_of(pcap, 64, 1 << 20), c->cus * c->cfg.photon_bpc))
+                                                : grid_of(pcap, 256);
+        for (int j = 1; j <= rounds; ++j) {
             int in = (j - 1) & 1, out = j & 1;
             const bool ordered = c->cfg.photon_order != 0;
-            TIMED(K_EXTEND_PHOTON, extend(c, vcap, c->pq[in].p0, c->pq[in].p1, &cnt->pcount[in], &cnt->pcount[out],
+            TIMED(K_EXTEND_PHOTON, extend(c, pcap, c->pq[in].p0, c->pq[in].p1, &cnt->pcount[in], &cnt->pcount[out],
                                           &cnt->photon_rays, s, ordered));
+            if (j == 1 && lp)
+                TIMED(K_LIGHT_PHOTON,
+                      hipLaunchKernelGGL(k_lp_first, dim3(grid_of(c->n_lp, 256)), dim3(256), 0, s, A, c->pq[0], c->hits,
+                                         (const int32_t*)c->oct_nodes, (const OctState*)c->oct_states,
+                                         (const OctParams*)c->oct_prm_dev, (const OctDyn*)c->oct_dyn));
             if (ordered) {
                 // photons in the spatial order of their hits
                 prof_begin(c, K_PHOTON_ORDER, s);
                 scan_exclusive(c->bcount, c->bstart, c->n_bins + 1, c->bsums, s);
-                hipLaunchKernelGGL(k_bin_scatter, dim3(grid_of(vcap, 256)), dim3(256), 0, s, (const int32_t*)c->pbin,
+                hipLaunchKernelGGL(k_bin_scatter, dim3(grid_of(pcap, 256)), dim3(256), 0, s, (const int32_t*)c->pbin,
                                    (const int32_t*)&cnt->pcount[in], c->bcount, (const int32_t*)c->bstart, c->porder);
                 prof_end(c, s);
             }
@@ -2131,15 +2329,15 @@ extern "C" neb_status neb_get_scene_image(neb_ctx c, int32_t scene, float* rgb, 
     float scale = it > 0 ? 1.0f / (float)it : 0.f;
     if (is_dev) {
         hipLaunchKernelGGL(k_mean_image, dim3(grid_of(n, 256)), dim3(256), 0, s, c->img + off, c->img + N + off,
-                           c->img + 2 * N + off, rgb, n, scale);
+                           c->img + 2 * N + off, c->img + 3 * N + off, rgb, n, scale);
         HIP_TRY(hipGetLastError());
         return NEB_OK;
     }
-    std::vector<float> h(3 * (size_t)n);
+    std::vector<float> h(4 * (size_t)n);
     HIP_TRY(hipStreamSynchronize(s));
-    for (int t = 0; t < 3; ++t)
+    for (int t = 0; t < 4; ++t)
         HIP_TRY(hipMemcpy(h.data() + t * n, c->img + t * N + off, n * 4, hipMemcpyDeviceToHost));
-    for (int64_t i = 0; i < n; ++i) rgb[i] = (h[i] + h[n + i] + h[2 * n + i]) * scale;
+    for (int64_t i = 0; i < n; ++i) rgb[i] = (h[i] + h[n + i] + h[2 * n + i] + h[3 * n + i]) * scale;
     return NEB_OK;
 }
 
@@ -2167,6 +2365,17 @@ extern "C" neb_status neb_get_scene_technique_images(neb_ctx c, int32_t scene, f
 
 extern "C" neb_status neb_get_technique_images(neb_ctx c, float* e, float* E, float* P, int32_t is_dev, void* stream) {
     return neb_get_scene_technique_images(c, 0, e, E, P, is_dev, stream);
+}
+
+extern "C" neb_status neb_get_scene_light_photon_image(neb_ctx c, int32_t scene, float* LP, int32_t is_dev,
+                                                       void* stream) {
+    if (!LP) return fail(NEB_ERR_INVALID_ARG, "null pointer");
+    neb_status st = check_scene_ready(c, scene);
+    if (st != NEB_OK) return st;
+    const int64_t n = 3 * (int64_t)c->prm[scene].width * c->prm[scene].height;
+    const int64_t N = 3 * (int64_t)c->npix, off = 3 * (int64_t)c->pix_base[scene];
+    int it = scene_iters(c, scene);
+    return copy_out(c->img + 3 * N + off, LP, is_dev, it > 0 ? 1.0f / (float)it : 0.f, (hipStream_t)stream, n);
 }
 
 extern "C" neb_status neb_query_density(neb_ctx c, const float* pos, const float* nrm, int32_t n, float* out,
@@ -2248,6 +2457,7 @@ extern "C" neb_status neb_get_stats(neb_ctx c, neb_stats* out) {
     out->photon_continued = (int64_t)h.photon_continued;
     out->grid_cells = (int64_t)h.grid_cells;
     out->candidates = (int64_t)h.candidates;
+    out->light_photons = (int64_t)h.light_photons;
     if (c->ready) {
         // octree fields: summed over the scenes of the batch (depth: the deepest)
         for (int s = 0; s < c->n_scenes; ++s) {

@@ -22,7 +22,7 @@ FLAG_SINGLE_THREAD_OCTREE, FLAG_RECORD_PATHS, FLAG_NO_PHOTONS = 1, 2, 4
 EXPORTS = [
     "neb_create", "neb_create_batch", "neb_set_scene", "neb_set_batch_scene", "neb_render", "neb_use_graph",
     "neb_autotune", "neb_set_launch_config", "neb_get_launch_config", "neb_get_image", "neb_get_scene_image",
-    "neb_get_technique_images", "neb_get_scene_technique_images",
+    "neb_get_technique_images", "neb_get_scene_technique_images", "neb_get_scene_light_photon_image",
     "neb_query_density", "neb_get_stats", "neb_get_path_records", "neb_get_octree", "neb_get_scene_octree",
     "neb_profile_kernels", "neb_get_kernel_profile", "neb_reset",
     "neb_destroy", "neb_status_string", "neb_last_error",
@@ -42,7 +42,7 @@ class Params(ctypes.Structure):
                 ("octree_capacity", ctypes.c_int32), ("merge_radius", ctypes.c_float),
                 ("seed", ctypes.c_uint32), ("scene_id", ctypes.c_uint32), ("density_mode", ctypes.c_int32),
                 ("analytic_rho0", ctypes.c_float), ("analytic_cam_weight", ctypes.c_float),
-                ("flags", ctypes.c_int32), ("spp", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("spp", ctypes.c_int32), ("light_photons", ctypes.c_int32)]
 
 
 class LaunchConfig(ctypes.Structure):
@@ -59,7 +59,7 @@ class Stats(ctypes.Structure):
         "iterations", "paths", "vertices", "photons", "photon_segments", "merges", "nee_visible", "events",
         "rays", "oct_capacity", "oct_allocated", "oct_depth", "oct_overflow", "oct_ledger", "oct_deposits",
         "oct_rejected", "oct_lost", "photon_items", "photon_continued", "grid_cells", "candidates",
-        "camera_rays", "shadow_rays", "bvh_nodes", "bvh_tris")]
+        "camera_rays", "shadow_rays", "bvh_nodes", "bvh_tris", "light_photons")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -119,6 +119,7 @@ def lib():
             "neb_get_scene_image": ([_P, i32, _P, i32, _P], i32),
             "neb_get_technique_images": ([_P, _P, _P, _P, i32, _P], i32),
             "neb_get_scene_technique_images": ([_P, i32, _P, _P, _P, i32, _P], i32),
+            "neb_get_scene_light_photon_image": ([_P, i32, _P, i32, _P], i32),
             "neb_query_density": ([_P, _P, _P, i32, _P, i32, _P], i32),
             "neb_get_stats": ([_P, ctypes.POINTER(Stats)], i32),
             "neb_get_path_records": ([_P, _P, i64], i32),
@@ -195,6 +196,7 @@ def make_params(scene, density_mode=DENSITY_OCTREE_ROBUST, flags=0, rho0=0.0, ca
     p.analytic_cam_weight = cam_weight
     p.flags = flags
     p.spp = over.get("spp", 0)
+    p.light_photons = over.get("light_photons", 0)
     return p
 
 
@@ -283,11 +285,14 @@ class BatchRenderer:
         return out
 
     def technique_images_host(self, scene=0):
+        """Mean radiance per technique: random hits e, NEE E, NEB photons P
+        and conventional light photons LP (zero without light photons)."""
         P = self.params_list[scene]
-        e, E, Pi = (np.zeros((P.height, P.width, 3), np.float32) for _ in range(3))
+        e, E, Pi, LP = (np.zeros((P.height, P.width, 3), np.float32) for _ in range(4))
         _check(lib().neb_get_scene_technique_images(self.h, int(scene), _np_ptr(e), _np_ptr(E), _np_ptr(Pi), 0,
                                                     None))
-        return {"e": e, "E": E, "P": Pi}
+        _check(lib().neb_get_scene_light_photon_image(self.h, int(scene), _np_ptr(LP), 0, None))
+        return {"e": e, "E": E, "P": Pi, "LP": LP}
 
     def stats(self):
         s = Stats()
