@@ -182,13 +182,25 @@ def rel_rmse(img, ref):
     return float(np.sqrt(np.mean((img.astype(np.float64) - ref) ** 2)) / np.mean(ref))
 
 
-def learned_comparison(stream, spp=64, train_iterations=4, ref_spp=256, check_every=4):
-    """The room with the learned density (4 training iterations, then the
-    model) against the plain octree form, both to `spp`, each checked every
-    `check_every` iterations against a plain render of ref_spp with another
-    seed.  Reports the plain form's relative RMSE at `spp` and the time
-    each form needs to reach it (render time only: GPU events around the
-    render calls, the RMSE checks excluded)."""
+def quality_comparison(stream, spp=64, ref_spp=1024, train_iterations=4, check_every=4):
+    """Error against time on the room for four forms, each rendered to
+    `spp` and checked every `check_every` iterations against a reference:
+    - plain: NEB with the robust octree density (the headline form);
+    - single_probe: NEB with the one-probe octree density;
+    - light_photons: NEB plus one conventional light photon per pixel and
+      iteration (the optional technique of Sec. 4);
+    - learned: NEB with the learned density (trained on the octree for the
+      first `train_iterations` iterations, then used with region-gated
+      octree fallback).
+    The reference is path tracing with NEE and light photons (no NEB
+    photons, so no density estimate enters it) at `ref_spp` with another
+    seed.  Reports each form's relative RMSE and mean deviation at `spp`,
+    and the time each form needs to reach the lowest RMSE the plain form
+    reaches on its way to `spp` (its error grows again later: the robust
+    query's density on curved and edged geometry decays over the
+    iterations), with the speedup over the plain form's time to that RMSE
+    (render time only: GPU events around the render calls, the checks
+    excluded)."""
     import numpy as np
     import torch
     from neb_inputs import room
@@ -204,9 +216,10 @@ def learned_comparison(stream, spp=64, train_iterations=4, ref_spp=256, check_ev
         return a.elapsed_time(b) / 1e3
 
     sc = room()
+    nlp = sc.width * sc.height
     ref_sc = sc.with_settings(seed=sc.seed + 1000)
-    R = neb.Renderer(ref_sc)
-    R.render(ref_spp, stream=stream)
+    R = neb.Renderer(ref_sc, flags=neb.FLAG_NO_PHOTONS, light_photons=nlp)
+    ref_s = timed(lambda: R.render(ref_spp, stream=stream))
     ref = R.image_host().astype(np.float64)
     R.close()
 
@@ -214,38 +227,52 @@ def learned_comparison(stream, spp=64, train_iterations=4, ref_spp=256, check_ev
         t, curve = 0.0, []
         for it in range(check_every, spp + 1, check_every):
             t += timed(lambda: R.render(check_every, stream=stream))
-            curve.append((it, t, rel_rmse(R.image_host(), ref)))
+            img = R.image_host().astype(np.float64)
+            curve.append((it, t, rel_rmse(img, ref), img.mean() / ref.mean() - 1))
         return curve
 
+    curves = {}
     P = neb.Renderer(sc)
-    plain = progression(P)
+    curves["plain"] = progression(P)
     P.close()
+    P = neb.Renderer(sc, density_mode=neb.DENSITY_OCTREE)
+    curves["single_probe"] = progression(P)
+    P.close()
+    Lp = neb.Renderer(sc, light_photons=nlp)
+    curves["light_photons"] = progression(Lp)
+    Lp.close()
     M = neb.Renderer(sc, density_mode=neb.DENSITY_MLP)
     M.configure_mlp(train_iterations=train_iterations)
-    learned = progression(M)
+    curves["learned"] = progression(M)
     status = M.mlp_status()
     M.close()
-    target = plain[-1][2]
+    best = min(curves["plain"], key=lambda r: r[2])
+    target = best[2]
 
     def time_to(curve):
-        for it, t, e in curve:
+        for it, t, e, _ in curve:
             if e <= target:
                 return it, t
         return None, None
 
-    it_l, t_l = time_to(learned)
-    return {"workload": "room 512x512, %d spp; learned density trained on the octree for %d iterations "
-                        "(250 Adam steps x 65536 each), then used with region-gated octree fallback" %
-                        (spp, train_iterations),
-            "reference": "plain octree form, %d spp, seed %d" % (ref_spp, ref_sc.seed),
-            "plain_rel_rmse": round(target, 5), "plain_s": round(plain[-1][1], 4),
-            "learned_rel_rmse": round(learned[-1][2], 5), "learned_s": round(learned[-1][1], 4),
-            "learned_spp_to_equal_rmse": it_l, "learned_s_to_equal_rmse": None if t_l is None else round(t_l, 4),
-            "speedup_to_equal_rmse": None if t_l is None else round(plain[-1][1] / t_l, 3),
-            "curves": {"plain": [[i, round(t, 4), round(e, 5)] for i, t, e in plain],
-                       "learned": [[i, round(t, 4), round(e, 5)] for i, t, e in learned]},
-            "model": {k: status[k] for k in ("adam_steps", "last_loss", "probes", "probes_bad", "regions_probed",
-                                             "regions_disabled", "fallback_queries")}}
+    forms = {}
+    for name, c in curves.items():
+        it, t = time_to(c)
+        forms[name] = {"rel_rmse": round(c[-1][2], 5), "mean_deviation": round(c[-1][3], 5),
+                       "s": round(c[-1][1], 4), "ms_per_spp": round(1e3 * c[-1][1] / spp, 3),
+                       "min_rel_rmse": round(min(r[2] for r in c), 5),
+                       "spp_to_target": it, "s_to_target": None if t is None else round(t, 4),
+                       "speedup_to_target": None if t is None else round(best[1] / t, 3),
+                       "curve": [[i, round(tt, 4), round(e, 5)] for i, tt, e, _ in c]}
+    return {"workload": "room 512x512, %d spp per form; light photons: %d per iteration; learned density "
+                        "trained on the octree for %d iterations (250 Adam steps x 65536 each)" %
+                        (spp, nlp, train_iterations),
+            "reference": "path tracing with NEE and %d light photons per iteration, %d spp, seed %d (%.1f s)" %
+                         (nlp, ref_spp, ref_sc.seed, ref_s),
+            "target": "the plain form's lowest relative RMSE, %.5f at %d spp" % (target, best[0]),
+            "forms": forms,
+            "learned_model": {k: status[k] for k in ("adam_steps", "last_loss", "probes", "probes_bad",
+                                                     "regions_probed", "regions_disabled", "fallback_queries")}}
 
 
 def main():
@@ -256,7 +283,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event pass")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-scene batching comparison")
-    ap.add_argument("--no-learned", action="store_true", help="skip the learned-density comparison")
+    ap.add_argument("--no-quality", "--no-learned", dest="no_quality", action="store_true",
+                    help="skip the error-against-time comparison (plain, light photons, learned density)")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the launch shapes on this workload first (default: the library's defaults)")
     ap.add_argument("--launch-config", default=None,
@@ -369,8 +397,8 @@ def main():
     R.close()
     if not args.no_batch:
         out["batch"] = batch_comparison(stream)
-    if not args.no_learned:
-        out["learned"] = learned_comparison(stream)
+    if not args.no_quality:
+        out["quality"] = quality_comparison(stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
