@@ -911,6 +911,8 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
     __shared__ int2 queue[128];
     __shared__ float4 tp[64][2];  // per lane's photon: (-d, X), (Phi / (pi r^2), deepest mergeable depth | light bit)
     __shared__ float te[64];      // per lane's photon: weight of its own technique in the MIS denominator
+    __shared__ float sval[64][3]; // contributions of a flushed batch
+    __shared__ int sdst[64];      // their pixels (bit 30: light-photon image), -1 for none
     const int lane = threadIdx.x;
     const unsigned long long below = (1ull << lane) - 1ull;
     const int n = *count_in;
@@ -920,7 +922,12 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
     unsigned segs = 0, merges = 0, items = 0, cont = 0, cells = 0, cands = 0;
     int qn = 0;  // queue length, identical in every lane
 
+    // Evaluates up to 64 queued pairs, one per lane, then adds them to the
+    // images with three lanes per pair (one colour channel each), so that the
+    // three atomics of a pair go out in one instruction to one cache line.
     auto flush = [&](int count) {
+        int dst = -1;
+        f3 val = mk3(0.f, 0.f, 0.f);
         if (lane < count) {
             int2 pr = queue[lane];
             float4 t0 = tp[pr.x][0], t1 = tp[pr.x][1];
@@ -938,10 +945,24 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
                     float4 v3 = mr[2];
                     float T = bsdf_pdf(mv, nv, wv, wd) * t0.w;
                     float C = te[pr.x] + ((k >= 2) ? bsdf_pdf(mv, nv, wd, wv) * v3.w * v2.w : 0.f);
-                    int vpix = fbits(mr[3].x);
-                    atomic_add3((km & 256) ? img.LP : img.P, vpix, xyz(v3) * f * xyz(t1) * (1.0f / (C + T)));
+                    dst = fbits(mr[3].x) | ((km & 256) ? (1 << 30) : 0);
+                    val = xyz(v3) * f * xyz(t1) * (1.0f / (C + T));
                     ++merges;
                 }
+            }
+        }
+        sdst[lane] = dst;
+        sval[lane][0] = val.x;
+        sval[lane][1] = val.y;
+        sval[lane][2] = val.z;
+        __syncthreads();
+        const int sub = lane / 3, ch = lane - 3 * sub;
+        for (int b = 0; b < count; b += 21) {
+            const int m = b + sub;
+            if (sub < 21 && m < count) {
+                const int d = sdst[m];
+                if (d >= 0)
+                    atomicAdd(((d & (1 << 30)) ? img.LP : img.P) + 3 * (size_t)(d & ((1 << 30) - 1)) + ch, sval[m][ch]);
             }
         }
     };
