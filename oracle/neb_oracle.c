@@ -32,6 +32,9 @@
  *     (sign-encoded child index, threshold 4), and the class of Appendix B
  *     (its initialisation, the 1000-iteration fill limit, the minimum-area
  *     clamp and the five-probe robust query with the upper median).
+ *   - the two estimators Sec. 5 tried before the octree, over the
+ *     iteration's NEE vertices: the fixed-radius count (naive estimator)
+ *     and the k-nearest-neighbour estimate (k >= 4), both by brute force.
  *   - the plane-box area is NOT evaluated with eq. (area); the oracle uses
  *     the plain definition: the area of the convex polygon obtained by
  *     clipping the plane with the box (the GPU uses eq. (area)).
@@ -147,13 +150,16 @@ typedef struct {
     double merge_radius;
     uint64_t seed;
     uint32_t scene_id;
-    int32_t density_mode;          /* 0 octree single probe, 1 octree robust, 3 analytic */
+    int32_t density_mode;          /* 0 octree single probe, 1 octree robust, 3 analytic,
+                                      4 fixed radius, 5 k nearest neighbours */
     double analytic_rho0, analytic_cam_weight;
     int32_t enable_photons;        /* 0: n_P = 0 (plain PT with MIS over e and E) */
     int32_t win_x0, win_y0, win_x1, win_y1;   /* pixel window, exclusive end; 0,0,0,0 = all */
     int32_t n_threads;
     int32_t record_paths;          /* record vertex sequences of the first iteration */
     int32_t light_photons;         /* n_LP: conventional light photons per iteration (0 = none) */
+    double density_radius;         /* R of the fixed-radius and nearest-neighbour providers (modes 4, 5) */
+    int32_t knn_k;                 /* k of the nearest-neighbour provider (mode 5) */
 } o_params;
 
 typedef struct {
@@ -942,6 +948,7 @@ typedef struct {
     int nvert;
     int *v_path, *v_depth;
     double* v_rho;
+    double* v_pos;                /* positions of this iteration's vertices, 3 per vertex */
     /* emission events */
     int nev, cap_ev;
     int *ev_path, *ev_depth, *ev_tri;
@@ -1066,13 +1073,53 @@ static light_sample sample_light(const o_iter* it, v3 x, v3 nx, const double u[4
     return ls;
 }
 
+/* The two density estimators Sec. 5 compares the octree with, over this
+ * iteration's NEE vertices only (3-D distances, per unit area per
+ * iteration):
+ *  - mode 4, fixed radius (the naive estimator): the number of vertices
+ *    within R of x, over pi R^2;
+ *  - mode 5, k nearest neighbours: k / (pi d_k^2), d_k the distance from x
+ *    to its k-th nearest vertex (a vertex at x is its own nearest); when
+ *    fewer than k vertices lie within R, the mode-4 estimate. */
+static double set_density(const double* pts, int n, v3 x, int mode, double R, int k) {
+    double R2 = R * R, best[64];
+    int m = 0;
+    for (int i = 0; i < n; ++i) {
+        v3 d = sub(mk(pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]), x);
+        double d2 = dot(d, d);
+        if (!(d2 < R2)) continue;
+        if (mode == 5) {
+            /* keep the k smallest squared distances, ascending */
+            int j = m < k ? m : k - 1;
+            if (m >= k && d2 >= best[k - 1]) { ++m; continue; }
+            while (j > 0 && best[j - 1] > d2) { best[j] = best[j - 1]; --j; }
+            best[j] = d2;
+        }
+        ++m;
+    }
+    if (mode == 5 && m >= k) return (double)k / (PI * best[k - 1]);
+    return (double)m / (PI * R2);
+}
+
 static double query_density(const o_iter* it, v3 x, v3 n) {
-    switch (it->prm->density_mode) {
+    const o_params* p = it->prm;
+    switch (p->density_mode) {
     case 0: return octree_density(it->oct, x, n, 0, NULL);
     case 1: return octree_density_robust(it->oct, x, n);
-    case 3: return it->prm->analytic_rho0 + it->prm->analytic_cam_weight * camera_hit_density(&it->cam, x, n);
+    case 3: return p->analytic_rho0 + p->analytic_cam_weight * camera_hit_density(&it->cam, x, n);
+    case 4:
+    case 5: return set_density(it->v_pos, it->nvert, x, p->density_mode, p->density_radius, p->knn_k);
     }
     return 0.0;
+}
+
+/* test hook: the mode-4/5 estimators of n_query points over a point set */
+int32_t orc_point_density(const double* pts, int32_t n, const double* q, int32_t n_query, int32_t mode,
+                          double radius, int32_t k, double* out) {
+    if (n < 0 || n_query < 0 || (mode != 4 && mode != 5) || !(radius > 0.0) || k < 1 || k > 64) return -1;
+    for (int32_t i = 0; i < n_query; ++i)
+        out[i] = set_density(pts, n, mk(q[3 * i], q[3 * i + 1], q[3 * i + 2]), mode, radius, k);
+    return 0;
 }
 
 typedef struct { double *e, *E, *P, *LP; o_stats st; } o_accum;
@@ -1325,6 +1372,9 @@ int32_t orc_render(const o_scene* s, const o_params* prm, int32_t n_iter, int32_
         return -1;
     if ((prm->density_mode == 0 || prm->density_mode == 1) && !oct) return -1;
     if (prm->light_photons < 0) return -1;
+    if ((prm->density_mode == 4 || prm->density_mode == 5) &&
+        (!(prm->density_radius > 0.0) || prm->knn_k < 1 || prm->knn_k > 64))
+        return -1;
     const int L_lp = prm->max_path_len >= 2 ? prm->light_photons : 0;
     o_iter it;
     memset(&it, 0, sizeof(it));
@@ -1346,6 +1396,7 @@ int32_t orc_render(const o_scene* s, const o_params* prm, int32_t n_iter, int32_
     it.pixel = calloc((size_t)it.npath, sizeof(int));
     it.v_path = calloc(nslot, sizeof(int)); it.v_depth = calloc(nslot, sizeof(int));
     it.v_rho = calloc(nslot, sizeof(double));
+    it.v_pos = calloc(3 * nslot, sizeof(double));
     for (int yy = y0, p = 0; yy < y1; ++yy)
         for (int xx = x0; xx < x1; ++xx, ++p) it.pixel[p] = yy * prm->width + xx;
     int nth = nthreads_of(prm);
@@ -1390,6 +1441,10 @@ int32_t orc_render(const o_scene* s, const o_params* prm, int32_t n_iter, int32_
                 float f[3] = {(float)x.x, (float)x.y, (float)x.z};
                 octree_insert(oct, f);
             }
+        }
+        for (int q = 0; q < it.nvert; ++q) {
+            v3 x = it.pos[IDX(&it, it.v_path[q], it.v_depth[q])];
+            it.v_pos[3 * q] = x.x; it.v_pos[3 * q + 1] = x.y; it.v_pos[3 * q + 2] = x.z;
         }
         /* pass 2 (a): densities */
 #ifdef _OPENMP
@@ -1456,7 +1511,7 @@ int32_t orc_render(const o_scene* s, const o_params* prm, int32_t n_iter, int32_
         st->oct_rejected = info[6];
     }
     free(it.pos); free(it.nrml); free(it.wo); free(it.tau); free(it.mat); free(it.prim);
-    free(it.vid); free(it.nhit); free(it.pixel); free(it.v_path); free(it.v_depth); free(it.v_rho);
+    free(it.vid); free(it.nhit); free(it.pixel); free(it.v_path); free(it.v_depth); free(it.v_rho); free(it.v_pos);
     free(it.ev_path); free(it.ev_depth); free(it.ev_tri); free(it.ev_val);
     return 0;
 }

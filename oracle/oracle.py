@@ -44,7 +44,8 @@ class Params(ctypes.Structure):
                 ("win_x0", ctypes.c_int32), ("win_y0", ctypes.c_int32),
                 ("win_x1", ctypes.c_int32), ("win_y1", ctypes.c_int32),
                 ("n_threads", ctypes.c_int32), ("record_paths", ctypes.c_int32),
-                ("light_photons", ctypes.c_int32)]
+                ("light_photons", ctypes.c_int32), ("density_radius", ctypes.c_double),
+                ("knn_k", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -62,7 +63,7 @@ class Stats(ctypes.Structure):
 
 RECORD_DTYPE = np.dtype([("type", "<i4"), ("mat", "<i4"), ("prim", "<i4"), ("pos", "<f4", (3,))])
 
-DENSITY_SINGLE, DENSITY_ROBUST, DENSITY_ANALYTIC = 0, 1, 3
+DENSITY_SINGLE, DENSITY_ROBUST, DENSITY_ANALYTIC, DENSITY_RADIUS, DENSITY_KNN = 0, 1, 3, 4, 5
 
 _P = ctypes.c_void_p
 _D = ctypes.POINTER(ctypes.c_double)
@@ -104,6 +105,9 @@ def lib():
                                                    ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                                    ctypes.c_int32, ctypes.c_double, _P]
         L.orc_path_technique_densities.restype = ctypes.c_int32
+        L.orc_point_density.argtypes = [_P, ctypes.c_int32, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                        ctypes.c_int32, _P]
+        L.orc_point_density.restype = ctypes.c_int32
         _lib = L
     return _lib
 
@@ -167,6 +171,17 @@ def technique_densities(pos, nrm, mats, p_light, hittable, rho, radius, photons=
     if n_lp is None:
         n = 2 + max(0, L - 2)
     return out[:n]
+
+
+def point_density(points, queries, mode, radius, k=4):
+    """Fixed-radius (mode 4) or k-nearest-neighbour (mode 5) density at the
+    query points over the point set (per unit area)."""
+    pts = np.ascontiguousarray(points, np.float64).reshape(-1, 3)
+    q = np.ascontiguousarray(queries, np.float64).reshape(-1, 3)
+    out = np.zeros(len(q))
+    if lib().orc_point_density(_ptr(pts), len(pts), _ptr(q), len(q), int(mode), float(radius), int(k), _ptr(out)):
+        raise ValueError("bad point-density arguments")
+    return out
 
 
 class Octree:
@@ -251,7 +266,7 @@ class OracleScene:
 
 
 def make_params(scene, density_mode=DENSITY_ROBUST, enable_photons=True, window=None, n_threads=0,
-                record=False, rho0=0.0, cam_weight=0.0, light_photons=0, **over):
+                record=False, rho0=0.0, cam_weight=0.0, light_photons=0, density_radius=0.0, knn_k=8, **over):
     p = Params()
     p.width = over.get("width", scene.width)
     p.height = over.get("height", scene.height)
@@ -269,12 +284,14 @@ def make_params(scene, density_mode=DENSITY_ROBUST, enable_photons=True, window=
     p.n_threads = n_threads
     p.record_paths = int(record)
     p.light_photons = int(light_photons)
+    p.density_radius = float(density_radius)
+    p.knn_k = int(knn_k)
     return p
 
 
 def render(scene, n_iter=None, first_iter=1, density_mode=DENSITY_ROBUST, enable_photons=True,
            window=None, n_threads=0, record=False, rho0=0.0, cam_weight=0.0, oscene=None,
-           octree=None, light_photons=0, **over):
+           octree=None, light_photons=0, density_radius=0.0, knn_k=8, **over):
     """Render `n_iter` progressive iterations (1 spp each).  Returns a dict
     with per-technique image sums (H, W, 3): e, E, P and, with
     `light_photons` > 0 conventional photons per iteration, LP; their sum,
@@ -282,7 +299,7 @@ def render(scene, n_iter=None, first_iter=1, density_mode=DENSITY_ROBUST, enable
     records."""
     osc = oscene or OracleScene(scene)
     prm = make_params(scene, density_mode, enable_photons, window, n_threads, record, rho0,
-                      cam_weight, light_photons, **over)
+                      cam_weight, light_photons, density_radius, knn_k, **over)
     n_iter = scene.spp if n_iter is None else n_iter
     oct_ = octree
     if oct_ is None and density_mode in (DENSITY_SINGLE, DENSITY_ROBUST):
