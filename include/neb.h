@@ -52,7 +52,14 @@ enum {
     NEB_DENSITY_OCTREE_ROBUST = 1, /* median of five probes (Appendix B, default) */
     NEB_DENSITY_MLP = 2,           /* learned density fitted to the robust octree, with octree
                                       fallback per region (see neb_configure_mlp) */
-    NEB_DENSITY_ANALYTIC = 3       /* test hook: rho0 + w * primary-hit density of the camera */
+    NEB_DENSITY_ANALYTIC = 3,      /* test hook: rho0 + w * primary-hit density of the camera */
+    NEB_DENSITY_RADIUS = 4,        /* fixed-radius count over the iteration's NEE vertices (the naive
+                                      estimator Sec. 5 tried first): vertices within density_radius,
+                                      over pi density_radius^2 */
+    NEB_DENSITY_KNN = 5            /* k nearest neighbours over the iteration's NEE vertices (Sec. 5's
+                                      second estimator): k / (pi d_k^2), d_k the distance to the k-th
+                                      nearest vertex (a vertex at the query point counts); the mode-4
+                                      estimate when fewer than k lie within density_radius */
 };
 
 /* neb_params.flags */
@@ -81,6 +88,8 @@ typedef struct {
                                   with the view vertices (the optional technique of Sec. 4,
                                   eq. stdphotonpdf, weighted into eq. misw); 0 = none, at most
                                   2^26; not with NEB_DENSITY_MLP */
+    float density_radius;      /* NEB_DENSITY_RADIUS, NEB_DENSITY_KNN: search radius (> 0) */
+    int32_t knn_k;             /* NEB_DENSITY_KNN: k, 1 .. 16 */
 } neb_params;
 
 /* Launch shapes of the traversal and photon kernels (neb_autotune picks
@@ -245,6 +254,18 @@ neb_status neb_get_technique_images(neb_ctx ctx, float* e, float* E, float* P, i
                                     void* stream);
 neb_status neb_get_scene_technique_images(neb_ctx ctx, int32_t scene, float* e, float* E, float* P,
                                           int32_t is_device_ptr, void* stream);
+
+/* The two alternative density providers on a point set (Sec. 5): the
+ * density of n_query points over n points, per unit area, by
+ * NEB_DENSITY_RADIUS (mode 4) or NEB_DENSITY_KNN (mode 5) with the given
+ * radius and k, exactly as a render computes them over its NEE vertices.
+ * points: n*3 floats, queries: n_query*3 floats, out: n_query floats, all
+ * device memory on the current device; stream-ordered (the call allocates
+ * and frees a temporary grid, and returns after the work is done).
+ * n may be 0 (all densities 0).  NEB_ERR_INVALID_ARG for a bad mode,
+ * radius or k, or negative sizes. */
+neb_status neb_point_density(const float* points, int32_t n, const float* queries, int32_t n_query, int32_t mode,
+                             float radius, int32_t k, float* out, void* stream);
 
 /* Mean radiance of the conventional light-photon merges (LP, Sec. 4,
  * eq. stdphotonpdf) of scene `scene`: height*width*3 floats, zero when the

@@ -98,7 +98,10 @@ struct SceneInfo {
     int32_t n_lp;       // light photons per iteration
     int32_t lp_base;    // first global light-photon index of the scene
     float nlp;          // n_LP as a float (0: no light photons)
-    float pad2;
+    float dr;           // density radius (modes 4, 5)
+    float inv_dcell;    // 1 / density-grid cell size
+    int32_t knn_k;      // k (mode 5)
+    int32_t pad3;
 };
 
 // Merge grid keyed by (hash of scene and cell, depth - 1): the records of
@@ -116,6 +119,17 @@ struct Grid {
     int32_t D;        // depth classes = longest maxlen - 1
 };
 
+// Density grid of the alternative providers: every NEE vertex of the
+// iteration, keyed by the hash of its scene and its cell of size
+// 2 * density radius (so a query ball touches at most 8 cells).
+struct DGrid {
+    int32_t* count;   // T + 1 entries (the last stays 0)
+    int32_t* start;   // T + 1 entries
+    float4* pts;      // (pos, scene) in bucket order
+    int32_t* sums;    // scan block sums
+    int32_t T;        // buckets (power of two)
+};
+
 struct RenderArgs {
     SceneView S;
     const SceneInfo* sc;
@@ -128,6 +142,7 @@ struct RenderArgs {
     int32_t density_mode;
     const int32_t* lp_base;   // n_scenes + 1 entries: light photons of the scenes before
     int32_t n_lp;             // light photons of all scenes per iteration
+    DGrid dg;                 // NEB_DENSITY_RADIUS / NEB_DENSITY_KNN
 };
 
 __device__ __forceinline__ int fbits(float f) { return __float_as_int(f); }
@@ -440,16 +455,129 @@ __global__ void __launch_bounds__(256) k_shade(RenderArgs A, PathQ in, const int
 // ---------------------------------------------------------------------------
 // pass 2 (a): density at every NEE vertex
 // ---------------------------------------------------------------------------
+// Bucket of a cell: the cells of one 4 x 4 x 4 block take 64 consecutive
+// buckets (Morton order inside the block), the blocks are hashed with the
+// scene.  The <= 8 cells around a photon hit, and the cells of neighbouring
+// hits, then share a few cache lines of the count/start tables.
+__device__ __forceinline__ uint32_t cell_hash(int cx, int cy, int cz, int scene, int32_t T) {
+    const uint32_t lo = (uint32_t)((cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2) | ((cx & 2) << 2) | ((cy & 2) << 3) |
+                                   ((cz & 2) << 4));
+    const uint32_t hi = ((uint32_t)(cx >> 2) * 73856093u) ^ ((uint32_t)(cy >> 2) * 19349663u) ^
+                        ((uint32_t)(cz >> 2) * 83492791u) ^ ((uint32_t)scene * 2654435761u);
+    return ((hi << 6) | lo) & (uint32_t)(T - 1);
+}
+__device__ __forceinline__ uint32_t point_hash(f3 p, float inv_cell, int scene, int32_t T) {
+    return cell_hash((int)floorf(p.x * inv_cell), (int)floorf(p.y * inv_cell), (int)floorf(p.z * inv_cell), scene, T);
+}
+
+// Fixed-radius count (mode 4) or k-th-neighbour distance (mode 5) at x over
+// the points of scene s in the density grid: the buckets of the <= 8 cells
+// the ball of radius R touches (a bucket counted once even when two cells
+// share it; points of other cells or scenes in a bucket fail the tests).
+// Mode 5 keeps the 16 smallest squared distances in registers, sorted, by a
+// min/max pass over all of them per point.
+constexpr int kKnnMax = 16;
+__device__ __forceinline__ float set_density(const DGrid& D, int s, f3 x, float R, float inv_cell, int mode, int k) {
+    const float R2 = R * R;
+    float best[kKnnMax];
+#pragma unroll
+    for (int t = 0; t < kKnnMax; ++t) best[t] = 3.0e38f;
+    int m = 0;
+    const float rr = R * 1.00001f;
+    const int lx = (int)floorf((x.x - rr) * inv_cell), hx = min((int)floorf((x.x + rr) * inv_cell), lx + 1);
+    const int ly = (int)floorf((x.y - rr) * inv_cell), hy = min((int)floorf((x.y + rr) * inv_cell), ly + 1);
+    const int lz = (int)floorf((x.z - rr) * inv_cell), hz = min((int)floorf((x.z + rr) * inv_cell), lz + 1);
+    uint32_t seen[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int cx = lx + (c & 1), cy = ly + ((c >> 1) & 1), cz = lz + ((c >> 2) & 1);
+        const uint32_t h = cell_hash(cx, cy, cz, s, D.T);
+        bool use = cx <= hx && cy <= hy && cz <= hz;
+        seen[c] = use ? h : 0xFFFFFFFFu;
+#pragma unroll
+        for (int q = 0; q < c; ++q) use = use && seen[q] != h;
+        if (!use) continue;
+        const int e1 = D.start[h + 1];
+        for (int e = D.start[h]; e < e1; ++e) {
+            const float4 p = D.pts[e];
+            const f3 dv = xyz(p) - x;
+            const float d2 = dot3(dv, dv);
+            if (!(d2 < R2) || fbits(p.w) != s) continue;
+            ++m;
+            if (mode == NEB_DENSITY_KNN) {
+                float v = d2;
+#pragma unroll
+                for (int t = 0; t < kKnnMax; ++t) {
+                    const float lo = fminf(best[t], v);
+                    v = fmaxf(best[t], v);
+                    best[t] = lo;
+                }
+            }
+        }
+    }
+    if (mode == NEB_DENSITY_KNN && m >= k) {
+        float dk = best[0];
+#pragma unroll
+        for (int t = 1; t < kKnnMax; ++t)
+            if (t == k - 1) dk = best[t];
+        return (float)k / (NEB_PI * dk);
+    }
+    return (float)m / (NEB_PI * R2);
+}
+
 // density of NEE vertices at x (geometric normal nn) in scene s, from the
-// octree or the analytic test density
+// octree, the density grid or the analytic test density
 __device__ __forceinline__ float point_density(const RenderArgs& A, int s, f3 x, f3 nn, const int32_t* __restrict__ nodes,
                                                const OctState* ost, const OctParams* prm, float scale) {
     if (A.density_mode == NEB_DENSITY_ANALYTIC) {
         const SceneInfo& I = A.sc[s];
         return I.rho0 + I.cam_w * cam_hit_density(I.cam, x, nn);
     }
+    if (A.density_mode == NEB_DENSITY_RADIUS || A.density_mode == NEB_DENSITY_KNN) {
+        const SceneInfo& I = A.sc[s];
+        return set_density(A.dg, s, x, I.dr, I.inv_dcell, A.density_mode, I.knn_k);
+    }
     if (A.density_mode == NEB_DENSITY_OCTREE) return oct_query(nodes, prm[s], scale, ost[s].depth, x, nn, false, nullptr);
     return oct_query_robust(nodes, prm[s], scale, ost[s].depth, x, nn);
+}
+
+// density grid over this iteration's NEE vertices: count -> scan -> scatter
+// (count returns to zero after the scatter)
+__global__ void __launch_bounds__(256) k_dgrid_count(const SceneInfo* sc, VertexStore V, const int32_t* n_vertices,
+                                                     DGrid D) {
+    const int n = *n_vertices;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int s = tag_scene(fbits(V.v1[i].w));
+        atomicAdd(&D.count[point_hash(xyz(V.v0[i]), sc[s].inv_dcell, s, D.T)], 1);
+    }
+}
+__global__ void __launch_bounds__(256) k_dgrid_scatter(const SceneInfo* sc, VertexStore V, const int32_t* n_vertices,
+                                                       DGrid D) {
+    const int n = *n_vertices;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int s = tag_scene(fbits(V.v1[i].w));
+        const f3 p = xyz(V.v0[i]);
+        const uint32_t h = point_hash(p, sc[s].inv_dcell, s, D.T);
+        D.pts[D.start[h] + atomicSub(&D.count[h], 1) - 1] = f4(p, ibits(s));
+    }
+}
+
+// the same over a plain point set (neb_point_density; one scene, 0)
+__global__ void __launch_bounds__(256) k_pset_count(const float* pts, int32_t n, float inv_cell, DGrid D) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        atomicAdd(&D.count[point_hash(mk3(pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]), inv_cell, 0, D.T)], 1);
+}
+__global__ void __launch_bounds__(256) k_pset_scatter(const float* pts, int32_t n, float inv_cell, DGrid D) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const f3 p = mk3(pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]);
+        const uint32_t h = point_hash(p, inv_cell, 0, D.T);
+        D.pts[D.start[h] + atomicSub(&D.count[h], 1) - 1] = f4(p, ibits(0));
+    }
+}
+__global__ void __launch_bounds__(256) k_pset_query(const float* q, int32_t n, DGrid D, float R, float inv_cell, int mode,
+                                                    int k, float* out) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        out[i] = set_density(D, 0, mk3(q[3 * i], q[3 * i + 1], q[3 * i + 2]), R, inv_cell, mode, k);
 }
 
 __global__ void __launch_bounds__(256) k_density(RenderArgs A, VertexStore V, const int32_t* n_vertices,
@@ -737,21 +865,6 @@ __global__ void __launch_bounds__(256) k_lp_first(RenderArgs A, PhotonQ pq, int2
 // merge structure: hash grid of cell size 2r over the non-delta view vertices
 // (count -> exclusive scan -> scatter); count[] returns to zero after scatter
 // ---------------------------------------------------------------------------
-// Bucket of a cell: the cells of one 4 x 4 x 4 block take 64 consecutive
-// buckets (Morton order inside the block), the blocks are hashed with the
-// scene.  The <= 8 cells around a photon hit, and the cells of neighbouring
-// hits, then share a few cache lines of the count/start tables.
-__device__ __forceinline__ uint32_t cell_hash(int cx, int cy, int cz, int scene, int32_t T) {
-    const uint32_t lo = (uint32_t)((cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2) | ((cx & 2) << 2) | ((cy & 2) << 3) |
-                                   ((cz & 2) << 4));
-    const uint32_t hi = ((uint32_t)(cx >> 2) * 73856093u) ^ ((uint32_t)(cy >> 2) * 19349663u) ^
-                        ((uint32_t)(cz >> 2) * 83492791u) ^ ((uint32_t)scene * 2654435761u);
-    return ((hi << 6) | lo) & (uint32_t)(T - 1);
-}
-__device__ __forceinline__ uint32_t point_hash(f3 p, float inv_cell, int scene, int32_t T) {
-    return cell_hash((int)floorf(p.x * inv_cell), (int)floorf(p.y * inv_cell), (int)floorf(p.z * inv_cell), scene, T);
-}
-
 __device__ __forceinline__ int64_t grid_key(const Grid& G, uint32_t h, int depth) {
     return (int64_t)h * G.D + (depth - 1);
 }
@@ -1356,6 +1469,7 @@ struct neb_ctx_s {
     int32_t* slots = nullptr;
     neb_path_record* recs = nullptr;
     Grid G{};
+    DGrid dg{};  // NEB_DENSITY_RADIUS / NEB_DENSITY_KNN
     // spatial order of photon hits
     int32_t *pbin = nullptr, *porder = nullptr, *bcount = nullptr, *bstart = nullptr, *bsums = nullptr;
     int32_t bin_bits = 0, n_bins = 0;
@@ -1391,11 +1505,11 @@ struct neb_ctx_s {
 
 enum KernelId {
     K_CAMERA, K_EXTEND_CAMERA, K_SHADE, K_OCTREE_INSERT, K_DENSITY, K_NEE, K_GRID_BUILD, K_EXTEND_PHOTON, K_PHOTON,
-    K_FINALIZE, K_MLP_TRAIN, K_PHOTON_ORDER, K_MISC, K_LIGHT_PHOTON, K_COUNT
+    K_FINALIZE, K_MLP_TRAIN, K_PHOTON_ORDER, K_MISC, K_LIGHT_PHOTON, K_DENSITY_GRID, K_COUNT
 };
 static const char* kKernelNames[K_COUNT] = {"camera", "extend_camera", "shade", "octree_insert", "density", "nee",
                                             "grid_build", "extend_photon", "photon_merge", "finalize", "mlp_train",
-                                            "photon_order", "misc", "light_photon"};
+                                            "photon_order", "misc", "light_photon", "density_grid"};
 
 static void prof_harvest(neb_ctx c) {
     if (c->prof_used == 0) return;
@@ -1553,8 +1667,15 @@ static neb_status check_params(const neb_params* p) {
     if (p->octree_capacity < 1 || p->octree_capacity > (1 << 29)) return fail(NEB_ERR_INVALID_ARG, "octree capacity out of range");
     if (!(p->merge_radius > 0.f) || !std::isfinite(p->merge_radius)) return fail(NEB_ERR_INVALID_ARG, "merge radius must be > 0");
     if (p->density_mode != NEB_DENSITY_OCTREE && p->density_mode != NEB_DENSITY_OCTREE_ROBUST &&
-        p->density_mode != NEB_DENSITY_ANALYTIC && p->density_mode != NEB_DENSITY_MLP)
+        p->density_mode != NEB_DENSITY_ANALYTIC && p->density_mode != NEB_DENSITY_MLP &&
+        p->density_mode != NEB_DENSITY_RADIUS && p->density_mode != NEB_DENSITY_KNN)
         return fail(NEB_ERR_INVALID_ARG, "unknown density mode");
+    if (p->density_mode == NEB_DENSITY_RADIUS || p->density_mode == NEB_DENSITY_KNN) {
+        if (!(p->density_radius > 0.f) || !std::isfinite(p->density_radius))
+            return fail(NEB_ERR_INVALID_ARG, "density_radius must be > 0");
+        if (p->density_mode == NEB_DENSITY_KNN && (p->knn_k < 1 || p->knn_k > kKnnMax))
+            return fail(NEB_ERR_INVALID_ARG, "knn_k out of range (1 .. 16)");
+    }
     if (!std::isfinite(p->analytic_rho0) || !std::isfinite(p->analytic_cam_weight))
         return fail(NEB_ERR_INVALID_ARG, "analytic density parameters must be finite");
     if (p->spp < 0) return fail(NEB_ERR_INVALID_ARG, "spp must be >= 0");
@@ -1667,6 +1788,13 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
     ALLOC(c->G.sorted, vcap);
     ALLOC(c->G.mrec, 4 * vcap);
     ALLOC(c->G.sums, scan_scratch(gkeys));
+    if (c->density_mode == NEB_DENSITY_RADIUS || c->density_mode == NEB_DENSITY_KNN) {
+        c->dg.T = c->G.T;
+        ALLOC(c->dg.count, (int64_t)c->dg.T + 1);
+        ALLOC(c->dg.start, (int64_t)c->dg.T + 1);
+        ALLOC(c->dg.pts, vcap);
+        ALLOC(c->dg.sums, scan_scratch((int64_t)c->dg.T + 1));
+    }
     ALLOC(c->img, 12 * npix);
     ALLOC(c->cnt, 1);
     ALLOC(c->oct_nodes, oct_total);
@@ -1707,6 +1835,9 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
 #undef ALLOC
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(gkeys, 256)), dim3(256), 0, nullptr, c->G.count, 0, gkeys);
+        if (c->dg.count)
+            hipLaunchKernelGGL(k_fill_i32, dim3(grid_of((int64_t)c->dg.T + 1, 256)), dim3(256), 0, nullptr, c->dg.count,
+                               0, (int64_t)c->dg.T + 1);
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(c->n_bins + 2, 256)), dim3(256), 0, nullptr, c->bcount, 0,
                            (int64_t)c->n_bins + 2);
         hipLaunchKernelGGL(k_fill_f32, dim3(grid_of(12 * npix, 256)), dim3(256), 0, nullptr, c->img, 0.f, 12 * npix);
@@ -1982,6 +2113,9 @@ static neb_status prepare(neb_ctx c) {
         I.n_lp = P.max_path_len >= 2 ? P.light_photons : 0;
         I.lp_base = c->lp_base[s];
         I.nlp = (float)I.n_lp;
+        I.dr = P.density_radius;
+        I.inv_dcell = P.density_radius > 0.f ? 1.0f / (2.0001f * P.density_radius) : 0.f;
+        I.knn_k = P.knn_k;
         OctParams& O = c->oct_prm[s];
         octree_params_init(O, H.bmin, H.bmax, O.root, P.octree_capacity);
         nb += H.bvh.n_nodes;
@@ -2070,6 +2204,7 @@ static RenderArgs make_args(neb_ctx c) {
     A.density_mode = c->density_mode;
     A.lp_base = c->lp_base_dev;
     A.n_lp = c->n_lp;
+    A.dg = c->dg;
     return A;
 }
 
@@ -2139,7 +2274,17 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
                                           record ? c->recs : (neb_path_record*)nullptr));
     }
     // deposits of this iteration's NEE vertices into their scenes' octrees
-    if (c->density_mode != NEB_DENSITY_ANALYTIC && !model) {
+    const bool set_mode = c->density_mode == NEB_DENSITY_RADIUS || c->density_mode == NEB_DENSITY_KNN;
+    if (set_mode) {
+        // density grid over this iteration's NEE vertices
+        prof_begin(c, K_DENSITY_GRID, s);
+        hipLaunchKernelGGL(k_dgrid_count, dim3(grid_of(vcap, 256)), dim3(256), 0, s, (const SceneInfo*)c->sc_dev, c->V,
+                           (const int32_t*)&cnt->n_vertices, c->dg);
+        scan_exclusive(c->dg.count, c->dg.start, (int64_t)c->dg.T + 1, c->dg.sums, s);
+        hipLaunchKernelGGL(k_dgrid_scatter, dim3(grid_of(vcap, 256)), dim3(256), 0, s, (const SceneInfo*)c->sc_dev,
+                           c->V, (const int32_t*)&cnt->n_vertices, c->dg);
+        prof_end(c, s);
+    } else if (c->density_mode != NEB_DENSITY_ANALYTIC && !model) {
         hipError_t e;
         const float* pos = (const float*)c->V.v0;
         const int32_t* tagw = (const int32_t*)c->V.v1 + 3;
@@ -2386,6 +2531,41 @@ extern "C" neb_status neb_get_scene_technique_images(neb_ctx c, int32_t scene, f
 
 extern "C" neb_status neb_get_technique_images(neb_ctx c, float* e, float* E, float* P, int32_t is_dev, void* stream) {
     return neb_get_scene_technique_images(c, 0, e, E, P, is_dev, stream);
+}
+
+extern "C" neb_status neb_point_density(const float* points, int32_t n, const float* queries, int32_t n_query,
+                                        int32_t mode, float radius, int32_t k, float* out, void* stream) {
+    if (n < 0 || n_query < 0) return fail(NEB_ERR_INVALID_ARG, "negative size");
+    if (mode != NEB_DENSITY_RADIUS && mode != NEB_DENSITY_KNN) return fail(NEB_ERR_INVALID_ARG, "mode must be 4 or 5");
+    if (!(radius > 0.f) || !std::isfinite(radius)) return fail(NEB_ERR_INVALID_ARG, "radius must be > 0");
+    if (mode == NEB_DENSITY_KNN && (k < 1 || k > kKnnMax)) return fail(NEB_ERR_INVALID_ARG, "k out of range (1 .. 16)");
+    if (n_query == 0) return NEB_OK;
+    if (!queries || !out || (n > 0 && !points)) return fail(NEB_ERR_INVALID_ARG, "null pointer");
+    hipStream_t s = (hipStream_t)stream;
+    DGrid D{};
+    D.T = (int32_t)std::max<uint64_t>(1024, std::min<uint64_t>(next_pow2((uint64_t)std::max(n, 1)) / 2, 1u << 23));
+    std::vector<void*> tmp;
+    hipError_t e = dalloc(tmp, &D.count, (size_t)D.T + 1);
+    if (e == hipSuccess) e = dalloc(tmp, &D.start, (size_t)D.T + 1);
+    if (e == hipSuccess) e = dalloc(tmp, &D.pts, (size_t)std::max(n, 1));
+    if (e == hipSuccess) e = dalloc(tmp, &D.sums, (size_t)scan_scratch((int64_t)D.T + 1));
+    if (e != hipSuccess) {
+        free_list(tmp);
+        return oom_or_device(e, "neb_point_density");
+    }
+    const float inv_cell = 1.0f / (2.0001f * radius);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_of((int64_t)D.T + 1, 256)), dim3(256), 0, s, D.count, 0,
+                       (int64_t)D.T + 1);
+    if (n > 0) hipLaunchKernelGGL(k_pset_count, dim3(grid_of(n, 256)), dim3(256), 0, s, points, n, inv_cell, D);
+    scan_exclusive(D.count, D.start, (int64_t)D.T + 1, D.sums, s);
+    if (n > 0) hipLaunchKernelGGL(k_pset_scatter, dim3(grid_of(n, 256)), dim3(256), 0, s, points, n, inv_cell, D);
+    hipLaunchKernelGGL(k_pset_query, dim3(grid_of(n_query, 256)), dim3(256), 0, s, queries, n_query, D, radius, inv_cell,
+                       (int)mode, (int)k, out);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    free_list(tmp);
+    if (e != hipSuccess) return oom_or_device(e, "neb_point_density");
+    return NEB_OK;
 }
 
 extern "C" neb_status neb_get_scene_light_photon_image(neb_ctx c, int32_t scene, float* LP, int32_t is_dev,

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libneb.so")
 _lib = None
 
 NEB_OK = 0
-DENSITY_OCTREE, DENSITY_OCTREE_ROBUST, DENSITY_MLP, DENSITY_ANALYTIC = 0, 1, 2, 3
+DENSITY_OCTREE, DENSITY_OCTREE_ROBUST, DENSITY_MLP, DENSITY_ANALYTIC, DENSITY_RADIUS, DENSITY_KNN = 0, 1, 2, 3, 4, 5
 MLP_PARAMS = 13569
 FLAG_SINGLE_THREAD_OCTREE, FLAG_RECORD_PATHS, FLAG_NO_PHOTONS = 1, 2, 4
 
@@ -23,7 +23,7 @@ EXPORTS = [
     "neb_create", "neb_create_batch", "neb_set_scene", "neb_set_batch_scene", "neb_render", "neb_use_graph",
     "neb_autotune", "neb_set_launch_config", "neb_get_launch_config", "neb_get_image", "neb_get_scene_image",
     "neb_get_technique_images", "neb_get_scene_technique_images", "neb_get_scene_light_photon_image",
-    "neb_query_density", "neb_get_stats", "neb_get_path_records", "neb_get_octree", "neb_get_scene_octree",
+    "neb_query_density", "neb_point_density", "neb_get_stats", "neb_get_path_records", "neb_get_octree", "neb_get_scene_octree",
     "neb_profile_kernels", "neb_get_kernel_profile", "neb_reset",
     "neb_destroy", "neb_status_string", "neb_last_error",
     "neb_configure_mlp", "neb_get_mlp_status", "neb_get_mlp_weights", "neb_mlp_create", "neb_mlp_set_normalization",
@@ -42,7 +42,8 @@ class Params(ctypes.Structure):
                 ("octree_capacity", ctypes.c_int32), ("merge_radius", ctypes.c_float),
                 ("seed", ctypes.c_uint32), ("scene_id", ctypes.c_uint32), ("density_mode", ctypes.c_int32),
                 ("analytic_rho0", ctypes.c_float), ("analytic_cam_weight", ctypes.c_float),
-                ("flags", ctypes.c_int32), ("spp", ctypes.c_int32), ("light_photons", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("spp", ctypes.c_int32), ("light_photons", ctypes.c_int32),
+                ("density_radius", ctypes.c_float), ("knn_k", ctypes.c_int32)]
 
 
 class LaunchConfig(ctypes.Structure):
@@ -121,6 +122,7 @@ def lib():
             "neb_get_scene_technique_images": ([_P, i32, _P, _P, _P, i32, _P], i32),
             "neb_get_scene_light_photon_image": ([_P, i32, _P, i32, _P], i32),
             "neb_query_density": ([_P, _P, _P, i32, _P, i32, _P], i32),
+            "neb_point_density": ([_P, i32, _P, i32, i32, ctypes.c_float, i32, _P, _P], i32),
             "neb_get_stats": ([_P, ctypes.POINTER(Stats)], i32),
             "neb_get_path_records": ([_P, _P, i64], i32),
             "neb_get_octree": ([_P, _P, i32, _P], i32),
@@ -197,7 +199,26 @@ def make_params(scene, density_mode=DENSITY_OCTREE_ROBUST, flags=0, rho0=0.0, ca
     p.flags = flags
     p.spp = over.get("spp", 0)
     p.light_photons = over.get("light_photons", 0)
+    p.density_radius = over.get("density_radius", 0.0)
+    p.knn_k = over.get("knn_k", 8)
     return p
+
+
+def point_density(points, queries, mode, radius, k=8, out=None, stream=None):
+    """Fixed-radius (DENSITY_RADIUS) or k-nearest-neighbour (DENSITY_KNN)
+    density of the query points over the point set, per unit area
+    (neb_point_density).  points (n, 3) and queries (m, 3): float32 device
+    tensors; returns an (m,) float32 device tensor."""
+    import torch
+    assert points.dtype == torch.float32 and queries.dtype == torch.float32
+    assert points.is_contiguous() and queries.is_contiguous()
+    m = queries.shape[0]
+    if out is None:
+        out = torch.empty(m, dtype=torch.float32, device=queries.device)
+    _check(lib().neb_point_density(_dev_ptr(points) if points.numel() else None, points.shape[0],
+                                   _dev_ptr(queries), m, int(mode), float(radius), int(k), _dev_ptr(out),
+                                   _stream(stream)))
+    return out
 
 
 def _scene_arrays(scene):

@@ -73,3 +73,38 @@ def test_invalid_arguments_are_rejected_without_a_device():
     one[1].spp = 0
     one[0].density_mode = one[1].density_mode = 2
     assert L.neb_create_batch(one, 2, ctypes.byref(h)) == -1          # learned density: one scene only
+
+
+def test_light_photon_and_density_provider_arguments_without_a_device():
+    """Light photons, the alternative density providers and the point-set
+    density entry point validate their arguments before any HIP call."""
+    import ctypes
+    from paper_1909_00573_amd import neb
+    if not os.path.exists(neb.LIB_PATH):
+        pytest.skip("libneb.so not built")
+    L = neb.lib()
+    h = ctypes.c_void_p()
+    p = neb.Params()
+    p.width, p.height, p.max_path_len, p.octree_capacity, p.merge_radius = 8, 8, 4, 64, 0.01
+    p.light_photons = -1
+    assert L.neb_create(ctypes.byref(p), ctypes.byref(h)) == -1
+    p.light_photons = (1 << 26) + 1
+    assert L.neb_create(ctypes.byref(p), ctypes.byref(h)) == -1
+    p.light_photons, p.density_mode = 64, 2
+    assert L.neb_create(ctypes.byref(p), ctypes.byref(h)) == -1          # light photons with the learned density
+    p.light_photons = 0
+    for mode in (4, 5):
+        p.density_mode, p.density_radius, p.knn_k = mode, 0.0, 8
+        assert L.neb_create(ctypes.byref(p), ctypes.byref(h)) == -1      # radius must be > 0
+    p.density_mode, p.density_radius, p.knn_k = 5, 0.1, 17
+    assert L.neb_create(ctypes.byref(p), ctypes.byref(h)) == -1          # k above 16
+    p.density_mode = 6
+    assert L.neb_create(ctypes.byref(p), ctypes.byref(h)) == -1          # unknown mode
+    # neb_point_density: mode, radius, k and sizes; an empty query set is a no-op
+    assert L.neb_point_density(None, 0, None, 1, 3, ctypes.c_float(0.1), 4, None, None) == -1
+    assert L.neb_point_density(None, 0, None, 1, 4, ctypes.c_float(0.0), 4, None, None) == -1
+    assert L.neb_point_density(None, 0, None, 1, 5, ctypes.c_float(0.1), 0, None, None) == -1
+    assert L.neb_point_density(None, -1, None, 1, 4, ctypes.c_float(0.1), 4, None, None) == -1
+    assert L.neb_point_density(None, 5, None, 0, 4, ctypes.c_float(0.1), 4, None, None) == 0
+    assert L.neb_point_density(None, 5, None, 3, 4, ctypes.c_float(0.1), 4, None, None) == -1   # null pointers
+    assert L.neb_get_scene_light_photon_image(None, 0, None, 0, None) == -1
