@@ -32,6 +32,8 @@
  *     (sign-encoded child index, threshold 4), and the class of Appendix B
  *     (its initialisation, the 1000-iteration fill limit, the minimum-area
  *     clamp and the five-probe robust query with the upper median).
+ *   - NEE recycling (Sec. 6): every vertex averages the light samples of
+ *     the NEE vertices within a radius, n_E of eq. misw being their number.
  *   - the two estimators Sec. 5 tried before the octree, over the
  *     iteration's NEE vertices: the fixed-radius count (naive estimator)
  *     and the k-nearest-neighbour estimate (k >= 4), both by brute force.
@@ -58,6 +60,9 @@
  *     there, but they emit photons); occluded NEEs emit no photon.
  *   - delta BSDF pdfs are the discrete lobe probabilities.
  *   - no Russian roulette; geometric normals only; no eta^2 scaling.
+ *   - NEE recycling borrows a neighbour's visibility and light point; the
+ *     neighbour's own sample counts although it may be occluded from the
+ *     receiver; not combined with light photons.
  *   - light photons: area lights emit with the cosine lobe around their
  *     normal, point lights uniformly over the sphere; the light vertex of
  *     their paths is the sampled light point; the density rho_{L-1} that
@@ -160,6 +165,7 @@ typedef struct {
     int32_t light_photons;         /* n_LP: conventional light photons per iteration (0 = none) */
     double density_radius;         /* R of the fixed-radius and nearest-neighbour providers (modes 4, 5) */
     int32_t knn_k;                 /* k of the nearest-neighbour provider (mode 5) */
+    double nee_radius;             /* NEE recycling radius (0 = each vertex uses its own NEE only) */
 } o_params;
 
 typedef struct {
@@ -846,6 +852,7 @@ typedef struct {
     double r2pi;           /* pi r^2 */
     int photons;           /* n_P > 0 */
     double n_lp;           /* n_LP, light photons per iteration (0 = none) */
+    double n_e;            /* n_E, NEE samples at x_{L-1} (1; with NEE recycling the events found there) */
 } o_path;
 
 /* index of the conventional-photon technique LP_k in the technique list */
@@ -883,7 +890,7 @@ static void path_densities(const o_path* P, double* out) {
         pE = P->p_light;
         for (int i = 1; i <= L - 2; ++i) pE *= f[i];
     }
-    out[1] = pE;
+    out[1] = P->n_e * pE;
     for (int k = 1; k <= L - 2; ++k) {
         double pp = 0.0;
         if (P->photons && P->rho > 0.0 && !mat_is_delta(P->mat[k])) {
@@ -935,6 +942,8 @@ typedef struct {
     int nhit;                     /* number of hits (vertices 1..nhit) */
 } path_hdr;
 
+typedef struct { int tri, pl; v3 x, n; double p_light, d2, dist; v3 w, dE; int hittable; } light_sample;
+
 typedef struct {
     const o_scene* s;
     const o_params* prm;
@@ -949,6 +958,9 @@ typedef struct {
     int *v_path, *v_depth;
     double* v_rho;
     double* v_pos;                /* positions of this iteration's vertices, 3 per vertex */
+    double* v_ne;                 /* n_E per vertex: 1, or with NEE recycling the NEE vertices within the radius */
+    light_sample* v_ls;           /* each vertex's own light sample (NEE recycling) */
+    int* v_lsok;                  /* 1 when that sample is unoccluded with nonzero dE */
     /* emission events */
     int nev, cap_ev;
     int *ev_path, *ev_depth, *ev_tri;
@@ -1032,8 +1044,6 @@ static void path_from_camera(const o_iter* it, int p, int k, o_path* P) {
         P->vn[i] = it->nrml[IDX(it, p, i)];
     }
 }
-
-typedef struct { int tri, pl; v3 x, n; double p_light, d2, dist; v3 w, dE; int hittable; } light_sample;
 
 static light_sample sample_light(const o_iter* it, v3 x, v3 nx, const double u[4]) {
     const o_scene* s = it->s;
@@ -1141,6 +1151,8 @@ static void nee_and_photon(const o_iter* it, int vi, int iter, o_accum* acc) {
     double u[4];
     uniforms(it->key, (uint32_t)pix, (uint32_t)iter, (uint32_t)m, TAG_NEE, u);
     light_sample ls = sample_light(it, x, n, u);
+    const int recycle = prm->nee_radius > 0.0;
+    if (recycle) { it->v_ls[vi] = ls; it->v_lsok[vi] = 0; }
     if (is_zero(ls.dE)) return;
     v3 so = offset_origin(s, x, n, ls.w);
     v3 sd = sub(ls.x, so);
@@ -1148,8 +1160,9 @@ static void nee_and_photon(const o_iter* it, int vi, int iter, o_accum* acc) {
     acc->st.rays += 1;
     if (occluded(s, so, scl(sd, 1.0 / sl), (1.0 - 1e-5) * sl)) return;
     acc->st.nee_visible += 1;
+    if (recycle) it->v_lsok[vi] = 1;
     double r2pi = PI * prm->merge_radius * prm->merge_radius;
-    if (!mat_is_delta(mt)) {
+    if (!recycle && !mat_is_delta(mt)) {
         v3 f = bsdf_f(mt, n, wo, ls.w);
         if (!is_zero(f)) {
             o_path P;
@@ -1159,6 +1172,7 @@ static void nee_and_photon(const o_iter* it, int vi, int iter, o_accum* acc) {
             P.p_light = ls.p_light; P.hittable = ls.hittable; P.rho = rho; P.r2pi = r2pi;
             P.photons = prm->enable_photons;
             P.n_lp = prm->light_photons;
+            P.n_e = 1.0;
             double w = mis_weight(&P, 1);
             add_px(acc->E, pix, scl(hmul(hmul(tau, f), ls.dE), w));
         }
@@ -1215,6 +1229,7 @@ static void nee_and_photon(const o_iter* it, int vi, int iter, o_accum* acc) {
                 P.p_light = ls.p_light; P.hittable = ls.hittable; P.rho = rho; P.r2pi = r2pi;
                 P.photons = 1;
                 P.n_lp = prm->light_photons;
+                P.n_e = it->v_ne[vi];
                 double w = mis_weight(&P, 1 + k);
                 v3 c = scl(hmul(hmul(it->tau[qid], f), phi), w / r2pi);
                 add_px(acc->P, it->pixel[it->v_path[q]], c);
@@ -1229,6 +1244,58 @@ static void nee_and_photon(const o_iter* it, int vi, int iter, o_accum* acc) {
         o = offset_origin(s, y, ny, bs.dir);
         d = bs.dir;
     }
+}
+
+/* NEE recycling (Sec. 6, the subsection on reusing NEE events): vertex vi
+ * evaluates the light samples of every NEE vertex within the recycling
+ * radius (its own included) with its own BSDF and averages them; n_E in
+ * eq. misw becomes the number of events found.  A light sample does not
+ * depend on the receiving point (light by power, point uniform on it), so
+ * only its visibility, tested from the vertex that drew it, is borrowed. */
+static void recycled_nee(const o_iter* it, int vi, o_accum* acc) {
+    const o_scene* s = it->s;
+    const o_params* prm = it->prm;
+    int p = it->v_path[vi], m = it->v_depth[vi];
+    size_t id = IDX(it, p, m);
+    v3 x = it->pos[id], n = it->nrml[id], wo = it->wo[id], tau = it->tau[id];
+    const o_material* mt = &s->mats[it->mat[id]];
+    if (mat_is_delta(mt)) return;
+    double R2 = prm->nee_radius * prm->nee_radius, ne = it->v_ne[vi];
+    double r2pi = PI * prm->merge_radius * prm->merge_radius;
+    v3 sum = mk(0, 0, 0);
+    for (int q = 0; q < it->nvert; ++q) {
+        if (!it->v_lsok[q]) continue;
+        v3 dq = sub(mk(it->v_pos[3 * q], it->v_pos[3 * q + 1], it->v_pos[3 * q + 2]), x);
+        if (!(dot(dq, dq) < R2)) continue;
+        const light_sample* L = &it->v_ls[q];
+        v3 dv = sub(L->x, x);
+        double d2 = dot(dv, dv);
+        v3 w = scl(dv, 1.0 / sqrt(d2));
+        double cx = fabs(dot(n, w));
+        v3 dE, ln;
+        if (L->tri >= 0) {
+            double cl = -dot(L->n, w);
+            if (!(cl > 0.0) || !(cx > 0.0)) continue;
+            dE = scl(from_f(s->mats[s->mat[L->tri]].emission), cx * cl / (d2 * L->p_light));
+            ln = L->n;
+        } else {
+            if (!(cx > 0.0)) continue;
+            dE = scl(from_f(s->pl[L->pl].power), cx / (4.0 * PI * d2 * L->p_light));
+            ln = scl(w, -1.0);
+        }
+        v3 f = bsdf_f(mt, n, wo, w);
+        if (is_zero(f)) continue;
+        o_path P;
+        P.L = m + 1;
+        path_from_camera(it, p, m, &P);
+        P.seg_a[m] = x; P.seg_b[m] = L->x; P.na[m] = n; P.nb[m] = ln;
+        P.p_light = L->p_light; P.hittable = L->hittable; P.rho = it->v_rho[vi]; P.r2pi = r2pi;
+        P.photons = prm->enable_photons;
+        P.n_lp = 0.0;
+        P.n_e = ne;
+        sum = add(sum, scl(hmul(hmul(tau, f), dE), mis_weight(&P, 1)));
+    }
+    add_px(acc->E, it->pixel[p], scl(sum, 1.0 / ne));
 }
 
 static void emission_event(const o_iter* it, int e, o_accum* acc) {
@@ -1247,6 +1314,7 @@ static void emission_event(const o_iter* it, int e, o_accum* acc) {
     P.r2pi = PI * it->prm->merge_radius * it->prm->merge_radius;
     P.photons = it->prm->enable_photons;
     P.n_lp = it->prm->light_photons;
+    P.n_e = l >= 2 ? it->v_ne[it->vid[IDX(it, p, l - 1)]] : 1.0;
     double w = mis_weight(&P, 0);
     add_px(acc->e, it->pixel[p], scl(it->ev_val[e], w));
 }
@@ -1340,6 +1408,7 @@ static void light_photon(const o_iter* it, int i, int iter, o_accum* acc) {
                 P.p_light = p_light; P.hittable = hittable; P.rho = rho1; P.r2pi = r2pi;
                 P.photons = prm->enable_photons;
                 P.n_lp = nlp;
+                P.n_e = 1.0;
                 double w = mis_weight(&P, lp_tech(P.L, k));
                 add_px(acc->LP, it->pixel[it->v_path[q]], scl(hmul(hmul(it->tau[qid], f), phi), w / r2pi));
                 acc->st.merges += 1;
@@ -1372,6 +1441,7 @@ int32_t orc_render(const o_scene* s, const o_params* prm, int32_t n_iter, int32_
         return -1;
     if ((prm->density_mode == 0 || prm->density_mode == 1) && !oct) return -1;
     if (prm->light_photons < 0) return -1;
+    if (prm->nee_radius < 0.0 || (prm->nee_radius > 0.0 && prm->light_photons > 0)) return -1;
     if ((prm->density_mode == 4 || prm->density_mode == 5) &&
         (!(prm->density_radius > 0.0) || prm->knn_k < 1 || prm->knn_k > 64))
         return -1;
@@ -1397,6 +1467,9 @@ int32_t orc_render(const o_scene* s, const o_params* prm, int32_t n_iter, int32_
     it.v_path = calloc(nslot, sizeof(int)); it.v_depth = calloc(nslot, sizeof(int));
     it.v_rho = calloc(nslot, sizeof(double));
     it.v_pos = calloc(3 * nslot, sizeof(double));
+    it.v_ne = calloc(nslot, sizeof(double));
+    it.v_ls = calloc(nslot, sizeof(light_sample));
+    it.v_lsok = calloc(nslot, sizeof(int));
     for (int yy = y0, p = 0; yy < y1; ++yy)
         for (int xx = x0; xx < x1; ++xx, ++p) it.pixel[p] = yy * prm->width + xx;
     int nth = nthreads_of(prm);
@@ -1454,6 +1527,23 @@ int32_t orc_render(const o_scene* s, const o_params* prm, int32_t n_iter, int32_
             size_t id = IDX(&it, it.v_path[q], it.v_depth[q]);
             it.v_rho[q] = query_density(&it, it.pos[id], it.nrml[id]);
         }
+        /* n_E: the NEE events each vertex will use (recycling: all NEE
+         * vertices within the radius, the vertex itself included) */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nth)
+#endif
+        for (int q = 0; q < it.nvert; ++q) {
+            it.v_ne[q] = 1.0;
+            if (prm->nee_radius > 0.0) {
+                double R2 = prm->nee_radius * prm->nee_radius, c = 0.0;
+                for (int j = 0; j < it.nvert; ++j) {
+                    double dx = it.v_pos[3 * j] - it.v_pos[3 * q], dy = it.v_pos[3 * j + 1] - it.v_pos[3 * q + 1];
+                    double dz = it.v_pos[3 * j + 2] - it.v_pos[3 * q + 2];
+                    if (dx * dx + dy * dy + dz * dz < R2) c += 1.0;
+                }
+                it.v_ne[q] = c;
+            }
+        }
         /* pass 2 (b, c): NEE and photons */
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 8) num_threads(nth)
@@ -1465,6 +1555,20 @@ int32_t orc_render(const o_scene* s, const o_params* prm, int32_t n_iter, int32_
             int t = 0;
 #endif
             nee_and_photon(&it, q, iter, &acc[t]);
+        }
+        /* pass 2 (b'): NEE recycling */
+        if (prm->nee_radius > 0.0) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nth)
+#endif
+            for (int q = 0; q < it.nvert; ++q) {
+#ifdef _OPENMP
+                int t = omp_get_thread_num();
+#else
+                int t = 0;
+#endif
+                recycled_nee(&it, q, &acc[t]);
+            }
         }
         /* pass 2 (d): conventional light photons */
         if (L_lp > 0) {
@@ -1512,6 +1616,7 @@ int32_t orc_render(const o_scene* s, const o_params* prm, int32_t n_iter, int32_
     }
     free(it.pos); free(it.nrml); free(it.wo); free(it.tau); free(it.mat); free(it.prim);
     free(it.vid); free(it.nhit); free(it.pixel); free(it.v_path); free(it.v_depth); free(it.v_rho); free(it.v_pos);
+    free(it.v_ne); free(it.v_ls); free(it.v_lsok);
     free(it.ev_path); free(it.ev_depth); free(it.ev_tri); free(it.ev_val);
     return 0;
 }
@@ -1544,7 +1649,7 @@ int32_t orc_path_technique_densities(int32_t L, const double* pos, const double*
         P.vn[i] = mk(nrmv[3 * i], nrmv[3 * i + 1], nrmv[3 * i + 2]);
     }
     P.p_light = p_light; P.hittable = hittable; P.rho = rho;
-    P.r2pi = PI * radius * radius; P.photons = photons; P.n_lp = n_lp;
+    P.r2pi = PI * radius * radius; P.photons = photons; P.n_lp = n_lp; P.n_e = 1.0;
     path_densities(&P, out);
     return n_techniques(L);
 }

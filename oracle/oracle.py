@@ -45,7 +45,7 @@ class Params(ctypes.Structure):
                 ("win_x1", ctypes.c_int32), ("win_y1", ctypes.c_int32),
                 ("n_threads", ctypes.c_int32), ("record_paths", ctypes.c_int32),
                 ("light_photons", ctypes.c_int32), ("density_radius", ctypes.c_double),
-                ("knn_k", ctypes.c_int32)]
+                ("knn_k", ctypes.c_int32), ("nee_radius", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -266,7 +266,8 @@ class OracleScene:
 
 
 def make_params(scene, density_mode=DENSITY_ROBUST, enable_photons=True, window=None, n_threads=0,
-                record=False, rho0=0.0, cam_weight=0.0, light_photons=0, density_radius=0.0, knn_k=8, **over):
+                record=False, rho0=0.0, cam_weight=0.0, light_photons=0, density_radius=0.0, knn_k=8,
+                nee_radius=0.0, **over):
     p = Params()
     p.width = over.get("width", scene.width)
     p.height = over.get("height", scene.height)
@@ -286,12 +287,13 @@ def make_params(scene, density_mode=DENSITY_ROBUST, enable_photons=True, window=
     p.light_photons = int(light_photons)
     p.density_radius = float(density_radius)
     p.knn_k = int(knn_k)
+    p.nee_radius = float(nee_radius)
     return p
 
 
 def render(scene, n_iter=None, first_iter=1, density_mode=DENSITY_ROBUST, enable_photons=True,
            window=None, n_threads=0, record=False, rho0=0.0, cam_weight=0.0, oscene=None,
-           octree=None, light_photons=0, density_radius=0.0, knn_k=8, **over):
+           octree=None, light_photons=0, density_radius=0.0, knn_k=8, nee_radius=0.0, **over):
     """Render `n_iter` progressive iterations (1 spp each).  Returns a dict
     with per-technique image sums (H, W, 3): e, E, P and, with
     `light_photons` > 0 conventional photons per iteration, LP; their sum,
@@ -299,7 +301,7 @@ def render(scene, n_iter=None, first_iter=1, density_mode=DENSITY_ROBUST, enable
     records."""
     osc = oscene or OracleScene(scene)
     prm = make_params(scene, density_mode, enable_photons, window, n_threads, record, rho0,
-                      cam_weight, light_photons, density_radius, knn_k, **over)
+                      cam_weight, light_photons, density_radius, knn_k, nee_radius, **over)
     n_iter = scene.spp if n_iter is None else n_iter
     oct_ = octree
     if oct_ is None and density_mode in (DENSITY_SINGLE, DENSITY_ROBUST):
