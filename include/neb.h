@@ -90,6 +90,11 @@ typedef struct {
                                   2^26; not with NEB_DENSITY_MLP */
     float density_radius;      /* NEB_DENSITY_RADIUS, NEB_DENSITY_KNN: search radius (> 0) */
     int32_t knn_k;             /* NEB_DENSITY_KNN: k, 1 .. 16 */
+    float nee_radius;          /* NEE recycling (Sec. 6, the subsection on reusing NEE events): > 0
+                                  makes every vertex average the light samples of the NEE vertices
+                                  within this radius (its own included), n_E of eq. misw being their
+                                  number; 0 = off.  The same on/off for every scene of a batch; not
+                                  with light_photons */
 } neb_params;
 
 /* Launch shapes of the traversal and photon kernels (neb_autotune picks

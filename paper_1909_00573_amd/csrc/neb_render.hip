@@ -74,6 +74,8 @@ struct PhotonQ {
 struct VertexStore {
     float4 *v0, *v1, *v2, *v3;
     float* rho;
+    float* ne;       // NEE recycling: n_E, the NEE vertices within the radius (null: 1)
+    float4* lsrec;   // NEE recycling: each vertex's light point and light (-1: no contribution)
 };
 struct Images {
     float *e, *E, *P, *LP;
@@ -101,7 +103,9 @@ struct SceneInfo {
     float dr;           // density radius (modes 4, 5)
     float inv_dcell;    // 1 / density-grid cell size
     int32_t knn_k;      // k (mode 5)
-    int32_t pad3;
+    float nee_r;        // NEE recycling radius (0: off)
+    float inv_ncell;    // 1 / recycling-grid cell size
+    int32_t pad4;
 };
 
 // Merge grid keyed by (hash of scene and cell, depth - 1): the records of
@@ -126,6 +130,7 @@ struct DGrid {
     int32_t* count;   // T + 1 entries (the last stays 0)
     int32_t* start;   // T + 1 entries
     float4* pts;      // (pos, scene) in bucket order
+    int32_t* vidx;    // vertex index of each entry (NEE recycling grid only)
     int32_t* sums;    // scan block sums
     int32_t T;        // buckets (power of two)
 };
@@ -143,6 +148,8 @@ struct RenderArgs {
     const int32_t* lp_base;   // n_scenes + 1 entries: light photons of the scenes before
     int32_t n_lp;             // light photons of all scenes per iteration
     DGrid dg;                 // NEB_DENSITY_RADIUS / NEB_DENSITY_KNN
+    DGrid ng;                 // NEE recycling: the NEE vertices by cells of 2 * recycling radius
+    int32_t recycle;          // NEE recycling on
 };
 
 __device__ __forceinline__ int fbits(float f) { return __float_as_int(f); }
@@ -470,7 +477,8 @@ __device__ __forceinline__ uint32_t point_hash(f3 p, float inv_cell, int scene, 
     return cell_hash((int)floorf(p.x * inv_cell), (int)floorf(p.y * inv_cell), (int)floorf(p.z * inv_cell), scene, T);
 }
 
-// Fixed-radius count (mode 4) or k-th-neighbour distance (mode 5) at x over
+// Fixed-radius count (mode 4), k-th-neighbour distance (mode 5) or the bare
+// number of points within R (mode 0) at x over
 // the points of scene s in the density grid: the buckets of the <= 8 cells
 // the ball of radius R touches (a bucket counted once even when two cells
 // share it; points of other cells or scenes in a bucket fail the tests).
@@ -515,6 +523,7 @@ __device__ __forceinline__ float set_density(const DGrid& D, int s, f3 x, float 
             }
         }
     }
+    if (mode == 0) return (float)m;
     if (mode == NEB_DENSITY_KNN && m >= k) {
         float dk = best[0];
 #pragma unroll
@@ -543,22 +552,37 @@ __device__ __forceinline__ float point_density(const RenderArgs& A, int s, f3 x,
 
 // density grid over this iteration's NEE vertices: count -> scan -> scatter
 // (count returns to zero after the scatter)
+// (recycling = 1: the cells of the NEE recycling radius, and each entry's
+// vertex index is kept)
 __global__ void __launch_bounds__(256) k_dgrid_count(const SceneInfo* sc, VertexStore V, const int32_t* n_vertices,
-                                                     DGrid D) {
+                                                     DGrid D, int recycling) {
     const int n = *n_vertices;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const int s = tag_scene(fbits(V.v1[i].w));
-        atomicAdd(&D.count[point_hash(xyz(V.v0[i]), sc[s].inv_dcell, s, D.T)], 1);
+        const float inv = recycling ? sc[s].inv_ncell : sc[s].inv_dcell;
+        atomicAdd(&D.count[point_hash(xyz(V.v0[i]), inv, s, D.T)], 1);
     }
 }
 __global__ void __launch_bounds__(256) k_dgrid_scatter(const SceneInfo* sc, VertexStore V, const int32_t* n_vertices,
-                                                       DGrid D) {
+                                                       DGrid D, int recycling) {
     const int n = *n_vertices;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const int s = tag_scene(fbits(V.v1[i].w));
         const f3 p = xyz(V.v0[i]);
-        const uint32_t h = point_hash(p, sc[s].inv_dcell, s, D.T);
-        D.pts[D.start[h] + atomicSub(&D.count[h], 1) - 1] = f4(p, ibits(s));
+        const uint32_t h = point_hash(p, recycling ? sc[s].inv_ncell : sc[s].inv_dcell, s, D.T);
+        const int pos = D.start[h] + atomicSub(&D.count[h], 1) - 1;
+        D.pts[pos] = f4(p, ibits(s));
+        if (recycling) D.vidx[pos] = i;
+    }
+}
+
+// NEE recycling: n_E of every vertex, the NEE vertices within the radius
+__global__ void __launch_bounds__(256) k_nee_count(RenderArgs A, VertexStore V, const int32_t* n_vertices) {
+    const int n = *n_vertices;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int s = tag_scene(fbits(V.v1[i].w));
+        const SceneInfo& I = A.sc[s];
+        V.ne[i] = set_density(A.ng, s, xyz(V.v0[i]), I.nee_r, I.inv_ncell, 0, 1);
     }
 }
 
@@ -598,6 +622,7 @@ struct LightSample {
     f3 x, n, w, dE;
     float d2, cos_l, p_light;
     bool hittable;
+    int lid;  // light pool index
 };
 
 // lights of one scene: [base, base + count) of the light pool, selected by
@@ -629,7 +654,8 @@ __device__ __forceinline__ LightSample sample_light(const SceneView& S, int base
     ls.hittable = false;
     ls.p_light = 0.f;
     ls.cos_l = 0.f;
-    const float4* L = S.lights + 5 * (size_t)pick_light(S, base, count, u.u[0]);
+    ls.lid = pick_light(S, base, count, u.u[0]);
+    const float4* L = S.lights + 5 * (size_t)ls.lid;
     float4 l0 = L[0], l1 = L[1], l2 = L[2], l3 = L[3];
     float psel = l0.w;
     if (l1.w > 0.f) {  // emissive triangle
@@ -703,11 +729,13 @@ __global__ void __launch_bounds__(kTraceBlock) k_nee(RenderArgs A, VertexStore V
         s.ev = 0;
         // light photons: emission density p_{l -> l-1} from the light point toward x
         float rem = 0.f;
+        // NEE recycling: the sample is kept for the neighbours, L_E comes later
+        if (A.recycle) V.lsrec[i] = f4(ls.x, ibits(ok ? ls.lid : -1));
         if (ok) {
             ++vis;
             rem = emission_density(ls.hittable, ls.cos_l, fabsf(dot3(nrm, ls.w)), ls.d2);
             bool dnon = !mat_delta(m.type);
-            if (dnon) {
+            if (dnon && !A.recycle) {
                 f3 f = bsdf_f(m, nrm, wo, ls.w);
                 if (!is_zero3(f)) {
                     float Am1 = (k >= 2) ? bsdf_pdf(m, nrm, ls.w, wo) * a3.w * a2.w : 0.f;
@@ -732,7 +760,9 @@ __global__ void __launch_bounds__(kTraceBlock) k_nee(RenderArgs A, VertexStore V
             // with light photons every merge of this photon gains the factor 1 + c
             // (c = n_LP p_{l -> l-1} / rho): folded into the flux and into U
             float c1 = 1.0f + I.nlp * rem / rho;
-            float U1 = ((fo + dnon) / (rho * I.r2pi) + (c1 - 1.0f) * dnon) / c1;
+            // n_E NEE events at this vertex (NEE recycling), else 1
+            const float ne = A.recycle ? V.ne[i] : 1.0f;
+            float U1 = ((fo + dnon * ne) / (rho * I.r2pi) + (c1 - 1.0f) * dnon) / c1;
             float hp = fabsf(dot3(nrm, s.dir)) / s.pdf;
             f3 phi = ls.dE * (1.0f / (rho * c1)) * s.w;
             pq.p0[slot] = f4(offset_origin(x, nrm, s.dir, I.eps), ibits(pixel));
@@ -858,6 +888,76 @@ __global__ void __launch_bounds__(256) k_lp_first(RenderArgs A, PhotonQ pq, int2
         }
         pq.p2[i] = f4(xyz(b2) * (1.0f / c1), e);
         pq.pu[i] = X;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pass 2 (b'): NEE recycling (Sec. 6, the subsection on reusing NEE events)
+// ---------------------------------------------------------------------------
+// Every non-delta vertex evaluates the light samples of the n_E NEE vertices
+// within the recycling radius (its own included) with its own BSDF: a light
+// sample does not depend on the receiver, only the visibility tested by the
+// vertex that drew it is borrowed.  With n_E samples of technique E the
+// balance heuristic gives each sample c_j / (n_E + f_m / p_l + rho pi r^2 A).
+__global__ void __launch_bounds__(256) k_nee_recycle(RenderArgs A, VertexStore V, const int32_t* n_vertices,
+                                                     Images img) {
+    const int n = *n_vertices;
+    const SceneView& S = A.S;
+    const DGrid& D = A.ng;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float4 a1 = V.v1[i];
+        const int tg = fbits(a1.w);
+        const neb_material& m = S.mats[tag_mat(tg)];
+        if (mat_delta(m.type)) continue;
+        const float4 a0 = V.v0[i], a2 = V.v2[i], a3 = V.v3[i];
+        const int k = tag_depth(tg), s = tag_scene(tg);
+        const SceneInfo& I = A.sc[s];
+        const f3 x = xyz(a0), nrm = xyz(a1), wo = xyz(a2), tau = xyz(a3);
+        const float rho = V.rho[i], ne = V.ne[i];
+        const float R = I.nee_r, R2 = R * R, inv = I.inv_ncell, rr = R * 1.00001f;
+        const int lx = (int)floorf((x.x - rr) * inv), hx = min((int)floorf((x.x + rr) * inv), lx + 1);
+        const int ly = (int)floorf((x.y - rr) * inv), hy = min((int)floorf((x.y + rr) * inv), ly + 1);
+        const int lz = (int)floorf((x.z - rr) * inv), hz = min((int)floorf((x.z + rr) * inv), lz + 1);
+        f3 sum = mk3(0.f, 0.f, 0.f);
+        uint32_t seen[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int cx = lx + (c & 1), cy = ly + ((c >> 1) & 1), cz = lz + ((c >> 2) & 1);
+            const uint32_t h = cell_hash(cx, cy, cz, s, D.T);
+            bool use = cx <= hx && cy <= hy && cz <= hz;
+            seen[c] = use ? h : 0xFFFFFFFFu;
+#pragma unroll
+            for (int q = 0; q < c; ++q) use = use && seen[q] != h;
+            if (!use) continue;
+            const int e1 = D.start[h + 1];
+            for (int e = D.start[h]; e < e1; ++e) {
+                const float4 p = D.pts[e];
+                const f3 dq = xyz(p) - x;
+                if (!(dot3(dq, dq) < R2) || fbits(p.w) != s) continue;
+                const float4 rec = V.lsrec[D.vidx[e]];
+                const int lid = fbits(rec.w);
+                if (lid < 0) continue;
+                const float4* L = S.lights + 5 * (size_t)lid;
+                const float4 l0 = L[0], l1 = L[1];
+                const bool area = l1.w > 0.f;
+                const f3 dv = xyz(rec) - x;
+                const float d2 = dot3(dv, dv);
+                const f3 w = dv * rsqrtf(d2);
+                const float cx = fabsf(dot3(nrm, w));
+                const float p_light = area ? l0.w / l1.w : l0.w;
+                float cl = 1.f;
+                if (area) cl = -dot3(xyz(L[4]), w);
+                if (!(cl > 0.f) || !(cx > 0.f)) continue;
+                const f3 dE = xyz(L[3]) * (cx * cl / (d2 * p_light));
+                const f3 f = bsdf_f(m, nrm, wo, w);
+                if (is_zero3(f)) continue;
+                float den = ne;
+                if (area) den += bsdf_pdf(m, nrm, wo, w) * cl / (d2 * p_light);
+                if (A.photons && k >= 2) den += rho * I.r2pi * bsdf_pdf(m, nrm, w, wo) * a3.w * a2.w;
+                sum = sum + tau * f * dE * (1.0f / den);
+            }
+        }
+        if (!is_zero3(sum)) atomic_add3(img.E, fbits(a0.w), sum);
     }
 }
 
@@ -1254,14 +1354,15 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
 // pass 3: emitter hits
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_finalize(RenderArgs A, const float4* ev0, const float4* ev1,
-                                                  const int32_t* n_events, const float* rho, Images img) {
+                                                  const int32_t* n_events, const float* rho, const float* ne,
+                                                  Images img) {
     int n = *n_events;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         float4 a = ev0[i], b = ev1[i];
         float w = 1.0f;
         if (a.w > 0.f) {
             int pv = fbits(b.z);
-            float ratio = b.y;
+            float ratio = b.y * (ne ? ne[pv] : 1.0f);  // n_E at x_{l-1} (NEE recycling)
             if (A.photons) ratio += rho[pv] * b.x;
             w = 1.0f / (1.0f + a.w * ratio);
         }
@@ -1473,6 +1574,8 @@ struct neb_ctx_s {
     neb_path_record* recs = nullptr;
     Grid G{};
     DGrid dg{};  // NEB_DENSITY_RADIUS / NEB_DENSITY_KNN
+    DGrid ng{};  // NEE recycling
+    int recycle = 0;
     // spatial order of photon hits
     int32_t *pbin = nullptr, *porder = nullptr, *bcount = nullptr, *bstart = nullptr, *bsums = nullptr;
     int32_t bin_bits = 0, n_bins = 0;
@@ -1508,11 +1611,11 @@ struct neb_ctx_s {
 
 enum KernelId {
     K_CAMERA, K_EXTEND_CAMERA, K_SHADE, K_OCTREE_INSERT, K_DENSITY, K_NEE, K_GRID_BUILD, K_EXTEND_PHOTON, K_PHOTON,
-    K_FINALIZE, K_MLP_TRAIN, K_PHOTON_ORDER, K_MISC, K_LIGHT_PHOTON, K_DENSITY_GRID, K_COUNT
+    K_FINALIZE, K_MLP_TRAIN, K_PHOTON_ORDER, K_MISC, K_LIGHT_PHOTON, K_DENSITY_GRID, K_NEE_RECYCLE, K_COUNT
 };
 static const char* kKernelNames[K_COUNT] = {"camera", "extend_camera", "shade", "octree_insert", "density", "nee",
                                             "grid_build", "extend_photon", "photon_merge", "finalize", "mlp_train",
-                                            "photon_order", "misc", "light_photon", "density_grid"};
+                                            "photon_order", "misc", "light_photon", "density_grid", "nee_recycle"};
 
 static void prof_harvest(neb_ctx c) {
     if (c->prof_used == 0) return;
@@ -1684,6 +1787,10 @@ static neb_status check_params(const neb_params* p) {
     if (p->spp < 0) return fail(NEB_ERR_INVALID_ARG, "spp must be >= 0");
     if (p->light_photons < 0 || p->light_photons > (1 << 26))
         return fail(NEB_ERR_INVALID_ARG, "light_photons out of range (0 .. 2^26)");
+    if (!(p->nee_radius >= 0.f) || !std::isfinite(p->nee_radius))
+        return fail(NEB_ERR_INVALID_ARG, "nee_radius must be >= 0");
+    if (p->nee_radius > 0.f && p->light_photons > 0)
+        return fail(NEB_ERR_INVALID_ARG, "NEE recycling is not combined with light photons");
     return NEB_OK;
 }
 
@@ -1699,6 +1806,8 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
         const neb_params& p = params[s];
         if (p.density_mode != params[0].density_mode || p.flags != params[0].flags)
             return fail(NEB_ERR_INVALID_ARG, "every scene of a batch needs the same density mode and flags");
+        if ((p.nee_radius > 0.f) != (params[0].nee_radius > 0.f))
+            return fail(NEB_ERR_INVALID_ARG, "NEE recycling must be on for every scene of a batch or for none");
         int64_t np = (int64_t)p.width * p.height;
         npix += np;
         vcap += np * std::max(1, p.max_path_len - 1);
@@ -1754,6 +1863,7 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
     c->density_mode = params[0].density_mode;
     c->flags = params[0].flags;
     c->photons = (c->flags & NEB_FLAG_NO_PHOTONS) ? 0 : 1;
+    c->recycle = params[0].nee_radius > 0.f ? 1 : 0;
     {
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
@@ -1791,6 +1901,16 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
     ALLOC(c->G.sorted, vcap);
     ALLOC(c->G.mrec, 4 * vcap);
     ALLOC(c->G.sums, scan_scratch(gkeys));
+    if (c->recycle) {
+        c->ng.T = c->G.T;
+        ALLOC(c->ng.count, (int64_t)c->ng.T + 1);
+        ALLOC(c->ng.start, (int64_t)c->ng.T + 1);
+        ALLOC(c->ng.pts, vcap);
+        ALLOC(c->ng.vidx, vcap);
+        ALLOC(c->ng.sums, scan_scratch((int64_t)c->ng.T + 1));
+        ALLOC(c->V.ne, vcap);
+        ALLOC(c->V.lsrec, vcap);
+    }
     if (c->density_mode == NEB_DENSITY_RADIUS || c->density_mode == NEB_DENSITY_KNN) {
         c->dg.T = c->G.T;
         ALLOC(c->dg.count, (int64_t)c->dg.T + 1);
@@ -1841,6 +1961,9 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
         if (c->dg.count)
             hipLaunchKernelGGL(k_fill_i32, dim3(grid_of((int64_t)c->dg.T + 1, 256)), dim3(256), 0, nullptr, c->dg.count,
                                0, (int64_t)c->dg.T + 1);
+        if (c->ng.count)
+            hipLaunchKernelGGL(k_fill_i32, dim3(grid_of((int64_t)c->ng.T + 1, 256)), dim3(256), 0, nullptr, c->ng.count,
+                               0, (int64_t)c->ng.T + 1);
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(c->n_bins + 2, 256)), dim3(256), 0, nullptr, c->bcount, 0,
                            (int64_t)c->n_bins + 2);
         hipLaunchKernelGGL(k_fill_f32, dim3(grid_of(12 * npix, 256)), dim3(256), 0, nullptr, c->img, 0.f, 12 * npix);
@@ -2119,6 +2242,8 @@ static neb_status prepare(neb_ctx c) {
         I.dr = P.density_radius;
         I.inv_dcell = P.density_radius > 0.f ? 1.0f / (2.0001f * P.density_radius) : 0.f;
         I.knn_k = P.knn_k;
+        I.nee_r = P.nee_radius;
+        I.inv_ncell = P.nee_radius > 0.f ? 1.0f / (2.0001f * P.nee_radius) : 0.f;
         OctParams& O = c->oct_prm[s];
         octree_params_init(O, H.bmin, H.bmax, O.root, P.octree_capacity);
         nb += H.bvh.n_nodes;
@@ -2208,6 +2333,8 @@ static RenderArgs make_args(neb_ctx c) {
     A.lp_base = c->lp_base_dev;
     A.n_lp = c->n_lp;
     A.dg = c->dg;
+    A.ng = c->ng;
+    A.recycle = c->recycle;
     return A;
 }
 
@@ -2282,10 +2409,10 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
         // density grid over this iteration's NEE vertices
         prof_begin(c, K_DENSITY_GRID, s);
         hipLaunchKernelGGL(k_dgrid_count, dim3(grid_of(vcap, 256)), dim3(256), 0, s, (const SceneInfo*)c->sc_dev, c->V,
-                           (const int32_t*)&cnt->n_vertices, c->dg);
+                           (const int32_t*)&cnt->n_vertices, c->dg, 0);
         scan_exclusive(c->dg.count, c->dg.start, (int64_t)c->dg.T + 1, c->dg.sums, s);
         hipLaunchKernelGGL(k_dgrid_scatter, dim3(grid_of(vcap, 256)), dim3(256), 0, s, (const SceneInfo*)c->sc_dev,
-                           c->V, (const int32_t*)&cnt->n_vertices, c->dg);
+                           c->V, (const int32_t*)&cnt->n_vertices, c->dg, 0);
         prof_end(c, s);
     } else if (c->density_mode != NEB_DENSITY_ANALYTIC && !model) {
         hipError_t e;
@@ -2330,12 +2457,27 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
                                             (const OctState*)c->oct_states, (const OctParams*)c->oct_prm_dev,
                                             (const OctDyn*)c->oct_dyn));
     }
+    // NEE recycling: the vertices by cells of the recycling radius and n_E
+    if (c->recycle) {
+        prof_begin(c, K_NEE_RECYCLE, s);
+        hipLaunchKernelGGL(k_dgrid_count, dim3(grid_of(vcap, 256)), dim3(256), 0, s, (const SceneInfo*)c->sc_dev, c->V,
+                           (const int32_t*)&cnt->n_vertices, c->ng, 1);
+        scan_exclusive(c->ng.count, c->ng.start, (int64_t)c->ng.T + 1, c->ng.sums, s);
+        hipLaunchKernelGGL(k_dgrid_scatter, dim3(grid_of(vcap, 256)), dim3(256), 0, s, (const SceneInfo*)c->sc_dev,
+                           c->V, (const int32_t*)&cnt->n_vertices, c->ng, 1);
+        hipLaunchKernelGGL(k_nee_count, dim3(grid_of(vcap, 256)), dim3(256), 0, s, A, c->V,
+                           (const int32_t*)&cnt->n_vertices);
+        prof_end(c, s);
+    }
     // light photons take the first entries of photon queue 0, the NEB photons follow
     const bool lp = c->n_lp > 0;
     if (lp)
         TIMED(K_LIGHT_PHOTON, hipLaunchKernelGGL(k_lp_emit, dim3(grid_of(c->n_lp, 256)), dim3(256), 0, s, A,
                                                  c->pq[0], &cnt->pcount[0]));
     TIMED(K_NEE, nee(c, A, im, s));
+    if (c->recycle)
+        TIMED(K_NEE_RECYCLE, hipLaunchKernelGGL(k_nee_recycle, dim3(grid_of(vcap, 256)), dim3(256), 0, s, A, c->V,
+                                                (const int32_t*)&cnt->n_vertices, im));
     // bounces: NEB photons make at most maxlen - 2 segments, light photons maxlen - 1
     const int rounds = std::max((c->photons && L >= 3) ? L - 2 : 0, lp ? L - 1 : 0);
     const int64_t pcap = c->pcap;
@@ -2379,7 +2521,8 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
     // pass 3
     TIMED(K_FINALIZE, hipLaunchKernelGGL(k_finalize, dim3(grid_of(c->ecap, 256)), dim3(256), 0, s, A,
                                          (const float4*)c->ev0, (const float4*)c->ev1,
-                                         (const int32_t*)&cnt->n_events, (const float*)c->V.rho, im));
+                                         (const int32_t*)&cnt->n_events, (const float*)c->V.rho,
+                                         (const float*)c->V.ne, im));
     hipLaunchKernelGGL(k_iter_end, dim3(1), dim3(1), 0, s, cnt);
     // learned density, training iterations: this iteration's vertices with
     // rho > 0 form the pool, then Adam steps on batches drawn from it

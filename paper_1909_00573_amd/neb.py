@@ -43,7 +43,7 @@ class Params(ctypes.Structure):
                 ("seed", ctypes.c_uint32), ("scene_id", ctypes.c_uint32), ("density_mode", ctypes.c_int32),
                 ("analytic_rho0", ctypes.c_float), ("analytic_cam_weight", ctypes.c_float),
                 ("flags", ctypes.c_int32), ("spp", ctypes.c_int32), ("light_photons", ctypes.c_int32),
-                ("density_radius", ctypes.c_float), ("knn_k", ctypes.c_int32)]
+                ("density_radius", ctypes.c_float), ("knn_k", ctypes.c_int32), ("nee_radius", ctypes.c_float)]
 
 
 class LaunchConfig(ctypes.Structure):
@@ -201,6 +201,7 @@ def make_params(scene, density_mode=DENSITY_OCTREE_ROBUST, flags=0, rho0=0.0, ca
     p.light_photons = over.get("light_photons", 0)
     p.density_radius = over.get("density_radius", 0.0)
     p.knn_k = over.get("knn_k", 8)
+    p.nee_radius = over.get("nee_radius", 0.0)
     return p
 
 

@@ -108,3 +108,23 @@ def test_light_photon_and_density_provider_arguments_without_a_device():
     assert L.neb_point_density(None, 5, None, 0, 4, ctypes.c_float(0.1), 4, None, None) == 0
     assert L.neb_point_density(None, 5, None, 3, 4, ctypes.c_float(0.1), 4, None, None) == -1   # null pointers
     assert L.neb_get_scene_light_photon_image(None, 0, None, 0, None) == -1
+
+
+def test_recycling_arguments_without_a_device():
+    import ctypes
+    from paper_1909_00573_amd import neb
+    if not os.path.exists(neb.LIB_PATH):
+        pytest.skip("libneb.so not built")
+    L = neb.lib()
+    h = ctypes.c_void_p()
+    p = neb.Params()
+    p.width, p.height, p.max_path_len, p.octree_capacity, p.merge_radius = 8, 8, 4, 64, 0.01
+    p.nee_radius = -0.1
+    assert L.neb_create(ctypes.byref(p), ctypes.byref(h)) == -1
+    p.nee_radius, p.light_photons = 0.1, 16
+    assert L.neb_create(ctypes.byref(p), ctypes.byref(h)) == -1          # not with light photons
+    two = (neb.Params * 2)()
+    for q in two:
+        q.width, q.height, q.max_path_len, q.octree_capacity, q.merge_radius = 8, 8, 4, 64, 0.01
+    two[0].nee_radius = 0.1
+    assert L.neb_create_batch(two, 2, ctypes.byref(h)) == -1           # on for one scene only
