@@ -194,7 +194,9 @@ def quality_comparison(stream, spp=64, ref_spp=1024, train_iterations=4, check_e
       octree fallback);
     - fixed_radius, knn: NEB with the two estimators Sec. 5 tried before
       the octree, over each iteration's NEE vertices (radius 0.04 m; k = 8
-      within 0.04 m).
+      within 0.04 m);
+    - path_tracing, path_tracing_recycled: no photons, NEE as usual or
+      recycled from the NEE vertices within 0.02 m (Sec. 6's experiment).
     Each form also reports its density stage per iteration (octree
     deposits and queries, or density-grid build and queries; GPU events).
     The reference is path tracing with NEE and light photons (no NEB
@@ -240,14 +242,16 @@ def quality_comparison(stream, spp=64, ref_spp=1024, train_iterations=4, check_e
         prof = R.kernel_profile()
         R.profile_kernels(False)
         density_ms[name] = round(sum(prof.get(k, {"total_ms": 0.0})["total_ms"]
-                                     for k in ("octree_insert", "density", "density_grid")) / spp, 4)
+                                     for k in ("octree_insert", "density", "density_grid", "nee_recycle")) / spp, 4)
         return curve
 
     curves = {}
     for name, kw in (("plain", {}), ("single_probe", {"density_mode": neb.DENSITY_OCTREE}),
                      ("light_photons", {"light_photons": nlp}),
                      ("fixed_radius", {"density_mode": neb.DENSITY_RADIUS, "density_radius": 0.04}),
-                     ("knn", {"density_mode": neb.DENSITY_KNN, "density_radius": 0.04, "knn_k": 8})):
+                     ("knn", {"density_mode": neb.DENSITY_KNN, "density_radius": 0.04, "knn_k": 8}),
+                     ("path_tracing", {"flags": neb.FLAG_NO_PHOTONS}),
+                     ("path_tracing_recycled", {"flags": neb.FLAG_NO_PHOTONS, "nee_radius": 0.02})):
         P = neb.Renderer(sc, **kw)
         curves[name] = progression(name, P)
         P.close()

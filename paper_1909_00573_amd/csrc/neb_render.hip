@@ -2405,7 +2405,11 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
     }
     // deposits of this iteration's NEE vertices into their scenes' octrees
     const bool set_mode = c->density_mode == NEB_DENSITY_RADIUS || c->density_mode == NEB_DENSITY_KNN;
-    if (set_mode) {
+    // without NEB photons rho enters nothing (flux, MIS), so the density
+    // stage is skipped (the learned density still trains on it)
+    const bool need_rho = c->photons || c->mlp_mode;
+    if (!need_rho) {
+    } else if (set_mode) {
         // density grid over this iteration's NEE vertices
         prof_begin(c, K_DENSITY_GRID, s);
         hipLaunchKernelGGL(k_dgrid_count, dim3(grid_of(vcap, 256)), dim3(256), 0, s, (const SceneInfo*)c->sc_dev, c->V,
@@ -2451,7 +2455,7 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
                            (const int32_t*)c->oct_nodes, (const OctState*)c->oct_states, P0,
                            (const OctDyn*)c->oct_dyn, c->mlp_cnt);
         prof_end(c, s);
-    } else {
+    } else if (need_rho) {
         TIMED(K_DENSITY, hipLaunchKernelGGL(k_density, dim3(grid_of(vcap, 256)), dim3(256), 0, s, A, c->V,
                                             (const int32_t*)&cnt->n_vertices, (const int32_t*)c->oct_nodes,
                                             (const OctState*)c->oct_states, (const OctParams*)c->oct_prm_dev,

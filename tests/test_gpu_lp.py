@@ -186,7 +186,8 @@ def test_room_full_size_light_photons_keep_the_mean(neb):
         imgs[name] = R.image_host().astype(np.float64)
         st = R.stats()
         assert st["light_photons"] == n_iter * lp
-        assert st["oct_ledger"] == st["oct_deposits"] == st["vertices"]
+        # without NEB photons no density is needed and the octree takes no deposits
+        assert st["oct_ledger"] == st["oct_deposits"] == (st["vertices"] if flags == 0 else 0)
         if lp:
             tech = R.technique_images_host()
             assert tech["LP"].sum() > 0.3 * sum(x.sum() for x in tech.values())
