@@ -85,7 +85,13 @@ def cpu_baseline(target_s=11.0):
     side = int(max(16, min(256, 16 * (target_s / max(dt, 1e-3)) ** 0.5)))
     r, dt = run(side)
     paths = side * side
-    return {"value": paths / dt, "unit": "camera paths/s", "cores": cores, "kind": "oracle",
+    host = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            host = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": paths / dt, "unit": "camera paths/s", "cores": cores, "kind": "oracle", "host_cpu": host,
             "sample": f"{side}x{side} pixel window at the centre of the 512x512 room, 1 iteration, full NEB "
                       f"(photons {int(r['stats']['photons'])}, merges {int(r['stats']['merges'])}) in {dt:.2f} s",
             "photons_per_s": r["stats"]["photons"] / dt}
@@ -119,6 +125,49 @@ def committed_traffic(kernel):
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def city_block_run(stream, steps=8, warmup=2):
+    """Throughput on the city block (100 x 100 m, ~1.01 M triangles, 1024
+    point lights sampled by power, 1024 x 1024, path length 10, octree 2^24
+    nodes, merge radius 0.1 m): the largest workload, timed like the room
+    (inputs resident, warm-up, then a reset).  Its recipe covers the
+    ground many times over with boxes (83 000 footprints of 0.3-5 m on
+    10 000 m^2) and puts the lights at 0.5-10 m, mostly inside that mass,
+    so few NEE connections are unoccluded: it measures traversal and the
+    octree at a million triangles more than photon transport."""
+    import torch
+    from neb_inputs import city_block
+    from paper_1909_00573_amd import neb
+    t0 = time.perf_counter()
+    sc = city_block()
+    R = neb.Renderer(sc)
+    setup = time.perf_counter() - t0
+    R.render(warmup, stream=stream)
+    torch.cuda.synchronize()
+    R.reset()
+    s0 = R.stats()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    R.render(steps, stream=stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    sec = a.elapsed_time(b) / 1e3
+    st = R.stats()
+    R.close()
+    npix = sc.width * sc.height
+    return {"workload": "city block: 100x100 m, %d triangles, mirror torus, %d point lights; %dx%d, path length %d, "
+                        "octree 2^24 nodes, merge radius %.2f m, robust octree density" %
+                        (sc.n_tris, len(sc.point_lights), sc.width, sc.height, sc.max_path_len, sc.merge_radius),
+            "steps": steps, "ms_per_step": round(1e3 * sec / steps, 3),
+            "camera_paths_per_s": round(npix * steps / sec, 1),
+            "photons_per_s": round((st["photons"] - s0["photons"]) / sec, 1),
+            "photon_segments_per_s": round((st["photon_segments"] - s0["photon_segments"]) / sec, 1),
+            "work_per_step": {k: round((st[k] - s0[k]) / steps) for k in
+                              ("vertices", "nee_visible", "photons", "photon_segments", "merges", "camera_rays",
+                               "shadow_rays", "bvh_nodes")},
+            "host_setup_s": round(setup, 1)}
 
 
 def batch_comparison(stream, cfg_trials=1):
@@ -300,6 +349,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-scene batching comparison")
     ap.add_argument("--no-quality", "--no-learned", dest="no_quality", action="store_true",
                     help="skip the error-against-time comparison (plain, light photons, learned density)")
+    ap.add_argument("--no-city", action="store_true", help="skip the city-block throughput run")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the launch shapes on this workload first (default: the library's defaults)")
     ap.add_argument("--launch-config", default=None,
@@ -410,6 +460,8 @@ def main():
         "roofline": roof, "kernels": kernels, "launch_config": launch_cfg,
     }
     R.close()
+    if not args.no_city:
+        out["city_block"] = city_block_run(stream)
     if not args.no_batch:
         out["batch"] = batch_comparison(stream)
     if not args.no_quality:
