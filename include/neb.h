@@ -75,7 +75,8 @@ enum { NEB_MAT_LAMBERT = 0, NEB_MAT_MIRROR = 1, NEB_MAT_DIELECTRIC = 2, NEB_MAT_
 typedef struct {
     int32_t width, height;     /* image size in pixels, 1 .. 8192 */
     int32_t max_path_len;      /* maximum path length in segments (camera = vertex 0), 1 .. 16 */
-    int32_t octree_capacity;   /* octree nodes; rounded up to 8n+1 (Appendix B initialize) */
+    int32_t octree_capacity;   /* child nodes, rounded up to whole blocks of 8, plus the root:
+                                  1 + 8*ceil(n/8) nodes (Appendix B initialize), 1 .. 2^29 */
     float merge_radius;        /* r of the uniform merge kernel 1/(pi r^2), Sec. 3.2 */
     uint32_t seed, scene_id;   /* Philox-4x32-10 key (seed, scene_id) */
     int32_t density_mode;      /* NEB_DENSITY_* */
@@ -184,8 +185,8 @@ neb_status neb_create(const neb_params* params, neb_ctx* out);
 /* A context that renders n_scenes (1..256) independent scenes together:
  * every stage of an iteration (Sec. 3 passes 1-3) is one launch over all
  * scenes, which share the BVH pool (one tree per scene), the octree node
- * pool (scene s owns octree_capacity nodes of params[s], Sec. 5) and the
- * queues.  params: n_scenes host entries; image size, path length, octree
+ * pool (scene s owns the 1 + 8*ceil(octree_capacity/8) nodes of params[s],
+ * Sec. 5) and the queues.  params: n_scenes host entries; image size, path length, octree
  * capacity, merge radius, RNG key, analytic density terms and spp may
  * differ per scene; density_mode and flags must be equal (else
  * NEB_ERR_INVALID_ARG).  A scene takes part in iterations 1..spp (all if
@@ -407,8 +408,9 @@ void neb_mlp_destroy(neb_mlp mlp);
 /* ---------------------------------------------------------------------- */
 
 /* Octree over [scene_min, scene_max] (host, 3 floats each; enlarged by 0.1 %
- * per side as in Appendix B initialize) with `capacity` nodes rounded up to
- * 8n+1.  The root starts as an empty leaf; iteration 1 is set. */
+ * per side as in Appendix B initialize) holding the root and `capacity`
+ * child nodes rounded up to whole blocks of 8 (1 + 8*ceil(capacity/8)
+ * nodes).  The root starts as an empty leaf; iteration 1 is set. */
 neb_status neb_octree_create(const float scene_min[3], const float scene_max[3], int32_t capacity,
                              neb_octree* out);
 
