@@ -549,6 +549,9 @@ __device__ __forceinline__ void wave_add_u64(unsigned long long* dst, unsigned v
     if ((threadIdx.x & 63) == 0 && s) atomicAdd(dst, s);
 }
 
+// this block's stripe of the work statistics
+__device__ __forceinline__ StatLine& stat_line(Counters* c) { return c->st[blockIdx.x & (kStatStripes - 1)]; }
+
 // wave-aggregated slot reservation: returns this lane's index in a queue
 // whose tail is *counter; lanes with take == false get -1
 __device__ __forceinline__ int wave_reserve(int* counter, bool take) {

@@ -40,13 +40,15 @@ struct OctDyn {
 };
 
 // device-resident octree state updated by atomics
+// the allocation counter (hit by every split) and the deposit tally (one
+// atomic per wave of every insertion launch) in cache lines of their own
 struct OctState {
-    int32_t alloc;
+    alignas(128) int32_t alloc;
     int32_t depth;
     int32_t overflow;
     int32_t rejected;
     unsigned long long block_iter_sum;
-    unsigned long long deposits;
+    alignas(128) unsigned long long deposits;
     unsigned long long lost;
 };
 
@@ -82,20 +84,33 @@ struct SceneView {
 };
 
 // device counters of one context
-struct Counters {
-    int32_t qcount[2];       // camera path queues
-    int32_t pcount[2];       // photon queues
-    int32_t n_vertices;
-    int32_t n_events;
-    int32_t iter;            // current iteration (incremented at the start of each one)
-    int32_t lp_count;        // light photons emitted this iteration (the first entries of photon queue 0)
-    int32_t trace_next;      // next ray of a closest-hit launch (reset by its last block)
-    int32_t trace_done;      // blocks of that launch that finished
+// Work statistics, striped: a block adds into stripe blockIdx.x mod
+// kStatStripes, so the end-of-kernel atomics of concurrent waves spread over
+// separate cache lines instead of serialising on one; the host sums the
+// stripes.
+constexpr int kStatStripes = 16;
+struct alignas(128) StatLine {
     unsigned long long paths, vertices, photons, photon_segments, merges, nee_visible, events;
     unsigned long long camera_rays, shadow_rays, photon_rays;
     unsigned long long photon_items, photon_continued, grid_cells, candidates;
     unsigned long long bvh_nodes, bvh_tris;   // traversal work of closest-hit and shadow rays
     unsigned long long light_photons;
+};
+
+// Device counters.  Every queue counter sits in a cache line of its own:
+// atomics on one line are serialised by the cache, and counters that
+// different kernels (or one kernel's reservations and its statistics) hit
+// at the same time must not share one.
+struct Counters {
+    alignas(128) int32_t qcount[2];  // camera path queues
+    alignas(128) int32_t pcount[2];  // photon queues
+    alignas(128) int32_t n_vertices;
+    alignas(128) int32_t n_events;
+    alignas(128) int32_t iter;       // current iteration (incremented at the start of each one)
+    alignas(128) int32_t lp_count;   // light photons emitted this iteration (the first entries of photon queue 0)
+    alignas(128) int32_t trace_next; // next ray of a closest-hit launch (reset by its last block)
+    alignas(128) int32_t trace_done; // blocks of that launch that finished
+    StatLine st[kStatStripes];
 };
 
 // octree (neb_octree.hip)

@@ -239,8 +239,8 @@ __global__ void k_iter_begin(Counters* c, OctDyn* dyn, int32_t freeze) {
     *dyn = d;
 }
 __global__ void k_iter_end(Counters* c) {
-    c->vertices += (unsigned long long)c->n_vertices;
-    c->events += (unsigned long long)c->n_events;
+    c->st[0].vertices += (unsigned long long)c->n_vertices;
+    c->st[0].events += (unsigned long long)c->n_events;
 }
 __global__ void k_mean_image(const float* e, const float* E, const float* P, const float* LP, float* out, int64_t n,
                              float scale) {
@@ -277,7 +277,7 @@ __global__ void __launch_bounds__(256) k_camera(RenderArgs A, PathQ q) {
             ++started;
         }
     }
-    wave_add_u64(&A.cnt->paths, started);
+    wave_add_u64(&stat_line(A.cnt).paths, started);
 }
 
 // Spatial bins of photon hits: a 2^bits-per-axis grid over each scene's
@@ -322,7 +322,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_extend(SceneView S, const Scene
                                                         const float4* __restrict__ org,
                                                         const float4* __restrict__ dir, const int32_t* count,
                                                         int32_t* next_count, int2* __restrict__ hits,
-                                                        unsigned long long* rays, Counters* cnt, HitBins B) {
+                                                        int photon_rays, Counters* cnt, HitBins B) {
     __shared__ int stack[kStack * kTraceBlock];
     const int n = *count;
     if (blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
@@ -367,9 +367,10 @@ __global__ void __launch_bounds__(kTraceBlock) k_extend(SceneView S, const Scene
         cnt->trace_next = 0;
         cnt->trace_done = 0;
     }
-    wave_add_u64(rays, traced);
-    wave_add_u64(&cnt->bvh_nodes, nodes);
-    wave_add_u64(&cnt->bvh_tris, tris);
+    StatLine& L = stat_line(cnt);
+    wave_add_u64(photon_rays ? &L.photon_rays : &L.camera_rays, traced);
+    wave_add_u64(&L.bvh_nodes, nodes);
+    wave_add_u64(&L.bvh_tris, tris);
 }
 
 __global__ void __launch_bounds__(256) k_shade(RenderArgs A, PathQ in, const int32_t* count_in, const int2* hits,
@@ -771,11 +772,12 @@ __global__ void __launch_bounds__(kTraceBlock) k_nee(RenderArgs A, VertexStore V
             pq.pu[slot] = U1;
         }
     }
-    wave_add_u64(&cnt->nee_visible, vis);
-    wave_add_u64(&cnt->photons, emitted);
-    wave_add_u64(&cnt->shadow_rays, rays);
-    wave_add_u64(&cnt->bvh_nodes, nodes);
-    wave_add_u64(&cnt->bvh_tris, tris);
+    StatLine& L = stat_line(cnt);
+    wave_add_u64(&L.nee_visible, vis);
+    wave_add_u64(&L.photons, emitted);
+    wave_add_u64(&L.shadow_rays, rays);
+    wave_add_u64(&L.bvh_nodes, nodes);
+    wave_add_u64(&L.bvh_tris, tris);
 }
 
 // ---------------------------------------------------------------------------
@@ -838,7 +840,7 @@ __global__ void __launch_bounds__(256) k_lp_emit(RenderArgs A, PhotonQ pq, int32
             pq.pu[slot] = ibits(lid);
         }
     }
-    wave_add_u64(&cnt->light_photons, emitted);
+    wave_add_u64(&stat_line(cnt).light_photons, emitted);
 }
 
 // First hit y of each light photon (after the first closest-hit pass).  The
@@ -1106,12 +1108,16 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const int32_t* __restrict__
 
 // ---------------------------------------------------------------------------
 // photon bounce: merge with view vertices around the hit, then scatter.
-// One photon per lane (many independent candidate streams in flight, which
-// is what a gather over cache-resident records needs).  Each lane walks the
-// concatenated candidate ranges of its photon's cells; accepted (lane,
-// vertex) pairs are compacted into an LDS queue and evaluated 64 at a time
-// by the whole wave, so the BSDF, the MIS weight and the image atomics run
-// with every lane busy instead of with the ~10 % of lanes that accepted.
+// A wave takes 64 photons, one per lane; each lane finds the candidate
+// ranges of its photon's cells.  The wave then walks the concatenation of
+// all 64 photons' candidate lists together: consecutive lanes take
+// consecutive candidates (a wave-wide scan of the lanes' counts maps a
+// position back to its photon and cell), so the candidate loads of a step
+// are contiguous runs of a cell's records and the number of steps follows
+// the wave's total, not its longest list.  Accepted (photon, vertex) pairs
+// are compacted into an LDS queue and evaluated 64 at a time by the whole
+// wave, so the BSDF, the MIS weight and the image atomics run with every
+// lane busy instead of with the ~15 % of candidates that are accepted.
 // One wave per block.
 // ---------------------------------------------------------------------------
 // Photons are taken in the spatial order `order` (null: queue order).  Blocks
@@ -1126,6 +1132,11 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
     __shared__ float te[64];      // per lane's photon: weight of its own technique in the MIS denominator
     __shared__ float sval[64][3]; // contributions of a flushed batch
     __shared__ int sdst[64];      // their pixels (bit 30: light-photon image), -1 for none
+    __shared__ int wbase[65];     // exclusive scan of the lanes' candidate counts
+    __shared__ int coff[64][8];   // per lane's cell c: first record minus its offset in the lane's list
+    __shared__ int cend[64][8];   // per lane's cell c: end of its range in the lane's list
+    __shared__ float4 ty[64];     // per lane's photon: hit point, r^2
+    __shared__ int tsid[64];      // per lane's photon: scene
     const int lane = threadIdx.x;
     const unsigned long long below = (1ull << lane) - 1ull;
     const int n = *count_in;
@@ -1269,36 +1280,65 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
         }
         int total = pre[8];
         cands += (unsigned)total;
+        // the wave's candidate list: photon p's entries start at wbase[p];
+        // its cell c covers [cend[p][c-1], cend[p][c]) of them, record
+        // coff[p][c] + position
+        int incl = total;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            int v = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += v;
+        }
+        const int wsum = __shfl(incl, 63, 64);
+        wbase[lane + 1] = incl;
+        if (lane == 0) wbase[0] = 0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            coff[lane][c] = lo[c] - pre[c];
+            cend[lane][c] = pre[c + 1];
+        }
+        ty[lane] = f4(y, r2);
+        tsid[lane] = sid;
         __syncthreads();
-        // eight candidates per lane per step: their loads are independent, and
-        // more of them in flight hide more of the gather latency (measured:
-        // 2, 4, 8, 12, 16 per step -> 3.50, 3.08, 2.91, 2.97, 2.98 ms per
-        // room iteration)
+        // eight positions per lane per step, their loads independent (measured
+        // on the room: 4 and 8 equal, both 22 % faster than one photon's list
+        // per lane with eight loads in flight)
         constexpr int kU = 8;
-        for (int k = 0;; k += kU) {
-            if (!__any(k < total)) break;
-            int ev[kU];
+        for (int t = 0; t < wsum; t += 64 * kU) {
+            int ev[kU], pv[kU];
             float4 cd[kU];
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                const int kk = k + u;
-                int e = -1;
+                const int kk = t + u * 64 + lane;
+                int e = -1, p = 0;
+                if (kk < wsum) {
+                    // p: the last photon whose list starts at or before kk
 #pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    if (kk >= pre[c] && kk < pre[c + 1]) e = lo[c] + (kk - pre[c]);
-                ev[u] = kk < total ? e : -1;
+                    for (int st = 32; st; st >>= 1)
+                        if (wbase[p + st] <= kk) p += st;
+                    const int rk = kk - wbase[p];
+                    int c = 0;
+#pragma unroll
+                    for (int q = 0; q < 7; ++q) c += cend[p][q] <= rk;
+                    e = coff[p][c] + rk;
+                }
+                ev[u] = e;
+                pv[u] = p;
             }
 #pragma unroll
             for (int u = 0; u < kU; ++u) cd[u] = ev[u] >= 0 ? G.sorted[ev[u]] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
-                f3 dv = xyz(cd[u]) - y;
-                // a bucket may also hold another scene's cell
-                bool acc = ev[u] >= 0 && dot3(dv, dv) < r2 && fbits(cd[u].w) == sid;
-                // the record index: its merge data sits at G.mrec[4 e]
+                bool acc = false;
+                if (ev[u] >= 0) {
+                    const float4 yp = ty[pv[u]];
+                    f3 dv = xyz(cd[u]) - xyz(yp);
+                    // a bucket may also hold another scene's cell
+                    acc = dot3(dv, dv) < yp.w && fbits(cd[u].w) == tsid[pv[u]];
+                }
                 unsigned long long m = __ballot(acc);
                 if (m) {
-                    if (acc) queue[qn + __popcll(m & below)] = make_int2(lane, ev[u]);
+                    if (acc) queue[qn + __popcll(m & below)] = make_int2(pv[u], ev[u]);
                     qn += __popcll(m);
                     if (qn >= 64) {
                         __syncthreads();
@@ -1342,12 +1382,13 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
         }
         __syncthreads();
     }
-    wave_add_u64(&cnt->photon_segments, segs);
-    wave_add_u64(&cnt->merges, merges);
-    wave_add_u64(&cnt->photon_items, items);
-    wave_add_u64(&cnt->photon_continued, cont);
-    wave_add_u64(&cnt->grid_cells, cells);
-    wave_add_u64(&cnt->candidates, cands);
+    StatLine& L = stat_line(cnt);
+    wave_add_u64(&L.photon_segments, segs);
+    wave_add_u64(&L.merges, merges);
+    wave_add_u64(&L.photon_items, items);
+    wave_add_u64(&L.photon_continued, cont);
+    wave_add_u64(&L.grid_cells, cells);
+    wave_add_u64(&L.candidates, cands);
 }
 
 // ---------------------------------------------------------------------------
@@ -2340,13 +2381,14 @@ static RenderArgs make_args(neb_ctx c) {
 
 template <int kStack>
 static void launch_extend(neb_ctx c, int64_t cap, const float4* org, const float4* dir, int32_t* count, int32_t* next,
-                          unsigned long long* rays, const HitBins& B, hipStream_t s) {
+                          int rays, const HitBins& B, hipStream_t s) {
     hipLaunchKernelGGL(k_extend<kStack>, dim3(trace_grid(c, cap, c->cfg.trace_bpc)), dim3(kTraceBlock), 0, s, c->view,
                        (const SceneInfo*)c->sc_dev, org, dir, (const int32_t*)count, next, c->hits, rays, c->cnt, B);
 }
 
+// rays: 0 counts camera rays, 1 photon rays
 static void extend(neb_ctx c, int64_t cap, const float4* org, const float4* dir, int32_t* count, int32_t* next,
-                   unsigned long long* rays, hipStream_t s, bool bin = false) {
+                   int rays, hipStream_t s, bool bin = false) {
     HitBins B{};
     if (bin) {
         B.bin = c->pbin;
@@ -2397,7 +2439,7 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
     for (int k = 1; k <= L; ++k) {
         int in = (k - 1) & 1, out = k & 1;
         TIMED(K_EXTEND_CAMERA,
-              extend(c, npix, c->q[in].q0, c->q[in].q1, &cnt->qcount[in], &cnt->qcount[out], &cnt->camera_rays, s));
+              extend(c, npix, c->q[in].q0, c->q[in].q1, &cnt->qcount[in], &cnt->qcount[out], 0, s));
         TIMED(K_SHADE, hipLaunchKernelGGL(k_shade, dim3(grid_of(npix, 256)), dim3(256), 0, s, A, c->q[in],
                                           &cnt->qcount[in], c->hits, c->q[out], &cnt->qcount[out], c->V,
                                           &cnt->n_vertices, c->ev0, c->ev1, &cnt->n_events, c->slots,
@@ -2502,7 +2544,7 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
             int in = (j - 1) & 1, out = j & 1;
             const bool ordered = c->cfg.photon_order != 0;
             TIMED(K_EXTEND_PHOTON, extend(c, pcap, c->pq[in].p0, c->pq[in].p1, &cnt->pcount[in], &cnt->pcount[out],
-                                          &cnt->photon_rays, s, ordered));
+                                          1, s, ordered));
             if (j == 1 && lp)
                 TIMED(K_LIGHT_PHOTON,
                       hipLaunchKernelGGL(k_lp_first, dim3(grid_of(c->n_lp, 256)), dim3(256), 0, s, A, c->pq[0], c->hits,
@@ -2787,9 +2829,30 @@ static neb_status octree_info(const int32_t* pool, const OctState* state, int32_
 
 extern "C" neb_status neb_get_stats(neb_ctx c, neb_stats* out) {
     if (!c || !out) return fail(NEB_ERR_INVALID_ARG, "null pointer");
-    Counters h;
+    Counters hc;
     HIP_TRY(hipStreamSynchronize(c->last_stream));
-    HIP_TRY(hipMemcpy(&h, c->cnt, sizeof(h), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&hc, c->cnt, sizeof(hc), hipMemcpyDeviceToHost));
+    StatLine h{};
+    for (int k = 0; k < kStatStripes; ++k) {
+        const StatLine& L = hc.st[k];
+        h.paths += L.paths;
+        h.vertices += L.vertices;
+        h.photons += L.photons;
+        h.photon_segments += L.photon_segments;
+        h.merges += L.merges;
+        h.nee_visible += L.nee_visible;
+        h.events += L.events;
+        h.camera_rays += L.camera_rays;
+        h.shadow_rays += L.shadow_rays;
+        h.photon_rays += L.photon_rays;
+        h.photon_items += L.photon_items;
+        h.photon_continued += L.photon_continued;
+        h.grid_cells += L.grid_cells;
+        h.candidates += L.candidates;
+        h.bvh_nodes += L.bvh_nodes;
+        h.bvh_tris += L.bvh_tris;
+        h.light_photons += L.light_photons;
+    }
     std::memset(out, 0, sizeof(*out));
     out->iterations = c->iter;
     out->paths = (int64_t)h.paths;
