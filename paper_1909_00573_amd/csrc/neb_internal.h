@@ -97,6 +97,13 @@ struct alignas(128) StatLine {
     unsigned long long light_photons;
 };
 
+// A closest-hit launch hands out its rays through kWorkParts counters, one
+// cache line each (its blocks run on eight XCDs; one counter per XCD).
+constexpr int kWorkParts = 8;
+struct alignas(128) WorkLine {
+    int32_t next;
+};
+
 // Device counters.  Every queue counter sits in a cache line of its own:
 // atomics on one line are serialised by the cache, and counters that
 // different kernels (or one kernel's reservations and its statistics) hit
@@ -108,7 +115,7 @@ struct Counters {
     alignas(128) int32_t n_events;
     alignas(128) int32_t iter;       // current iteration (incremented at the start of each one)
     alignas(128) int32_t lp_count;   // light photons emitted this iteration (the first entries of photon queue 0)
-    alignas(128) int32_t trace_next; // next ray of a closest-hit launch (reset by its last block)
+    WorkLine trace_next[kWorkParts]; // per part: rays a closest-hit launch handed out (reset by its last block)
     alignas(128) int32_t trace_done; // blocks of that launch that finished
     StatLine st[kStatStripes];
 };

@@ -328,18 +328,26 @@ __global__ void __launch_bounds__(kTraceBlock) k_extend(SceneView S, const Scene
     if (blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
     unsigned traced = 0, nodes = 0, tris = 0;
     // Each lane holds one ray; a lane whose ray ends takes the next one from
-    // the launch's work counter (one atomic per wave), so short rays do not
-    // leave lanes idle behind long ones.
+    // a work counter (one atomic per wave), so short rays do not leave lanes
+    // idle behind long ones.  The queue is cut into chunks of kChunk rays
+    // dealt round-robin to `parts` parts, each with a counter of its own;
+    // block b draws from part b mod parts (blocks b, b + 8, ... share an
+    // XCD), so the counters' atomics are spread over eight cache lines while
+    // every part's rays stay spread over the whole queue.
     constexpr int kSteps = 16;
+    constexpr int kChunk = 256;
+    const int parts = min(kWorkParts, (int)gridDim.x), part = blockIdx.x % parts;
+    int32_t* next = &cnt->trace_next[part].next;
     int i = -1;  // this lane's ray; >= n once the queue is exhausted
     TraceState T;
     f3 o = mk3(0.f, 0.f, 0.f), dd = mk3(0.f, 0.f, 1.f);
     int sid = 0;
     for (;;) {
         const bool need = i < 0;
-        const int got = wave_reserve(&cnt->trace_next, need);
+        const int got = wave_reserve(next, need);
         if (need) {
-            i = got < n ? got : n;
+            const int64_t g = ((int64_t)(got / kChunk) * parts + part) * kChunk + got % kChunk;
+            i = g < n ? (int)g : n;
             if (i < n) {
                 float4 d4 = dir[i];
                 sid = tag_scene(fbits(d4.w));
@@ -364,7 +372,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_extend(SceneView S, const Scene
     // the last block to finish resets the work counter for the next launch
     __syncthreads();
     if (threadIdx.x == 0 && atomicAdd(&cnt->trace_done, 1) == (int)gridDim.x - 1) {
-        cnt->trace_next = 0;
+        for (int k = 0; k < kWorkParts; ++k) cnt->trace_next[k].next = 0;
         cnt->trace_done = 0;
     }
     StatLine& L = stat_line(cnt);
