@@ -1577,9 +1577,9 @@ struct HostScene {
 // stack is raised to the shallowest that holds the deepest tree)
 struct LaunchCfg {
     int stack = 32;        // LDS traversal stack entries per lane: 32, 48 or 64
-    int trace_bpc = 8;     // closest-hit blocks (one wave each) per CU; 0 = one block per 64 queue slots,
-                           // -1 = as many as the LDS holds
-    int nee_bpc = -1;      // NEE (shadow-ray) blocks per CU, same conventions
+    int trace_bpc = 16;    // closest-hit blocks (one wave each) per CU; 0 = one block per 64 queue slots,
+                           // -1 = as many as the LDS holds (clamped to that for deeper stacks)
+    int nee_bpc = 16;      // NEE (shadow-ray) blocks per CU, same conventions
     int photon_bpc = 8;    // photon-merge blocks (one wave each) per CU; 0 = one block per 256 queue slots
     int photon_order = 0;  // merge photons in the spatial order of their hits
 };
@@ -1764,7 +1764,7 @@ static int lds_blocks_per_cu(int stack) { return (160 * 1024) / (stack * kTraceB
 // blocks of a traversal launch over a queue of at most cap rays, with bpc
 // blocks per CU (0: one block per 64 queue slots, -1: as many as the LDS holds)
 static int trace_grid(neb_ctx c, int64_t cap, int bpc) {
-    if (bpc < 0) bpc = lds_blocks_per_cu(c->cfg.stack);
+    if (bpc < 0 || bpc > lds_blocks_per_cu(c->cfg.stack)) bpc = lds_blocks_per_cu(c->cfg.stack);
     if (bpc > 0) return std::max(1, c->cus * bpc);
     return grid_of(cap, kTraceBlock, 1 << 20);
 }
@@ -3002,8 +3002,9 @@ extern "C" neb_status neb_set_launch_config(neb_ctx c, const neb_launch_config* 
 extern "C" neb_status neb_get_launch_config(neb_ctx c, neb_launch_config* cfg) {
     if (!c || !cfg) return fail(NEB_ERR_INVALID_ARG, "null pointer");
     cfg->bvh_stack = c->cfg.stack;
-    cfg->trace_blocks_per_cu = c->cfg.trace_bpc < 0 ? lds_blocks_per_cu(c->cfg.stack) : c->cfg.trace_bpc;
-    cfg->nee_blocks_per_cu = c->cfg.nee_bpc < 0 ? lds_blocks_per_cu(c->cfg.stack) : c->cfg.nee_bpc;
+    const int maxb = lds_blocks_per_cu(c->cfg.stack);
+    cfg->trace_blocks_per_cu = c->cfg.trace_bpc < 0 ? maxb : std::min(c->cfg.trace_bpc, maxb);
+    cfg->nee_blocks_per_cu = c->cfg.nee_bpc < 0 ? maxb : std::min(c->cfg.nee_bpc, maxb);
     cfg->photon_blocks_per_cu = c->cfg.photon_bpc;
     cfg->photon_order = c->cfg.photon_order;
     return NEB_OK;
@@ -3047,7 +3048,8 @@ extern "C" neb_status neb_autotune(neb_ctx c, int32_t trial_iterations, void* st
         if (st != NEB_OK) break;
         if (stack <= c->forest_depth) continue;
         int maxb = lds_blocks_per_cu(stack);
-        for (int b : {0, 4, 8, maxb}) {
+        for (int b : {0, 4, 8, 12, 16, maxb}) {
+            if (b > maxb) continue;
             neb_launch_config cfg{stack, b, -1, best.photon_blocks_per_cu, best.photon_order};
             double ms = 0.0;
             st = time_config(c, cfg, trial_iterations, trace_k, 2, s, ms);
@@ -3061,8 +3063,9 @@ extern "C" neb_status neb_autotune(neb_ctx c, int32_t trial_iterations, void* st
     }
     best_ms = 1e300;
     const int nee_k[1] = {K_NEE};
-    for (int b : {0, 4, 8, lds_blocks_per_cu(best.bvh_stack)}) {
+    for (int b : {0, 4, 8, 12, 16, lds_blocks_per_cu(best.bvh_stack)}) {
         if (st != NEB_OK) break;
+        if (b > lds_blocks_per_cu(best.bvh_stack)) continue;
         neb_launch_config cfg{best.bvh_stack, best.trace_blocks_per_cu, b, best.photon_blocks_per_cu,
                               best.photon_order};
         double ms = 0.0;
