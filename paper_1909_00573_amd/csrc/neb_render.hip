@@ -381,22 +381,43 @@ __global__ void __launch_bounds__(kTraceBlock) k_extend(SceneView S, const Scene
     wave_add_u64(&L.bvh_tris, tris);
 }
 
-__global__ void __launch_bounds__(256) k_shade(RenderArgs A, PathQ in, const int32_t* count_in, const int2* hits,
-                                               PathQ out, int32_t* count_out, VertexStore V, int32_t* n_vertices,
-                                               float4* ev0, float4* ev1, int32_t* n_events, int32_t* slots,
-                                               neb_path_record* rec) {
-    int n = *count_in;
+// One thread per path.  The three appends (emitter event, NEE vertex,
+// continuing path) are reserved once per block and queue: the four waves'
+// counts meet in LDS and one thread per queue takes the block's slots with
+// one atomic, four times fewer than one per wave (returning atomics on one
+// counter are serialised).  Every thread runs the same number of rounds so
+// that the block can meet at its barriers.
+constexpr int kShadeBlock = 256;
+__global__ void __launch_bounds__(kShadeBlock) k_shade(RenderArgs A, PathQ in, const int32_t* count_in,
+                                                       const int2* hits, PathQ out, int32_t* count_out,
+                                                       VertexStore V, int32_t* n_vertices, float4* ev0, float4* ev1,
+                                                       int32_t* n_events, int32_t* slots, neb_path_record* rec) {
+    constexpr int kWaves = kShadeBlock / 64;
+    __shared__ int wc[3][kWaves];  // per queue and wave: appends of this round
+    __shared__ int bb[3];          // per queue: the block's first slot
+    const int n = *count_in;
     const SceneView& S = A.S;
     const int iter = A.cnt->iter;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        float4 a0 = in.q0[i], a1 = in.q1[i], a2 = in.q2[i], a3 = in.q3[i];
-        int2 h = hits[i];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int base = blockIdx.x * kShadeBlock; base < n; base += gridDim.x * kShadeBlock) {
+        const int i = base + threadIdx.x;
+        const bool valid = i < n;
+        float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0, a2 = a0, a3 = a0;
+        int2 h = make_int2(0, -1);
+        if (valid) {
+            a0 = in.q0[i];
+            a1 = in.q1[i];
+            a2 = in.q2[i];
+            a3 = in.q3[i];
+            h = hits[i];
+        }
         int pixel = fbits(a0.w), tg = fbits(a1.w);
         int k = tag_depth(tg), sid = tag_scene(tg);
         const SceneInfo& I = A.sc[sid];
-        neb_path_record* rc = rec ? rec + (size_t)pixel * A.L + (k - 1) : nullptr;
-        bool alive = h.y >= 0;
-        if (!alive && rc) {
+        neb_path_record* rc = (rec && valid) ? rec + (size_t)pixel * A.L + (k - 1) : nullptr;
+        bool alive = valid && h.y >= 0;
+        if (valid && !alive && rc) {
             rc->type = 5;
             rc->mat = -1;
             rc->prim = -1;
@@ -420,9 +441,44 @@ __global__ void __launch_bounds__(256) k_shade(RenderArgs A, PathQ in, const int
             rc->pos[2] = x.z;
         }
         // emitter hit: stored for pass 3 (its MIS weight needs rho at x_{l-1})
-        bool emit = alive && mat_emits(m) && cin > 0.f && S.prim_light[prim] >= 0;
-        int eslot = wave_reserve(n_events, emit);
+        const bool emit = alive && mat_emits(m) && cin > 0.f && S.prim_light[prim] >= 0;
+        const bool store = alive && !mat_black(m) && k <= I.L - 1;
+        float g = (k >= 2) ? a3.y / fabsf(cin) : 0.f;
+        float B = (k >= 2) ? a3.x + a3.z : 0.f;
+        Sample smp;
+        smp.ev = 0;
+        if (store) {
+            U4 u = uniforms(I.k0, I.k1, (uint32_t)(pixel - I.pix_base), (uint32_t)iter, (uint32_t)k, kTagBsdf);
+            smp = bsdf_sample(m, nrm, wo, u);
+        }
+        const bool go = smp.ev != 0;
+        if (go && rc) rc->type = smp.ev;
+        // the block's slots in the three queues
+        const unsigned long long me = __ballot(emit), ms = __ballot(store), mg = __ballot(go);
+        if (lane == 0) {
+            wc[0][wid] = __popcll(me);
+            wc[1][wid] = __popcll(ms);
+            wc[2][wid] = __popcll(mg);
+        }
+        __syncthreads();
+        if (threadIdx.x < 3) {
+            const int q = threadIdx.x;
+            int tot = 0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) tot += wc[q][w];
+            int32_t* ctr = q == 0 ? n_events : (q == 1 ? n_vertices : count_out);
+            bb[q] = tot ? atomicAdd(ctr, tot) : 0;
+        }
+        __syncthreads();
+        int pe = bb[0], ps = bb[1], pg = bb[2];
+        for (int w = 0; w < wid; ++w) {
+            pe += wc[0][w];
+            ps += wc[1][w];
+            pg += wc[2][w];
+        }
+        __syncthreads();  // wc and bb are rewritten by the next round
         if (emit) {
+            const int eslot = pe + __popcll(me & below);
             float q = 0.f, D = a3.z;
             if (k > 1) {
                 int lid = S.prim_light[prim];
@@ -436,10 +492,7 @@ __global__ void __launch_bounds__(256) k_shade(RenderArgs A, PathQ in, const int
             ev0[eslot] = f4(tau * load3(m.emission), q);
             ev1[eslot] = make_float4(a3.x * I.r2pi, D, a3.w, ibits(pixel));
         }
-        bool store = alive && !mat_black(m) && k <= I.L - 1;
-        float g = (k >= 2) ? a3.y / fabsf(cin) : 0.f;
-        float B = (k >= 2) ? a3.x + a3.z : 0.f;
-        int vid = wave_reserve(n_vertices, store);
+        const int vid = store ? ps + __popcll(ms & below) : -1;
         if (store) {
             V.v0[vid] = f4(x, ibits(pixel));
             V.v1[vid] = f4(nrm, ibits(make_vtag(k, sid, mid)));
@@ -447,22 +500,14 @@ __global__ void __launch_bounds__(256) k_shade(RenderArgs A, PathQ in, const int
             V.v3[vid] = f4(tau, g);
             if (slots) slots[(size_t)(k - 1) * A.npix + pixel] = vid;
         }
-        Sample s;
-        s.ev = 0;
-        if (store) {
-            U4 u = uniforms(I.k0, I.k1, (uint32_t)(pixel - I.pix_base), (uint32_t)iter, (uint32_t)k, kTagBsdf);
-            s = bsdf_sample(m, nrm, wo, u);
-        }
-        bool go = s.ev != 0;
-        if (go && rc) rc->type = s.ev;
-        int slot = wave_reserve(count_out, go);
         if (go) {
-            float Acur = (k >= 2) ? bsdf_pdf(m, nrm, s.dir, wo) * g * B : 0.f;
-            float gp = fabsf(dot3(nrm, s.dir)) / s.pdf;
+            const int slot = pg + __popcll(mg & below);
+            float Acur = (k >= 2) ? bsdf_pdf(m, nrm, smp.dir, wo) * g * B : 0.f;
+            float gp = fabsf(dot3(nrm, smp.dir)) / smp.pdf;
             float dnon = mat_delta(m.type) ? 0.f : 1.f;
-            out.q0[slot] = f4(offset_origin(x, nrm, s.dir, I.eps), ibits(pixel));
-            out.q1[slot] = f4(s.dir, ibits(make_tag(k + 1, sid)));
-            out.q2[slot] = f4(tau * s.w, s.pdf);
+            out.q0[slot] = f4(offset_origin(x, nrm, smp.dir, I.eps), ibits(pixel));
+            out.q1[slot] = f4(smp.dir, ibits(make_tag(k + 1, sid)));
+            out.q2[slot] = f4(tau * smp.w, smp.pdf);
             out.q3[slot] = make_float4(Acur, gp, dnon, ibits(vid));
         }
     }
@@ -2448,7 +2493,7 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
         int in = (k - 1) & 1, out = k & 1;
         TIMED(K_EXTEND_CAMERA,
               extend(c, npix, c->q[in].q0, c->q[in].q1, &cnt->qcount[in], &cnt->qcount[out], 0, s));
-        TIMED(K_SHADE, hipLaunchKernelGGL(k_shade, dim3(grid_of(npix, 256)), dim3(256), 0, s, A, c->q[in],
+        TIMED(K_SHADE, hipLaunchKernelGGL(k_shade, dim3(grid_of(npix, kShadeBlock)), dim3(kShadeBlock), 0, s, A, c->q[in],
                                           &cnt->qcount[in], c->hits, c->q[out], &cnt->qcount[out], c->V,
                                           &cnt->n_vertices, c->ev0, c->ev1, &cnt->n_events, c->slots,
                                           record ? c->recs : (neb_path_record*)nullptr));
