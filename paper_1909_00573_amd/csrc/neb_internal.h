@@ -40,17 +40,29 @@ struct OctDyn {
 };
 
 // device-resident octree state updated by atomics
-// the allocation counter (hit by every split) and the deposit tally (one
-// atomic per wave of every insertion launch) in cache lines of their own
+// The allocation counter (hit by every split), the split tallies and the
+// deposit tally (one atomic per wave of every insertion launch) sit in cache
+// lines of their own; the deposit tally is striped over kDepositStripes
+// lines (a block adds into stripe blockIdx.x mod kDepositStripes), its value
+// is the sum of the stripes (oct_deposits).
+constexpr int kDepositStripes = 16;
+struct alignas(128) TallyLine {
+    unsigned long long v;
+};
 struct OctState {
     alignas(128) int32_t alloc;
-    int32_t depth;
+    alignas(128) int32_t depth;
     int32_t overflow;
     int32_t rejected;
     unsigned long long block_iter_sum;
-    alignas(128) unsigned long long deposits;
     unsigned long long lost;
+    TallyLine deposits[kDepositStripes];
 };
+__host__ __device__ inline unsigned long long oct_deposits(const OctState& st) {
+    unsigned long long d = 0;
+    for (int k = 0; k < kDepositStripes; ++k) d += st.deposits[k].v;
+    return d;
+}
 
 // a standalone octree (the Appendix-B surface of the C ABI)
 struct Octree {

@@ -253,7 +253,7 @@ __device__ __forceinline__ void oct_account(OctState* states, int scene, int cou
             S.depth = max(S.depth, __shfl_xor(S.depth, off, 64));
         }
         if (lane == leader) {
-            if (c) atomicAdd(&states[ls].deposits, c);
+            if (c) atomicAdd(&states[ls].deposits[blockIdx.x & (kDepositStripes - 1)].v, c);
             if (r) atomicAdd(&states[ls].rejected, r);
             flush_tally(states + ls, S);
         }
@@ -317,7 +317,7 @@ __global__ void k_oct_insert_single(int32_t* nodes, OctState* states, const OctP
         const float* pp = pos + (size_t)stride * item;
         int s = item_scene(scene_word, stride, shift, item);
         int r = oct_insert(nodes, states + s, prm[s], D, mk3(pp[0], pp[1], pp[2]));
-        if (r == kInsCounted) states[s].deposits += 1;
+        if (r == kInsCounted) states[s].deposits[0].v += 1;
         if (r == kInsRejected) states[s].rejected += 1;
         if (r == kInsDeferred) states[s].lost += 1;  // impossible without concurrency
     }
@@ -352,7 +352,7 @@ __global__ void k_oct_init(int32_t* nodes, OctState* st, OctDyn* dyn, int32_t ro
         st->overflow = 0;
         st->rejected = 0;
         st->block_iter_sum = 0;
-        st->deposits = 0;
+        for (int k = 0; k < kDepositStripes; ++k) st->deposits[k].v = 0;
         st->lost = 0;
         if (dyn) *dyn = d0;
     }
@@ -370,7 +370,7 @@ __global__ void k_oct_clear(int32_t* nodes, OctState* st, int32_t root, int32_t 
 // kernel can read alloc while this one resets the sums)
 __global__ void k_oct_clear_ledger(OctState* st) {
     st->block_iter_sum = 0;
-    st->deposits = 0;
+    for (int k = 0; k < kDepositStripes; ++k) st->deposits[k].v = 0;
 }
 
 __global__ void k_oct_clear_counter(int32_t* c) { *c = 0; }

@@ -2873,7 +2873,7 @@ static neb_status octree_info(const int32_t* pool, const OctState* state, int32_
     info[1] = used;
     info[2] = st.depth;
     info[3] = leaf - (int64_t)kOctSplitFactor * (int64_t)st.block_iter_sum;
-    info[4] = (int64_t)st.deposits;
+    info[4] = (int64_t)oct_deposits(st);
     info[5] = st.overflow;
     info[6] = st.rejected;
     info[7] = (int64_t)st.lost;
