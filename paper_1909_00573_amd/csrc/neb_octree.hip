@@ -19,11 +19,13 @@
 //    leaf splits it on the spot, and the lanes beyond the cap follow the
 //    pointer their own wave has just published; so a full leaf without a
 //    pointer was always filled by another wave.  Such a deposit is deferred
-//    to a queue retried by the next launch (the kernel boundary guarantees
-//    the split has been published).  A deposit is deferred at most once per
-//    level, so kOctMaxDepth + 1 retry rounds bound the work.  (Re-reading
-//    the word a bounded number of times instead was measured slower: a
-//    wave keeps looping while any lane waits);
+//    to a queue retried by the next round, once that wave's split is
+//    certainly published: rounds 1 .. kOctLaunchRounds - 1 are launches of
+//    their own (the kernel boundary), later rounds run in one block,
+//    separated by the block's barrier and an agent-scope acquire.  A deposit is deferred at
+//    most once per level, so kOctMaxDepth + 1 retry rounds bound the work.
+//    (Re-reading the word a bounded number of times instead was measured
+//    slower: a wave keeps looping while any lane waits);
 //  - no increment is overwritten by the pointer store (deposits never
 //    count past the threshold), so the ledger
 //        S = sum(leaf counts) - 4 * sum(iteration of each allocated block)
@@ -46,6 +48,10 @@ __device__ __forceinline__ int32_t ld_node(const int32_t* p) {
 }
 
 enum { kInsRejected = 0, kInsCounted = 1, kInsDeferred = 2 };
+
+// deposit rounds run as launches of their own (measured: while a reset tree
+// grows, rounds 1-3 still hold many deferred items; afterwards only round 1)
+constexpr int kOctLaunchRounds = 4;
 
 __device__ __forceinline__ int child_index(const float q[3], int level) {
     float sc = (float)(1 << level);
@@ -265,24 +271,18 @@ __device__ __forceinline__ int item_scene(const int32_t* scene_word, int stride,
     return scene_word ? ((scene_word[(size_t)stride * item] >> shift) & 0xFF) : 0;
 }
 
-// Deposit items [0, n) (round 0, items == nullptr) or the deferred items of
-// the previous round.  Positions are float3 (stride 3) or the xyz of float4
-// records (stride 4); the octree of an item is read from scene_word.
-// Deferred items go to defer_out; the counter of the round after next is
-// cleared here (three counters rotate).
-__global__ void __launch_bounds__(256) k_oct_insert(int32_t* nodes, OctState* states, const OctParams* prm,
-                                                    const OctDyn* dyn, const float* __restrict__ pos, int stride,
-                                                    const int32_t* __restrict__ scene_word, int shift,
-                                                    const int32_t* __restrict__ items, const int32_t* n_dev,
-                                                    int32_t n_host, int32_t* __restrict__ defer_out,
-                                                    int32_t* defer_count, int32_t* clear_count) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *clear_count = 0;
-    const OctDyn D = *dyn;
-    int32_t n = n_dev ? min(*n_dev, n_host) : n_host;
-    if (D.stop_filling) return;
-    int64_t stride_all = (int64_t)gridDim.x * blockDim.x;
-    int64_t nn = (n + stride_all - 1) / stride_all * stride_all;  // uniform trip count per wave
-    for (int64_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += stride_all) {
+// One pass of deposits over n items, by threads t0, t0 + step, ...: items
+// [0, n) (items == nullptr) or the listed ones.  Positions are float3
+// (stride 3) or the xyz of float4 records (stride 4); the octree of an item
+// is read from scene_word.  Deferred items go to defer_out.
+__device__ __forceinline__ void oct_insert_pass(int32_t* nodes, OctState* states, const OctParams* prm,
+                                                const OctDyn& D, const float* __restrict__ pos, int stride,
+                                                const int32_t* __restrict__ scene_word, int shift,
+                                                const int32_t* __restrict__ items, int32_t n, int64_t t0,
+                                                int64_t step, int32_t* __restrict__ defer_out,
+                                                int32_t* defer_count) {
+    int64_t nn = (n + step - 1) / step * step;  // uniform trip count per wave
+    for (int64_t i = t0; i < nn; i += step) {
         bool has = i < n;
         int32_t item = 0;
         f3 pt = mk3(0.f, 0.f, 0.f);
@@ -300,6 +300,63 @@ __global__ void __launch_bounds__(256) k_oct_insert(int32_t* nodes, OctState* st
         oct_account(states, s, has && r == kInsCounted, has && r == kInsRejected, tally);
         int slot = wave_reserve(defer_count, defer);
         if (defer) defer_out[slot] = item;
+    }
+}
+
+// Round 0 (items == nullptr: items [0, n)) or one of the rounds 1 ..
+// kOctLaunchRounds - 1 (the items deferred in the round before) of a
+// deposit; the counter of the round after next is cleared here (three
+// counters rotate).
+__global__ void __launch_bounds__(256) k_oct_insert(int32_t* nodes, OctState* states, const OctParams* prm,
+                                                    const OctDyn* dyn, const float* __restrict__ pos, int stride,
+                                                    const int32_t* __restrict__ scene_word, int shift,
+                                                    const int32_t* __restrict__ items, const int32_t* n_dev,
+                                                    int32_t n_host, int32_t* __restrict__ defer_out,
+                                                    int32_t* defer_count, int32_t* clear_count) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *clear_count = 0;
+    const OctDyn D = *dyn;
+    int32_t n = n_dev ? min(*n_dev, n_host) : n_host;
+    if (D.stop_filling) return;
+    oct_insert_pass(nodes, states, prm, D, pos, stride, scene_word, shift, items, n,
+                    blockIdx.x * (int64_t)blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x, defer_out,
+                    defer_count);
+}
+
+// Rounds kOctLaunchRounds .. kOctMaxDepth + 1 in one block (after the
+// launched rounds hardly any item is left, even while a reset tree grows):
+// the block's barrier separates the rounds, and an agent-scope acquire
+// after it makes the splits of the round before visible to this CU (what a
+// new launch would do).  Round r reads list (r - 1) & 1 counted by
+// cnt[r % 3] and appends to list r & 1 counted by cnt[(r + 1) % 3].  Items
+// still deferred after the last round cannot occur (each round resolves at
+// least one level) and would be reported as lost.
+__global__ void __launch_bounds__(256) k_oct_insert_tail(int32_t* nodes, OctState* states, const OctParams* prm,
+                                                         const OctDyn* dyn, const float* __restrict__ pos, int stride,
+                                                         const int32_t* __restrict__ scene_word, int shift,
+                                                         int32_t* defer0, int32_t* defer1, int32_t* cnt,
+                                                         int32_t n_host) {
+    __shared__ int32_t sn;
+    const OctDyn D = *dyn;
+    if (D.stop_filling) return;
+    int r = kOctLaunchRounds;
+    for (; r <= kOctMaxDepth + 1; ++r) {
+        int32_t* in_cnt = cnt + (r % 3);
+        int32_t* out_cnt = cnt + ((r + 1) % 3);
+        if (threadIdx.x == 0) {
+            sn = min(__hip_atomic_load(in_cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT), n_host);
+            __hip_atomic_store(out_cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        const int32_t n = sn;
+        if (n == 0) break;
+        oct_insert_pass(nodes, states, prm, D, pos, stride, scene_word, shift, (r & 1) ? defer0 : defer1, n,
+                        threadIdx.x, blockDim.x, (r & 1) ? defer1 : defer0, out_cnt);
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    if (r > kOctMaxDepth + 1 && threadIdx.x == 0) {
+        int32_t rem = __hip_atomic_load(cnt + ((kOctMaxDepth + 2) % 3), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (rem) atomicAdd(&states->lost, (unsigned long long)rem);
     }
 }
 
@@ -321,12 +378,6 @@ __global__ void k_oct_insert_single(int32_t* nodes, OctState* states, const OctP
         if (r == kInsRejected) states[s].rejected += 1;
         if (r == kInsDeferred) states[s].lost += 1;  // impossible without concurrency
     }
-}
-
-// deposits still deferred after the last round are reported as lost (to the
-// first state; they cannot occur, see above)
-__global__ void k_oct_report_lost(OctState* st, const int32_t* remaining) {
-    if (*remaining) atomicAdd(&st->lost, (unsigned long long)*remaining);
 }
 
 __global__ void __launch_bounds__(256) k_oct_density_xyz(const int32_t* __restrict__ nodes, const OctState* st,
@@ -417,14 +468,14 @@ hipError_t octree_insert_rounds(int32_t* nodes, OctState* states, const OctParam
     hipLaunchKernelGGL(k_oct_clear_counter, dim3(1), dim3(1), 0, s, cnt + 1);
     hipLaunchKernelGGL(k_oct_insert, dim3(grid_for(n_host, 256)), dim3(256), 0, s, nodes, states, prm, dyn, pos, stride,
                        scene_word, shift, (const int32_t*)nullptr, n_dev, n_host, defer[0], cnt + 1, cnt + 2);
-    for (int r = 1; r <= kOctMaxDepth + 1; ++r) {
+    for (int r = 1; r < kOctLaunchRounds; ++r) {
         hipLaunchKernelGGL(k_oct_insert, dim3(std::min(grid_for(n_host, 256), 1024)), dim3(256), 0, s, nodes, states,
-                           prm, dyn, pos, stride, scene_word,
-                           shift, (const int32_t*)defer[(r - 1) & 1], (const int32_t*)(cnt + (r % 3)), n_host,
-                           defer[r & 1], cnt + ((r + 1) % 3), cnt + ((r + 2) % 3));
+                           prm, dyn, pos, stride, scene_word, shift, (const int32_t*)defer[(r - 1) & 1],
+                           (const int32_t*)(cnt + (r % 3)), n_host, defer[r & 1], cnt + ((r + 1) % 3),
+                           cnt + ((r + 2) % 3));
     }
-    hipLaunchKernelGGL(k_oct_report_lost, dim3(1), dim3(1), 0, s, states,
-                       (const int32_t*)(cnt + ((kOctMaxDepth + 2) % 3)));
+    hipLaunchKernelGGL(k_oct_insert_tail, dim3(1), dim3(256), 0, s, nodes, states, prm, dyn, pos, stride, scene_word,
+                       shift, defer[0], defer[1], cnt, n_host);
     return hipGetLastError();
 }
 
