@@ -113,8 +113,9 @@ struct SceneInfo {
 // j bounces may merge with (depth <= maxlen - 1 - j) form one contiguous
 // prefix.
 struct Grid {
-    int32_t* count;   // T * D + 1 entries (the last stays 0)
+    int32_t* count;   // T * D + 1 entries (the last stays 0); zeroed by the scan that reads them
     int32_t* start;   // T * D + 1 entries
+    int32_t* rank;    // per view vertex: its place among the vertices of its key
     float4* sorted;   // (pos, scene) in (cell, depth) order
     float4* mrec;     // 4 per record, same order: what a merge needs of the view vertex:
                       // (n, tag), (wo, B), (tau, g), (pixel, -, -, -)
@@ -122,6 +123,13 @@ struct Grid {
     int32_t T;        // hash buckets (power of two)
     int32_t D;        // depth classes = longest maxlen - 1
 };
+
+// prefix sums are scanned in tiles of kScanTile elements (a tile per block
+// of kScanBlock threads, kScanPer each)
+constexpr int kScanPer = 16;
+constexpr int kScanBlock = 256;
+constexpr int kScanTile = kScanPer * kScanBlock;
+
 
 // Density grid of the alternative providers: every NEE vertex of the
 // iteration, keyed by the hash of its scene and its cell of size
@@ -1018,7 +1026,9 @@ __global__ void __launch_bounds__(256) k_nee_recycle(RenderArgs A, VertexStore V
 
 // ---------------------------------------------------------------------------
 // merge structure: hash grid of cell size 2r over the non-delta view vertices
-// (count -> exclusive scan -> scatter); count[] returns to zero after scatter
+// (count, which also gives each vertex its rank within its key -> exclusive
+// scan, which zeroes the counts for the next iteration -> scatter to
+// start[key] + rank)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int64_t grid_key(const Grid& G, uint32_t h, int depth) {
     return (int64_t)h * G.D + (depth - 1);
@@ -1031,7 +1041,7 @@ __global__ void __launch_bounds__(256) k_grid_count(const neb_material* mats, co
         int tg = fbits(V.v1[i].w);
         if (mat_delta(mats[tag_mat(tg)].type)) continue;
         int s = tag_scene(tg);
-        atomicAdd(&G.count[grid_key(G, point_hash(xyz(V.v0[i]), sc[s].inv_cell, s, G.T), tag_depth(tg))], 1);
+        G.rank[i] = atomicAdd(&G.count[grid_key(G, point_hash(xyz(V.v0[i]), sc[s].inv_cell, s, G.T), tag_depth(tg))], 1);
     }
 }
 
@@ -1046,7 +1056,7 @@ __global__ void __launch_bounds__(256) k_grid_scatter(const neb_material* mats, 
         float4 a0 = V.v0[i];
         f3 p = xyz(a0);
         int64_t key = grid_key(G, point_hash(p, sc[s].inv_cell, s, G.T), tag_depth(tg));
-        int pos = G.start[key] + atomicSub(&G.count[key], 1) - 1;
+        int pos = G.start[key] + G.rank[i];
         G.sorted[pos] = f4(p, ibits(s));
         float4* m = G.mrec + 4 * (size_t)pos;
         m[0] = a1;
@@ -1056,10 +1066,7 @@ __global__ void __launch_bounds__(256) k_grid_scatter(const neb_material* mats, 
     }
 }
 
-// exclusive scan in three launches: 4096 elements per block of 256 threads
-constexpr int kScanPer = 16;
-constexpr int kScanBlock = 256;
-constexpr int kScanTile = kScanPer * kScanBlock;
+// exclusive scan: 4096 elements per block of 256 threads
 
 __device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int& total) {
     int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -1077,22 +1084,54 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int& total) 
     return wbase + x - v;
 }
 
-__global__ void __launch_bounds__(kScanBlock) k_scan_tiles(const int32_t* in, int32_t* out, int32_t* sums, int64_t n) {
+// zero_in: clear the input after reading it (in and out must not alias)
+__global__ void __launch_bounds__(kScanBlock) k_scan_tiles(int32_t* in, int32_t* out, int32_t* sums, int64_t n,
+                                                           int zero_in) {
     __shared__ int sh[4];
     int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
     int loc[kScanPer];
     int s = 0;
+    if (base + kScanPer <= n && (((uintptr_t)(in + base)) & 15) == 0) {
+        // a whole run of 16 ints, as four 16-byte loads
+        const int4* v = reinterpret_cast<const int4*>(in + base);
 #pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-        loc[k] = (base + k < n) ? in[base + k] : 0;
-        s += loc[k];
+        for (int k = 0; k < kScanPer / 4; ++k) {
+            int4 w = v[k];
+            loc[4 * k] = w.x;
+            loc[4 * k + 1] = w.y;
+            loc[4 * k + 2] = w.z;
+            loc[4 * k + 3] = w.w;
+        }
+        if (zero_in) {
+            int4* z = reinterpret_cast<int4*>(in + base);
+#pragma unroll
+            for (int k = 0; k < kScanPer / 4; ++k) z[k] = make_int4(0, 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k) {
+            loc[k] = (base + k < n) ? in[base + k] : 0;
+            if (zero_in && base + k < n) in[base + k] = 0;
+        }
     }
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) s += loc[k];
     int total;
     int pre = block_exclusive_scan(s, sh, total);
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
-        if (base + k < n) out[base + k] = pre;
-        pre += loc[k];
+        const int v = loc[k];
+        loc[k] = pre;
+        pre += v;
+    }
+    if (base + kScanPer <= n && (((uintptr_t)(out + base)) & 15) == 0) {
+        int4* o = reinterpret_cast<int4*>(out + base);
+#pragma unroll
+        for (int k = 0; k < kScanPer / 4; ++k) o[k] = make_int4(loc[4 * k], loc[4 * k + 1], loc[4 * k + 2], loc[4 * k + 3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k)
+            if (base + k < n) out[base + k] = loc[k];
     }
     if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
@@ -1119,9 +1158,18 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_sums(int32_t* sums, int32_t
 __global__ void __launch_bounds__(kScanBlock) k_scan_add(int32_t* out, const int32_t* sums, int64_t n) {
     int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
     int add = sums[blockIdx.x];
+    if (base + kScanPer <= n && (((uintptr_t)(out + base)) & 15) == 0) {
+        int4* o = reinterpret_cast<int4*>(out + base);
 #pragma unroll
-    for (int k = 0; k < kScanPer; ++k)
-        if (base + k < n) out[base + k] += add;
+        for (int k = 0; k < kScanPer / 4; ++k) {
+            int4 w = o[k];
+            o[k] = make_int4(w.x + add, w.y + add, w.z + add, w.w + add);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanPer; ++k)
+            if (base + k < n) out[base + k] += add;
+    }
 }
 
 // scratch ints needed by scan_exclusive for n elements (all levels)
@@ -1134,11 +1182,14 @@ static int64_t scan_scratch(int64_t n) {
     return std::max<int64_t>(tot, 1);
 }
 
-// exclusive prefix sum of n ints (in and out may alias): tiles of 4096,
-// then the tile sums recursively, then the offsets added back
-static void scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* scratch, hipStream_t s) {
+// exclusive prefix sum of n ints (in and out may alias unless zero_in):
+// tiles of 4096, then the tile sums recursively, then the offsets added
+// back; zero_in clears the input as it is read
+static void scan_exclusive(int32_t* in, int32_t* out, int64_t n, int32_t* scratch, hipStream_t s,
+                           bool zero_in = false) {
     int64_t nb = (n + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, out, scratch, n);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nb), dim3(kScanBlock), 0, s, in, out, scratch, n,
+                       zero_in ? 1 : 0);
     if (nb <= kScanTile) {
         hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanBlock), 0, s, scratch, (int32_t)nb);
     } else {
@@ -1992,6 +2043,7 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
     int64_t gkeys = (int64_t)c->G.T * c->G.D + 1;
     ALLOC(c->G.count, gkeys);
     ALLOC(c->G.start, gkeys);
+    ALLOC(c->G.rank, vcap);
     ALLOC(c->G.sorted, vcap);
     ALLOC(c->G.mrec, 4 * vcap);
     ALLOC(c->G.sums, scan_scratch(gkeys));
@@ -2586,7 +2638,7 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
         prof_begin(c, K_GRID_BUILD, s);
         hipLaunchKernelGGL(k_grid_count, dim3(grid_of(vcap, 256)), dim3(256), 0, s, (const neb_material*)c->view.mats,
                            (const SceneInfo*)c->sc_dev, c->V, (const int32_t*)&cnt->n_vertices, c->G);
-        scan_exclusive(c->G.count, c->G.start, n, c->G.sums, s);
+        scan_exclusive(c->G.count, c->G.start, n, c->G.sums, s, true);
         hipLaunchKernelGGL(k_grid_scatter, dim3(grid_of(vcap, 256)), dim3(256), 0, s,
                            (const neb_material*)c->view.mats, (const SceneInfo*)c->sc_dev, c->V,
                            (const int32_t*)&cnt->n_vertices, c->G);
