@@ -474,16 +474,18 @@ struct TraceState {
     int sp;
 };
 
-__device__ __forceinline__ void trace_begin(TraceState& T, int root, f3 o, f3 d) {
+__device__ __forceinline__ void trace_begin(TraceState& T, int root, f3 o, f3 d, float tmax = INFINITY) {
     T.r = ray_pre(o, d);
-    T.best = INFINITY;
+    T.best = tmax;
     T.prim = -1;
     T.node = root;
     T.sp = 0;
 }
 
-// returns true when the ray is done (T.best, T.prim hold the closest hit)
-template <int kStack>
+// returns true when the ray is done (T.best, T.prim hold the closest hit
+// below the tmax of trace_begin; kAnyHit: T.prim >= 0 once any hit below
+// tmax is found, which ends the ray)
+template <int kStack, bool kAnyHit = false>
 __device__ __forceinline__ bool trace_steps(const SceneView& S, TraceState& T, int* stack, int max_steps,
                                             unsigned& nodes, unsigned& tris) {
     const RayPre& r = T.r;
@@ -500,11 +502,12 @@ __device__ __forceinline__ bool trace_steps(const SceneView& S, TraceState& T, i
             for (int k = lk.x; k < lk.x + lk.z; ++k) {
                 const float4* tp = S.tri + 3 * k;
                 float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
-                float t = tri_hit(r, xyz(p0), xyz(p1), xyz(p2), T.best * 1.0000001f);
+                float t = tri_hit(r, xyz(p0), xyz(p1), xyz(p2), kAnyHit ? T.best : T.best * 1.0000001f);
                 int id = __float_as_int(p0.w);
                 if (t > 0.f && (t < T.best || (t == T.best && id < T.prim))) {
                     T.best = t;
                     T.prim = id;
+                    if (kAnyHit) return true;
                 }
             }
             h0 = false;
@@ -514,11 +517,12 @@ __device__ __forceinline__ bool trace_steps(const SceneView& S, TraceState& T, i
             for (int k = lk.y; k < lk.y + lk.w; ++k) {
                 const float4* tp = S.tri + 3 * k;
                 float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
-                float t = tri_hit(r, xyz(p0), xyz(p1), xyz(p2), T.best * 1.0000001f);
+                float t = tri_hit(r, xyz(p0), xyz(p1), xyz(p2), kAnyHit ? T.best : T.best * 1.0000001f);
                 int id = __float_as_int(p0.w);
                 if (t > 0.f && (t < T.best || (t == T.best && id < T.prim))) {
                     T.best = t;
                     T.prim = id;
+                    if (kAnyHit) return true;
                 }
             }
             h1 = false;
@@ -551,6 +555,27 @@ __device__ __forceinline__ void wave_add_u64(unsigned long long* dst, unsigned v
 
 // this block's stripe of the work statistics
 __device__ __forceinline__ StatLine& stat_line(Counters* c) { return c->st[blockIdx.x & (kStatStripes - 1)]; }
+
+// Block-wide slot reservation in one queue whose tail is *counter: one
+// atomic per block (the waves' counts meet in wc[kWaves] and bb, LDS).  Every
+// thread of the block must call it; lanes with take == false get -1.
+template <int kWaves>
+__device__ __forceinline__ int block_reserve(int32_t* counter, bool take, int* wc, int* bb) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const unsigned long long m = __ballot(take);
+    if (lane == 0) wc[wid] = __popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int w = 0; w < kWaves; ++w) tot += wc[w];
+        *bb = tot ? atomicAdd(counter, tot) : 0;
+    }
+    __syncthreads();
+    int base = *bb;
+    for (int w = 0; w < wid; ++w) base += wc[w];
+    __syncthreads();  // wc and bb are rewritten by the next call
+    return take ? base + __popcll(m & ((1ull << lane) - 1ull)) : -1;
+}
 
 // wave-aggregated slot reservation: returns this lane's index in a queue
 // whose tail is *counter; lanes with take == false get -1

@@ -125,6 +125,7 @@ struct Counters {
     alignas(128) int32_t pcount[2];  // photon queues
     alignas(128) int32_t n_vertices;
     alignas(128) int32_t n_events;
+    alignas(128) int32_t n_shadow;   // NEE shadow rays queued this iteration
     alignas(128) int32_t iter;       // current iteration (incremented at the start of each one)
     alignas(128) int32_t lp_count;   // light photons emitted this iteration (the first entries of photon queue 0)
     WorkLine trace_next[kWorkParts]; // per part: rays a closest-hit launch handed out (reset by its last block)

@@ -236,6 +236,7 @@ __global__ void k_iter_begin(Counters* c, OctDyn* dyn, int32_t freeze) {
     c->pcount[1] = 0;
     c->n_vertices = 0;
     c->n_events = 0;
+    c->n_shadow = 0;
     c->lp_count = 0;
     int oit = it < freeze ? it : freeze;
     int ic = oit < kOctFillIterations ? oit : kOctFillIterations;
@@ -323,17 +324,21 @@ __device__ __forceinline__ int hit_bin(const HitBins& B, int scene, f3 y) {
 
 // closest hit for a queue of rays given as (origin, direction) float4 arrays
 // (the direction's w is a tag word naming the scene); also clears the
-// counter of the queue the next kernel appends to, and optionally counts
+// counter of the queue the next kernel appends to (if any).  kAnyHit: shadow
+// rays, each ending at tmax[i]; vis[origin's w word] gets 1 if nothing is
+// hit before it, else 0 (no hits are written).  ray_kind names the statistic
+// the rays count in: 0 camera, 1 photon, 2 shadow rays.  Optionally counts
 // the hits per spatial bin
-template <int kStack>
+template <int kStack, bool kAnyHit>
 __global__ void __launch_bounds__(kTraceBlock) k_extend(SceneView S, const SceneInfo* sc,
                                                         const float4* __restrict__ org,
                                                         const float4* __restrict__ dir, const int32_t* count,
                                                         int32_t* next_count, int2* __restrict__ hits,
-                                                        int photon_rays, Counters* cnt, HitBins B) {
+                                                        int ray_kind, Counters* cnt, HitBins B,
+                                                        const float* __restrict__ tmax, int32_t* __restrict__ vis) {
     __shared__ int stack[kStack * kTraceBlock];
     const int n = *count;
-    if (blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
+    if (next_count && blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
     unsigned traced = 0, nodes = 0, tris = 0;
     // Each lane holds one ray; a lane whose ray ends takes the next one from
     // a work counter (one atomic per wave), so short rays do not leave lanes
@@ -361,14 +366,18 @@ __global__ void __launch_bounds__(kTraceBlock) k_extend(SceneView S, const Scene
                 sid = tag_scene(fbits(d4.w));
                 o = xyz(org[i]);
                 dd = xyz(d4);
-                trace_begin(T, sc[sid].bvh_root, o, dd);
+                trace_begin(T, sc[sid].bvh_root, o, dd, kAnyHit ? tmax[i] : INFINITY);
             }
         }
         const bool act = i < n;
         if (!__any(act)) break;
-        if (act && trace_steps<kStack>(S, T, stack + threadIdx.x, kSteps, nodes, tris)) {
-            hits[i] = make_int2(fbits(T.best), T.prim);
-            if (B.bin) {
+        if (act && trace_steps<kStack, kAnyHit>(S, T, stack + threadIdx.x, kSteps, nodes, tris)) {
+            if (kAnyHit) {
+                vis[fbits(org[i].w)] = T.prim < 0 ? 1 : 0;
+            } else {
+                hits[i] = make_int2(fbits(T.best), T.prim);
+            }
+            if (!kAnyHit && B.bin) {
                 int b = T.prim >= 0 ? hit_bin(B, sid, o + dd * T.best) : B.n_bins;
                 B.bin[i] = b;
                 atomicAdd(&B.count[b], 1);
@@ -384,7 +393,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_extend(SceneView S, const Scene
         cnt->trace_done = 0;
     }
     StatLine& L = stat_line(cnt);
-    wave_add_u64(photon_rays ? &L.photon_rays : &L.camera_rays, traced);
+    wave_add_u64(ray_kind == 0 ? &L.camera_rays : (ray_kind == 1 ? &L.photon_rays : &L.shadow_rays), traced);
     wave_add_u64(&L.bvh_nodes, nodes);
     wave_add_u64(&L.bvh_tris, tris);
 }
@@ -392,10 +401,10 @@ __global__ void __launch_bounds__(kTraceBlock) k_extend(SceneView S, const Scene
 // One thread per path.  The three appends (emitter event, NEE vertex,
 // continuing path) are reserved once per block and queue: the four waves'
 // counts meet in LDS and one thread per queue takes the block's slots with
-// one atomic, four times fewer than one per wave (returning atomics on one
+// one atomic, sixteen times fewer than one per wave (returning atomics on one
 // counter are serialised).  Every thread runs the same number of rounds so
 // that the block can meet at its barriers.
-constexpr int kShadeBlock = 256;
+constexpr int kShadeBlock = 1024;
 __global__ void __launch_bounds__(kShadeBlock) k_shade(RenderArgs A, PathQ in, const int32_t* count_in,
                                                        const int2* hits, PathQ out, int32_t* count_out,
                                                        VertexStore V, int32_t* n_vertices, float4* ev0, float4* ev1,
@@ -755,18 +764,82 @@ __device__ __forceinline__ LightSample sample_light(const SceneView& S, int base
     return ls;
 }
 
-template <int kStack>
-__global__ void __launch_bounds__(kTraceBlock) k_nee(RenderArgs A, VertexStore V, const int32_t* n_vertices,
-                                                     Images img, PhotonQ pq, int32_t* pcount) {
-    __shared__ int stack[kStack * kTraceBlock];
-    int n = *n_vertices;
+// NEE (Sec. 3.1) in three launches over the vertices: k_nee_rays draws each
+// vertex's light sample and queues a shadow ray where the sample carries
+// energy (slots reserved once per block of 1024); a closest-hit launch in
+// any-hit mode traces the queue (a lane takes the next ray when its own
+// ends, so vertices without a ray leave no lane idle during traversal);
+// k_nee_finish draws the same sample again (same stream), adds L_E and emits
+// the NEB photon of every visible vertex.
+constexpr int kNeeBlock = 1024;
+__global__ void __launch_bounds__(kNeeBlock) k_nee_rays(RenderArgs A, VertexStore V, const int32_t* n_vertices,
+                                                        float4* __restrict__ s0, float4* __restrict__ s1,
+                                                        float* __restrict__ stmax, int32_t* n_shadow) {
+    __shared__ int wc[kNeeBlock / 64];
+    __shared__ int bb;
+    const int n = *n_vertices;
+    const SceneView& S = A.S;
+    const int iter = A.cnt->iter;
+    for (int base = blockIdx.x * kNeeBlock; base < n; base += gridDim.x * kNeeBlock) {
+        const int i = base + threadIdx.x;
+        bool ray = false;
+        f3 so = mk3(0.f, 0.f, 0.f), dir = so;
+        float tmax = 0.f;
+        int sid = 0;
+        if (i < n) {
+            float4 a0 = V.v0[i], a1 = V.v1[i];
+            f3 x = xyz(a0), nrm = xyz(a1);
+            int pixel = fbits(a0.w), tg = fbits(a1.w);
+            int k = tag_depth(tg);
+            sid = tag_scene(tg);
+            const SceneInfo& I = A.sc[sid];
+            U4 u = uniforms(I.k0, I.k1, (uint32_t)(pixel - I.pix_base), (uint32_t)iter, (uint32_t)k, kTagNee);
+            LightSample ls = sample_light(S, I.light_base, I.n_lights, x, nrm, u);
+            ray = !is_zero3(ls.dE);
+            if (ray) {
+                so = offset_origin(x, nrm, ls.w, I.eps);
+                f3 sd = ls.x - so;
+                float sl = sqrtf(dot3(sd, sd));
+                dir = sd * (1.0f / sl);
+                tmax = (1.0f - 1e-5f) * sl;
+            }
+        }
+        const int slot = block_reserve<kNeeBlock / 64>(n_shadow, ray, wc, &bb);
+        if (ray) {
+            s0[slot] = f4(so, ibits(i));
+            s1[slot] = f4(dir, ibits(make_tag(0, sid)));
+            stmax[slot] = tmax;
+        }
+    }
+}
+
+// vis[i]: 1 if vertex i's shadow ray reached the light (read only where the
+// sample carries energy, i.e. where k_nee_rays queued a ray)
+__global__ void __launch_bounds__(kNeeBlock) k_nee_finish(RenderArgs A, VertexStore V, const int32_t* n_vertices,
+                                                          const int32_t* __restrict__ visible, Images img,
+                                                          PhotonQ pq, int32_t* pcount) {
+    __shared__ int wc[kNeeBlock / 64];
+    __shared__ int bb;
+    const int n = *n_vertices;
     const SceneView& S = A.S;
     Counters* cnt = A.cnt;
     const int iter = cnt->iter;
-    unsigned vis = 0, emitted = 0, rays = 0, nodes = 0, tris = 0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        float4 a0 = V.v0[i], a1 = V.v1[i], a2 = V.v2[i], a3 = V.v3[i];
-        float rho = V.rho[i];
+    unsigned vis = 0, emitted = 0;
+    for (int base = blockIdx.x * kNeeBlock; base < n; base += gridDim.x * kNeeBlock) {
+        const int i = base + threadIdx.x;
+        const bool valid = i < n;
+        bool photon = false;
+        Sample s;
+        s.ev = 0;
+        float4 a0 = make_float4(0.f, 0.f, 0.f, 0.f), a1 = a0, a2 = a0, a3 = a0;
+        float rho = 0.f;
+        if (valid) {
+            a0 = V.v0[i];
+            a1 = V.v1[i];
+            a2 = V.v2[i];
+            a3 = V.v3[i];
+            rho = V.rho[i];
+        }
         f3 x = xyz(a0), nrm = xyz(a1), wo = xyz(a2), tau = xyz(a3);
         int pixel = fbits(a0.w);
         int tg = fbits(a1.w);
@@ -774,47 +847,39 @@ __global__ void __launch_bounds__(kTraceBlock) k_nee(RenderArgs A, VertexStore V
         const SceneInfo& I = A.sc[sid];
         const uint32_t lpix = (uint32_t)(pixel - I.pix_base);
         const neb_material& m = S.mats[mid];
-        U4 u = uniforms(I.k0, I.k1, lpix, (uint32_t)iter, (uint32_t)k, kTagNee);
-        LightSample ls = sample_light(S, I.light_base, I.n_lights, x, nrm, u);
-        bool ok = !is_zero3(ls.dE);
-        if (ok) {
-            f3 so = offset_origin(x, nrm, ls.w, I.eps);
-            f3 sd = ls.x - so;
-            float sl = sqrtf(dot3(sd, sd));
-            float tt;
-            ++rays;
-            ok = trace<true, kStack>(S, I.bvh_root, so, sd * (1.0f / sl), (1.0f - 1e-5f) * sl, tt, stack + threadIdx.x,
-                                     nodes, tris) < 0;
-        }
-        bool photon = false;
-        Sample s;
-        s.ev = 0;
+        LightSample ls;
+        ls.dE = mk3(0.f, 0.f, 0.f);
         // light photons: emission density p_{l -> l-1} from the light point toward x
         float rem = 0.f;
-        // NEE recycling: the sample is kept for the neighbours, L_E comes later
-        if (A.recycle) V.lsrec[i] = f4(ls.x, ibits(ok ? ls.lid : -1));
-        if (ok) {
-            ++vis;
-            rem = emission_density(ls.hittable, ls.cos_l, fabsf(dot3(nrm, ls.w)), ls.d2);
-            bool dnon = !mat_delta(m.type);
-            if (dnon && !A.recycle) {
-                f3 f = bsdf_f(m, nrm, wo, ls.w);
-                if (!is_zero3(f)) {
-                    float Am1 = (k >= 2) ? bsdf_pdf(m, nrm, ls.w, wo) * a3.w * a2.w : 0.f;
-                    float ratio = 1.0f;
-                    if (ls.hittable) ratio += bsdf_pdf(m, nrm, wo, ls.w) * ls.cos_l / (ls.d2 * ls.p_light);
-                    if (A.photons) ratio += rho * I.r2pi * Am1;
-                    ratio += I.nlp * I.r2pi * rem * (Am1 + 1.0f);
-                    atomic_add3(img.E, pixel, tau * f * ls.dE * (1.0f / ratio));
+        if (valid) {
+            U4 u = uniforms(I.k0, I.k1, lpix, (uint32_t)iter, (uint32_t)k, kTagNee);
+            ls = sample_light(S, I.light_base, I.n_lights, x, nrm, u);
+            const bool ok = !is_zero3(ls.dE) && visible[i] != 0;
+            // NEE recycling: the sample is kept for the neighbours, L_E comes later
+            if (A.recycle) V.lsrec[i] = f4(ls.x, ibits(ok ? ls.lid : -1));
+            if (ok) {
+                ++vis;
+                rem = emission_density(ls.hittable, ls.cos_l, fabsf(dot3(nrm, ls.w)), ls.d2);
+                bool dnon = !mat_delta(m.type);
+                if (dnon && !A.recycle) {
+                    f3 f = bsdf_f(m, nrm, wo, ls.w);
+                    if (!is_zero3(f)) {
+                        float Am1 = (k >= 2) ? bsdf_pdf(m, nrm, ls.w, wo) * a3.w * a2.w : 0.f;
+                        float ratio = 1.0f;
+                        if (ls.hittable) ratio += bsdf_pdf(m, nrm, wo, ls.w) * ls.cos_l / (ls.d2 * ls.p_light);
+                        if (A.photons) ratio += rho * I.r2pi * Am1;
+                        ratio += I.nlp * I.r2pi * rem * (Am1 + 1.0f);
+                        atomic_add3(img.E, pixel, tau * f * ls.dE * (1.0f / ratio));
+                    }
+                }
+                if (A.photons && rho > 0.f) {
+                    U4 up = uniforms(I.k0, I.k1, lpix, (uint32_t)iter, (uint32_t)(16 * k), kTagPhoton);
+                    s = bsdf_sample(m, nrm, ls.w, up);
+                    photon = s.ev != 0;
                 }
             }
-            if (A.photons && rho > 0.f) {
-                U4 up = uniforms(I.k0, I.k1, lpix, (uint32_t)iter, (uint32_t)(16 * k), kTagPhoton);
-                s = bsdf_sample(m, nrm, ls.w, up);
-                photon = s.ev != 0;
-            }
         }
-        int slot = wave_reserve(pcount, photon);
+        const int slot = block_reserve<kNeeBlock / 64>(pcount, photon, wc, &bb);
         if (photon) {
             ++emitted;
             float fo = ls.hittable ? bsdf_pdf(m, nrm, s.dir, ls.w) * ls.cos_l / (ls.d2 * ls.p_light) : 0.f;
@@ -836,9 +901,6 @@ __global__ void __launch_bounds__(kTraceBlock) k_nee(RenderArgs A, VertexStore V
     StatLine& L = stat_line(cnt);
     wave_add_u64(&L.nee_visible, vis);
     wave_add_u64(&L.photons, emitted);
-    wave_add_u64(&L.shadow_rays, rays);
-    wave_add_u64(&L.bvh_nodes, nodes);
-    wave_add_u64(&L.bvh_tris, tris);
 }
 
 // ---------------------------------------------------------------------------
@@ -1712,6 +1774,9 @@ struct neb_ctx_s {
     // per-iteration pools
     PathQ q[2]{};
     PhotonQ pq[2]{};
+    float4 *sq0 = nullptr, *sq1 = nullptr;  // NEE shadow rays: (origin, vertex), (direction, tag)
+    float* sqt = nullptr;                   // their tmax
+    int32_t* svis = nullptr;                // per vertex: 1 if its shadow ray reached the light
     int2* hits = nullptr;
     VertexStore V{};
     float4 *ev0 = nullptr, *ev1 = nullptr;
@@ -2029,6 +2094,10 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
         ALLOC(c->pq[b].pu, c->pcap);
     }
     ALLOC(c->hits, std::max<int64_t>(npix, c->pcap));
+    ALLOC(c->sq0, vcap);
+    ALLOC(c->sq1, vcap);
+    ALLOC(c->sqt, vcap);
+    ALLOC(c->svis, vcap);
     ALLOC(c->V.v0, vcap);
     ALLOC(c->V.v1, vcap);
     ALLOC(c->V.v2, vcap);
@@ -2487,8 +2556,18 @@ static RenderArgs make_args(neb_ctx c) {
 template <int kStack>
 static void launch_extend(neb_ctx c, int64_t cap, const float4* org, const float4* dir, int32_t* count, int32_t* next,
                           int rays, const HitBins& B, hipStream_t s) {
-    hipLaunchKernelGGL(k_extend<kStack>, dim3(trace_grid(c, cap, c->cfg.trace_bpc)), dim3(kTraceBlock), 0, s, c->view,
-                       (const SceneInfo*)c->sc_dev, org, dir, (const int32_t*)count, next, c->hits, rays, c->cnt, B);
+    hipLaunchKernelGGL((k_extend<kStack, false>), dim3(trace_grid(c, cap, c->cfg.trace_bpc)), dim3(kTraceBlock), 0, s,
+                       c->view, (const SceneInfo*)c->sc_dev, org, dir, (const int32_t*)count, next, c->hits, rays,
+                       c->cnt, B, (const float*)nullptr, (int32_t*)nullptr);
+}
+
+// the queued NEE shadow rays, any-hit, with the NEE launch shape
+template <int kStack>
+static void launch_shadow(neb_ctx c, hipStream_t s) {
+    hipLaunchKernelGGL((k_extend<kStack, true>), dim3(trace_grid(c, c->vcap, c->cfg.nee_bpc)), dim3(kTraceBlock), 0, s,
+                       c->view, (const SceneInfo*)c->sc_dev, (const float4*)c->sq0, (const float4*)c->sq1,
+                       (const int32_t*)&c->cnt->n_shadow, (int32_t*)nullptr, (int2*)nullptr, 2, c->cnt, HitBins{},
+                       (const float*)c->sqt, c->svis);
 }
 
 // rays: 0 counts camera rays, 1 photon rays
@@ -2508,16 +2587,14 @@ static void extend(neb_ctx c, int64_t cap, const float4* org, const float4* dir,
 }
 
 static void nee(neb_ctx c, const RenderArgs& A, Images im, hipStream_t s) {
-    dim3 g(trace_grid(c, c->vcap, c->cfg.nee_bpc)), b(kTraceBlock);
-    if (c->cfg.stack == 32)
-        hipLaunchKernelGGL(k_nee<32>, g, b, 0, s, A, c->V, (const int32_t*)&c->cnt->n_vertices, im, c->pq[0],
-                           &c->cnt->pcount[0]);
-    else if (c->cfg.stack == 48)
-        hipLaunchKernelGGL(k_nee<48>, g, b, 0, s, A, c->V, (const int32_t*)&c->cnt->n_vertices, im, c->pq[0],
-                           &c->cnt->pcount[0]);
-    else
-        hipLaunchKernelGGL(k_nee<64>, g, b, 0, s, A, c->V, (const int32_t*)&c->cnt->n_vertices, im, c->pq[0],
-                           &c->cnt->pcount[0]);
+    const int grid = grid_of(c->vcap, kNeeBlock);
+    hipLaunchKernelGGL(k_nee_rays, dim3(grid), dim3(kNeeBlock), 0, s, A, c->V, (const int32_t*)&c->cnt->n_vertices,
+                       c->sq0, c->sq1, c->sqt, &c->cnt->n_shadow);
+    if (c->cfg.stack == 32) launch_shadow<32>(c, s);
+    else if (c->cfg.stack == 48) launch_shadow<48>(c, s);
+    else launch_shadow<64>(c, s);
+    hipLaunchKernelGGL(k_nee_finish, dim3(grid), dim3(kNeeBlock), 0, s, A, c->V, (const int32_t*)&c->cnt->n_vertices,
+                       (const int32_t*)c->svis, im, c->pq[0], &c->cnt->pcount[0]);
 }
 
 // Enqueues one iteration.  Every argument is fixed for the context (the
