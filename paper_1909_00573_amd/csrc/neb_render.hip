@@ -266,14 +266,20 @@ __global__ void k_scale_image(const float* a, float* out, int64_t n, float scale
 // ---------------------------------------------------------------------------
 // one camera ray per pixel of every scene still taking part; the live rays
 // are compacted into the queue
-__global__ void __launch_bounds__(256) k_camera(RenderArgs A, PathQ q) {
+// camera rays of the scenes active in this iteration, queue slots reserved
+// once per block of kCameraBlock threads
+constexpr int kCameraBlock = 1024;
+__global__ void __launch_bounds__(kCameraBlock) k_camera(RenderArgs A, PathQ q) {
+    __shared__ int wc[kCameraBlock / 64];
+    __shared__ int bb;
     const int iter = A.cnt->iter;
     unsigned started = 0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < A.npix; i += gridDim.x * blockDim.x) {
-        int s = scene_of_pixel(A.pix_base, A.n_scenes, i);
+    for (int base = blockIdx.x * kCameraBlock; base < A.npix; base += gridDim.x * kCameraBlock) {
+        const int i = base + threadIdx.x;
+        int s = i < A.npix ? scene_of_pixel(A.pix_base, A.n_scenes, i) : 0;
         const SceneInfo& I = A.sc[s];
-        bool act = scene_active(I, iter);
-        int slot = wave_reserve(&A.cnt->qcount[0], act);
+        bool act = i < A.npix && scene_active(I, iter);
+        int slot = block_reserve<kCameraBlock / 64>(&A.cnt->qcount[0], act, wc, &bb);
         if (act) {
             int local = i - I.pix_base;
             int px = local % I.cam.w, py = local / I.cam.w;
@@ -2616,7 +2622,8 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
     if (record)
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_of((int64_t)npix * L * 6, 256)), dim3(256), 0, s, (int32_t*)c->recs, 0,
                            (int64_t)npix * L * 6);
-    TIMED(K_CAMERA, hipLaunchKernelGGL(k_camera, dim3(grid_of(npix, 256)), dim3(256), 0, s, A, c->q[0]));
+    TIMED(K_CAMERA, hipLaunchKernelGGL(k_camera, dim3(grid_of(npix, kCameraBlock)), dim3(kCameraBlock), 0, s, A,
+                                       c->q[0]));
     // pass 1
     for (int k = 1; k <= L; ++k) {
         int in = (k - 1) & 1, out = k & 1;

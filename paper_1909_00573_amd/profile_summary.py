@@ -15,9 +15,13 @@ from collections import defaultdict
 
 
 def short_name(name):
+    """Kernel name without namespace and arguments; template arguments are
+    kept (without spaces) so that instantiations stay apart."""
     name = re.sub(r"\(.*", "", name)
-    name = re.sub(r"<.*?>", "", name)
-    return name.split("::")[-1].strip()
+    name = re.sub(r"^void ", "", name.strip())
+    m = re.match(r"(.*?)(<.*>)?$", name)
+    base, targs = m.group(1), (m.group(2) or "")
+    return base.split("::")[-1].strip() + targs.replace(" ", "")
 
 
 def stats(path):
