@@ -1780,6 +1780,10 @@ struct neb_ctx_s {
     // per-iteration pools
     PathQ q[2]{};
     PhotonQ pq[2]{};
+    // a second stream (default priority) for the merge-grid build, forked
+    // after shading and joined before the photon bounces
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     float4 *sq0 = nullptr, *sq1 = nullptr;  // NEE shadow rays: (origin, vertex), (direction, tag)
     float* sqt = nullptr;                   // their tmax
     int32_t* svis = nullptr;                // per vertex: 1 if its shadow ray reached the light
@@ -1947,6 +1951,9 @@ static void destroy_ctx(neb_ctx c) {
     drop_graph(c);
     mlp_free(c->mlp);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     free_list(c->scene_allocs);
     free_list(c->allocs);
     for (auto& e : c->prof_ev) (void)hipEventDestroy(e);
@@ -2634,6 +2641,32 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
                                           &cnt->n_vertices, c->ev0, c->ev1, &cnt->n_events, c->slots,
                                           record ? c->recs : (neb_path_record*)nullptr));
     }
+    // bounces: NEB photons make at most maxlen - 2 segments, light photons maxlen - 1
+    const bool lp = c->n_lp > 0;
+    const int rounds = std::max((c->photons && L >= 3) ? L - 2 : 0, lp ? L - 1 : 0);
+    // The merge grid needs only this iteration's view vertices: it is built on
+    // the side stream while the octree deposits, the density and NEE (latency
+    // bound, the chip half idle) run here.
+    if (rounds > 0) {
+        if (!c->side) {
+            HIP_TRY(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+            HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+            HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+        }
+        HIP_TRY(hipEventRecord(c->ev_fork, s));
+        HIP_TRY(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+        hipStream_t g = c->side;
+        int64_t n = (int64_t)c->G.T * c->G.D + 1;
+        prof_begin(c, K_GRID_BUILD, g);
+        hipLaunchKernelGGL(k_grid_count, dim3(grid_of(vcap, 256)), dim3(256), 0, g, (const neb_material*)c->view.mats,
+                           (const SceneInfo*)c->sc_dev, c->V, (const int32_t*)&cnt->n_vertices, c->G);
+        scan_exclusive(c->G.count, c->G.start, n, c->G.sums, g, true);
+        hipLaunchKernelGGL(k_grid_scatter, dim3(grid_of(vcap, 256)), dim3(256), 0, g,
+                           (const neb_material*)c->view.mats, (const SceneInfo*)c->sc_dev, c->V,
+                           (const int32_t*)&cnt->n_vertices, c->G);
+        prof_end(c, g);
+        HIP_TRY(hipEventRecord(c->ev_join, g));
+    }
     // deposits of this iteration's NEE vertices into their scenes' octrees
     const bool set_mode = c->density_mode == NEB_DENSITY_RADIUS || c->density_mode == NEB_DENSITY_KNN;
     // without NEB photons rho enters nothing (flux, MIS), so the density
@@ -2705,7 +2738,6 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
         prof_end(c, s);
     }
     // light photons take the first entries of photon queue 0, the NEB photons follow
-    const bool lp = c->n_lp > 0;
     if (lp)
         TIMED(K_LIGHT_PHOTON, hipLaunchKernelGGL(k_lp_emit, dim3(grid_of(c->n_lp, 256)), dim3(256), 0, s, A,
                                                  c->pq[0], &cnt->pcount[0]));
@@ -2713,20 +2745,10 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
     if (c->recycle)
         TIMED(K_NEE_RECYCLE, hipLaunchKernelGGL(k_nee_recycle, dim3(grid_of(vcap, 256)), dim3(256), 0, s, A, c->V,
                                                 (const int32_t*)&cnt->n_vertices, im));
-    // bounces: NEB photons make at most maxlen - 2 segments, light photons maxlen - 1
-    const int rounds = std::max((c->photons && L >= 3) ? L - 2 : 0, lp ? L - 1 : 0);
     const int64_t pcap = c->pcap;
     if (rounds > 0) {
-        // merge grid over this iteration's view vertices
-        int64_t n = (int64_t)c->G.T * c->G.D + 1;
-        prof_begin(c, K_GRID_BUILD, s);
-        hipLaunchKernelGGL(k_grid_count, dim3(grid_of(vcap, 256)), dim3(256), 0, s, (const neb_material*)c->view.mats,
-                           (const SceneInfo*)c->sc_dev, c->V, (const int32_t*)&cnt->n_vertices, c->G);
-        scan_exclusive(c->G.count, c->G.start, n, c->G.sums, s, true);
-        hipLaunchKernelGGL(k_grid_scatter, dim3(grid_of(vcap, 256)), dim3(256), 0, s,
-                           (const neb_material*)c->view.mats, (const SceneInfo*)c->sc_dev, c->V,
-                           (const int32_t*)&cnt->n_vertices, c->G);
-        prof_end(c, s);
+        // the merge grid of the side stream
+        HIP_TRY(hipStreamWaitEvent(s, c->ev_join, 0));
         const int pgrid = c->cfg.photon_bpc > 0 ? std::max(1, std::min(grid_of(pcap, 64, 1 << 20), c->cus * c->cfg.photon_bpc))
                                                 : grid_of(pcap, 256);
         for (int j = 1; j <= rounds; ++j) {
