@@ -1780,10 +1780,11 @@ struct neb_ctx_s {
     // per-iteration pools
     PathQ q[2]{};
     PhotonQ pq[2]{};
-    // a second stream (default priority) for the merge-grid build, forked
-    // after shading and joined before the photon bounces
+    // a second stream (default priority) for NEE's shadow rays and the
+    // merge-grid build, forked after shading; joined before NEE's
+    // contributions (ev_nee) and before the photon bounces (ev_join)
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_nee = nullptr, ev_join = nullptr;
     float4 *sq0 = nullptr, *sq1 = nullptr;  // NEE shadow rays: (origin, vertex), (direction, tag)
     float* sqt = nullptr;                   // their tmax
     int32_t* svis = nullptr;                // per vertex: 1 if its shadow ray reached the light
@@ -1954,6 +1955,7 @@ static void destroy_ctx(neb_ctx c) {
     if (c->side) (void)hipStreamDestroy(c->side);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->ev_nee) (void)hipEventDestroy(c->ev_nee);
     free_list(c->scene_allocs);
     free_list(c->allocs);
     for (auto& e : c->prof_ev) (void)hipEventDestroy(e);
@@ -2599,15 +2601,22 @@ static void extend(neb_ctx c, int64_t cap, const float4* org, const float4* dir,
     else launch_extend<64>(c, cap, org, dir, count, next, rays, B, s);
 }
 
-static void nee(neb_ctx c, const RenderArgs& A, Images im, hipStream_t s) {
+// NEE, first part: light samples and the shadow-ray queue, then the shadow
+// rays (they need the vertices only, not rho)
+static void nee_rays(neb_ctx c, const RenderArgs& A, hipStream_t s) {
     const int grid = grid_of(c->vcap, kNeeBlock);
     hipLaunchKernelGGL(k_nee_rays, dim3(grid), dim3(kNeeBlock), 0, s, A, c->V, (const int32_t*)&c->cnt->n_vertices,
                        c->sq0, c->sq1, c->sqt, &c->cnt->n_shadow);
     if (c->cfg.stack == 32) launch_shadow<32>(c, s);
     else if (c->cfg.stack == 48) launch_shadow<48>(c, s);
     else launch_shadow<64>(c, s);
-    hipLaunchKernelGGL(k_nee_finish, dim3(grid), dim3(kNeeBlock), 0, s, A, c->V, (const int32_t*)&c->cnt->n_vertices,
-                       (const int32_t*)c->svis, im, c->pq[0], &c->cnt->pcount[0]);
+}
+
+// NEE, second part: contributions and NEB photons (needs rho)
+static void nee_finish(neb_ctx c, const RenderArgs& A, Images im, hipStream_t s) {
+    hipLaunchKernelGGL(k_nee_finish, dim3(grid_of(c->vcap, kNeeBlock)), dim3(kNeeBlock), 0, s, A, c->V,
+                       (const int32_t*)&c->cnt->n_vertices, (const int32_t*)c->svis, im, c->pq[0],
+                       &c->cnt->pcount[0]);
 }
 
 // Enqueues one iteration.  Every argument is fixed for the context (the
@@ -2644,17 +2653,22 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
     // bounces: NEB photons make at most maxlen - 2 segments, light photons maxlen - 1
     const bool lp = c->n_lp > 0;
     const int rounds = std::max((c->photons && L >= 3) ? L - 2 : 0, lp ? L - 1 : 0);
-    // The merge grid needs only this iteration's view vertices: it is built on
-    // the side stream while the octree deposits, the density and NEE (latency
-    // bound, the chip half idle) run here.
+    // NEE's shadow rays and the merge grid need only this iteration's
+    // vertices: they run on the side stream while the octree deposits and
+    // the density (latency bound, the chip half idle) run here.
+    if (!c->side) {
+        HIP_TRY(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&c->ev_nee, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    }
+    HIP_TRY(hipEventRecord(c->ev_fork, s));
+    HIP_TRY(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+    prof_begin(c, K_NEE, c->side);
+    nee_rays(c, A, c->side);
+    prof_end(c, c->side);
+    HIP_TRY(hipEventRecord(c->ev_nee, c->side));
     if (rounds > 0) {
-        if (!c->side) {
-            HIP_TRY(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
-            HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-            HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
-        }
-        HIP_TRY(hipEventRecord(c->ev_fork, s));
-        HIP_TRY(hipStreamWaitEvent(c->side, c->ev_fork, 0));
         hipStream_t g = c->side;
         int64_t n = (int64_t)c->G.T * c->G.D + 1;
         prof_begin(c, K_GRID_BUILD, g);
@@ -2741,7 +2755,8 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
     if (lp)
         TIMED(K_LIGHT_PHOTON, hipLaunchKernelGGL(k_lp_emit, dim3(grid_of(c->n_lp, 256)), dim3(256), 0, s, A,
                                                  c->pq[0], &cnt->pcount[0]));
-    TIMED(K_NEE, nee(c, A, im, s));
+    HIP_TRY(hipStreamWaitEvent(s, c->ev_nee, 0));
+    TIMED(K_NEE, nee_finish(c, A, im, s));
     if (c->recycle)
         TIMED(K_NEE_RECYCLE, hipLaunchKernelGGL(k_nee_recycle, dim3(grid_of(vcap, 256)), dim3(256), 0, s, A, c->V,
                                                 (const int32_t*)&cnt->n_vertices, im));
