@@ -40,11 +40,14 @@ def algorithmic_bytes(stats, name, npix, vertices):
     re-reads are excluded: this is the algorithmic minimum."""
     s = stats
     if name == "photon_merge":
-        # photon state + U + hit in, next state out, two cell bounds per cell,
-        # one packed (pos, id) per candidate, three vertex words + pixel and
-        # a 3-float image atomic (read + write) per accepted merge
-        return (s["photon_items"] * (48 + 4 + 8) + s["photon_continued"] * 52 + s["grid_cells"] * 8 +
+        # photon state + U + hit in, two cell bounds per cell, one packed
+        # (pos, id) per candidate, three vertex words + pixel and a 3-float
+        # image atomic (read + write) per accepted merge
+        return (s["photon_items"] * (48 + 4 + 8) + s["grid_cells"] * 8 +
                 s["candidates"] * 16 + s["merges"] * (52 + 24))  # a merge reads 52 of its 64-byte record
+    if name == "photon_scatter":
+        # photon state + U + hit + the hit triangle's normal word in, next state out
+        return s["photon_items"] * (48 + 4 + 8 + 16) + s["photon_continued"] * 52
     if name == "shade":
         rays = s["rays_camera"]
         return rays * (64 + 8) + vertices * 64 + s["continued_camera"] * 64 + s["events"] * 32
@@ -60,6 +63,47 @@ def algorithmic_bytes(stats, name, npix, vertices):
     if name == "finalize":
         return s["events"] * (32 + 4 + 24)
     return None
+
+
+def kernel_pass(R, stream, steps, npix):
+    """Render `steps` iterations after a reset with an event pair around
+    each launch (on the stream it runs on); returns the roofline of the
+    kernel with the most time and every kernel's totals."""
+    import torch
+    R.reset()
+    torch.cuda.synchronize()
+    s1 = R.stats()
+    R.profile_kernels(True)
+    R.render(steps, stream=stream)
+    torch.cuda.synchronize()
+    prof = R.kernel_profile()
+    R.profile_kernels(False)
+    s2 = R.stats()
+    d = {k: s2[k] - s1[k] for k in s2 if isinstance(s2[k], int)}
+    d["rays_camera"] = d["camera_rays"]
+    d["continued_camera"] = d["camera_rays"] - npix * steps  # every ray after the first bounce
+    vertices = d["vertices"]
+    kernels, best, roof = {}, None, None
+    for name, v in prof.items():
+        nb = algorithmic_bytes(d, name, npix, vertices)
+        kernels[name] = {"launches": v["launches"], "ms": round(v["total_ms"], 3),
+                         "avg_us": round(1e3 * v["total_ms"] / max(1, v["launches"]), 2)}
+        if nb is not None:
+            kernels[name]["algorithmic_GBs"] = round(nb / (v["total_ms"] * 1e-3) / 1e9, 1)
+        if best is None or v["total_ms"] > prof[best]["total_ms"]:
+            best = name
+    nb = algorithmic_bytes(d, best, npix, vertices)
+    if nb is not None:
+        v = prof[best]
+        per_launch = nb / v["launches"]
+        achieved = per_launch / (v["total_ms"] * 1e-3 / v["launches"]) / 1e9
+        traffic = committed_traffic(best)
+        roof = {"kernel": best, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else int(traffic),
+                "algorithmic_bytes_per_launch": int(per_launch),
+                "avg_launch_us": round(1e3 * v["total_ms"] / v["launches"], 2)}
+    return roof, kernels
 
 
 def cpu_baseline(target_s=11.0):
@@ -350,6 +394,8 @@ def main():
     ap.add_argument("--no-quality", "--no-learned", dest="no_quality", action="store_true",
                     help="skip the error-against-time comparison (plain, light photons, learned density)")
     ap.add_argument("--no-city", action="store_true", help="skip the city-block throughput run")
+    ap.add_argument("--no-serialized", action="store_true",
+                    help="skip the per-kernel pass with every launch on one stream")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the launch shapes on this workload first (default: the library's defaults)")
     ap.add_argument("--launch-config", default=None,
@@ -405,41 +451,19 @@ def main():
     photons = st["photons"] - s0["photons"]
 
     # per-kernel pass: same steps again with an event pair around each launch
-    roof, kernels = None, {}
+    roof, kernels, roof_ser, kernels_ser = None, {}, None, {}
     if not args.no_profile:
-        R.reset()
-        torch.cuda.synchronize()
-        s1 = R.stats()
-        R.profile_kernels(True)
-        R.render(args.steps, stream=stream)
-        torch.cuda.synchronize()
-        prof = R.kernel_profile()
-        R.profile_kernels(False)
-        s2 = R.stats()
-        d = {k: s2[k] - s1[k] for k in s2 if isinstance(s2[k], int)}
-        d["rays_camera"] = d["camera_rays"]
-        d["continued_camera"] = d["camera_rays"] - npix * args.steps  # every ray after the first bounce
-        vertices = d["vertices"]
-        best = None
-        for name, v in prof.items():
-            nb = algorithmic_bytes(d, name, npix, vertices)
-            kernels[name] = {"launches": v["launches"], "ms": round(v["total_ms"], 3),
-                             "avg_us": round(1e3 * v["total_ms"] / max(1, v["launches"]), 2)}
-            if nb is not None:
-                kernels[name]["algorithmic_GBs"] = round(nb / (v["total_ms"] * 1e-3) / 1e9, 1)
-            if best is None or v["total_ms"] > prof[best]["total_ms"]:
-                best = name
-        nb = algorithmic_bytes(d, best, npix, vertices)
-        if nb is not None:
-            v = prof[best]
-            per_launch = nb / v["launches"]
-            achieved = per_launch / (v["total_ms"] * 1e-3 / v["launches"]) / 1e9
-            traffic = committed_traffic(best)
-            roof = {"kernel": best, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": None if traffic is None else int(traffic),
-                    "algorithmic_bytes_per_launch": int(per_launch),
-                    "avg_launch_us": round(1e3 * v["total_ms"] / v["launches"], 2)}
+        roof, kernels = kernel_pass(R, stream, args.steps, npix)
+    if not args.no_profile and not args.no_serialized:
+        # the same once more with every launch on one stream: each kernel's
+        # duration alone (the roofline above is the kernel as it runs,
+        # beside the launches that overlap it)
+        cfg = R.launch_config()
+        R.set_launch_config(cfg["bvh_stack"], cfg["trace_blocks_per_cu"], cfg["photon_blocks_per_cu"],
+                            cfg["photon_order"], cfg["nee_blocks_per_cu"], concurrent=0)
+        roof_ser, kernels_ser = kernel_pass(R, stream, args.steps, npix)
+        R.set_launch_config(cfg["bvh_stack"], cfg["trace_blocks_per_cu"], cfg["photon_blocks_per_cu"],
+                            cfg["photon_order"], cfg["nee_blocks_per_cu"], concurrent=cfg["concurrent"])
 
     out = {
         "metric": METRIC, "value": round(paths / sec, 1), "unit": "camera paths/s", "n_gpus": 1,
@@ -458,6 +482,7 @@ def main():
                           ("vertices", "photons", "photon_segments", "merges", "candidates", "grid_cells",
                            "camera_rays", "shadow_rays", "bvh_nodes", "bvh_tris")},
         "roofline": roof, "kernels": kernels, "launch_config": launch_cfg,
+        "roofline_serialized": roof_ser, "kernels_serialized": kernels_ser,
     }
     R.close()
     if not args.no_city:

@@ -102,7 +102,7 @@ typedef struct {
  * them; results do not depend on them).  Defaults: the shallowest stack
  * that holds every BVH, 16 resident closest-hit and 16 NEE blocks per CU
  * (at most as many as the LDS holds for the stack), 8 photon-merge blocks
- * per CU, queue order. */
+ * per CU, queue order, concurrent. */
 typedef struct {
     int32_t bvh_stack;            /* LDS traversal stack entries per lane: 32, 48 or 64; must
                                      exceed the depth of every scene's BVH */
@@ -114,6 +114,10 @@ typedef struct {
                                      0 = one block per 256 queue slots */
     int32_t photon_order;         /* 1: merge photons in the spatial (Morton) order of their hits,
                                      each XCD taking a contiguous share; 0: queue order */
+    int32_t concurrent;           /* 1 (default): NEE's shadow rays and the merge grid run on a
+                                     second stream beside the octree deposits and the density, each
+                                     bounce's merges beside the next bounce's closest hits; 0: every
+                                     launch on the caller's stream, one after another */
 } neb_launch_config;
 
 /* One material per entry; emission is radiance leaving the front side of

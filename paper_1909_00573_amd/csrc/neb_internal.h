@@ -123,6 +123,7 @@ struct alignas(128) WorkLine {
 struct Counters {
     alignas(128) int32_t qcount[2];  // camera path queues
     alignas(128) int32_t pcount[2];  // photon queues
+    alignas(128) int32_t mcount[2];  // photon queue lengths for the merge launches (copied by the scatter)
     alignas(128) int32_t n_vertices;
     alignas(128) int32_t n_events;
     alignas(128) int32_t n_shadow;   // NEE shadow rays queued this iteration

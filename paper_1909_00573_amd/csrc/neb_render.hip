@@ -1297,8 +1297,7 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const int32_t* __restrict__
 // takes one contiguous eighth of the ordered photons: neighbouring photons
 // then share that XCD's L2 for their cells and candidates.
 __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const int32_t* count_in, const int2* hits,
-                                               PhotonQ out, int32_t* count_out, Grid G, Images img,
-                                               const int32_t* __restrict__ order) {
+                                               Grid G, Images img, const int32_t* __restrict__ order) {
     __shared__ int2 queue[128];
     __shared__ float4 tp[64][2];  // per lane's photon: (-d, X), (Phi / (pi r^2), deepest mergeable depth | light bit)
     __shared__ float te[64];      // per lane's photon: weight of its own technique in the MIS denominator
@@ -1315,7 +1314,7 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
     const SceneView& S = A.S;
     Counters* cnt = A.cnt;
     const int iter = cnt->iter;
-    unsigned segs = 0, merges = 0, items = 0, cont = 0, cells = 0, cands = 0;
+    unsigned segs = 0, merges = 0, items = 0, cells = 0, cands = 0;
     int qn = 0;  // queue length, identical in every lane
 
     // Evaluates up to 64 queued pairs, one per lane, then adds them to the
@@ -1530,37 +1529,84 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
             flush(qn);
             qn = 0;
         }
-        // scatter
-        bool go = false;
-        Sample s;
-        s.ev = 0;
-        if (hit && j < I.L - 2 && !mat_black(my)) {
-            U4 u = uniforms(I.k0, I.k1, (uint32_t)(opix - I.pix_base), (uint32_t)iter, (uint32_t)(16 * odepth + j),
-                            kTagPhoton);
-            s = bsdf_sample(my, ny, -d, u);
-            go = s.ev != 0;
-        }
-        int slot = wave_reserve(count_out, go);
-        cont += go;
-        if (go) {
-            f3 wd = -d;
-            float prev = bsdf_pdf(my, ny, s.dir, wd);
-            float Un = (mat_delta(my.type) ? 0.f : ef) + prev * X;
-            float hp = fabsf(dot3(ny, s.dir)) / s.pdf;
-            out.p0[slot] = f4(offset_origin(y, ny, s.dir, I.eps), ibits(opix));
-            out.p1[slot] = f4(s.dir, ibits(make_tag(16 * odepth + j + 1, sid)));
-            out.p2[slot] = f4(xyz(b2) * s.w, hp);
-            out.pu[slot] = Un;
-        }
         __syncthreads();
     }
     StatLine& L = stat_line(cnt);
     wave_add_u64(&L.photon_segments, segs);
     wave_add_u64(&L.merges, merges);
     wave_add_u64(&L.photon_items, items);
-    wave_add_u64(&L.photon_continued, cont);
     wave_add_u64(&L.grid_cells, cells);
     wave_add_u64(&L.candidates, cands);
+}
+
+// The scatter of a photon bounce (Sec. 3.2): every photon that hit a
+// surface below its last bounce samples the BSDF there and continues; its
+// factor U gains the term of the hit vertex.  A launch of its own, so that
+// the merges of the bounce (k_photon, which reads the same queue and hits)
+// can run beside the next bounce's closest-hit launch.  Slots are reserved
+// once per block; count_copy receives the input count for the merge launch
+// (the closest-hit launch that follows clears the count it read).
+constexpr int kScatterBlock = 1024;
+__global__ void __launch_bounds__(kScatterBlock) k_pscatter(RenderArgs A, PhotonQ in, const int32_t* count_in,
+                                                            const int2* __restrict__ hits, PhotonQ out,
+                                                            int32_t* count_out, int32_t* count_copy) {
+    __shared__ int wc[kScatterBlock / 64];
+    __shared__ int bb;
+    const int n = *count_in;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *count_copy = n;
+    const SceneView& S = A.S;
+    Counters* cnt = A.cnt;
+    const int iter = cnt->iter;
+    unsigned cont = 0;
+    for (int base = blockIdx.x * kScatterBlock; base < n; base += gridDim.x * kScatterBlock) {
+        const int i = base + threadIdx.x;
+        bool go = false;
+        float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+        float Un = 0.f;
+        const int2 h = i < n ? hits[i] : make_int2(0, -1);
+        if (h.y >= 0) {
+            const float4 b0 = in.p0[i], b1 = in.p1[i], b2 = in.p2[i];
+            const float U = in.pu[i];
+            const int tg = fbits(b1.w);
+            const int code = tag_depth(tg), sid = tag_scene(tg);
+            const int j = code & 15, odepth = code >> 4, opix = fbits(b0.w);
+            const SceneInfo& I = A.sc[sid];
+            const f3 d = xyz(b1);
+            const f3 y = xyz(b0) + d * ibits(h.x);
+            const float4 pn = S.prim_n[h.y];
+            const f3 ny = xyz(pn);
+            const neb_material& my = S.mats[fbits(pn.w)];
+            if (j < I.L - 2 && !mat_black(my)) {
+                // a light photon at its first hit brings the weight of its own
+                // technique in p2.w and X in U; every other photon has weight 1
+                // and X = h U
+                const bool lfirst = code == 0;
+                const float hh = b2.w / fabsf(dot3(ny, d));
+                const float X = lfirst ? U : hh * U, ef = lfirst ? b2.w : 1.0f;
+                U4 u = uniforms(I.k0, I.k1, (uint32_t)(opix - I.pix_base), (uint32_t)iter, (uint32_t)(16 * odepth + j),
+                                kTagPhoton);
+                Sample s = bsdf_sample(my, ny, -d, u);
+                go = s.ev != 0;
+                if (go) {
+                    const float prev = bsdf_pdf(my, ny, s.dir, -d);
+                    Un = (mat_delta(my.type) ? 0.f : ef) + prev * X;
+                    const float hp = fabsf(dot3(ny, s.dir)) / s.pdf;
+                    r0 = f4(offset_origin(y, ny, s.dir, I.eps), ibits(opix));
+                    r1 = f4(s.dir, ibits(make_tag(16 * odepth + j + 1, sid)));
+                    r2 = f4(xyz(b2) * s.w, hp);
+                }
+            }
+        }
+        const int slot = block_reserve<kScatterBlock / 64>(count_out, go, wc, &bb);
+        if (go) {
+            ++cont;
+            out.p0[slot] = r0;
+            out.p1[slot] = r1;
+            out.p2[slot] = r2;
+            out.pu[slot] = Un;
+        }
+    }
+    wave_add_u64(&stat_line(cnt).photon_continued, cont);
 }
 
 // ---------------------------------------------------------------------------
@@ -1746,6 +1792,7 @@ struct LaunchCfg {
     int nee_bpc = 16;      // NEE (shadow-ray) blocks per CU, same conventions
     int photon_bpc = 8;    // photon-merge blocks (one wave each) per CU; 0 = one block per 256 queue slots
     int photon_order = 0;  // merge photons in the spatial order of their hits
+    int concurrent = 1;    // second stream for the work that can run beside other work
 };
 
 struct neb_ctx_s {
@@ -1784,7 +1831,8 @@ struct neb_ctx_s {
     // merge-grid build, forked after shading; joined before NEE's
     // contributions (ev_nee) and before the photon bounces (ev_join)
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_nee = nullptr, ev_join = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_nee = nullptr, ev_join = nullptr, ev_merge = nullptr;
+    int2* hits2 = nullptr;  // the photon bounces alternate between hits and hits2
     float4 *sq0 = nullptr, *sq1 = nullptr;  // NEE shadow rays: (origin, vertex), (direction, tag)
     float* sqt = nullptr;                   // their tmax
     int32_t* svis = nullptr;                // per vertex: 1 if its shadow ray reached the light
@@ -1832,11 +1880,13 @@ struct neb_ctx_s {
 
 enum KernelId {
     K_CAMERA, K_EXTEND_CAMERA, K_SHADE, K_OCTREE_INSERT, K_DENSITY, K_NEE, K_GRID_BUILD, K_EXTEND_PHOTON, K_PHOTON,
-    K_FINALIZE, K_MLP_TRAIN, K_PHOTON_ORDER, K_MISC, K_LIGHT_PHOTON, K_DENSITY_GRID, K_NEE_RECYCLE, K_COUNT
+    K_FINALIZE, K_MLP_TRAIN, K_PHOTON_ORDER, K_MISC, K_LIGHT_PHOTON, K_DENSITY_GRID, K_NEE_RECYCLE, K_PHOTON_SCATTER,
+    K_COUNT
 };
 static const char* kKernelNames[K_COUNT] = {"camera", "extend_camera", "shade", "octree_insert", "density", "nee",
                                             "grid_build", "extend_photon", "photon_merge", "finalize", "mlp_train",
-                                            "photon_order", "misc", "light_photon", "density_grid", "nee_recycle"};
+                                            "photon_order", "misc", "light_photon", "density_grid", "nee_recycle",
+                                            "photon_scatter"};
 
 static void prof_harvest(neb_ctx c) {
     if (c->prof_used == 0) return;
@@ -1956,6 +2006,7 @@ static void destroy_ctx(neb_ctx c) {
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->ev_nee) (void)hipEventDestroy(c->ev_nee);
+    if (c->ev_merge) (void)hipEventDestroy(c->ev_merge);
     free_list(c->scene_allocs);
     free_list(c->allocs);
     for (auto& e : c->prof_ev) (void)hipEventDestroy(e);
@@ -2109,6 +2160,7 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
         ALLOC(c->pq[b].pu, c->pcap);
     }
     ALLOC(c->hits, std::max<int64_t>(npix, c->pcap));
+    ALLOC(c->hits2, c->pcap);
     ALLOC(c->sq0, vcap);
     ALLOC(c->sq1, vcap);
     ALLOC(c->sqt, vcap);
@@ -2570,9 +2622,9 @@ static RenderArgs make_args(neb_ctx c) {
 
 template <int kStack>
 static void launch_extend(neb_ctx c, int64_t cap, const float4* org, const float4* dir, int32_t* count, int32_t* next,
-                          int rays, const HitBins& B, hipStream_t s) {
+                          int rays, const HitBins& B, int2* hits, hipStream_t s) {
     hipLaunchKernelGGL((k_extend<kStack, false>), dim3(trace_grid(c, cap, c->cfg.trace_bpc)), dim3(kTraceBlock), 0, s,
-                       c->view, (const SceneInfo*)c->sc_dev, org, dir, (const int32_t*)count, next, c->hits, rays,
+                       c->view, (const SceneInfo*)c->sc_dev, org, dir, (const int32_t*)count, next, hits, rays,
                        c->cnt, B, (const float*)nullptr, (int32_t*)nullptr);
 }
 
@@ -2585,9 +2637,10 @@ static void launch_shadow(neb_ctx c, hipStream_t s) {
                        (const float*)c->sqt, c->svis);
 }
 
-// rays: 0 counts camera rays, 1 photon rays
+// rays: 0 counts camera rays, 1 photon rays; hits: c->hits if null
 static void extend(neb_ctx c, int64_t cap, const float4* org, const float4* dir, int32_t* count, int32_t* next,
-                   int rays, hipStream_t s, bool bin = false) {
+                   int rays, hipStream_t s, bool bin = false, int2* hits = nullptr) {
+    if (!hits) hits = c->hits;
     HitBins B{};
     if (bin) {
         B.bin = c->pbin;
@@ -2596,9 +2649,9 @@ static void extend(neb_ctx c, int64_t cap, const float4* org, const float4* dir,
         B.bits = c->bin_bits;
         B.n_bins = c->n_bins;
     }
-    if (c->cfg.stack == 32) launch_extend<32>(c, cap, org, dir, count, next, rays, B, s);
-    else if (c->cfg.stack == 48) launch_extend<48>(c, cap, org, dir, count, next, rays, B, s);
-    else launch_extend<64>(c, cap, org, dir, count, next, rays, B, s);
+    if (c->cfg.stack == 32) launch_extend<32>(c, cap, org, dir, count, next, rays, B, hits, s);
+    else if (c->cfg.stack == 48) launch_extend<48>(c, cap, org, dir, count, next, rays, B, hits, s);
+    else launch_extend<64>(c, cap, org, dir, count, next, rays, B, hits, s);
 }
 
 // NEE, first part: light samples and the shadow-ray queue, then the shadow
@@ -2661,15 +2714,18 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
         HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
         HIP_TRY(hipEventCreateWithFlags(&c->ev_nee, hipEventDisableTiming));
         HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&c->ev_merge, hipEventDisableTiming));
     }
+    // the second stream, or the caller's when the launches are serialised
+    hipStream_t t = c->cfg.concurrent ? c->side : s;
     HIP_TRY(hipEventRecord(c->ev_fork, s));
-    HIP_TRY(hipStreamWaitEvent(c->side, c->ev_fork, 0));
-    prof_begin(c, K_NEE, c->side);
-    nee_rays(c, A, c->side);
-    prof_end(c, c->side);
-    HIP_TRY(hipEventRecord(c->ev_nee, c->side));
+    HIP_TRY(hipStreamWaitEvent(t, c->ev_fork, 0));
+    prof_begin(c, K_NEE, t);
+    nee_rays(c, A, t);
+    prof_end(c, t);
+    HIP_TRY(hipEventRecord(c->ev_nee, t));
     if (rounds > 0) {
-        hipStream_t g = c->side;
+        hipStream_t g = t;
         int64_t n = (int64_t)c->G.T * c->G.D + 1;
         prof_begin(c, K_GRID_BUILD, g);
         hipLaunchKernelGGL(k_grid_count, dim3(grid_of(vcap, 256)), dim3(256), 0, g, (const neb_material*)c->view.mats,
@@ -2768,14 +2824,18 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
                                                 : grid_of(pcap, 256);
         for (int j = 1; j <= rounds; ++j) {
             int in = (j - 1) & 1, out = j & 1;
+            int2* hj = (j & 1) ? c->hits : c->hits2;  // the merges of bounce j - 1 read the other one
             const bool ordered = c->cfg.photon_order != 0;
             TIMED(K_EXTEND_PHOTON, extend(c, pcap, c->pq[in].p0, c->pq[in].p1, &cnt->pcount[in], &cnt->pcount[out],
-                                          1, s, ordered));
+                                          1, s, ordered, hj));
             if (j == 1 && lp)
                 TIMED(K_LIGHT_PHOTON,
-                      hipLaunchKernelGGL(k_lp_first, dim3(grid_of(c->n_lp, 256)), dim3(256), 0, s, A, c->pq[0], c->hits,
+                      hipLaunchKernelGGL(k_lp_first, dim3(grid_of(c->n_lp, 256)), dim3(256), 0, s, A, c->pq[0], hj,
                                          (const int32_t*)c->oct_nodes, (const OctState*)c->oct_states,
                                          (const OctParams*)c->oct_prm_dev, (const OctDyn*)c->oct_dyn));
+            // the merges of bounce j - 1 read queue `out`, which this bounce's
+            // scatter writes, and the photon order
+            if (j > 1) HIP_TRY(hipStreamWaitEvent(s, c->ev_merge, 0));
             if (ordered) {
                 // photons in the spatial order of their hits
                 prof_begin(c, K_PHOTON_ORDER, s);
@@ -2784,11 +2844,22 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
                                    (const int32_t*)&cnt->pcount[in], c->bcount, (const int32_t*)c->bstart, c->porder);
                 prof_end(c, s);
             }
-            TIMED(K_PHOTON, hipLaunchKernelGGL(k_photon, dim3(pgrid), dim3(64), 0, s, A, c->pq[in],
-                                               (const int32_t*)&cnt->pcount[in], (const int2*)c->hits, c->pq[out],
-                                               &cnt->pcount[out], c->G, im,
-                                               ordered ? (const int32_t*)c->porder : (const int32_t*)nullptr));
+            TIMED(K_PHOTON_SCATTER,
+                  hipLaunchKernelGGL(k_pscatter, dim3(grid_of(pcap, kScatterBlock)), dim3(kScatterBlock), 0, s, A,
+                                     c->pq[in], (const int32_t*)&cnt->pcount[in], (const int2*)hj, c->pq[out],
+                                     &cnt->pcount[out], &cnt->mcount[j & 1]));
+            // the merges of bounce j on the side stream, beside the closest
+            // hits of bounce j + 1
+            HIP_TRY(hipEventRecord(c->ev_fork, s));
+            HIP_TRY(hipStreamWaitEvent(t, c->ev_fork, 0));
+            prof_begin(c, K_PHOTON, t);
+            hipLaunchKernelGGL(k_photon, dim3(pgrid), dim3(64), 0, t, A, c->pq[in],
+                               (const int32_t*)&cnt->mcount[j & 1], (const int2*)hj, c->G, im,
+                               ordered ? (const int32_t*)c->porder : (const int32_t*)nullptr);
+            prof_end(c, t);
+            HIP_TRY(hipEventRecord(c->ev_merge, t));
         }
+        HIP_TRY(hipStreamWaitEvent(s, c->ev_merge, 0));
     }
     // pass 3
     TIMED(K_FINALIZE, hipLaunchKernelGGL(k_finalize, dim3(grid_of(c->ecap, 256)), dim3(256), 0, s, A,
@@ -3203,11 +3274,13 @@ static neb_status apply_config(neb_ctx c, const neb_launch_config& cfg) {
     if (cfg.photon_blocks_per_cu < 0 || cfg.photon_blocks_per_cu > 64)
         return fail(NEB_ERR_INVALID_ARG, "photon_blocks_per_cu out of range (0..64)");
     if (cfg.photon_order != 0 && cfg.photon_order != 1) return fail(NEB_ERR_INVALID_ARG, "photon_order must be 0 or 1");
+    if (cfg.concurrent != 0 && cfg.concurrent != 1) return fail(NEB_ERR_INVALID_ARG, "concurrent must be 0 or 1");
     c->cfg.stack = cfg.bvh_stack;
     c->cfg.trace_bpc = cfg.trace_blocks_per_cu;
     c->cfg.nee_bpc = cfg.nee_blocks_per_cu;
     c->cfg.photon_bpc = cfg.photon_blocks_per_cu;
     c->cfg.photon_order = cfg.photon_order;
+    c->cfg.concurrent = cfg.concurrent;
     drop_graph(c);
     return NEB_OK;
 }
@@ -3225,6 +3298,7 @@ extern "C" neb_status neb_get_launch_config(neb_ctx c, neb_launch_config* cfg) {
     cfg->nee_blocks_per_cu = c->cfg.nee_bpc < 0 ? maxb : std::min(c->cfg.nee_bpc, maxb);
     cfg->photon_blocks_per_cu = c->cfg.photon_bpc;
     cfg->photon_order = c->cfg.photon_order;
+    cfg->concurrent = c->cfg.concurrent;
     return NEB_OK;
 }
 
@@ -3258,7 +3332,7 @@ extern "C" neb_status neb_autotune(neb_ctx c, int32_t trial_iterations, void* st
     bool was_on = c->prof_on;
     c->prof_on = true;
     LaunchCfg keep = c->cfg;
-    neb_launch_config best{c->cfg.stack, -1, -1, c->cfg.photon_bpc, c->cfg.photon_order};
+    neb_launch_config best{c->cfg.stack, -1, -1, c->cfg.photon_bpc, c->cfg.photon_order, c->cfg.concurrent};
     st = render_n(c, 1, s);  // warm-up: octree and caches
     double best_ms = 1e300;
     const int trace_k[2] = {K_EXTEND_CAMERA, K_EXTEND_PHOTON};
@@ -3268,7 +3342,7 @@ extern "C" neb_status neb_autotune(neb_ctx c, int32_t trial_iterations, void* st
         int maxb = lds_blocks_per_cu(stack);
         for (int b : {0, 4, 8, 12, 16, maxb}) {
             if (b > maxb) continue;
-            neb_launch_config cfg{stack, b, -1, best.photon_blocks_per_cu, best.photon_order};
+            neb_launch_config cfg{stack, b, -1, best.photon_blocks_per_cu, best.photon_order, best.concurrent};
             double ms = 0.0;
             st = time_config(c, cfg, trial_iterations, trace_k, 2, s, ms);
             if (st != NEB_OK) break;
@@ -3285,7 +3359,7 @@ extern "C" neb_status neb_autotune(neb_ctx c, int32_t trial_iterations, void* st
         if (st != NEB_OK) break;
         if (b > lds_blocks_per_cu(best.bvh_stack)) continue;
         neb_launch_config cfg{best.bvh_stack, best.trace_blocks_per_cu, b, best.photon_blocks_per_cu,
-                              best.photon_order};
+                              best.photon_order, best.concurrent};
         double ms = 0.0;
         st = time_config(c, cfg, trial_iterations, nee_k, 1, s, ms);
         if (st != NEB_OK) break;
@@ -3296,13 +3370,14 @@ extern "C" neb_status neb_autotune(neb_ctx c, int32_t trial_iterations, void* st
     }
     best_ms = 1e300;
     // the photon stage: ordering (which also adds to the photon traversal) and the merge grid
-    const int photon_k[3] = {K_PHOTON, K_PHOTON_ORDER, K_EXTEND_PHOTON};
+    const int photon_k[4] = {K_PHOTON, K_PHOTON_ORDER, K_EXTEND_PHOTON, K_PHOTON_SCATTER};
     for (int order : {1, 0}) {
         for (int pb : {0, 8, 16, 32, 64}) {
             if (st != NEB_OK) break;
-            neb_launch_config cfg{best.bvh_stack, best.trace_blocks_per_cu, best.nee_blocks_per_cu, pb, order};
+            neb_launch_config cfg{best.bvh_stack, best.trace_blocks_per_cu, best.nee_blocks_per_cu, pb, order,
+                                  best.concurrent};
             double ms = 0.0;
-            st = time_config(c, cfg, trial_iterations, photon_k, 3, s, ms);
+            st = time_config(c, cfg, trial_iterations, photon_k, 4, s, ms);
             if (st != NEB_OK) break;
             if (ms < best_ms) {
                 best_ms = ms;

@@ -49,7 +49,7 @@ class Params(ctypes.Structure):
 class LaunchConfig(ctypes.Structure):
     _fields_ = [("bvh_stack", ctypes.c_int32), ("trace_blocks_per_cu", ctypes.c_int32),
                 ("nee_blocks_per_cu", ctypes.c_int32), ("photon_blocks_per_cu", ctypes.c_int32),
-                ("photon_order", ctypes.c_int32)]
+                ("photon_order", ctypes.c_int32), ("concurrent", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -281,8 +281,9 @@ class BatchRenderer:
         return cfg.as_dict()
 
     def set_launch_config(self, bvh_stack, trace_blocks_per_cu, photon_blocks_per_cu, photon_order=0,
-                          nee_blocks_per_cu=-1):
-        cfg = LaunchConfig(bvh_stack, trace_blocks_per_cu, nee_blocks_per_cu, photon_blocks_per_cu, photon_order)
+                          nee_blocks_per_cu=-1, concurrent=1):
+        cfg = LaunchConfig(bvh_stack, trace_blocks_per_cu, nee_blocks_per_cu, photon_blocks_per_cu, photon_order,
+                           concurrent)
         _check(lib().neb_set_launch_config(self.h, ctypes.byref(cfg)))
 
     def launch_config(self):

@@ -185,7 +185,9 @@ def test_autotune_changes_speed_not_results(neb, batch_scenes):
     assert T.launch_config() == cfg
     assert T.stats()["iterations"] == 0  # reset after tuning
     F = neb.BatchRenderer(scenes, flags=neb.FLAG_SINGLE_THREAD_OCTREE, spp=spp)
-    F.set_launch_config(64, 4, 8, 1 - cfg["photon_order"])  # the other photon order
+    assert cfg["concurrent"] in (0, 1)
+    # the other photon order, every launch on one stream
+    F.set_launch_config(64, 4, 8, 1 - cfg["photon_order"], concurrent=0)
     T.render(3)
     F.render(3)
     for s in range(len(scenes)):
