@@ -121,7 +121,7 @@ struct Grid {
                       // (n, tag), (wo, B), (tau, g), (pixel, -, -, -)
     int32_t* sums;    // scan block sums, all levels
     int32_t T;        // hash buckets (power of two)
-    int32_t D;        // depth classes = longest maxlen - 1
+    int32_t D;        // depth classes: longest maxlen - 1, rounded up to a multiple of 8
 };
 
 // prefix sums are scanned in tiles of kScanTile elements (a tile per block
@@ -2174,7 +2174,8 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
     ALLOC(c->ev1, ecap);
     if (c->flags & NEB_FLAG_SINGLE_THREAD_OCTREE) ALLOC(c->slots, slot_cap);
     if (c->flags & NEB_FLAG_RECORD_PATHS) ALLOC(c->recs, npix * L);
-    c->G.D = std::max(1, L - 1);
+    // depth classes padded to 8: a cell's row is one aligned 32-byte sector
+    c->G.D = (std::max(1, L - 1) + 7) & ~7;
     c->G.T = (int32_t)std::max<uint64_t>(1024, std::min<uint64_t>(next_pow2((uint64_t)vcap) / 2, 1u << 23));
     int64_t gkeys = (int64_t)c->G.T * c->G.D + 1;
     ALLOC(c->G.count, gkeys);

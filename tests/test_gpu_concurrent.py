@@ -1,0 +1,84 @@
+"""Concurrent launches (the default: NEE's shadow rays and the merge grid on
+a second stream beside the octree deposits and the density, each bounce's
+merges beside the next bounce's closest hits) against every launch on one
+stream.  The two orders of execution must give the same estimator: with
+the deterministic single-thread octree the trees, the work statistics and
+the per-technique images agree up to the order of floating-point
+additions, for plain NEB, with light photons, with NEE recycling and for a
+batch of scenes; eager launches and graph replays agree too."""
+import numpy as np
+import pytest
+
+from neb_inputs import tiny_box, box_room
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def neb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1909_00573_amd import neb as N
+    N.lib()
+    return N
+
+
+def _close(a, b, rtol=2e-4):
+    a = a.astype(np.float64)
+    b = b.astype(np.float64)
+    return np.all(np.abs(a - b) <= rtol * np.abs(a) + 1e-6 * max(np.abs(a).max(), 1e-30))
+
+
+def _pair(neb, make, n_iter, graph=False):
+    out = []
+    for conc in (1, 0):
+        R = make()
+        cfg = R.launch_config()
+        R.set_launch_config(cfg["bvh_stack"], cfg["trace_blocks_per_cu"], cfg["photon_blocks_per_cu"],
+                            cfg["photon_order"], cfg["nee_blocks_per_cu"], concurrent=conc)
+        if graph:
+            R.use_graph(True)
+        R.render(n_iter)
+        out.append((R.technique_images_host(), R.stats(), R.octree()[0]))
+        R.close()
+    return out
+
+
+@pytest.mark.parametrize("kw", [{}, {"light_photons": 4096}, {"nee_radius": 0.03}])
+def test_concurrent_equals_serial(neb, kw):
+    sc = tiny_box(width=48, height=40, max_path_len=6)
+    (ta, sa, oa), (tb, sb, ob) = _pair(neb, lambda: neb.Renderer(sc, flags=neb.FLAG_SINGLE_THREAD_OCTREE, **kw), 4)
+    assert np.array_equal(oa, ob)
+    for k in ("vertices", "photons", "photon_segments", "merges", "candidates", "shadow_rays", "nee_visible",
+              "light_photons"):
+        assert sa[k] == sb[k], k
+    for t in ("e", "E", "P", "LP"):
+        assert _close(ta[t], tb[t]), t
+    assert sa["merges"] > 0
+
+
+def test_concurrent_equals_serial_batch_and_graph(neb):
+    scenes = [box_room(n_tris=2000, n_lights=3, res=64, seed=5 + k, scene_id=k) for k in range(3)]
+    make = lambda: neb.BatchRenderer(scenes, flags=neb.FLAG_SINGLE_THREAD_OCTREE)
+    for graph in (False, True):
+        (ta, sa), (tb, sb) = _pair_batch(neb, make, 3, graph)
+        assert sa["merges"] == sb["merges"] and sa["vertices"] == sb["vertices"]
+        for s in range(len(scenes)):
+            for t in ("e", "E", "P"):
+                assert _close(ta[s][t], tb[s][t]), (graph, s, t)
+
+
+def _pair_batch(neb, make, n_iter, graph):
+    out = []
+    for conc in (1, 0):
+        B = make()
+        cfg = B.launch_config()
+        B.set_launch_config(cfg["bvh_stack"], cfg["trace_blocks_per_cu"], cfg["photon_blocks_per_cu"],
+                            cfg["photon_order"], cfg["nee_blocks_per_cu"], concurrent=conc)
+        if graph:
+            B.use_graph(True)
+        B.render(n_iter)
+        out.append(([B.technique_images_host(s) for s in range(len(B.scenes))], B.stats()))
+        B.close()
+    return out
