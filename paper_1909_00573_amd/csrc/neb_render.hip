@@ -1827,11 +1827,12 @@ struct neb_ctx_s {
     // per-iteration pools
     PathQ q[2]{};
     PhotonQ pq[2]{};
-    // a second stream (default priority) for NEE's shadow rays and the
-    // merge-grid build, forked after shading; joined before NEE's
-    // contributions (ev_nee) and before the photon bounces (ev_join)
+    // a second stream (default priority) for NEE's shadow rays, the
+    // merge-grid build and the merges, forked after shading; joined before
+    // NEE's contributions (ev_nee), before each bounce's scatter and at the
+    // end of the bounces (ev_merge)
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_nee = nullptr, ev_join = nullptr, ev_merge = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_nee = nullptr, ev_merge = nullptr;
     int2* hits2 = nullptr;  // the photon bounces alternate between hits and hits2
     float4 *sq0 = nullptr, *sq1 = nullptr;  // NEE shadow rays: (origin, vertex), (direction, tag)
     float* sqt = nullptr;                   // their tmax
@@ -2004,7 +2005,6 @@ static void destroy_ctx(neb_ctx c) {
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->side) (void)hipStreamDestroy(c->side);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->ev_nee) (void)hipEventDestroy(c->ev_nee);
     if (c->ev_merge) (void)hipEventDestroy(c->ev_merge);
     free_list(c->scene_allocs);
@@ -2714,7 +2714,6 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
         HIP_TRY(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
         HIP_TRY(hipEventCreateWithFlags(&c->ev_nee, hipEventDisableTiming));
-        HIP_TRY(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
         HIP_TRY(hipEventCreateWithFlags(&c->ev_merge, hipEventDisableTiming));
     }
     // the second stream, or the caller's when the launches are serialised
@@ -2736,7 +2735,6 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
                            (const neb_material*)c->view.mats, (const SceneInfo*)c->sc_dev, c->V,
                            (const int32_t*)&cnt->n_vertices, c->G);
         prof_end(c, g);
-        HIP_TRY(hipEventRecord(c->ev_join, g));
     }
     // deposits of this iteration's NEE vertices into their scenes' octrees
     const bool set_mode = c->density_mode == NEB_DENSITY_RADIUS || c->density_mode == NEB_DENSITY_KNN;
@@ -2819,8 +2817,11 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
                                                 (const int32_t*)&cnt->n_vertices, im));
     const int64_t pcap = c->pcap;
     if (rounds > 0) {
-        // the merge grid of the side stream
-        HIP_TRY(hipStreamWaitEvent(s, c->ev_join, 0));
+        // the merge grid comes from the second stream, whose order puts it
+        // before every merge launch: the first bounce's closest hits and
+        // scatter need not wait for it.  (The shadow rays, the only other
+        // closest-hit launch there, are done: NEE's contributions waited
+        // for them; closest-hit launches share their work counters.)
         const int pgrid = c->cfg.photon_bpc > 0 ? std::max(1, std::min(grid_of(pcap, 64, 1 << 20), c->cus * c->cfg.photon_bpc))
                                                 : grid_of(pcap, 256);
         for (int j = 1; j <= rounds; ++j) {
