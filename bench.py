@@ -9,7 +9,10 @@ a 20k-triangle glass sphere (IOR 1.5) on a table and four emissive spheres,
 The 16 steps after the warm-up reproduce the workload's 16 spp.
 
 Launch shapes are the library's defaults (tuned for this workload), or
-tuned afresh with --autotune (they change the speed, not the result).
+tuned afresh with --autotune (they change the speed, not the result).  The
+timed iterations replay the captured iteration as a HIP graph (captured
+during the warm-up; --eager launches every kernel from the host instead);
+the per-kernel passes launch eagerly (their events need it).
 
 Prints one JSON line with camera paths/s (value), photons/s, the roofline
 of the dominant kernel (HIP-event durations on the launch stream, the
@@ -187,6 +190,7 @@ def city_block_run(stream, steps=8, warmup=2):
     sc = city_block()
     R = neb.Renderer(sc)
     setup = time.perf_counter() - t0
+    R.use_graph(True)  # the warm-up captures the iteration
     R.render(warmup, stream=stream)
     torch.cuda.synchronize()
     R.reset()
@@ -394,6 +398,7 @@ def main():
     ap.add_argument("--no-quality", "--no-learned", dest="no_quality", action="store_true",
                     help="skip the error-against-time comparison (plain, light photons, learned density)")
     ap.add_argument("--no-city", action="store_true", help="skip the city-block throughput run")
+    ap.add_argument("--eager", action="store_true", help="launch every kernel from the host (no graph replay)")
     ap.add_argument("--no-serialized", action="store_true",
                     help="skip the per-kernel pass with every launch on one stream")
     ap.add_argument("--autotune", action="store_true",
@@ -432,7 +437,9 @@ def main():
         launch_cfg = R.autotune(2, stream=stream)
     else:
         launch_cfg = R.launch_config()
-    # warm-up on a throw-away progression, then start the 16-spp render afresh
+    R.use_graph(not args.eager)
+    # warm-up on a throw-away progression (it captures the graph), then start
+    # the 16-spp render afresh
     R.render(args.warmup, stream=stream)
     torch.cuda.synchronize()
     R.reset()
@@ -482,6 +489,7 @@ def main():
                           ("vertices", "photons", "photon_segments", "merges", "candidates", "grid_cells",
                            "camera_rays", "shadow_rays", "bvh_nodes", "bvh_tris")},
         "roofline": roof, "kernels": kernels, "launch_config": launch_cfg,
+        "timed_launches": "eager" if args.eager else "graph replay",
         "roofline_serialized": roof_ser, "kernels_serialized": kernels_ser,
     }
     R.close()
