@@ -109,6 +109,11 @@ struct alignas(128) StatLine {
     unsigned long long light_photons;
 };
 
+// Photon queues (and their hit arrays) rotate over kPhotonBufs buffers, so
+// that the closest hits and scatter of a bounce can run while the merges of
+// the two bounces before it still read theirs.
+constexpr int kPhotonBufs = 3;
+
 // A closest-hit launch hands out its rays through kWorkParts counters, one
 // cache line each (its blocks run on eight XCDs; one counter per XCD).
 constexpr int kWorkParts = 8;
@@ -122,8 +127,8 @@ struct alignas(128) WorkLine {
 // at the same time must not share one.
 struct Counters {
     alignas(128) int32_t qcount[2];  // camera path queues
-    alignas(128) int32_t pcount[2];  // photon queues
-    alignas(128) int32_t mcount[2];  // photon queue lengths for the merge launches (copied by the scatter)
+    alignas(128) int32_t pcount[kPhotonBufs];  // photon queues
+    alignas(128) int32_t mcount[kPhotonBufs];  // their lengths for the merge launches (copied by the scatter)
     alignas(128) int32_t n_vertices;
     alignas(128) int32_t n_events;
     alignas(128) int32_t n_shadow;   // NEE shadow rays queued this iteration

@@ -232,8 +232,7 @@ __global__ void k_iter_begin(Counters* c, OctDyn* dyn, int32_t freeze) {
     c->iter = it;
     c->qcount[0] = 0;
     c->qcount[1] = 0;
-    c->pcount[0] = 0;
-    c->pcount[1] = 0;
+    for (int b = 0; b < kPhotonBufs; ++b) c->pcount[b] = 0;
     c->n_vertices = 0;
     c->n_events = 0;
     c->n_shadow = 0;
@@ -1826,14 +1825,16 @@ struct neb_ctx_s {
     int32_t* defer_cnt = nullptr;
     // per-iteration pools
     PathQ q[2]{};
-    PhotonQ pq[2]{};
+    PhotonQ pq[kPhotonBufs]{};
     // a second stream (default priority) for NEE's shadow rays, the
     // merge-grid build and the merges, forked after shading; joined before
-    // NEE's contributions (ev_nee), before each bounce's scatter and at the
-    // end of the bounces (ev_merge)
+    // NEE's contributions (ev_nee), before a bounce's scatter overwrites the
+    // queue that the merges two bounces back read, and at the end of the
+    // bounces (ev_merge[j]: the merges of bounce j)
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_nee = nullptr, ev_merge = nullptr;
-    int2* hits2 = nullptr;  // the photon bounces alternate between hits and hits2
+    hipEvent_t ev_fork = nullptr, ev_nee = nullptr;
+    hipEvent_t ev_merge[kMaxPathLen + 1]{};
+    int2* phits[kPhotonBufs]{};  // hit arrays of the photon queues (the first is hits)
     float4 *sq0 = nullptr, *sq1 = nullptr;  // NEE shadow rays: (origin, vertex), (direction, tag)
     float* sqt = nullptr;                   // their tmax
     int32_t* svis = nullptr;                // per vertex: 1 if its shadow ray reached the light
@@ -2006,7 +2007,8 @@ static void destroy_ctx(neb_ctx c) {
     if (c->side) (void)hipStreamDestroy(c->side);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_nee) (void)hipEventDestroy(c->ev_nee);
-    if (c->ev_merge) (void)hipEventDestroy(c->ev_merge);
+    for (auto& e : c->ev_merge)
+        if (e) (void)hipEventDestroy(e);
     free_list(c->scene_allocs);
     free_list(c->allocs);
     for (auto& e : c->prof_ev) (void)hipEventDestroy(e);
@@ -2154,13 +2156,16 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
         ALLOC(c->q[b].q1, npix);
         ALLOC(c->q[b].q2, npix);
         ALLOC(c->q[b].q3, npix);
+    }
+    for (int b = 0; b < kPhotonBufs; ++b) {
         ALLOC(c->pq[b].p0, c->pcap);
         ALLOC(c->pq[b].p1, c->pcap);
         ALLOC(c->pq[b].p2, c->pcap);
         ALLOC(c->pq[b].pu, c->pcap);
     }
     ALLOC(c->hits, std::max<int64_t>(npix, c->pcap));
-    ALLOC(c->hits2, c->pcap);
+    c->phits[0] = c->hits;
+    for (int b = 1; b < kPhotonBufs; ++b) ALLOC(c->phits[b], c->pcap);
     ALLOC(c->sq0, vcap);
     ALLOC(c->sq1, vcap);
     ALLOC(c->sqt, vcap);
@@ -2714,7 +2719,7 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
         HIP_TRY(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
         HIP_TRY(hipEventCreateWithFlags(&c->ev_nee, hipEventDisableTiming));
-        HIP_TRY(hipEventCreateWithFlags(&c->ev_merge, hipEventDisableTiming));
+        for (auto& e : c->ev_merge) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     }
     // the second stream, or the caller's when the launches are serialised
     hipStream_t t = c->cfg.concurrent ? c->side : s;
@@ -2825,8 +2830,9 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
         const int pgrid = c->cfg.photon_bpc > 0 ? std::max(1, std::min(grid_of(pcap, 64, 1 << 20), c->cus * c->cfg.photon_bpc))
                                                 : grid_of(pcap, 256);
         for (int j = 1; j <= rounds; ++j) {
-            int in = (j - 1) & 1, out = j & 1;
-            int2* hj = (j & 1) ? c->hits : c->hits2;  // the merges of bounce j - 1 read the other one
+            // bounce j reads queue `in` (and writes its hits), its scatter fills `out`
+            const int in = (j - 1) % kPhotonBufs, out = j % kPhotonBufs;
+            int2* hj = c->phits[in];
             const bool ordered = c->cfg.photon_order != 0;
             TIMED(K_EXTEND_PHOTON, extend(c, pcap, c->pq[in].p0, c->pq[in].p1, &cnt->pcount[in], &cnt->pcount[out],
                                           1, s, ordered, hj));
@@ -2835,33 +2841,35 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
                       hipLaunchKernelGGL(k_lp_first, dim3(grid_of(c->n_lp, 256)), dim3(256), 0, s, A, c->pq[0], hj,
                                          (const int32_t*)c->oct_nodes, (const OctState*)c->oct_states,
                                          (const OctParams*)c->oct_prm_dev, (const OctDyn*)c->oct_dyn));
-            // the merges of bounce j - 1 read queue `out`, which this bounce's
-            // scatter writes, and the photon order
-            if (j > 1) HIP_TRY(hipStreamWaitEvent(s, c->ev_merge, 0));
             if (ordered) {
-                // photons in the spatial order of their hits
+                // photons in the spatial order of their hits; the order array
+                // is shared, so the merges of the bounce before must be done
+                if (j > 1) HIP_TRY(hipStreamWaitEvent(s, c->ev_merge[j - 1], 0));
                 prof_begin(c, K_PHOTON_ORDER, s);
                 scan_exclusive(c->bcount, c->bstart, c->n_bins + 1, c->bsums, s);
                 hipLaunchKernelGGL(k_bin_scatter, dim3(grid_of(pcap, 256)), dim3(256), 0, s, (const int32_t*)c->pbin,
                                    (const int32_t*)&cnt->pcount[in], c->bcount, (const int32_t*)c->bstart, c->porder);
                 prof_end(c, s);
             }
+            // queue `out` was the input of bounce j + 1 - kPhotonBufs: its merges
+            // must be done before the scatter overwrites it
+            if (j + 1 - kPhotonBufs >= 1) HIP_TRY(hipStreamWaitEvent(s, c->ev_merge[j + 1 - kPhotonBufs], 0));
             TIMED(K_PHOTON_SCATTER,
                   hipLaunchKernelGGL(k_pscatter, dim3(grid_of(pcap, kScatterBlock)), dim3(kScatterBlock), 0, s, A,
                                      c->pq[in], (const int32_t*)&cnt->pcount[in], (const int2*)hj, c->pq[out],
-                                     &cnt->pcount[out], &cnt->mcount[j & 1]));
-            // the merges of bounce j on the side stream, beside the closest
-            // hits of bounce j + 1
+                                     &cnt->pcount[out], &cnt->mcount[in]));
+            // the merges of bounce j on the second stream, beside the closest
+            // hits and scatters of the bounces after it
             HIP_TRY(hipEventRecord(c->ev_fork, s));
             HIP_TRY(hipStreamWaitEvent(t, c->ev_fork, 0));
             prof_begin(c, K_PHOTON, t);
-            hipLaunchKernelGGL(k_photon, dim3(pgrid), dim3(64), 0, t, A, c->pq[in],
-                               (const int32_t*)&cnt->mcount[j & 1], (const int2*)hj, c->G, im,
+            hipLaunchKernelGGL(k_photon, dim3(pgrid), dim3(64), 0, t, A, c->pq[in], (const int32_t*)&cnt->mcount[in],
+                               (const int2*)hj, c->G, im,
                                ordered ? (const int32_t*)c->porder : (const int32_t*)nullptr);
             prof_end(c, t);
-            HIP_TRY(hipEventRecord(c->ev_merge, t));
+            HIP_TRY(hipEventRecord(c->ev_merge[j], t));
         }
-        HIP_TRY(hipStreamWaitEvent(s, c->ev_merge, 0));
+        HIP_TRY(hipStreamWaitEvent(s, c->ev_merge[rounds], 0));
     }
     // pass 3
     TIMED(K_FINALIZE, hipLaunchKernelGGL(k_finalize, dim3(grid_of(c->ecap, 256)), dim3(256), 0, s, A,
