@@ -10,9 +10,10 @@ The 16 steps after the warm-up reproduce the workload's 16 spp.
 
 Launch shapes are the library's defaults (tuned for this workload), or
 tuned afresh with --autotune (they change the speed, not the result).  The
-timed iterations replay the captured iteration as a HIP graph (captured
-during the warm-up; --eager launches every kernel from the host instead);
-the per-kernel passes launch eagerly (their events need it).
+timed iterations are launched from the host, each forking the next one's
+camera pass onto a third stream (--graph replays the captured iteration
+instead, which runs these branches less concurrently); the per-kernel
+passes launch eagerly too (their events need it).
 
 Prints one JSON line with camera paths/s (value), photons/s, the roofline
 of the dominant kernel (HIP-event durations on the launch stream, the
@@ -174,7 +175,7 @@ def committed_traffic(kernel):
         return None
 
 
-def city_block_run(stream, steps=8, warmup=2):
+def city_block_run(stream, graph, steps=8, warmup=2):
     """Throughput on the city block (100 x 100 m, ~1.01 M triangles, 1024
     point lights sampled by power, 1024 x 1024, path length 10, octree 2^24
     nodes, merge radius 0.1 m): the largest workload, timed like the room
@@ -190,7 +191,7 @@ def city_block_run(stream, steps=8, warmup=2):
     sc = city_block()
     R = neb.Renderer(sc)
     setup = time.perf_counter() - t0
-    R.use_graph(True)  # the warm-up captures the iteration
+    R.use_graph(graph)  # with graphs the warm-up captures the iteration
     R.render(warmup, stream=stream)
     torch.cuda.synchronize()
     R.reset()
@@ -250,10 +251,10 @@ def batch_comparison(stream, cfg_trials=1):
     B.reset()
     t_batch = timed(lambda: B.render(n_iter, stream=stream))
     st = B.stats()
-    # graph replay of the serialised iteration (replaying the two-stream
+    # graph replay of the serialised iteration (replaying the concurrent
     # iteration of this batch is much slower than launching it: 127 against
-    # 73 ms per iteration, while for the room it is the fastest form); the
-    # first call captures the graph inside the timed region
+    # 73 ms per iteration); the first call captures the graph inside the
+    # timed region
     B.set_launch_config(cfg["bvh_stack"], cfg["trace_blocks_per_cu"], cfg["photon_blocks_per_cu"],
                         cfg["photon_order"], cfg["nee_blocks_per_cu"], concurrent=0)
     B.reset()
@@ -404,7 +405,8 @@ def main():
     ap.add_argument("--no-quality", "--no-learned", dest="no_quality", action="store_true",
                     help="skip the error-against-time comparison (plain, light photons, learned density)")
     ap.add_argument("--no-city", action="store_true", help="skip the city-block throughput run")
-    ap.add_argument("--eager", action="store_true", help="launch every kernel from the host (no graph replay)")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the captured iteration as a HIP graph (default: launch from the host)")
     ap.add_argument("--no-serialized", action="store_true",
                     help="skip the per-kernel pass with every launch on one stream")
     ap.add_argument("--autotune", action="store_true",
@@ -443,7 +445,7 @@ def main():
         launch_cfg = R.autotune(2, stream=stream)
     else:
         launch_cfg = R.launch_config()
-    R.use_graph(not args.eager)
+    R.use_graph(args.graph)
     # warm-up on a throw-away progression (it captures the graph), then start
     # the 16-spp render afresh
     R.render(args.warmup, stream=stream)
@@ -495,12 +497,12 @@ def main():
                           ("vertices", "photons", "photon_segments", "merges", "candidates", "grid_cells",
                            "camera_rays", "shadow_rays", "bvh_nodes", "bvh_tris")},
         "roofline": roof, "kernels": kernels, "launch_config": launch_cfg,
-        "timed_launches": "eager" if args.eager else "graph replay",
+        "timed_launches": "graph replay" if args.graph else "eager",
         "roofline_serialized": roof_ser, "kernels_serialized": kernels_ser,
     }
     R.close()
     if not args.no_city:
-        out["city_block"] = city_block_run(stream)
+        out["city_block"] = city_block_run(stream, args.graph)
     if not args.no_batch:
         out["batch"] = batch_comparison(stream)
     if not args.no_quality:

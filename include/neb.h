@@ -116,8 +116,11 @@ typedef struct {
                                      each XCD taking a contiguous share; 0: queue order */
     int32_t concurrent;           /* 1 (default): NEE's shadow rays and the merge grid run on a
                                      second stream beside the octree deposits and the density, each
-                                     bounce's merges beside the next bounce's closest hits; 0: every
-                                     launch on the caller's stream, one after another */
+                                     bounce's merges beside the next bounce's closest hits, and
+                                     within one neb_render call each iteration but the last runs
+                                     the next one's camera pass on a third stream (the learned
+                                     density excepted); 0: every launch on the caller's stream,
+                                     one after another */
 } neb_launch_config;
 
 /* One material per entry; emission is radiance leaving the front side of
@@ -228,6 +231,9 @@ neb_status neb_set_batch_scene(neb_ctx ctx, int32_t scene, const float* vertices
 /* Runs n_iterations progressive iterations (one sample per pixel each) on
  * `stream`, continuing from the context's iteration counter; the octree
  * integrates its counts over the iterations (Sec. 5.3, time integration).
+ * Work forked onto the library's own streams is joined back into `stream`
+ * before the last iteration ends, so nothing is in flight between calls and
+ * the result does not depend on how the iterations are split over calls.
  * Returns after enqueueing; NEB_ERR_STATE unless every scene is set. */
 neb_status neb_render(neb_ctx ctx, int32_t n_iterations, void* stream);
 

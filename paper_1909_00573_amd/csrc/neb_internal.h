@@ -129,13 +129,16 @@ struct Counters {
     alignas(128) int32_t qcount[2];  // camera path queues
     alignas(128) int32_t pcount[kPhotonBufs];  // photon queues
     alignas(128) int32_t mcount[kPhotonBufs];  // their lengths for the merge launches (copied by the scatter)
-    alignas(128) int32_t n_vertices;
-    alignas(128) int32_t n_events;
+    alignas(128) int32_t n_vertices[2];  // per parity of the iteration (two vertex stores)
+    alignas(128) int32_t n_events[2];
     alignas(128) int32_t n_shadow;   // NEE shadow rays queued this iteration
     alignas(128) int32_t iter;       // current iteration (incremented at the start of each one)
+    alignas(128) int32_t iter_cam;   // iteration of the camera pass in flight (it may run one ahead)
     alignas(128) int32_t lp_count;   // light photons emitted this iteration (the first entries of photon queue 0)
     WorkLine trace_next[kWorkParts]; // per part: rays a closest-hit launch handed out (reset by its last block)
     alignas(128) int32_t trace_done; // blocks of that launch that finished
+    WorkLine cam_next[kWorkParts];   // the same for the camera pass's closest-hit launches, which may
+    alignas(128) int32_t cam_done;   // run beside the photon bounces' ones
     StatLine st[kStatStripes];
 };
 

@@ -230,11 +230,7 @@ __global__ void k_fill_f32(float* p, float v, int64_t n) {
 __global__ void k_iter_begin(Counters* c, OctDyn* dyn, int32_t freeze) {
     int it = c->iter + 1;
     c->iter = it;
-    c->qcount[0] = 0;
-    c->qcount[1] = 0;
     for (int b = 0; b < kPhotonBufs; ++b) c->pcount[b] = 0;
-    c->n_vertices = 0;
-    c->n_events = 0;
     c->n_shadow = 0;
     c->lp_count = 0;
     int oit = it < freeze ? it : freeze;
@@ -246,9 +242,19 @@ __global__ void k_iter_begin(Counters* c, OctDyn* dyn, int32_t freeze) {
     d.stop_filling = it > kOctFillIterations || it > freeze;
     *dyn = d;
 }
-__global__ void k_iter_end(Counters* c) {
-    c->st[0].vertices += (unsigned long long)c->n_vertices;
-    c->st[0].events += (unsigned long long)c->n_events;
+__global__ void k_iter_end(Counters* c, int parity) {
+    c->st[0].vertices += (unsigned long long)c->n_vertices[parity];
+    c->st[0].events += (unsigned long long)c->n_events[parity];
+}
+// Starts the camera pass of an iteration (it may run while the iteration
+// before still bounces photons): its own iteration counter, the path queues
+// and the vertex and event stores of its parity emptied.
+__global__ void k_cam_begin(Counters* c, int parity) {
+    c->iter_cam += 1;
+    c->qcount[0] = 0;
+    c->qcount[1] = 0;
+    c->n_vertices[parity] = 0;
+    c->n_events[parity] = 0;
 }
 __global__ void k_mean_image(const float* e, const float* E, const float* P, const float* LP, float* out, int64_t n,
                              float scale) {
@@ -271,7 +277,7 @@ constexpr int kCameraBlock = 1024;
 __global__ void __launch_bounds__(kCameraBlock) k_camera(RenderArgs A, PathQ q) {
     __shared__ int wc[kCameraBlock / 64];
     __shared__ int bb;
-    const int iter = A.cnt->iter;
+    const int iter = A.cnt->iter_cam;
     unsigned started = 0;
     for (int base = blockIdx.x * kCameraBlock; base < A.npix; base += gridDim.x * kCameraBlock) {
         const int i = base + threadIdx.x;
@@ -340,7 +346,8 @@ __global__ void __launch_bounds__(kTraceBlock) k_extend(SceneView S, const Scene
                                                         const float4* __restrict__ dir, const int32_t* count,
                                                         int32_t* next_count, int2* __restrict__ hits,
                                                         int ray_kind, Counters* cnt, HitBins B,
-                                                        const float* __restrict__ tmax, int32_t* __restrict__ vis) {
+                                                        const float* __restrict__ tmax, int32_t* __restrict__ vis,
+                                                        WorkLine* work, int32_t* work_done) {
     __shared__ int stack[kStack * kTraceBlock];
     const int n = *count;
     if (next_count && blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
@@ -355,7 +362,7 @@ __global__ void __launch_bounds__(kTraceBlock) k_extend(SceneView S, const Scene
     constexpr int kSteps = 32;  // node visits per round (8, 16, 32: 32 is 2 % faster)
     constexpr int kChunk = 256;
     const int parts = min(kWorkParts, (int)gridDim.x), part = blockIdx.x % parts;
-    int32_t* next = &cnt->trace_next[part].next;
+    int32_t* next = &work[part].next;
     int i = -1;  // this lane's ray; >= n once the queue is exhausted
     TraceState T;
     f3 o = mk3(0.f, 0.f, 0.f), dd = mk3(0.f, 0.f, 1.f);
@@ -393,9 +400,9 @@ __global__ void __launch_bounds__(kTraceBlock) k_extend(SceneView S, const Scene
     }
     // the last block to finish resets the work counter for the next launch
     __syncthreads();
-    if (threadIdx.x == 0 && atomicAdd(&cnt->trace_done, 1) == (int)gridDim.x - 1) {
-        for (int k = 0; k < kWorkParts; ++k) cnt->trace_next[k].next = 0;
-        cnt->trace_done = 0;
+    if (threadIdx.x == 0 && atomicAdd(work_done, 1) == (int)gridDim.x - 1) {
+        for (int k = 0; k < kWorkParts; ++k) work[k].next = 0;
+        *work_done = 0;
     }
     StatLine& L = stat_line(cnt);
     wave_add_u64(ray_kind == 0 ? &L.camera_rays : (ray_kind == 1 ? &L.photon_rays : &L.shadow_rays), traced);
@@ -419,7 +426,7 @@ __global__ void __launch_bounds__(kShadeBlock) k_shade(RenderArgs A, PathQ in, c
     __shared__ int bb[3];          // per queue: the block's first slot
     const int n = *count_in;
     const SceneView& S = A.S;
-    const int iter = A.cnt->iter;
+    const int iter = A.cnt->iter_cam;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const unsigned long long below = (1ull << lane) - 1ull;
     for (int base = blockIdx.x * kShadeBlock; base < n; base += gridDim.x * kShadeBlock) {
@@ -1839,8 +1846,18 @@ struct neb_ctx_s {
     float* sqt = nullptr;                   // their tmax
     int32_t* svis = nullptr;                // per vertex: 1 if its shadow ray reached the light
     int2* hits = nullptr;
+    // Two vertex and event stores, by the parity of the iteration: the
+    // camera pass of the next iteration (on a third stream, cam) fills one
+    // while this iteration's photon bounces and pass 3 read the other.  V,
+    // ev0, ev1, nvtx and nevt are the current iteration's.
+    VertexStore Vb[2]{};
+    float4 *ev0b[2]{}, *ev1b[2]{};
     VertexStore V{};
     float4 *ev0 = nullptr, *ev1 = nullptr;
+    int32_t *nvtx = nullptr, *nevt = nullptr;
+    int2* chits = nullptr;  // closest hits of the camera pass
+    hipStream_t cam = nullptr;
+    hipEvent_t ev_cam_fork = nullptr, ev_cam_done = nullptr;
     int32_t* slots = nullptr;
     neb_path_record* recs = nullptr;
     Grid G{};
@@ -1857,10 +1874,10 @@ struct neb_ctx_s {
     hipStream_t last_stream = nullptr;
     std::vector<void*> allocs;
     LaunchCfg cfg;
-    // captured iteration
+    // captured iterations, by (parity, camera pass inline, next camera pass forked)
     bool use_graph = false;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph[8]{};
+    hipGraphExec_t gexec[8]{};
     hipStream_t cap_stream = nullptr;
     // learned density (NEB_DENSITY_MLP)
     bool mlp_mode = false;
@@ -1892,9 +1909,10 @@ static const char* kKernelNames[K_COUNT] = {"camera", "extend_camera", "shade", 
 
 static void prof_harvest(neb_ctx c) {
     if (c->prof_used == 0) return;
-    (void)hipEventSynchronize(c->prof_ev[c->prof_used - 1]);
     for (int i = 0; i < c->prof_used; i += 2) {
         float ms = 0.f;
+        // the pairs sit on up to three streams: wait for each
+        (void)hipEventSynchronize(c->prof_ev[i + 1]);
         if (hipEventElapsedTime(&ms, c->prof_ev[i], c->prof_ev[i + 1]) == hipSuccess) {
             c->prof_ms[c->prof_kid[i / 2]] += ms;
             c->prof_launches[c->prof_kid[i / 2]] += 1;
@@ -1994,10 +2012,12 @@ static int trace_grid(neb_ctx c, int64_t cap, int bpc) {
 }
 
 static void drop_graph(neb_ctx c) {
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-    if (c->graph) (void)hipGraphDestroy(c->graph);
-    c->gexec = nullptr;
-    c->graph = nullptr;
+    for (int k = 0; k < 8; ++k) {
+        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+        if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+        c->gexec[k] = nullptr;
+        c->graph[k] = nullptr;
+    }
 }
 
 static void destroy_ctx(neb_ctx c) {
@@ -2005,6 +2025,9 @@ static void destroy_ctx(neb_ctx c) {
     mlp_free(c->mlp);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->cam) (void)hipStreamDestroy(c->cam);
+    if (c->ev_cam_fork) (void)hipEventDestroy(c->ev_cam_fork);
+    if (c->ev_cam_done) (void)hipEventDestroy(c->ev_cam_done);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_nee) (void)hipEventDestroy(c->ev_nee);
     for (auto& e : c->ev_merge)
@@ -2163,20 +2186,23 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
         ALLOC(c->pq[b].p2, c->pcap);
         ALLOC(c->pq[b].pu, c->pcap);
     }
-    ALLOC(c->hits, std::max<int64_t>(npix, c->pcap));
+    ALLOC(c->hits, c->pcap);
+    ALLOC(c->chits, npix);
     c->phits[0] = c->hits;
     for (int b = 1; b < kPhotonBufs; ++b) ALLOC(c->phits[b], c->pcap);
     ALLOC(c->sq0, vcap);
     ALLOC(c->sq1, vcap);
     ALLOC(c->sqt, vcap);
     ALLOC(c->svis, vcap);
-    ALLOC(c->V.v0, vcap);
-    ALLOC(c->V.v1, vcap);
-    ALLOC(c->V.v2, vcap);
-    ALLOC(c->V.v3, vcap);
-    ALLOC(c->V.rho, vcap);
-    ALLOC(c->ev0, ecap);
-    ALLOC(c->ev1, ecap);
+    for (int b = 0; b < 2; ++b) {
+        ALLOC(c->Vb[b].v0, vcap);
+        ALLOC(c->Vb[b].v1, vcap);
+        ALLOC(c->Vb[b].v2, vcap);
+        ALLOC(c->Vb[b].v3, vcap);
+        ALLOC(c->Vb[b].rho, vcap);
+        ALLOC(c->ev0b[b], ecap);
+        ALLOC(c->ev1b[b], ecap);
+    }
     if (c->flags & NEB_FLAG_SINGLE_THREAD_OCTREE) ALLOC(c->slots, slot_cap);
     if (c->flags & NEB_FLAG_RECORD_PATHS) ALLOC(c->recs, npix * L);
     // depth classes padded to 8: a cell's row is one aligned 32-byte sector
@@ -2196,8 +2222,10 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
         ALLOC(c->ng.pts, vcap);
         ALLOC(c->ng.vidx, vcap);
         ALLOC(c->ng.sums, scan_scratch((int64_t)c->ng.T + 1));
-        ALLOC(c->V.ne, vcap);
-        ALLOC(c->V.lsrec, vcap);
+        for (int b = 0; b < 2; ++b) {
+            ALLOC(c->Vb[b].ne, vcap);
+            ALLOC(c->Vb[b].lsrec, vcap);
+        }
     }
     if (c->density_mode == NEB_DENSITY_RADIUS || c->density_mode == NEB_DENSITY_KNN) {
         c->dg.T = c->G.T;
@@ -2631,7 +2659,9 @@ static void launch_extend(neb_ctx c, int64_t cap, const float4* org, const float
                           int rays, const HitBins& B, int2* hits, hipStream_t s) {
     hipLaunchKernelGGL((k_extend<kStack, false>), dim3(trace_grid(c, cap, c->cfg.trace_bpc)), dim3(kTraceBlock), 0, s,
                        c->view, (const SceneInfo*)c->sc_dev, org, dir, (const int32_t*)count, next, hits, rays,
-                       c->cnt, B, (const float*)nullptr, (int32_t*)nullptr);
+                       c->cnt, B, (const float*)nullptr, (int32_t*)nullptr,
+                       rays == 0 ? c->cnt->cam_next : c->cnt->trace_next,
+                       rays == 0 ? &c->cnt->cam_done : &c->cnt->trace_done);
 }
 
 // the queued NEE shadow rays, any-hit, with the NEE launch shape
@@ -2640,13 +2670,13 @@ static void launch_shadow(neb_ctx c, hipStream_t s) {
     hipLaunchKernelGGL((k_extend<kStack, true>), dim3(trace_grid(c, c->vcap, c->cfg.nee_bpc)), dim3(kTraceBlock), 0, s,
                        c->view, (const SceneInfo*)c->sc_dev, (const float4*)c->sq0, (const float4*)c->sq1,
                        (const int32_t*)&c->cnt->n_shadow, (int32_t*)nullptr, (int2*)nullptr, 2, c->cnt, HitBins{},
-                       (const float*)c->sqt, c->svis);
+                       (const float*)c->sqt, c->svis, c->cnt->trace_next, &c->cnt->trace_done);
 }
 
-// rays: 0 counts camera rays, 1 photon rays; hits: c->hits if null
+// rays: 0 counts camera rays (the camera pass, which has work counters of
+// its own: it may run beside the photon bounces), 1 photon rays
 static void extend(neb_ctx c, int64_t cap, const float4* org, const float4* dir, int32_t* count, int32_t* next,
-                   int rays, hipStream_t s, bool bin = false, int2* hits = nullptr) {
-    if (!hits) hits = c->hits;
+                   int rays, hipStream_t s, bool bin, int2* hits) {
     HitBins B{};
     if (bin) {
         B.bin = c->pbin;
@@ -2664,7 +2694,7 @@ static void extend(neb_ctx c, int64_t cap, const float4* org, const float4* dir,
 // rays (they need the vertices only, not rho)
 static void nee_rays(neb_ctx c, const RenderArgs& A, hipStream_t s) {
     const int grid = grid_of(c->vcap, kNeeBlock);
-    hipLaunchKernelGGL(k_nee_rays, dim3(grid), dim3(kNeeBlock), 0, s, A, c->V, (const int32_t*)&c->cnt->n_vertices,
+    hipLaunchKernelGGL(k_nee_rays, dim3(grid), dim3(kNeeBlock), 0, s, A, c->V, (const int32_t*)c->nvtx,
                        c->sq0, c->sq1, c->sqt, &c->cnt->n_shadow);
     if (c->cfg.stack == 32) launch_shadow<32>(c, s);
     else if (c->cfg.stack == 48) launch_shadow<48>(c, s);
@@ -2674,24 +2704,19 @@ static void nee_rays(neb_ctx c, const RenderArgs& A, hipStream_t s) {
 // NEE, second part: contributions and NEB photons (needs rho)
 static void nee_finish(neb_ctx c, const RenderArgs& A, Images im, hipStream_t s) {
     hipLaunchKernelGGL(k_nee_finish, dim3(grid_of(c->vcap, kNeeBlock)), dim3(kNeeBlock), 0, s, A, c->V,
-                       (const int32_t*)&c->cnt->n_vertices, (const int32_t*)c->svis, im, c->pq[0],
+                       (const int32_t*)c->nvtx, (const int32_t*)c->svis, im, c->pq[0],
                        &c->cnt->pcount[0]);
 }
 
-// Enqueues one iteration.  Every argument is fixed for the context (the
-// iteration number is read from device memory), so the same sequence can be
-// captured once and replayed.
-static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
+// Pass 1 of an iteration: camera paths traced and shaded into the vertex
+// and event stores of the given parity.  It reads nothing of the iteration
+// before, so it may run on its own stream beside that iteration's photon
+// bounces (its queues, hits and work counters are its own).
+static void enqueue_camera(neb_ctx c, hipStream_t s, int parity, bool record) {
     RenderArgs A = make_args(c);
     const int npix = c->npix, L = c->L;
-    const int64_t vcap = c->vcap;
     Counters* cnt = c->cnt;
-    Images im{c->img, c->img + 3 * (size_t)npix, c->img + 6 * (size_t)npix, c->img + 9 * (size_t)npix};
-    // learned density: train on the octree in iterations 1..T, then use the model
-    const int it = c->iter + 1;
-    const int T = c->mlp_mode ? c->mcfg.train_iterations : 0;
-    const bool model = c->mlp_mode && it > T;
-    hipLaunchKernelGGL(k_iter_begin, dim3(1), dim3(1), 0, s, cnt, c->oct_dyn, c->mlp_mode ? T : INT32_MAX);
+    hipLaunchKernelGGL(k_cam_begin, dim3(1), dim3(1), 0, s, cnt, parity);
     if (c->slots)
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(c->slot_cap, 256)), dim3(256), 0, s, c->slots, -1, c->slot_cap);
     if (record)
@@ -2699,28 +2724,73 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
                            (int64_t)npix * L * 6);
     TIMED(K_CAMERA, hipLaunchKernelGGL(k_camera, dim3(grid_of(npix, kCameraBlock)), dim3(kCameraBlock), 0, s, A,
                                        c->q[0]));
-    // pass 1
     for (int k = 1; k <= L; ++k) {
         int in = (k - 1) & 1, out = k & 1;
-        TIMED(K_EXTEND_CAMERA,
-              extend(c, npix, c->q[in].q0, c->q[in].q1, &cnt->qcount[in], &cnt->qcount[out], 0, s));
+        TIMED(K_EXTEND_CAMERA, extend(c, npix, c->q[in].q0, c->q[in].q1, &cnt->qcount[in], &cnt->qcount[out], 0, s,
+                                      false, c->chits));
         TIMED(K_SHADE, hipLaunchKernelGGL(k_shade, dim3(grid_of(npix, kShadeBlock)), dim3(kShadeBlock), 0, s, A, c->q[in],
-                                          &cnt->qcount[in], c->hits, c->q[out], &cnt->qcount[out], c->V,
-                                          &cnt->n_vertices, c->ev0, c->ev1, &cnt->n_events, c->slots,
+                                          &cnt->qcount[in], c->chits, c->q[out], &cnt->qcount[out], c->Vb[parity],
+                                          &cnt->n_vertices[parity], c->ev0b[parity], c->ev1b[parity],
+                                          &cnt->n_events[parity], c->slots,
                                           record ? c->recs : (neb_path_record*)nullptr));
     }
+}
+
+// the camera pass of the given parity on the third stream, after the work
+// queued on s so far
+static hipError_t fork_camera(neb_ctx c, hipStream_t s, int parity) {
+    hipError_t e = hipEventRecord(c->ev_cam_fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->cam, c->ev_cam_fork, 0);
+    if (e != hipSuccess) return e;
+    enqueue_camera(c, c->cam, parity, false);
+    return hipEventRecord(c->ev_cam_done, c->cam);
+}
+
+// Enqueues one iteration.  Every argument is fixed for the context (the
+// iteration number is read from device memory), so the same sequence can be
+// captured once and replayed.  parity picks the vertex and event stores;
+// cam_inline: the camera pass is enqueued here (else it ran beside the
+// iteration before); next: the next iteration's camera pass is forked onto
+// the third stream and joined at the end.
+static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, int parity, bool cam_inline, bool next, bool record) {
+    RenderArgs A = make_args(c);
+    const int npix = c->npix, L = c->L;
+    const int64_t vcap = c->vcap;
+    Counters* cnt = c->cnt;
+    Images im{c->img, c->img + 3 * (size_t)npix, c->img + 6 * (size_t)npix, c->img + 9 * (size_t)npix};
+    c->V = c->Vb[parity];
+    c->ev0 = c->ev0b[parity];
+    c->ev1 = c->ev1b[parity];
+    c->nvtx = &cnt->n_vertices[parity];
+    c->nevt = &cnt->n_events[parity];
+    int32_t* const nv = c->nvtx;
+    if (!c->side) {
+        HIP_TRY(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        HIP_TRY(hipStreamCreateWithFlags(&c->cam, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&c->ev_nee, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&c->ev_cam_fork, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&c->ev_cam_done, hipEventDisableTiming));
+        for (auto& e : c->ev_merge) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    // learned density: train on the octree in iterations 1..T, then use the model
+    const int it = c->iter + 1;
+    const int T = c->mlp_mode ? c->mcfg.train_iterations : 0;
+    const bool model = c->mlp_mode && it > T;
+    if (cam_inline) enqueue_camera(c, s, parity, record);
+    hipLaunchKernelGGL(k_iter_begin, dim3(1), dim3(1), 0, s, cnt, c->oct_dyn, c->mlp_mode ? T : INT32_MAX);
+    // The next iteration's camera pass writes the other parity's stores
+    // (pass 3 of the iteration before read them, and it is done) and its own
+    // queues, so it may start now, beside all of this iteration but its
+    // camera pass; with single-thread deposits it also refills the deposit
+    // slots, so it waits for this iteration's deposits.
+    if (next && !c->slots) HIP_TRY(fork_camera(c, s, parity ^ 1));
     // bounces: NEB photons make at most maxlen - 2 segments, light photons maxlen - 1
     const bool lp = c->n_lp > 0;
     const int rounds = std::max((c->photons && L >= 3) ? L - 2 : 0, lp ? L - 1 : 0);
     // NEE's shadow rays and the merge grid need only this iteration's
     // vertices: they run on the side stream while the octree deposits and
     // the density (latency bound, the chip half idle) run here.
-    if (!c->side) {
-        HIP_TRY(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
-        HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
-        HIP_TRY(hipEventCreateWithFlags(&c->ev_nee, hipEventDisableTiming));
-        for (auto& e : c->ev_merge) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    }
     // the second stream, or the caller's when the launches are serialised
     hipStream_t t = c->cfg.concurrent ? c->side : s;
     HIP_TRY(hipEventRecord(c->ev_fork, s));
@@ -2734,11 +2804,11 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
         int64_t n = (int64_t)c->G.T * c->G.D + 1;
         prof_begin(c, K_GRID_BUILD, g);
         hipLaunchKernelGGL(k_grid_count, dim3(grid_of(vcap, 256)), dim3(256), 0, g, (const neb_material*)c->view.mats,
-                           (const SceneInfo*)c->sc_dev, c->V, (const int32_t*)&cnt->n_vertices, c->G);
+                           (const SceneInfo*)c->sc_dev, c->V, (const int32_t*)nv, c->G);
         scan_exclusive(c->G.count, c->G.start, n, c->G.sums, g, true);
         hipLaunchKernelGGL(k_grid_scatter, dim3(grid_of(vcap, 256)), dim3(256), 0, g,
                            (const neb_material*)c->view.mats, (const SceneInfo*)c->sc_dev, c->V,
-                           (const int32_t*)&cnt->n_vertices, c->G);
+                           (const int32_t*)nv, c->G);
         prof_end(c, g);
     }
     // deposits of this iteration's NEE vertices into their scenes' octrees
@@ -2751,10 +2821,10 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
         // density grid over this iteration's NEE vertices
         prof_begin(c, K_DENSITY_GRID, s);
         hipLaunchKernelGGL(k_dgrid_count, dim3(grid_of(vcap, 256)), dim3(256), 0, s, (const SceneInfo*)c->sc_dev, c->V,
-                           (const int32_t*)&cnt->n_vertices, c->dg, 0);
+                           (const int32_t*)nv, c->dg, 0);
         scan_exclusive(c->dg.count, c->dg.start, (int64_t)c->dg.T + 1, c->dg.sums, s);
         hipLaunchKernelGGL(k_dgrid_scatter, dim3(grid_of(vcap, 256)), dim3(256), 0, s, (const SceneInfo*)c->sc_dev,
-                           c->V, (const int32_t*)&cnt->n_vertices, c->dg, 0);
+                           c->V, (const int32_t*)nv, c->dg, 0);
         prof_end(c, s);
     } else if (c->density_mode != NEB_DENSITY_ANALYTIC && !model) {
         hipError_t e;
@@ -2766,21 +2836,22 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
                                      (int32_t)c->slot_cap, s);
         else
             e = octree_insert_rounds(c->oct_nodes, c->oct_states, c->oct_prm_dev, c->oct_dyn, pos, 4, tagw, 8,
-                                     &cnt->n_vertices, (int32_t)vcap, c->defer, c->defer_cnt, s);
+                                     nv, (int32_t)vcap, c->defer, c->defer_cnt, s);
         prof_end(c, s);
         HIP_TRY(e);
     }
+    if (next && c->slots) HIP_TRY(fork_camera(c, s, parity ^ 1));
     // pass 2
     if (model) {
         const OctParams& P0 = c->oct_prm[0];
         prof_begin(c, K_DENSITY, s);
-        HIP_TRY(mlp_infer(c->mlp, (const float*)c->V.v0, 4, (const float*)c->V.v1, 4, &cnt->n_vertices,
+        HIP_TRY(mlp_infer(c->mlp, (const float*)c->V.v0, 4, (const float*)c->V.v1, 4, nv,
                           (int32_t)vcap, &P0, c->V.rho, 1, s));
         const int j = it - T;
         if (j == 1 || (j - 1) % c->mcfg.probe_every == 0) {
             const int n_probe = j == 1 ? (int)vcap : c->mcfg.probes;
             hipLaunchKernelGGL(k_mlp_probe, dim3(grid_of(n_probe, 256, 4096)), dim3(256), 0, s, c->V,
-                               (const int32_t*)&cnt->n_vertices, (const int32_t*)c->oct_nodes,
+                               (const int32_t*)nv, (const int32_t*)c->oct_nodes,
                                (const OctState*)c->oct_states, P0, (const OctDyn*)c->oct_dyn, j == 1 ? 1 : 0,
                                c->mcfg.probes, c->mcfg.seed, 0x50524F42u, (const Counters*)cnt, c->reg_total,
                                c->reg_bad, c->mcfg.max_rel_error, c->mlp_cnt);
@@ -2789,13 +2860,13 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
                                (const int32_t*)c->reg_bad, c->reg_gate, c->mlp_cnt);
         }
         hipLaunchKernelGGL(k_density_fallback, dim3(grid_of(vcap, 256)), dim3(256), 0, s, c->V,
-                           (const int32_t*)&cnt->n_vertices, (const int32_t*)c->reg_gate,
+                           (const int32_t*)nv, (const int32_t*)c->reg_gate,
                            (const int32_t*)c->oct_nodes, (const OctState*)c->oct_states, P0,
                            (const OctDyn*)c->oct_dyn, c->mlp_cnt);
         prof_end(c, s);
     } else if (need_rho) {
         TIMED(K_DENSITY, hipLaunchKernelGGL(k_density, dim3(grid_of(vcap, 256)), dim3(256), 0, s, A, c->V,
-                                            (const int32_t*)&cnt->n_vertices, (const int32_t*)c->oct_nodes,
+                                            (const int32_t*)nv, (const int32_t*)c->oct_nodes,
                                             (const OctState*)c->oct_states, (const OctParams*)c->oct_prm_dev,
                                             (const OctDyn*)c->oct_dyn));
     }
@@ -2803,12 +2874,12 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
     if (c->recycle) {
         prof_begin(c, K_NEE_RECYCLE, s);
         hipLaunchKernelGGL(k_dgrid_count, dim3(grid_of(vcap, 256)), dim3(256), 0, s, (const SceneInfo*)c->sc_dev, c->V,
-                           (const int32_t*)&cnt->n_vertices, c->ng, 1);
+                           (const int32_t*)nv, c->ng, 1);
         scan_exclusive(c->ng.count, c->ng.start, (int64_t)c->ng.T + 1, c->ng.sums, s);
         hipLaunchKernelGGL(k_dgrid_scatter, dim3(grid_of(vcap, 256)), dim3(256), 0, s, (const SceneInfo*)c->sc_dev,
-                           c->V, (const int32_t*)&cnt->n_vertices, c->ng, 1);
+                           c->V, (const int32_t*)nv, c->ng, 1);
         hipLaunchKernelGGL(k_nee_count, dim3(grid_of(vcap, 256)), dim3(256), 0, s, A, c->V,
-                           (const int32_t*)&cnt->n_vertices);
+                           (const int32_t*)nv);
         prof_end(c, s);
     }
     // light photons take the first entries of photon queue 0, the NEB photons follow
@@ -2819,7 +2890,7 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
     TIMED(K_NEE, nee_finish(c, A, im, s));
     if (c->recycle)
         TIMED(K_NEE_RECYCLE, hipLaunchKernelGGL(k_nee_recycle, dim3(grid_of(vcap, 256)), dim3(256), 0, s, A, c->V,
-                                                (const int32_t*)&cnt->n_vertices, im));
+                                                (const int32_t*)nv, im));
     const int64_t pcap = c->pcap;
     if (rounds > 0) {
         // the merge grid comes from the second stream, whose order puts it
@@ -2874,9 +2945,10 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
     // pass 3
     TIMED(K_FINALIZE, hipLaunchKernelGGL(k_finalize, dim3(grid_of(c->ecap, 256)), dim3(256), 0, s, A,
                                          (const float4*)c->ev0, (const float4*)c->ev1,
-                                         (const int32_t*)&cnt->n_events, (const float*)c->V.rho,
+                                         (const int32_t*)c->nevt, (const float*)c->V.rho,
                                          (const float*)c->V.ne, im));
-    hipLaunchKernelGGL(k_iter_end, dim3(1), dim3(1), 0, s, cnt);
+    hipLaunchKernelGGL(k_iter_end, dim3(1), dim3(1), 0, s, cnt, parity);
+    if (next) HIP_TRY(hipStreamWaitEvent(s, c->ev_cam_done, 0));
     // learned density, training iterations: this iteration's vertices with
     // rho > 0 form the pool, then Adam steps on batches drawn from it
     if (c->mlp_mode && !model) {
@@ -2885,7 +2957,7 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
         prof_begin(c, K_MLP_TRAIN, s);
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, c->tcount, 0, (int64_t)1);
         hipLaunchKernelGGL(k_mlp_collect, dim3(grid_of(vcap, 256)), dim3(256), 0, s, c->V,
-                           (const int32_t*)&cnt->n_vertices, c->tpos, c->tnrm, c->ttgt, c->tcount);
+                           (const int32_t*)nv, c->tpos, c->tnrm, c->ttgt, c->tcount);
         if (it == 1) HIP_TRY(mlp_norm_from_pool(c->mlp, c->ttgt, c->tcount, (int32_t)vcap, s));
         hipLaunchKernelGGL(k_fill_f32, dim3(1), dim3(64), 0, s, c->mlp.loss, 0.f, (int64_t)1);
         for (int k = 0; k < M.steps_per_iteration; ++k) {
@@ -2900,14 +2972,15 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, bool record) {
     return NEB_OK;
 }
 
-// captures one iteration on a private stream into an executable graph
-static neb_status capture(neb_ctx c) {
-    if (c->gexec) return NEB_OK;
+// captures one iteration (of the given parity and camera-pass placement) on
+// a private stream into an executable graph
+static neb_status capture(neb_ctx c, int parity, bool cam_inline, bool next, int key) {
+    if (c->gexec[key]) return NEB_OK;
     if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
     bool was = c->prof_on;
     c->prof_on = false;
-    neb_status st = enqueue_iteration(c, c->cap_stream, false);
+    neb_status st = enqueue_iteration(c, c->cap_stream, parity, cam_inline, next, false);
     c->prof_on = was;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
@@ -2925,24 +2998,33 @@ static neb_status capture(neb_ctx c) {
         (void)hipGraphDestroy(g);
         return fail(NEB_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
     }
-    c->graph = g;
-    c->gexec = x;
+    c->graph[key] = g;
+    c->gexec[key] = x;
     return NEB_OK;
 }
 
+// Iteration k of the call uses the stores of parity k & 1.  With the second
+// stream on, each iteration but the last forks the next one's camera pass
+// (none with the learned density, whose iterations differ); the last joins
+// everything, so nothing is in flight between calls.
 static neb_status render_n(neb_ctx c, int32_t n_iterations, hipStream_t s) {
+    bool cam_done = false;  // this iteration's camera pass ran beside the iteration before
     for (int i = 0; i < n_iterations; ++i) {
-        bool record = c->recs && c->first_iter_recorded == 0;
+        const int parity = i & 1;
+        const bool record = c->recs && c->first_iter_recorded == 0 && !cam_done;
+        const bool next = i + 1 < n_iterations && c->cfg.concurrent && !c->mlp_mode;
         if (c->use_graph && !c->prof_on && !record && !c->mlp_mode) {
-            neb_status st = capture(c);
+            const int key = 4 * parity + 2 * (cam_done ? 0 : 1) + (next ? 1 : 0);
+            neb_status st = capture(c, parity, !cam_done, next, key);
             if (st != NEB_OK) return st;
-            HIP_TRY(hipGraphLaunch(c->gexec, s));
+            HIP_TRY(hipGraphLaunch(c->gexec[key], s));
         } else {
-            neb_status st = enqueue_iteration(c, s, record);
+            neb_status st = enqueue_iteration(c, s, parity, !cam_done, next, record);
             if (st != NEB_OK) return st;
         }
         c->iter += 1;
         if (record) c->first_iter_recorded = c->iter;
+        cam_done = next;
     }
     return NEB_OK;
 }

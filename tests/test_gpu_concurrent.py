@@ -5,7 +5,12 @@ stream.  The two orders of execution must give the same estimator: with
 the deterministic single-thread octree the trees, the work statistics and
 the per-technique images agree up to the order of floating-point
 additions, for plain NEB, with light photons, with NEE recycling and for a
-batch of scenes; eager launches and graph replays agree too."""
+batch of scenes; eager launches and graph replays agree too.  With the
+second stream on, each iteration of a call but the last also runs the next
+iteration's camera pass on a third stream (from the iteration's start, or
+after the deposits when single-thread deposits share their slots with it);
+with the analytic density, which needs no octree, the parallel deposits
+are checked too, and so is splitting the iterations over several calls."""
 import numpy as np
 import pytest
 
@@ -82,3 +87,32 @@ def _pair_batch(neb, make, n_iter, graph):
         out.append(([B.technique_images_host(s) for s in range(len(B.scenes))], B.stats()))
         B.close()
     return out
+
+
+def _analytic(neb, conc, graph, calls):
+    sc = tiny_box(width=48, height=40, max_path_len=6)
+    R = neb.Renderer(sc, density_mode=neb.DENSITY_ANALYTIC, rho0=3000.0, cam_weight=1.0)
+    cfg = R.launch_config()
+    R.set_launch_config(cfg["bvh_stack"], cfg["trace_blocks_per_cu"], cfg["photon_blocks_per_cu"],
+                        cfg["photon_order"], cfg["nee_blocks_per_cu"], concurrent=conc)
+    R.use_graph(graph)
+    for n in calls:
+        R.render(n)
+    out = (R.technique_images_host(), R.stats())
+    R.close()
+    return out
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_next_camera_pass_beside_iteration(neb, graph):
+    ta, sa = _analytic(neb, 1, graph, [5])
+    tb, sb = _analytic(neb, 0, graph, [5])
+    tc, sc_ = _analytic(neb, 1, graph, [2, 1, 2])
+    for s_ in (sb, sc_):
+        for k in ("iterations", "camera_rays", "vertices", "photons", "photon_segments", "merges", "candidates",
+                  "shadow_rays", "nee_visible"):
+            assert sa[k] == s_[k], k
+    for t in ("e", "E", "P"):
+        assert _close(ta[t], tb[t]), t
+        assert _close(ta[t], tc[t]), t
+    assert sa["merges"] > 0 and sa["iterations"] == 5
