@@ -101,7 +101,7 @@ typedef struct {
 /* Launch shapes of the traversal and photon kernels (neb_autotune picks
  * them; results do not depend on them).  Defaults: the shallowest stack
  * that holds every BVH, 16 resident closest-hit and 16 NEE blocks per CU
- * (at most as many as the LDS holds for the stack), 8 photon-merge blocks
+ * (at most as many as the LDS holds for the stack), 24 photon-merge blocks
  * per CU, queue order, concurrent. */
 typedef struct {
     int32_t bvh_stack;            /* LDS traversal stack entries per lane: 32, 48 or 64; must

@@ -1796,7 +1796,7 @@ struct LaunchCfg {
     int trace_bpc = 16;    // closest-hit blocks (one wave each) per CU; 0 = one block per 64 queue slots,
                            // -1 = as many as the LDS holds (clamped to that for deeper stacks)
     int nee_bpc = 16;      // NEE (shadow-ray) blocks per CU, same conventions
-    int photon_bpc = 8;    // photon-merge blocks (one wave each) per CU; 0 = one block per 256 queue slots
+    int photon_bpc = 24;   // photon-merge blocks (one wave each) per CU; 0 = one block per 256 queue slots
     int photon_order = 0;  // merge photons in the spatial order of their hits
     int concurrent = 1;    // second stream for the work that can run beside other work
 };
