@@ -1837,7 +1837,8 @@ struct neb_ctx_s {
     // merge-grid build and the merges, forked after shading; joined before
     // NEE's contributions (ev_nee), before a bounce's scatter overwrites the
     // queue that the merges two bounces back read, and at the end of the
-    // bounces (ev_merge[j]: the merges of bounce j)
+    // bounces (ev_merge[j]: the merges of bounce j).  A third stream (cam,
+    // below) runs the next iteration's camera pass.
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_nee = nullptr;
     hipEvent_t ev_merge[kMaxPathLen + 1]{};
