@@ -146,11 +146,16 @@ def cpu_baseline(target_s=11.0):
 
 
 def source_digest():
-    """Digest of the sources that define the merge kernel's code."""
+    """Digest of the sources that define the merge kernel's code, with
+    comments and blank space removed (a comment edit keeps the counters)."""
+    import re
     h = hashlib.sha256()
     for f in ("neb_render.hip", "neb_device.h", "neb_internal.h"):
-        with open(os.path.join(ROOT, "paper_1909_00573_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1909_00573_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 
