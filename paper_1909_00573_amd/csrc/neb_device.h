@@ -261,20 +261,12 @@ __device__ __forceinline__ bool oct_norm(const OctParams& P, f3 p, float q[3]) {
     return true;
 }
 
-__device__ __forceinline__ float oct_query(const int32_t* __restrict__ nodes, const OctParams& P, float density_scale,
-                                           int depth, f3 p, f3 n, bool want_size, float* size_out) {
-    float q[3];
-    if (!oct_norm(P, p, q)) return 0.f;
-    int32_t grid = 1 << depth;
-    int32_t ix = (int32_t)(q[0] * (float)grid), iy = (int32_t)(q[1] * (float)grid),
-            iz = (int32_t)(q[2] * (float)grid);
-    int32_t v = nodes[P.root];
-    int32_t mask = grid;
-    while (v < 0) {
-        mask >>= 1;
-        int32_t c = ((ix & mask) ? 1 : 0) | ((iy & mask) ? 2 : 0) | ((iz & mask) ? 4 : 0);
-        v = nodes[c - v];
-    }
+// density of the leaf that a descent ended in: its word v, reached at mask
+// (grid / mask cells per axis), for the point p with integer cell
+// coordinates (ix, iy, iz) at the finest grid
+__device__ __forceinline__ float oct_leaf_density(const OctParams& P, float density_scale, int32_t grid, int32_t ix,
+                                                  int32_t iy, int32_t iz, int32_t v, int32_t mask, f3 p, f3 n,
+                                                  bool want_size, float* size_out) {
     int32_t cnt = v & kOctCountMask;
     if (cnt <= 0) return 0.f;
     int32_t res = grid / mask;
@@ -291,6 +283,23 @@ __device__ __forceinline__ float oct_query(const int32_t* __restrict__ nodes, co
     return density_scale * (float)cnt / fmaxf(min_area, area);
 }
 
+__device__ __forceinline__ float oct_query(const int32_t* __restrict__ nodes, const OctParams& P, float density_scale,
+                                           int depth, f3 p, f3 n, bool want_size, float* size_out) {
+    float q[3];
+    if (!oct_norm(P, p, q)) return 0.f;
+    int32_t grid = 1 << depth;
+    int32_t ix = (int32_t)(q[0] * (float)grid), iy = (int32_t)(q[1] * (float)grid),
+            iz = (int32_t)(q[2] * (float)grid);
+    int32_t v = nodes[P.root];
+    int32_t mask = grid;
+    while (v < 0) {
+        mask >>= 1;
+        int32_t c = ((ix & mask) ? 1 : 0) | ((iy & mask) ? 2 : 0) | ((iz & mask) ? 4 : 0);
+        v = nodes[c - v];
+    }
+    return oct_leaf_density(P, density_scale, grid, ix, iy, iz, v, mask, p, n, want_size, size_out);
+}
+
 // five probes in the tangent plane, upper median of the non-zero ones
 __device__ __forceinline__ float oct_query_robust(const int32_t* __restrict__ nodes, const OctParams& P,
                                                   float density_scale, int depth, f3 p, f3 n) {
@@ -303,9 +312,38 @@ __device__ __forceinline__ float oct_query_robust(const int32_t* __restrict__ no
     if (c0 > 0.f) d[cnt++] = c0;
     float off = diag * 1.1f;
     f3 probe[4] = {p + tx * off, p - tx * off, p + ty * off, p - ty * off};
+    // the four tangent probes descend together, one level per step, so that
+    // their node loads are in flight at once (each is the descent of
+    // oct_query; a probe outside the octree's box has density 0)
+    const int32_t grid = 1 << depth;
+    int32_t ix[4], iy[4], iz[4], v[4], mask[4];
+    const int32_t root = nodes[P.root];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        float r = oct_query(nodes, P, density_scale, depth, probe[i], n, false, nullptr);
+        float q[3];
+        const bool in = oct_norm(P, probe[i], q);
+        ix[i] = in ? (int32_t)(q[0] * (float)grid) : 0;
+        iy[i] = in ? (int32_t)(q[1] * (float)grid) : 0;
+        iz[i] = in ? (int32_t)(q[2] * (float)grid) : 0;
+        v[i] = in ? root : 0;
+        mask[i] = grid;
+    }
+    bool more = v[0] < 0 || v[1] < 0 || v[2] < 0 || v[3] < 0;
+    while (more) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (v[i] < 0) {
+                mask[i] >>= 1;
+                const int32_t c = ((ix[i] & mask[i]) ? 1 : 0) | ((iy[i] & mask[i]) ? 2 : 0) | ((iz[i] & mask[i]) ? 4 : 0);
+                v[i] = nodes[c - v[i]];
+            }
+        }
+        more = v[0] < 0 || v[1] < 0 || v[2] < 0 || v[3] < 0;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        float r = oct_leaf_density(P, density_scale, grid, ix[i], iy[i], iz[i], v[i], mask[i], probe[i], n, false,
+                                   nullptr);
         if (r > 0.f) d[cnt++] = r;
     }
     if (cnt == 0) return 0.f;
