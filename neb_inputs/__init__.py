@@ -10,6 +10,6 @@ from .scenes import (  # noqa: F401
     MAT_LAMBERT, MAT_MIRROR, MAT_DIELECTRIC, MAT_GGX,
     tiny_box, room, city_block, batch_rooms, box_room, furnace_sphere, disk_light_plane,
     point_light_plane,
-    random_triangle_soup, deposit_stream, plane_deposits, query_points,
+    random_triangle_soup, deposit_stream, plane_deposits, sphere_deposits, query_points,
     scene_by_name,
 )

@@ -536,6 +536,16 @@ def plane_deposits(n, seed, normal=(0.0, 1.0, 0.0), offset=0.437, lo=0.0, hi=1.0
     return p.astype(np.float32)
 
 
+def sphere_deposits(n, seed, center=(0.5, 0.5, 0.5), radius=0.1):
+    """n float32 points uniform on the sphere |x - center| = radius, and
+    their float32 outward unit normals."""
+    rng = np.random.default_rng(seed)
+    v = rng.normal(size=(n, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    p = np.asarray(center, np.float64) + radius * v
+    return p.astype(np.float32), v.astype(np.float32)
+
+
 def query_points(n, seed, lo=0.0, hi=1.0):
     """Random float32 query positions and unit float32 normals."""
     rng = np.random.default_rng(seed)

@@ -810,7 +810,14 @@ __global__ void __launch_bounds__(kNeeBlock) k_nee_rays(RenderArgs A, VertexStor
             ray = !is_zero3(ls.dE);
             if (ray) {
                 so = offset_origin(x, nrm, ls.w, I.eps);
-                f3 sd = ls.x - so;
+                // An area light's sample point, rounded to floats, can sit a
+                // few ulps behind its triangle; a grazing shadow ray would then
+                // cross the emitter before its end.  The ray aims at the point
+                // moved a tenth of the scene epsilon to the emitting side: a
+                // convex emitter lies wholly behind that plane, and no other
+                // surface comes that close to a light.
+                f3 tgt = ls.hittable ? ls.x + ls.n * (0.1f * I.eps) : ls.x;
+                f3 sd = tgt - so;
                 float sl = sqrtf(dot3(sd, sd));
                 dir = sd * (1.0f / sl);
                 tmax = (1.0f - 1e-5f) * sl;
@@ -2427,11 +2434,16 @@ static neb_status build_host_scene(const neb_params& prm, const float* vertices,
     double tot = 0.0;
     for (double x : w) tot += x;
     if (!(tot > 0.0)) return fail(NEB_ERR_INVALID_ARG, "scene lights carry no power");
+    // Uniforms are multiples of 2^-24, so u < c holds exactly when u is below
+    // c rounded up to that grid; the grid values are exact floats, and the
+    // device's float comparison then picks the light the exact cumulative
+    // sum picks (rounding c to the nearest float would move a boundary
+    // across a grid point now and then).
     H.cdf.assign(nl, 0.f);
     double acc = 0.0;
     for (int i = 0; i < nl; ++i) {
         acc += w[i];
-        H.cdf[i] = (float)(acc / tot);
+        H.cdf[i] = (float)(std::ceil(acc / tot * 16777216.0) / 16777216.0);
         H.lights[20 * (size_t)i + 3] = (float)(w[i] / tot);
     }
     H.cdf[nl - 1] = 1.0f;

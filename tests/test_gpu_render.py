@@ -141,8 +141,10 @@ def test_gpu_white_furnace(neb):
 
 
 def test_room_full_size_sampled_paths(neb, oracle):
-    """Room workload at its full 512x512 size: the paths of sampled pixels
-    equal the paths the oracle traces for exactly those pixels."""
+    """Room workload at its full 512x512 size: the paths of a 64 x 64 window
+    (4096 paths) equal the paths the oracle traces for exactly those
+    pixels.  View paths draw only the camera and BSDF streams of their own
+    pixel, so the oracle traces the window alone (its photons off)."""
     sc = room()
     g = neb.Renderer(sc, flags=neb.FLAG_RECORD_PATHS)
     g.render(1)
@@ -150,18 +152,20 @@ def test_room_full_size_sampled_paths(neb, oracle):
     st = g.stats()
     assert st["oct_ledger"] == st["oct_deposits"] == st["vertices"]
     rng = np.random.default_rng(0)
-    x0, y0 = int(rng.integers(0, 512 - 16)), int(rng.integers(0, 512 - 16))
-    win = (x0, y0, x0 + 16, y0 + 16)
+    x0, y0 = int(rng.integers(0, 512 - 64)), int(rng.integers(0, 512 - 64))
+    win = (x0, y0, x0 + 64, y0 + 64)
     ro = oracle.render(sc, n_iter=1, window=win, record=True, enable_photons=False)["records"]
-    pix = np.array([y * 512 + x for y in range(y0, y0 + 16) for x in range(x0, x0 + 16)])
-    frac, _ = path_agreement(rg[pix], ro, _diag(sc))
-    assert frac >= 0.99, frac
+    pix = np.array([y * 512 + x for y in range(y0, y0 + 64) for x in range(x0, x0 + 64)])
+    frac, same = path_agreement(rg[pix], ro, _diag(sc))
+    print(f"\nroom 512x512: {frac:.5f} of {len(same)} sampled view paths identical", flush=True)
+    assert frac >= 0.999, frac
 
 
 def test_city_block_full_size_sampled_paths(neb, oracle):
     """City block at its full size (1 M triangles, 1024 point lights, 5 %
-    GGX, 1024 x 1024, path length 10, octree 2^24): the paths of an 8 x 8
-    window equal the paths the oracle traces for exactly those pixels."""
+    GGX, 1024 x 1024, path length 10, octree 2^24): the paths of a 32 x 32
+    window (1024 paths) equal the paths the oracle traces for exactly
+    those pixels."""
     from neb_inputs import city_block
     sc = city_block()
     g = neb.Renderer(sc, flags=neb.FLAG_RECORD_PATHS)
@@ -172,14 +176,15 @@ def test_city_block_full_size_sampled_paths(neb, oracle):
     assert st["oct_deposits"] + st["oct_rejected"] == st["vertices"]
     W = sc.width
     rng = np.random.default_rng(3)
-    x0, y0 = int(rng.integers(0, W - 8)), int(rng.integers(W // 4, W - 8))
-    win = (x0, y0, x0 + 8, y0 + 8)
+    x0, y0 = int(rng.integers(0, W - 32)), int(rng.integers(W // 4, W - 32))
+    win = (x0, y0, x0 + 32, y0 + 32)
     ro = oracle.render(sc, n_iter=1, window=win, record=True, enable_photons=False)["records"]
-    pix = np.array([y * W + x for y in range(y0, y0 + 8) for x in range(x0, x0 + 8)])
-    frac, _ = path_agreement(rg[pix], ro, _diag(sc))
-    assert frac >= 0.98, frac
+    pix = np.array([y * W + x for y in range(y0, y0 + 32) for x in range(x0, x0 + 32)])
+    frac, same = path_agreement(rg[pix], ro, _diag(sc))
+    print(f"\ncity block: {frac:.5f} of {len(same)} sampled view paths identical", flush=True)
+    assert frac >= 0.998, frac
     # the window holds surface hits, not only sky
-    assert (rg[pix]["type"][:, 0] != 5).sum() >= 16
+    assert (rg[pix]["type"][:, 0] != 5).sum() >= 256
     g.close()
 
 
