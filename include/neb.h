@@ -118,9 +118,8 @@ typedef struct {
                                      second stream beside the octree deposits and the density, each
                                      bounce's merges beside the next bounce's closest hits, and
                                      within one neb_render call each iteration but the last runs
-                                     the next one's camera pass on a third stream (the learned
-                                     density excepted); 0: every launch on the caller's stream,
-                                     one after another */
+                                     the next one's camera pass on a third stream; 0: every launch
+                                     on the caller's stream, one after another */
 } neb_launch_config;
 
 /* One material per entry; emission is radiance leaving the front side of
@@ -354,18 +353,25 @@ const char* neb_last_error(void);
 
 typedef struct neb_mlp_s* neb_mlp;
 
-/* Settings of NEB_DENSITY_MLP.  The first train_iterations iterations use
- * the robust octree; after each, the NEE vertices with rho > 0 become the
- * training pool (position, normal, log rho) and steps_per_iteration Adam
- * steps are taken on batches of `batch` draws from it (mu, sigma are the
- * first pool's mean and standard deviation).  Later iterations take rho
- * from the model; the octree stops counting (it keeps the density of the
- * training iterations) and judges the model: all vertices of the first
- * model iteration, then `probes` random vertices every probe_every
- * iterations, are compared with the robust octree query; each of the 32^3
- * regions of the octree box keeps the model while the median of its probes'
- * relative errors is at most max_rel_error, else it falls back to the
- * octree query. */
+/* Settings of NEB_DENSITY_MLP.  The model stands in for the octree's
+ * density query (Sec. 5.3, eq. octdensity, and the five-probe median of
+ * Appendix B, get_density_robust), which stays the judge and the fallback.
+ * The first train_iterations iterations use the robust octree; after each,
+ * the NEE vertices with rho > 0 become the training pool (position, normal,
+ * log rho) and steps_per_iteration (0 allowed) Adam steps are taken on
+ * batches of `batch` draws from it (mu, sigma are the first pool's mean and
+ * standard deviation unless a model was given with neb_set_mlp_model).
+ * Later iterations take rho from the model; the octree stops counting (it
+ * keeps the density of the training iterations) and judges the model:
+ * every vertex of the first model iteration, then, every probe_every
+ * iterations, each vertex with probability probes / (vertices of the
+ * iteration) (its own draw from the probe stream, counter (pixel,
+ * iteration, depth)), is compared with the robust octree query.  A probe is
+ * over the bound when |rho_model - rho_octree| > max_rel_error * rho_octree
+ * (or rho_octree = 0 < rho_model).  Each of the 32^3 regions of the octree
+ * box keeps the model while at most a tenth of its probes so far are over
+ * the bound (the 90th percentile of their relative errors is within it),
+ * else its vertices take the octree query. */
 typedef struct {
     int32_t train_iterations;    /* default 4 */
     int32_t steps_per_iteration; /* default 250 */
@@ -385,6 +391,10 @@ typedef struct {
     int64_t probes, probes_bad;  /* probe comparisons so far, and those over the bound */
     int64_t regions_probed, regions_disabled;
     int64_t fallback_queries;    /* vertex densities taken from the octree in model iterations */
+    /* probes so far in the regions that keep the model, and those of them
+     * over the bound: their ratio estimates the fraction of model-served
+     * densities whose error exceeds max_rel_error */
+    int64_t probes_served, probes_served_bad;
 } neb_mlp_status;
 
 /* Sets the model settings of a context created with NEB_DENSITY_MLP (one
@@ -392,6 +402,19 @@ typedef struct {
  * contexts, NEB_ERR_INVALID_ARG for values out of range. */
 neb_status neb_configure_mlp(neb_ctx ctx, const neb_mlp_params* params);
 neb_status neb_get_mlp_status(neb_ctx ctx, neb_mlp_status* out);
+/* Gives the context a model (params: host, NEB_MLP_PARAMS floats in the
+ * flat layout below; log rho = mu + sigma * y) in place of the seeded
+ * initial weights, and restarts it.  The training iterations still fill the
+ * octree and take steps_per_iteration Adam steps from these weights (none
+ * with 0); mu and sigma are kept.  params == NULL returns to the seeded
+ * initial weights.  NEB_ERR_STATE for contexts without NEB_DENSITY_MLP,
+ * NEB_ERR_INVALID_ARG for non-finite values or sigma <= 0. */
+neb_status neb_set_mlp_model(neb_ctx ctx, const float* params, float mu, float sigma);
+/* The region gates (32^3 host int32 each; any may be NULL): gate[r] = 1
+ * while region r keeps the model, probes[r] and bad[r] its probe tallies.
+ * Region r = x + 32 (y + 32 z) of the cell (x, y, z) of the octree box cut
+ * 32 times per axis.  Synchronises the context's stream. */
+neb_status neb_get_mlp_gates(neb_ctx ctx, int32_t* gate, int32_t* probes, int32_t* bad);
 /* The context's model parameters (host, NEB_MLP_PARAMS floats). */
 neb_status neb_get_mlp_weights(neb_ctx ctx, float* params);
 

@@ -166,6 +166,15 @@ typedef struct {
     double density_radius;         /* R of the fixed-radius and nearest-neighbour providers (modes 4, 5) */
     int32_t knn_k;                 /* k of the nearest-neighbour provider (mode 5) */
     double nee_radius;             /* NEE recycling radius (0 = each vertex uses its own NEE only) */
+    /* learned-density runs: after iteration freeze_after (0 = never) the
+     * octree takes no deposits and keeps the scalars of that iteration */
+    int32_t freeze_after;
+    /* optional density hook, called once per iteration after the densities
+     * of pass 2 (a) with every NEE vertex of the iteration in canonical
+     * order: position, normal, pixel, depth, and rho (in: the provider's
+     * value, out: the value the iteration uses) */
+    void (*density_hook)(int32_t n, const double* pos, const double* nrm, const int32_t* pixel,
+                         const int32_t* depth, int32_t iter, double* rho);
 } o_params;
 
 typedef struct {
@@ -283,6 +292,14 @@ o_octree* orc_octree_create(const float smin[3], const float smax[3], int32_t ca
     o->density_scale = 1.0f;
     o->split_count = OCT_SPLIT_FACTOR;
     return o;
+}
+
+/* the octree's box as the cell addressing uses it */
+void orc_octree_box(const o_octree* o, float min_bound[3], float size_inv[3]) {
+    for (int i = 0; i < 3; ++i) {
+        min_bound[i] = o->min_bound[i];
+        size_inv[i] = o->size_inv[i];
+    }
 }
 
 void orc_octree_destroy(o_octree* o) {
@@ -1484,7 +1501,8 @@ int32_t orc_render(const o_scene* s, const o_params* prm, int32_t n_iter, int32_
     memset(st, 0, sizeof(*st));
     for (int32_t ii = 0; ii < n_iter; ++ii) {
         int iter = first_iter + ii;
-        if (oct) orc_octree_set_iteration(oct, iter);
+        const int frozen = prm->freeze_after > 0 && iter > prm->freeze_after;
+        if (oct && !frozen) orc_octree_set_iteration(oct, iter);
         memset(it.vid, 0, nslot * sizeof(int));
         it.nev = 0;
         o_record* r = (rec && ii == 0) ? rec : NULL;
@@ -1508,7 +1526,7 @@ int32_t orc_render(const o_scene* s, const o_params* prm, int32_t n_iter, int32_
                 }
             }
         /* deposits, sequential in canonical order */
-        if (oct) {
+        if (oct && !frozen) {
             for (int q = 0; q < it.nvert; ++q) {
                 v3 x = it.pos[IDX(&it, it.v_path[q], it.v_depth[q])];
                 float f[3] = {(float)x.x, (float)x.y, (float)x.z};
@@ -1526,6 +1544,22 @@ int32_t orc_render(const o_scene* s, const o_params* prm, int32_t n_iter, int32_
         for (int q = 0; q < it.nvert; ++q) {
             size_t id = IDX(&it, it.v_path[q], it.v_depth[q]);
             it.v_rho[q] = query_density(&it, it.pos[id], it.nrml[id]);
+        }
+        if (prm->density_hook && it.nvert > 0) {
+            double* hp = malloc(sizeof(double) * 6 * (size_t)it.nvert);
+            int32_t* hi = malloc(sizeof(int32_t) * 2 * (size_t)it.nvert);
+            for (int q = 0; q < it.nvert; ++q) {
+                size_t id = IDX(&it, it.v_path[q], it.v_depth[q]);
+                v3 x = it.pos[id], nn = it.nrml[id];
+                hp[3 * q] = x.x; hp[3 * q + 1] = x.y; hp[3 * q + 2] = x.z;
+                double* hn = hp + 3 * (size_t)it.nvert;
+                hn[3 * q] = nn.x; hn[3 * q + 1] = nn.y; hn[3 * q + 2] = nn.z;
+                hi[q] = it.pixel[it.v_path[q]];
+                hi[it.nvert + q] = it.v_depth[q];
+            }
+            prm->density_hook(it.nvert, hp, hp + 3 * (size_t)it.nvert, hi, hi + it.nvert, iter, it.v_rho);
+            free(hp);
+            free(hi);
         }
         /* n_E: the NEE events each vertex will use (recycling: all NEE
          * vertices within the radius, the vertex itself included) */

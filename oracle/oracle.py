@@ -45,7 +45,14 @@ class Params(ctypes.Structure):
                 ("win_x1", ctypes.c_int32), ("win_y1", ctypes.c_int32),
                 ("n_threads", ctypes.c_int32), ("record_paths", ctypes.c_int32),
                 ("light_photons", ctypes.c_int32), ("density_radius", ctypes.c_double),
-                ("knn_k", ctypes.c_int32), ("nee_radius", ctypes.c_double)]
+                ("knn_k", ctypes.c_int32), ("nee_radius", ctypes.c_double),
+                ("freeze_after", ctypes.c_int32), ("density_hook", ctypes.c_void_p)]
+
+
+# void hook(n, pos (n*3), nrm (n*3), pixel (n), depth (n), iteration, rho (n, in/out))
+DENSITY_HOOK = ctypes.CFUNCTYPE(None, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
+                                ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.POINTER(ctypes.c_double))
 
 
 class Stats(ctypes.Structure):
@@ -80,6 +87,7 @@ def lib():
         L.orc_octree_create.argtypes = [_P, _P, ctypes.c_int32]
         L.orc_octree_create.restype = _P
         L.orc_octree_destroy.argtypes = [_P]
+        L.orc_octree_box.argtypes = [_P, _P, _P]
         L.orc_octree_set_iteration.argtypes = [_P, ctypes.c_int32]
         L.orc_octree_clear_counters.argtypes = [_P]
         L.orc_octree_increment.argtypes = [_P, _P, ctypes.c_int64]
@@ -221,6 +229,13 @@ class Octree:
         b = np.ascontiguousarray(n, np.float64)
         return lib().orc_octree_density(self.h, _ptr(a), _ptr(b), int(robust))
 
+    def box(self):
+        """(min_bound, size_inv) float32 of the cell addressing."""
+        lo = np.zeros(3, np.float32)
+        inv = np.zeros(3, np.float32)
+        lib().orc_octree_box(self.h, _ptr(lo), _ptr(inv))
+        return lo, inv
+
     def export(self):
         info = np.zeros(8, np.int64)
         lib().orc_octree_export(self.h, None, 0, _ptr(info))
@@ -267,7 +282,7 @@ class OracleScene:
 
 def make_params(scene, density_mode=DENSITY_ROBUST, enable_photons=True, window=None, n_threads=0,
                 record=False, rho0=0.0, cam_weight=0.0, light_photons=0, density_radius=0.0, knn_k=8,
-                nee_radius=0.0, **over):
+                nee_radius=0.0, freeze_after=0, **over):
     p = Params()
     p.width = over.get("width", scene.width)
     p.height = over.get("height", scene.height)
@@ -288,20 +303,37 @@ def make_params(scene, density_mode=DENSITY_ROBUST, enable_photons=True, window=
     p.density_radius = float(density_radius)
     p.knn_k = int(knn_k)
     p.nee_radius = float(nee_radius)
+    p.freeze_after = int(freeze_after)
+    p.density_hook = None
     return p
 
 
 def render(scene, n_iter=None, first_iter=1, density_mode=DENSITY_ROBUST, enable_photons=True,
            window=None, n_threads=0, record=False, rho0=0.0, cam_weight=0.0, oscene=None,
-           octree=None, light_photons=0, density_radius=0.0, knn_k=8, nee_radius=0.0, **over):
+           octree=None, light_photons=0, density_radius=0.0, knn_k=8, nee_radius=0.0, freeze_after=0,
+           density_hook=None, **over):
     """Render `n_iter` progressive iterations (1 spp each).  Returns a dict
     with per-technique image sums (H, W, 3): e, E, P and, with
     `light_photons` > 0 conventional photons per iteration, LP; their sum,
     the mean image, the stats and, if requested, the first iteration's path
-    records."""
+    records.  freeze_after > 0 stops the octree's deposits after that
+    iteration (it keeps that iteration's scalars); density_hook(pos, nrm,
+    pixel, depth, iteration, rho) may overwrite each iteration's densities
+    (numpy arrays; rho holds the provider's values)."""
     osc = oscene or OracleScene(scene)
     prm = make_params(scene, density_mode, enable_photons, window, n_threads, record, rho0,
-                      cam_weight, light_photons, density_radius, knn_k, nee_radius, **over)
+                      cam_weight, light_photons, density_radius, knn_k, nee_radius, freeze_after, **over)
+    cb = None
+    if density_hook is not None:
+        def _hook(n, pos, nrm, pixel, depth, it, rho):
+            P = np.ctypeslib.as_array(pos, (n, 3))
+            N = np.ctypeslib.as_array(nrm, (n, 3))
+            px = np.ctypeslib.as_array(pixel, (n,))
+            dp = np.ctypeslib.as_array(depth, (n,))
+            r = np.ctypeslib.as_array(rho, (n,))
+            r[:] = density_hook(P.copy(), N.copy(), px.copy(), dp.copy(), int(it), r.copy())
+        cb = DENSITY_HOOK(_hook)
+        prm.density_hook = ctypes.cast(cb, ctypes.c_void_p)
     n_iter = scene.spp if n_iter is None else n_iter
     oct_ = octree
     if oct_ is None and density_mode in (DENSITY_SINGLE, DENSITY_ROBUST):

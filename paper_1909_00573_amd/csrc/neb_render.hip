@@ -1648,7 +1648,16 @@ __global__ void __launch_bounds__(256) k_finalize(RenderArgs A, const float4* ev
 // ---------------------------------------------------------------------------
 constexpr int kRegionRes = 32;  // regions of the octree box per axis (octree depth 5)
 constexpr int kRegions = kRegionRes * kRegionRes * kRegionRes;
-enum { kMlpCntProbes = 0, kMlpCntBad = 1, kMlpCntFallback = 2, kMlpCntDisabled = 3, kMlpCntProbed = 4, kMlpCnt = 8 };
+enum {
+    kMlpCntProbes = 0,
+    kMlpCntBad = 1,
+    kMlpCntFallback = 2,
+    kMlpCntDisabled = 3,
+    kMlpCntProbed = 4,
+    kMlpCntServed = 5,     // probes so far in regions that keep the model
+    kMlpCntServedBad = 6,  // ... of them over the bound
+    kMlpCnt = 8
+};
 
 __device__ __forceinline__ int region_of(const OctParams& P, f3 p) {
     float v[3] = {p.x, p.y, p.z};
@@ -1683,23 +1692,31 @@ __global__ void __launch_bounds__(256) k_mlp_collect(VertexStore V, const int32_
 }
 
 // Compares the model's density (already in V.rho) with the robust octree
-// query at every vertex (all != 0) or at n_probe random vertices, and adds
-// the comparisons to the per-region tallies.
+// query at every vertex (all != 0) or at a random subset, and adds the
+// comparisons to the per-region tallies.  A vertex of the subset is picked
+// by its own draw (pixel, iteration, depth; probe stream): with n vertices it
+// is probed when its 24-bit uniform u satisfies u * n < n_probe * 2^24, so
+// the expected number of probes is n_probe and the choice does not depend on
+// the order of the vertex store.
 __global__ void __launch_bounds__(256) k_mlp_probe(VertexStore V, const int32_t* n_vertices,
                                                    const int32_t* __restrict__ nodes, const OctState* ost,
                                                    OctParams P, const OctDyn* dyn, int all, int n_probe, uint32_t k0,
                                                    uint32_t k1, const Counters* cnt, int32_t* total, int32_t* bad,
                                                    float max_rel, unsigned long long* mc) {
     const int nv = *n_vertices;
-    const int count = all ? nv : (nv > 0 ? n_probe : 0);
     const int depth = ost->depth;
     const float scale = dyn->density_scale;
     const uint32_t it = (uint32_t)cnt->iter;
+    const uint64_t lim = (uint64_t)n_probe << 24;
     unsigned probes = 0, nbad = 0;
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < count; t += gridDim.x * blockDim.x) {
-        int i = t;
-        if (!all) i = (int)(((uint64_t)philox10(make_uint4((uint32_t)t, it, 0u, kTagProbe), k0, k1).x * (uint64_t)nv) >> 32);
-        f3 x = xyz(V.v0[i]), nn = xyz(V.v1[i]);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += gridDim.x * blockDim.x) {
+        float4 a0 = V.v0[i], a1 = V.v1[i];
+        if (!all) {
+            uint32_t x = philox10(make_uint4((uint32_t)fbits(a0.w), it, (uint32_t)tag_depth(fbits(a1.w)), kTagProbe),
+                                  k0, k1).x;
+            if ((uint64_t)(x >> 8) * (uint64_t)nv >= lim) continue;
+        }
+        f3 x = xyz(a0), nn = xyz(a1);
         float rm = V.rho[i];
         float ro = oct_query_robust(nodes, P, scale, depth, x, nn);
         bool b = ro > 0.f ? fabsf(rm - ro) > max_rel * ro : rm > 0.f;
@@ -1713,24 +1730,34 @@ __global__ void __launch_bounds__(256) k_mlp_probe(VertexStore V, const int32_t*
     wave_add_u64(mc + kMlpCntBad, nbad);
 }
 
-// a region keeps the model while the median of its probes' relative
-// errors is within the bound: at most half of them exceed it
+// A region keeps the model while at most a tenth of its probes so far exceed
+// the bound (the 90th percentile of their relative errors is within it); a
+// region without probes keeps it.  Also tallies the probes of the regions
+// that keep the model, and how many of those exceed the bound.
 __global__ void k_mlp_gate(const int32_t* total, const int32_t* bad, int32_t* gate, unsigned long long* mc) {
-    unsigned off = 0, probed = 0;
+    unsigned off = 0, probed = 0, served = 0, served_bad = 0;
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < kRegions; r += gridDim.x * blockDim.x) {
-        int t = total[r];
-        bool on = t == 0 || 2 * bad[r] <= t;
+        int t = total[r], b = bad[r];
+        bool on = t == 0 || 10 * b <= t;
         gate[r] = on ? 1 : 0;
         off += !on;
         probed += t > 0;
+        if (on) {
+            served += t;
+            served_bad += b;
+        }
     }
     wave_add_u64(mc + kMlpCntDisabled, off);
     wave_add_u64(mc + kMlpCntProbed, probed);
+    wave_add_u64(mc + kMlpCntServed, served);
+    wave_add_u64(mc + kMlpCntServedBad, served_bad);
 }
 
 __global__ void k_mlp_clear_gate_counts(unsigned long long* mc) {
     mc[kMlpCntDisabled] = 0;
     mc[kMlpCntProbed] = 0;
+    mc[kMlpCntServed] = 0;
+    mc[kMlpCntServedBad] = 0;
 }
 
 // vertices in disabled regions take the robust octree query instead
@@ -1891,6 +1918,11 @@ struct neb_ctx_s {
     bool mlp_mode = false;
     neb_mlp_params mcfg{};
     Mlp mlp;
+    // a model given by neb_set_mlp_model: its parameters and normalisation
+    // replace the seeded initial weights and the first pool's statistics
+    bool mlp_given = false;
+    std::vector<float> mlp_init;
+    float mlp_mu = 0.f, mlp_sigma = 1.f;
     float *tpos = nullptr, *tnrm = nullptr, *ttgt = nullptr;  // training pool
     int32_t* tcount = nullptr;
     int32_t *reg_total = nullptr, *reg_bad = nullptr, *reg_gate = nullptr;
@@ -2470,11 +2502,11 @@ static neb_status restart(neb_ctx c, hipStream_t s) {
     octree_dyn_for(d0, 1);
     HIP_TRY(octree_set_dyn(c->oct_dyn, d0, s));
     if (c->mlp_mode) {
-        std::vector<float> w = mlp_he_init(c->mcfg.seed);
+        std::vector<float> w = c->mlp_given ? c->mlp_init : mlp_he_init(c->mcfg.seed);
         HIP_TRY(hipStreamSynchronize(s));
         HIP_TRY(mlp_set_weights(c->mlp, w.data(), s));
         HIP_TRY(hipStreamSynchronize(s));
-        HIP_TRY(mlp_set_norm(c->mlp, 0.f, 1.f, s));
+        HIP_TRY(mlp_set_norm(c->mlp, c->mlp_given ? c->mlp_mu : 0.f, c->mlp_given ? c->mlp_sigma : 1.f, s));
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(kRegions, 256)), dim3(256), 0, s, c->reg_total, 0, (int64_t)kRegions);
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(kRegions, 256)), dim3(256), 0, s, c->reg_bad, 0, (int64_t)kRegions);
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(kRegions, 256)), dim3(256), 0, s, c->reg_gate, 1, (int64_t)kRegions);
@@ -2862,8 +2894,7 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, int parity, bool c
                           (int32_t)vcap, &P0, c->V.rho, 1, s));
         const int j = it - T;
         if (j == 1 || (j - 1) % c->mcfg.probe_every == 0) {
-            const int n_probe = j == 1 ? (int)vcap : c->mcfg.probes;
-            hipLaunchKernelGGL(k_mlp_probe, dim3(grid_of(n_probe, 256, 4096)), dim3(256), 0, s, c->V,
+            hipLaunchKernelGGL(k_mlp_probe, dim3(grid_of(vcap, 256, 4096)), dim3(256), 0, s, c->V,
                                (const int32_t*)nv, (const int32_t*)c->oct_nodes,
                                (const OctState*)c->oct_states, P0, (const OctDyn*)c->oct_dyn, j == 1 ? 1 : 0,
                                c->mcfg.probes, c->mcfg.seed, 0x50524F42u, (const Counters*)cnt, c->reg_total,
@@ -2971,7 +3002,7 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, int parity, bool c
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, c->tcount, 0, (int64_t)1);
         hipLaunchKernelGGL(k_mlp_collect, dim3(grid_of(vcap, 256)), dim3(256), 0, s, c->V,
                            (const int32_t*)nv, c->tpos, c->tnrm, c->ttgt, c->tcount);
-        if (it == 1) HIP_TRY(mlp_norm_from_pool(c->mlp, c->ttgt, c->tcount, (int32_t)vcap, s));
+        if (it == 1 && !c->mlp_given) HIP_TRY(mlp_norm_from_pool(c->mlp, c->ttgt, c->tcount, (int32_t)vcap, s));
         hipLaunchKernelGGL(k_fill_f32, dim3(1), dim3(64), 0, s, c->mlp.loss, 0.f, (int64_t)1);
         for (int k = 0; k < M.steps_per_iteration; ++k) {
             HIP_TRY(mlp_gradient(c->mlp, c->tpos, 3, c->tnrm, 3, c->ttgt, c->tcount, (int32_t)vcap, M.batch, 1, M.seed,
@@ -3017,15 +3048,18 @@ static neb_status capture(neb_ctx c, int parity, bool cam_inline, bool next, int
 }
 
 // Iteration k of the call uses the stores of parity k & 1.  With the second
-// stream on, each iteration but the last forks the next one's camera pass
-// (none with the learned density, whose iterations differ); the last joins
-// everything, so nothing is in flight between calls.
+// stream on, each iteration but the last forks the next one's camera pass;
+// the last joins everything, so nothing is in flight between calls.  (The
+// learned density's training, probes and fallback read only the current
+// parity's stores and the model's own buffers, so its iterations overlap
+// the same way; they are launched eagerly, since they differ from one
+// another.)
 static neb_status render_n(neb_ctx c, int32_t n_iterations, hipStream_t s) {
     bool cam_done = false;  // this iteration's camera pass ran beside the iteration before
     for (int i = 0; i < n_iterations; ++i) {
         const int parity = i & 1;
         const bool record = c->recs && c->first_iter_recorded == 0 && !cam_done;
-        const bool next = i + 1 < n_iterations && c->cfg.concurrent && !c->mlp_mode;
+        const bool next = i + 1 < n_iterations && c->cfg.concurrent;
         if (c->use_graph && !c->prof_on && !record && !c->mlp_mode) {
             const int key = 4 * parity + 2 * (cam_done ? 0 : 1) + (next ? 1 : 0);
             neb_status st = capture(c, parity, !cam_done, next, key);
@@ -3552,6 +3586,37 @@ extern "C" neb_status neb_configure_mlp(neb_ctx c, const neb_mlp_params* params)
     return NEB_OK;
 }
 
+extern "C" neb_status neb_set_mlp_model(neb_ctx c, const float* params, float mu, float sigma) {
+    if (!c) return fail(NEB_ERR_INVALID_ARG, "null context");
+    if (!c->mlp_mode) return fail(NEB_ERR_STATE, "context was not created with NEB_DENSITY_MLP");
+    if (!params) {
+        c->mlp_given = false;
+        c->mlp_init.clear();
+    } else {
+        if (!std::isfinite(mu) || !(sigma > 0.f) || !std::isfinite(sigma))
+            return fail(NEB_ERR_INVALID_ARG, "mu must be finite and sigma > 0");
+        for (int i = 0; i < kMlpParams; ++i)
+            if (!std::isfinite(params[i])) return fail(NEB_ERR_INVALID_ARG, "non-finite model parameter");
+        c->mlp_init.assign(params, params + kMlpParams);
+        c->mlp_mu = mu;
+        c->mlp_sigma = sigma;
+        c->mlp_given = true;
+    }
+    if (c->ready) return neb_reset(c);
+    return NEB_OK;
+}
+
+extern "C" neb_status neb_get_mlp_gates(neb_ctx c, int32_t* gate, int32_t* probes, int32_t* bad) {
+    if (!c) return fail(NEB_ERR_INVALID_ARG, "null context");
+    if (!c->mlp_mode) return fail(NEB_ERR_STATE, "context was not created with NEB_DENSITY_MLP");
+    if (!c->ready) return fail(NEB_ERR_STATE, "scene not set");
+    HIP_TRY(hipStreamSynchronize(c->last_stream));
+    if (gate) HIP_TRY(hipMemcpy(gate, c->reg_gate, 4 * (size_t)kRegions, hipMemcpyDeviceToHost));
+    if (probes) HIP_TRY(hipMemcpy(probes, c->reg_total, 4 * (size_t)kRegions, hipMemcpyDeviceToHost));
+    if (bad) HIP_TRY(hipMemcpy(bad, c->reg_bad, 4 * (size_t)kRegions, hipMemcpyDeviceToHost));
+    return NEB_OK;
+}
+
 extern "C" neb_status neb_get_mlp_status(neb_ctx c, neb_mlp_status* out) {
     if (!c || !out) return fail(NEB_ERR_INVALID_ARG, "null pointer");
     if (!c->mlp_mode) return fail(NEB_ERR_STATE, "context was not created with NEB_DENSITY_MLP");
@@ -3574,6 +3639,8 @@ extern "C" neb_status neb_get_mlp_status(neb_ctx c, neb_mlp_status* out) {
     out->regions_probed = (int64_t)mc[kMlpCntProbed];
     out->regions_disabled = (int64_t)mc[kMlpCntDisabled];
     out->fallback_queries = (int64_t)mc[kMlpCntFallback];
+    out->probes_served = (int64_t)mc[kMlpCntServed];
+    out->probes_served_bad = (int64_t)mc[kMlpCntServedBad];
     return NEB_OK;
 }
 

@@ -26,7 +26,7 @@ EXPORTS = [
     "neb_query_density", "neb_point_density", "neb_get_stats", "neb_get_path_records", "neb_get_octree", "neb_get_scene_octree",
     "neb_profile_kernels", "neb_get_kernel_profile", "neb_reset",
     "neb_destroy", "neb_status_string", "neb_last_error",
-    "neb_configure_mlp", "neb_get_mlp_status", "neb_get_mlp_weights", "neb_mlp_create", "neb_mlp_set_normalization",
+    "neb_configure_mlp", "neb_get_mlp_status", "neb_get_mlp_weights", "neb_set_mlp_model", "neb_get_mlp_gates", "neb_mlp_create", "neb_mlp_set_normalization",
     "neb_mlp_infer", "neb_mlp_gradient", "neb_mlp_train_step", "neb_mlp_get_params", "neb_mlp_destroy",
     "neb_octree_create", "neb_octree_set_iteration", "neb_octree_increment", "neb_octree_density",
     "neb_octree_clear_counters", "neb_octree_export", "neb_octree_destroy",
@@ -81,7 +81,8 @@ class MlpStatus(ctypes.Structure):
     _fields_ = [("phase", ctypes.c_int32), ("adam_steps", ctypes.c_int64), ("last_loss", ctypes.c_double),
                 ("mu", ctypes.c_float), ("sigma", ctypes.c_float), ("probes", ctypes.c_int64),
                 ("probes_bad", ctypes.c_int64), ("regions_probed", ctypes.c_int64),
-                ("regions_disabled", ctypes.c_int64), ("fallback_queries", ctypes.c_int64)]
+                ("regions_disabled", ctypes.c_int64), ("fallback_queries", ctypes.c_int64),
+                ("probes_served", ctypes.c_int64), ("probes_served_bad", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: (float(getattr(self, k)) if t in (ctypes.c_double, ctypes.c_float) else int(getattr(self, k)))
@@ -136,6 +137,8 @@ def lib():
             "neb_configure_mlp": ([_P, ctypes.POINTER(MlpParams)], i32),
             "neb_get_mlp_status": ([_P, ctypes.POINTER(MlpStatus)], i32),
             "neb_get_mlp_weights": ([_P, _P], i32),
+            "neb_set_mlp_model": ([_P, _P, ctypes.c_float, ctypes.c_float], i32),
+            "neb_get_mlp_gates": ([_P, _P, _P, _P], i32),
             "neb_mlp_create": ([_P, ctypes.c_uint32, i32, ctypes.POINTER(_P)], i32),
             "neb_mlp_set_normalization": ([_P, ctypes.c_float, ctypes.c_float, _P], i32),
             "neb_mlp_infer": ([_P, _P, _P, i32, _P, _P], i32),
@@ -371,6 +374,24 @@ class BatchRenderer:
         st = MlpStatus()
         _check(lib().neb_get_mlp_status(self.h, ctypes.byref(st)))
         return st.as_dict()
+
+    def set_mlp_model(self, params, mu, sigma):
+        """Use the given model (NEB_MLP_PARAMS floats; log rho = mu + sigma y)
+        instead of the seeded initial weights; None returns to those.
+        Restarts the context."""
+        if params is None:
+            _check(lib().neb_set_mlp_model(self.h, None, 0.0, 1.0))
+            return
+        w = np.ascontiguousarray(params, np.float32)
+        assert w.size == MLP_PARAMS
+        _check(lib().neb_set_mlp_model(self.h, _np_ptr(w), float(mu), float(sigma)))
+
+    def mlp_gates(self):
+        """Region gates and probe tallies, each (32, 32, 32) int32 indexed
+        [z, y, x] (region x + 32 (y + 32 z))."""
+        g, t, b = (np.zeros(32 ** 3, np.int32) for _ in range(3))
+        _check(lib().neb_get_mlp_gates(self.h, _np_ptr(g), _np_ptr(t), _np_ptr(b)))
+        return {"gate": g.reshape(32, 32, 32), "probes": t.reshape(32, 32, 32), "bad": b.reshape(32, 32, 32)}
 
     def mlp_weights(self):
         out = np.zeros(MLP_PARAMS, np.float32)

@@ -116,3 +116,33 @@ def test_next_camera_pass_beside_iteration(neb, graph):
         assert _close(ta[t], tb[t]), t
         assert _close(ta[t], tc[t]), t
     assert sa["merges"] > 0 and sa["iterations"] == 5
+
+
+def test_concurrent_equals_serial_learned_density(neb):
+    """The learned density (a given model, no training steps) with the next
+    iteration's camera pass on the third stream, against every launch on
+    one stream: same probes, gates, fallbacks and images."""
+    from oracle import mlp as M
+    theta = M.init_params(7).astype(np.float32)
+    sc = tiny_box(width=48, height=40, max_path_len=6)
+    out = []
+    for conc in (1, 0):
+        R = neb.Renderer(sc, density_mode=neb.DENSITY_MLP, flags=neb.FLAG_SINGLE_THREAD_OCTREE)
+        cfg = R.launch_config()
+        R.set_launch_config(cfg["bvh_stack"], cfg["trace_blocks_per_cu"], cfg["photon_blocks_per_cu"],
+                            cfg["photon_order"], cfg["nee_blocks_per_cu"], concurrent=conc)
+        R.configure_mlp(train_iterations=2, steps_per_iteration=0, probe_every=2, probes=500, max_rel_error=0.5)
+        R.set_mlp_model(theta, np.log(3000.0), 0.3)
+        R.render(7)
+        out.append((R.technique_images_host(), R.stats(), R.mlp_status(), R.mlp_gates()))
+        R.close()
+    (ta, sa, ma, ga), (tb, sb, mb, gb) = out
+    for k in ("vertices", "photons", "photon_segments", "merges", "nee_visible"):
+        assert sa[k] == sb[k], k
+    for k in ("probes", "probes_bad", "regions_probed", "regions_disabled", "fallback_queries", "probes_served"):
+        assert ma[k] == mb[k], k
+    assert ma["regions_disabled"] > 0 and ma["fallback_queries"] > 0 and ma["probes_served"] > 0
+    for k in ("gate", "probes", "bad"):
+        assert np.array_equal(ga[k], gb[k]), k
+    for t in ("e", "E", "P"):
+        assert _close(ta[t], tb[t]), t

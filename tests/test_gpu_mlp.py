@@ -134,9 +134,8 @@ def test_training_fits_a_smooth_density(neb):
 
 
 def test_render_with_learned_density(neb):
-    """Room at 128 x 128: two training iterations, then the model.  The
-    room's photon merges are dense enough for per-technique means to be
-    compared at 8 spp (the tiny box's caustics are not)."""
+    """Room at 128 x 128: two training iterations on the GPU's own kernels,
+    then the model with its probes, gates and octree fallback."""
     from neb_inputs import room
     sc = room(width=128, height=128)
     R = neb.Renderer(sc, density_mode=neb.DENSITY_MLP)
@@ -158,23 +157,10 @@ def test_render_with_learned_density(neb):
     tech = R.technique_images_host()
     for t in tech.values():
         assert np.all(np.isfinite(t))
-    # against the octree forms at the same spp: the same light transport.  E
-    # depends on rho only through the MIS weights.  P carries rho in the
-    # photon flux, so it moves with the density estimate: the model is fitted
-    # to the robust octree query, which on curved surfaces lies well below
-    # the one-probe query (and drifts lower over the iterations), and the
-    # model varies with the order of the gradient additions; its P must lie
-    # within 10 % of the range the two octree queries span
-    refs = {}
-    for mode in (neb.DENSITY_OCTREE_ROBUST, neb.DENSITY_OCTREE):
-        P = neb.Renderer(sc, density_mode=mode)
-        P.render(8)
-        refs[mode] = P.technique_images_host()
-        P.close()
-    assert abs(tech["E"].mean() / refs[neb.DENSITY_OCTREE_ROBUST]["E"].mean() - 1) < 0.03
-    lo = min(r["P"].mean() for r in refs.values())
-    hi = max(r["P"].mean() for r in refs.values())
-    assert 0.9 * lo <= tech["P"].mean() <= 1.1 * hi, (tech["P"].mean(), lo, hi)
+    # the served probes respect the gate: at most a tenth over the bound
+    assert s["probes_served_bad"] <= 0.1 * s["probes_served"]
+    # (the rendered images are compared with the oracle's evaluation of the
+    # same gated model in tests/test_gpu_mlp_oracle.py)
     # a tiny error bound sends every probed region back to the octree
     R.configure_mlp(train_iterations=2, steps_per_iteration=20, batch=4096, probe_every=2, probes=512,
                     max_rel_error=1e-7)
