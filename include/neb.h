@@ -283,6 +283,21 @@ neb_status neb_get_scene_technique_images(neb_ctx ctx, int32_t scene, float* e, 
 neb_status neb_point_density(const float* points, int32_t n, const float* queries, int32_t n_query, int32_t mode,
                              float radius, int32_t k, float* out, void* stream);
 
+/* neb_point_density for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments and results; it calls no hipMalloc, hipFree or
+ * allocating library routine and does not synchronise: the work is enqueued
+ * on `stream` and the call returns.  The grid lives in a fixed device array
+ * of the library (about 10.5 MB on every device it runs on, held until the
+ * process ends), so n is at most 524288 (2^19) points (NEB_ERR_CAPACITY
+ * beyond); n_query is not limited (queries and out are the caller's).  Every
+ * call on one device shares that array and rewrites all of it that it uses
+ * (the bucket counts are cleared by a kernel at the start of each call):
+ * calls that overlap on one device, e.g. on two streams without ordering,
+ * race and give wrong results. */
+neb_status neb_point_density_noalloc(const float* points, int32_t n, const float* queries, int32_t n_query,
+                                     int32_t mode, float radius, int32_t k, float* out, void* stream);
+
 /* Mean radiance of the conventional light-photon merges (LP, Sec. 4,
  * eq. stdphotonpdf) of scene `scene`: height*width*3 floats, zero when the
  * scene traces no light photons.  The image of neb_get_scene_image is the

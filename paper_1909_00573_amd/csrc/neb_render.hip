@@ -36,6 +36,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -3161,17 +3162,41 @@ extern "C" neb_status neb_get_technique_images(neb_ctx c, float* e, float* E, fl
     return neb_get_scene_technique_images(c, 0, e, E, P, is_dev, stream);
 }
 
-extern "C" neb_status neb_point_density(const float* points, int32_t n, const float* queries, int32_t n_query,
-                                        int32_t mode, float radius, int32_t k, float* out, void* stream) {
+static neb_status check_point_density(const float* points, int32_t n, const float* queries, int32_t n_query,
+                                      int32_t mode, float radius, int32_t k, float* out) {
     if (n < 0 || n_query < 0) return fail(NEB_ERR_INVALID_ARG, "negative size");
     if (mode != NEB_DENSITY_RADIUS && mode != NEB_DENSITY_KNN) return fail(NEB_ERR_INVALID_ARG, "mode must be 4 or 5");
     if (!(radius > 0.f) || !std::isfinite(radius)) return fail(NEB_ERR_INVALID_ARG, "radius must be > 0");
     if (mode == NEB_DENSITY_KNN && (k < 1 || k > kKnnMax)) return fail(NEB_ERR_INVALID_ARG, "k out of range (1 .. 16)");
-    if (n_query == 0) return NEB_OK;
-    if (!queries || !out || (n > 0 && !points)) return fail(NEB_ERR_INVALID_ARG, "null pointer");
+    if (n_query > 0 && (!queries || !out || (n > 0 && !points))) return fail(NEB_ERR_INVALID_ARG, "null pointer");
+    return NEB_OK;
+}
+
+// buckets of the point-set grid for n points
+static int32_t pset_buckets(int32_t n) {
+    return (int32_t)std::max<uint64_t>(1024, std::min<uint64_t>(next_pow2((uint64_t)std::max(n, 1)) / 2, 1u << 23));
+}
+
+// grid over the points (count, scan, scatter) and the queries, in stream order
+static void pset_enqueue(const DGrid& D, const float* points, int32_t n, const float* queries, int32_t n_query,
+                         int32_t mode, float radius, int32_t k, float* out, hipStream_t s) {
+    const float inv_cell = 1.0f / (2.0001f * radius);
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_of((int64_t)D.T + 1, 256)), dim3(256), 0, s, D.count, 0,
+                       (int64_t)D.T + 1);
+    if (n > 0) hipLaunchKernelGGL(k_pset_count, dim3(grid_of(n, 256)), dim3(256), 0, s, points, n, inv_cell, D);
+    scan_exclusive(D.count, D.start, (int64_t)D.T + 1, D.sums, s);
+    if (n > 0) hipLaunchKernelGGL(k_pset_scatter, dim3(grid_of(n, 256)), dim3(256), 0, s, points, n, inv_cell, D);
+    hipLaunchKernelGGL(k_pset_query, dim3(grid_of(n_query, 256)), dim3(256), 0, s, queries, n_query, D, radius, inv_cell,
+                       (int)mode, (int)k, out);
+}
+
+extern "C" neb_status neb_point_density(const float* points, int32_t n, const float* queries, int32_t n_query,
+                                        int32_t mode, float radius, int32_t k, float* out, void* stream) {
+    neb_status st = check_point_density(points, n, queries, n_query, mode, radius, k, out);
+    if (st != NEB_OK || n_query == 0) return st;
     hipStream_t s = (hipStream_t)stream;
     DGrid D{};
-    D.T = (int32_t)std::max<uint64_t>(1024, std::min<uint64_t>(next_pow2((uint64_t)std::max(n, 1)) / 2, 1u << 23));
+    D.T = pset_buckets(n);
     std::vector<void*> tmp;
     hipError_t e = dalloc(tmp, &D.count, (size_t)D.T + 1);
     if (e == hipSuccess) e = dalloc(tmp, &D.start, (size_t)D.T + 1);
@@ -3181,18 +3206,81 @@ extern "C" neb_status neb_point_density(const float* points, int32_t n, const fl
         free_list(tmp);
         return oom_or_device(e, "neb_point_density");
     }
-    const float inv_cell = 1.0f / (2.0001f * radius);
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_of((int64_t)D.T + 1, 256)), dim3(256), 0, s, D.count, 0,
-                       (int64_t)D.T + 1);
-    if (n > 0) hipLaunchKernelGGL(k_pset_count, dim3(grid_of(n, 256)), dim3(256), 0, s, points, n, inv_cell, D);
-    scan_exclusive(D.count, D.start, (int64_t)D.T + 1, D.sums, s);
-    if (n > 0) hipLaunchKernelGGL(k_pset_scatter, dim3(grid_of(n, 256)), dim3(256), 0, s, points, n, inv_cell, D);
-    hipLaunchKernelGGL(k_pset_query, dim3(grid_of(n_query, 256)), dim3(256), 0, s, queries, n_query, D, radius, inv_cell,
-                       (int)mode, (int)k, out);
+    pset_enqueue(D, points, n, queries, n_query, mode, radius, k, out, s);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     free_list(tmp);
     if (e != hipSuccess) return oom_or_device(e, "neb_point_density");
+    return NEB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The point-set densities without allocation: the grid of
+// neb_point_density lives in `scratch`, a fixed device array of its own on
+// every device, for callers that cannot allocate.  Its layout: bucket counts
+// and starts (kScratchBuckets + 1 ints each), the scan's block sums, then
+// the points in bucket order (float4, 256-byte aligned).
+// ---------------------------------------------------------------------------
+constexpr int32_t kScratchMaxPoints = 1 << 19;
+constexpr int32_t kScratchBuckets = 1 << 18;  // pset_buckets(kScratchMaxPoints)
+constexpr int64_t scan_scratch_c(int64_t n) {
+    int64_t tot = 0;
+    while (n > 1) {
+        n = (n + kScanTile - 1) / kScanTile;
+        tot += n;
+    }
+    return tot > 1 ? tot : 1;
+}
+constexpr size_t kScratchIntBytes =
+    ((4 * (2 * ((size_t)kScratchBuckets + 1) + (size_t)scan_scratch_c((int64_t)kScratchBuckets + 1))) + 255) & ~(size_t)255;
+constexpr size_t kScratchBytes = kScratchIntBytes + 16 * (size_t)kScratchMaxPoints;
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Device address of this device's `scratch` (the name is a host-side stand-in
+// in host code), looked up once per device with that device current.
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[256];
+
+static neb_status scratch_address(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return oom_or_device(e, "hipGetDevice");
+    if (dev < 0 || dev >= 256) return fail(NEB_ERR_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return fail(NEB_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                                                   hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return NEB_OK;
+}
+
+extern "C" neb_status neb_point_density_noalloc(const float* points, int32_t n, const float* queries,
+                                                int32_t n_query, int32_t mode, float radius, int32_t k, float* out,
+                                                void* stream) {
+    neb_status st = check_point_density(points, n, queries, n_query, mode, radius, k, out);
+    if (st != NEB_OK) return st;
+    if (n > kScratchMaxPoints)
+        return fail(NEB_ERR_CAPACITY, "neb_point_density_noalloc takes at most 524288 points (" +
+                                          std::to_string(n) + " given)");
+    if (n_query == 0) return NEB_OK;
+    void* base = nullptr;
+    st = scratch_address(&base);
+    if (st != NEB_OK) return st;
+    DGrid D{};
+    D.T = pset_buckets(n);
+    int32_t* ints = reinterpret_cast<int32_t*>(base);
+    D.count = ints;
+    D.start = ints + ((size_t)kScratchBuckets + 1);
+    D.sums = ints + 2 * ((size_t)kScratchBuckets + 1);
+    D.pts = reinterpret_cast<float4*>(reinterpret_cast<unsigned char*>(base) + kScratchIntBytes);
+    pset_enqueue(D, points, n, queries, n_query, mode, radius, k, out, (hipStream_t)stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return oom_or_device(e, "neb_point_density_noalloc");
     return NEB_OK;
 }
 

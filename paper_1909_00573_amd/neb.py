@@ -23,7 +23,7 @@ EXPORTS = [
     "neb_create", "neb_create_batch", "neb_set_scene", "neb_set_batch_scene", "neb_render", "neb_use_graph",
     "neb_autotune", "neb_set_launch_config", "neb_get_launch_config", "neb_get_image", "neb_get_scene_image",
     "neb_get_technique_images", "neb_get_scene_technique_images", "neb_get_scene_light_photon_image",
-    "neb_query_density", "neb_point_density", "neb_get_stats", "neb_get_path_records", "neb_get_octree", "neb_get_scene_octree",
+    "neb_query_density", "neb_point_density", "neb_point_density_noalloc", "neb_get_stats", "neb_get_path_records", "neb_get_octree", "neb_get_scene_octree",
     "neb_profile_kernels", "neb_get_kernel_profile", "neb_reset",
     "neb_destroy", "neb_status_string", "neb_last_error",
     "neb_configure_mlp", "neb_get_mlp_status", "neb_get_mlp_weights", "neb_set_mlp_model", "neb_get_mlp_gates", "neb_mlp_create", "neb_mlp_set_normalization",
@@ -124,6 +124,7 @@ def lib():
             "neb_get_scene_light_photon_image": ([_P, i32, _P, i32, _P], i32),
             "neb_query_density": ([_P, _P, _P, i32, _P, i32, _P], i32),
             "neb_point_density": ([_P, i32, _P, i32, i32, ctypes.c_float, i32, _P, _P], i32),
+            "neb_point_density_noalloc": ([_P, i32, _P, i32, i32, ctypes.c_float, i32, _P, _P], i32),
             "neb_get_stats": ([_P, ctypes.POINTER(Stats)], i32),
             "neb_get_path_records": ([_P, _P, i64], i32),
             "neb_get_octree": ([_P, _P, i32, _P], i32),
@@ -222,6 +223,18 @@ def point_density(points, queries, mode, radius, k=8, out=None, stream=None):
     _check(lib().neb_point_density(_dev_ptr(points) if points.numel() else None, points.shape[0],
                                    _dev_ptr(queries), m, int(mode), float(radius), int(k), _dev_ptr(out),
                                    _stream(stream)))
+    return out
+
+
+def point_density_noalloc(points, queries, mode, radius, k, out, stream=None):
+    """neb_point_density_noalloc: as point_density, into the caller's `out`
+    (an (m,) float32 device tensor), enqueued on `stream` without any
+    device allocation; at most 2^19 points."""
+    import torch
+    assert points.dtype == torch.float32 and queries.dtype == torch.float32 and out.dtype == torch.float32
+    _check(lib().neb_point_density_noalloc(_dev_ptr(points) if points.numel() else None, points.shape[0],
+                                           _dev_ptr(queries), queries.shape[0], int(mode), float(radius), int(k),
+                                           _dev_ptr(out), _stream(stream)))
     return out
 
 
