@@ -143,6 +143,8 @@ typedef struct {
 } neb_camera;
 
 typedef struct {
+    /* photons: NEB photons emitted (visible NEE samples with rho > 0, eq. flux),
+     * counted as they leave the virtual light, before their first scatter */
     int64_t iterations, paths, vertices, photons, photon_segments, merges, nee_visible, events, rays;
     /* octree: capacity, nodes allocated, depth, split failures, conserved ledger S
      * (sum of leaf counts - 4 * sum of the iteration of every allocated block),

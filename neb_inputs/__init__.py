@@ -8,7 +8,7 @@ sampling, no intersection, no density estimation.  Both the oracle under
 from .scenes import (  # noqa: F401
     MAT_DTYPE, LIGHT_DTYPE, CAM_DTYPE, Scene,
     MAT_LAMBERT, MAT_MIRROR, MAT_DIELECTRIC, MAT_GGX,
-    tiny_box, room, city_block, batch_rooms, box_room, furnace_sphere, disk_light_plane,
+    tiny_box, room, city_block, city_lots, batch_rooms, box_room, furnace_sphere, disk_light_plane,
     point_light_plane,
     random_triangle_soup, deposit_stream, plane_deposits, sphere_deposits, query_points,
     scene_by_name,

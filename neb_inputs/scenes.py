@@ -303,15 +303,22 @@ def room(width=512, height=512, spp=16, max_path_len=8, seed=7, glass_subdiv=5,
                  octree_capacity=1 << 20, merge_radius=0.02, seed=seed, scene_id=0)
 
 
-def city_block(width=1024, height=1024, spp=32, max_path_len=10, seed=3,
-               n_boxes=83000, n_lights=1024):
-    """100 x 100 m ground with ~83k random extruded boxes (footprint
-    0.3-5 m, height log-uniform 0.3-30 m, 12 triangles each; 5% GGX
-    alpha 0.05, the rest grey Lambert U[0.3, 0.8]), a 50k-triangle mirror
-    torus in one corner and 1024 point lights with power U[1, 100] W at
-    0.5-10 m height; 1024x1024, 32 spp, path length 10, octree 2^24
-    nodes, merge radius 0.1."""
+def city_block(width=1024, height=1024, spp=32, max_path_len=10, seed=3, lots=288, lot=2.1, n_lights=1024,
+               torus_quads=(200, 125), merge_radius=0.2, octree_capacity=1 << 24, light_height=(150.0, 250.0)):
+    """A city block of `lots` x `lots` building lots of `lot` metres (by
+    default 288 x 288 lots of 2.1 m: a 605 m square).  Each lot holds one
+    extruded box (12 triangles; footprint sides U[0.3, 2.0] m, height
+    log-uniform in [0.3, 30] m) placed at random inside the lot at least
+    5 cm from its edges, so no two boxes touch or interpenetrate; 5 % of the
+    boxes are white GGX alpha 0.05, the rest grey Lambert U[0.3, 0.8].  A
+    mirror torus (200 x 125 quads: 50 000 triangles) floats in one corner,
+    whose lots stay empty.  Point lights (power U[1, 100] W) hang 150-250 m
+    above the ground (aerial lighting: far above every box, a random light
+    is seen about 30 degrees up), uniform over the block.
+    1024 x 1024, 32 spp, path length 10, octree 2^24 nodes, merge radius
+    0.2 m; about 1.05 M triangles."""
     rng = np.random.default_rng(seed)
+    B = lots * lot
     rows = [{"albedo": (0.5, 0.5, 0.5)},
             {"type": MAT_MIRROR, "albedo": (0.95, 0.95, 0.95)}]
     n_grey = 16
@@ -321,16 +328,22 @@ def city_block(width=1024, height=1024, spp=32, max_path_len=10, seed=3,
     ggx = len(rows) - 1
     mats = _materials(rows)
     M = _Mesh()
-    M.grid_quad([0, 0, 0], [0, 0, 100], [100, 0, 0], 4, 4, 0)
-    # boxes, built vectorised
-    fx = rng.uniform(0.3, 5.0, n_boxes)
-    fz = rng.uniform(0.3, 5.0, n_boxes)
-    h = np.exp(rng.uniform(np.log(0.3), np.log(30.0), n_boxes))
-    x0 = rng.uniform(0.0, 100.0 - fx)
-    z0 = rng.uniform(0.0, 100.0 - fz)
-    keep = ~((x0 + fx > 82) & (z0 + fz > 82))          # leave the corner for the torus
-    fx, fz, h, x0, z0 = fx[keep], fz[keep], h[keep], x0[keep], z0[keep]
-    nb = len(fx)
+    M.grid_quad([0, 0, 0], [0, 0, B], [B, 0, 0], 4, 4, 0)
+    # one box per lot
+    R = min(5.0, 0.1 * B)
+    tc = np.array([B - 1.8 * R, 0.6 * R, B - 1.8 * R])
+    ix, iz = np.meshgrid(np.arange(lots), np.arange(lots), indexing="ij")
+    ix, iz = ix.ravel(), iz.ravel()
+    keep = ~((ix + 1) * lot > B - 3.6 * R) | ~((iz + 1) * lot > B - 3.6 * R)
+    ix, iz = ix[keep], iz[keep]
+    nb = len(ix)
+    margin = 0.05
+    fmax = min(2.0, lot - 2 * margin)
+    fx = rng.uniform(min(0.3, fmax), fmax, nb)
+    fz = rng.uniform(min(0.3, fmax), fmax, nb)
+    h = np.exp(rng.uniform(np.log(0.3), np.log(30.0), nb))
+    x0 = ix * lot + margin + rng.uniform(0, 1, nb) * (lot - 2 * margin - fx)
+    z0 = iz * lot + margin + rng.uniform(0, 1, nb) * (lot - 2 * margin - fz)
     lo = np.stack([x0, np.zeros(nb), z0], 1)
     hi = np.stack([x0 + fx, h, z0 + fz], 1)
     corners = np.zeros((nb, 8, 3))
@@ -352,19 +365,28 @@ def city_block(width=1024, height=1024, spp=32, max_path_len=10, seed=3,
     base = sum(len(a) for a in M.v[:-1])
     M.t.append(btris + base)
     M.m.append(np.repeat(bmat, 12))
-    tv, tt = torus([91.0, 3.0, 91.0], 5.0, 1.5, 200, 125)
+    tv, tt = torus(tc, R, 0.3 * R, torus_quads[0], torus_quads[1])
     M.add(tv, tt, 1)
     v, t, m = M.build()
     lights = np.zeros(n_lights, LIGHT_DTYPE)
-    lights["pos"][:, 0] = rng.uniform(0, 100, n_lights)
-    lights["pos"][:, 1] = rng.uniform(0.5, 10.0, n_lights)
-    lights["pos"][:, 2] = rng.uniform(0, 100, n_lights)
+    lights["pos"][:, 0] = rng.uniform(0, B, n_lights)
+    lights["pos"][:, 1] = rng.uniform(light_height[0], light_height[1], n_lights)
+    lights["pos"][:, 2] = rng.uniform(0, B, n_lights)
     p = rng.uniform(1.0, 100.0, n_lights)
     lights["power"] = np.stack([p, p, p], 1)
     return Scene("city_block", v, t, m, mats, lights,
-                 _camera([-8.0, 30.0, -8.0], [55.0, 0.0, 55.0], (0, 1, 0), 55.0),
+                 _camera([-0.05 * B, 0.45 * B, -0.05 * B], [0.5 * B, 0.0, 0.5 * B], (0, 1, 0), 45.0),
                  width=width, height=height, spp=spp, max_path_len=max_path_len,
-                 octree_capacity=1 << 24, merge_radius=0.1, seed=seed, scene_id=0)
+                 octree_capacity=octree_capacity, merge_radius=merge_radius, seed=seed, scene_id=0)
+
+
+def city_lots(width=48, height=48, spp=4, lots=12, n_lights=64, seed=3):
+    """The city block's recipe on a small block (12 x 12 lots of 2.1 m, 64
+    point lights, a 24 x 12-quad mirror torus): GGX boxes, a mirror and
+    power-sampled point lights at path length 10, small enough for the
+    brute-force oracle."""
+    return city_block(width=width, height=height, spp=spp, seed=seed, lots=lots, n_lights=n_lights,
+                      torus_quads=(24, 12), octree_capacity=1 << 20)
 
 
 def _box_room_scene(rng, n_target, n_lights, res, spp, seed, scene_id):
@@ -557,4 +579,4 @@ def query_points(n, seed, lo=0.0, hi=1.0):
 
 def scene_by_name(name, **kw):
     return {"tiny_box": tiny_box, "room": room, "city_block": city_block,
-            "furnace": furnace_sphere, "disk_light": disk_light_plane}[name](**kw)
+            "furnace": furnace_sphere, "disk_light": disk_light_plane, "city_lots": city_lots}[name](**kw)

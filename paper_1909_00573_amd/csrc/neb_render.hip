@@ -893,6 +893,9 @@ __global__ void __launch_bounds__(kNeeBlock) k_nee_finish(RenderArgs A, VertexSt
                     }
                 }
                 if (A.photons && rho > 0.f) {
+                    // the photon leaves the virtual light (counted), and enters
+                    // the queue if its first scatter at x survives
+                    ++emitted;
                     U4 up = uniforms(I.k0, I.k1, lpix, (uint32_t)iter, (uint32_t)(16 * k), kTagPhoton);
                     s = bsdf_sample(m, nrm, ls.w, up);
                     photon = s.ev != 0;
@@ -901,7 +904,6 @@ __global__ void __launch_bounds__(kNeeBlock) k_nee_finish(RenderArgs A, VertexSt
         }
         const int slot = block_reserve<kNeeBlock / 64>(pcount, photon, wc, &bb);
         if (photon) {
-            ++emitted;
             float fo = ls.hittable ? bsdf_pdf(m, nrm, s.dir, ls.w) * ls.cos_l / (ls.d2 * ls.p_light) : 0.f;
             float dnon = mat_delta(m.type) ? 0.f : 1.f;
             // with light photons every merge of this photon gains the factor 1 + c

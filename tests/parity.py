@@ -57,3 +57,33 @@ def path_agreement(rg, ro, diag, tol=1e-4):
 def scene_diag(sc):
     lo, hi = sc.bbox()
     return float(np.linalg.norm(hi.astype(np.float64) - lo))
+
+
+def leaf_cells(nodes):
+    """Leaf cells of an exported octree node array, keyed by their place in
+    the tree (depth, x, y, z at that depth), independent of the order in
+    which blocks were allocated: {key: count word}.  A word >= 0 is a leaf
+    (count, with a split-failed flag in bit 30), a word < 0 the index of
+    the first of eight children (child c = x + 2 y + 4 z)."""
+    nodes = np.asarray(nodes)
+    out = {}
+    stack = [(0, 0, 0, 0, 0)]
+    while stack:
+        idx, d, x, y, z = stack.pop()
+        w = int(nodes[idx])
+        if w >= 0:
+            out[(d, x, y, z)] = w
+            continue
+        first = -w
+        for c in range(8):
+            stack.append((first + c, d + 1, 2 * x + (c & 1), 2 * y + ((c >> 1) & 1), 2 * z + ((c >> 2) & 1)))
+    return out
+
+
+def cell_agreement(nodes_a, nodes_b):
+    """Fraction of the leaf cells of either tree that the other has with
+    the same count."""
+    a, b = leaf_cells(nodes_a), leaf_cells(nodes_b)
+    keys = set(a) | set(b)
+    same = sum(1 for k in keys if a.get(k) == b.get(k))
+    return same / max(1, len(keys))

@@ -176,7 +176,7 @@ def test_city_block_full_size_sampled_paths(neb, oracle):
     assert st["oct_deposits"] + st["oct_rejected"] == st["vertices"]
     W = sc.width
     rng = np.random.default_rng(3)
-    x0, y0 = int(rng.integers(0, W - 32)), int(rng.integers(W // 4, W - 32))
+    x0, y0 = int(rng.integers(0, W - 32)), int(rng.integers(W // 2, W - 32))
     win = (x0, y0, x0 + 32, y0 + 32)
     ro = oracle.render(sc, n_iter=1, window=win, record=True, enable_photons=False)["records"]
     pix = np.array([y * W + x for y in range(y0, y0 + 32) for x in range(x0, x0 + 32)])
