@@ -40,8 +40,10 @@ HBM_PEAK_GBS = 8000.0
 
 def algorithmic_bytes(stats, name, npix, vertices):
     """Bytes each kernel must move for the work it did (data layouts of the
-    library: 16-byte float4 state words, 4-byte ints).  Traversal and cache
-    re-reads are excluded: this is the algorithmic minimum."""
+    library: 16-byte float4 state words, 4-byte ints; the traversal kernels
+    count every BVH node (64 bytes) and triangle (48 bytes) they fetch).
+    Cache re-reads beyond that are excluded: this is the algorithmic
+    minimum for the work the counters saw."""
     s = stats
     if name == "photon_merge":
         # photon state + U + hit in, two cell bounds per cell, one packed
@@ -56,10 +58,15 @@ def algorithmic_bytes(stats, name, npix, vertices):
         rays = s["rays_camera"]
         return rays * (64 + 8) + vertices * 64 + s["continued_camera"] * 64 + s["events"] * 32
     if name == "nee":
-        return vertices * (64 + 4) + s["photons"] * 52 + s["nee_visible"] * 24
+        # light samples and shadow rays, their traversal (64-byte nodes,
+        # 48-byte triangles), contributions and photons
+        return (vertices * (64 + 4) + s["photons"] * 52 + s["nee_visible"] * 24 +
+                s["bvh_nodes_shadow"] * 64 + s["bvh_tris_shadow"] * 48)
     if name in ("extend_camera", "extend_photon"):
-        rays = s["rays_camera"] if name == "extend_camera" else s["photon_items"]
-        return rays * (16 + 16 + 8)
+        # ray in, hit out, and the traversal's node and triangle fetches
+        kind = "camera" if name == "extend_camera" else "photon"
+        rays = s["rays_camera"] if kind == "camera" else s["photon_items"]
+        return rays * (16 + 16 + 8) + s["bvh_nodes_" + kind] * 64 + s["bvh_tris_" + kind] * 48
     if name == "density":
         return vertices * (16 + 16 + 4)
     if name == "octree_insert":
@@ -180,15 +187,178 @@ def committed_traffic(kernel):
         return None
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+# multiply-adds of the model per sample, counted as 2 FLOP each: forward
+# 80x64 + 64x64 + 64x64 + 64; training adds the backward data pass through
+# W3 and W2 and the three weight-gradient products
+MLP_FWD_FLOP = 2 * (80 * 64 + 64 * 64 + 64 * 64 + 64)
+MLP_TRAIN_FLOP = MLP_FWD_FLOP + 2 * (64 * 64 + 64 * 64) + 2 * (80 * 64 + 64 * 64 + 64 * 64)
+
+
+def mlp_roofline(stream, n_query=1835008, batch=65536, reps=20):
+    """The learned density's kernels on the matrix cores: inference over
+    n_query points (the room's NEE vertex slots of one iteration) and
+    training steps (forward, backward, weight gradients, Adam) on batches of
+    `batch`, each timed with HIP events on the launch stream; FLOPs count
+    the model's multiply-adds, the peak is the dense bf16 one."""
+    import numpy as np
+    import torch
+    from neb_inputs import query_points
+    from paper_1909_00573_amd import neb
+    q, nn = query_points(n_query, 5)
+    Q = torch.from_numpy(q).cuda()
+    N = torch.from_numpy(nn).cuda()
+    T = torch.from_numpy(np.sin(7 * q[:batch, 0]).astype(np.float32) + 3.0).cuda()
+    m = neb.Mlp(seed=1, max_batch=batch)
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(k):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / 1e3 / k
+
+    t_inf = timed(lambda: m.infer(Q, N, stream=stream), reps)
+    Qb, Nb = Q[:batch].contiguous(), N[:batch].contiguous()
+    t_trn = timed(lambda: m.train_step(Qb, Nb, T, lr=1e-3, stream=stream), reps)
+    m.close()
+    out = {}
+    for name, t, flop in (("infer", t_inf, MLP_FWD_FLOP * n_query), ("train_step", t_trn, MLP_TRAIN_FLOP * batch)):
+        ach = flop / t / 1e12
+        out[name] = {"bound": "mfma", "achieved": round(ach, 2), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(ach / MFMA_BF16_PEAK_TFLOPS, 5), "us_per_call": round(1e6 * t, 1),
+                     "flop_per_call": int(flop)}
+    out["infer"]["queries"] = n_query
+    out["train_step"]["batch"] = batch
+    return out
+
+
+def atomics_run(stream, blocks=2048, ops=16):
+    """Device-scope atomic throughput (neb_atomic_probe): returning atomic
+    adds and compare-and-swap increments over 2^20 words (4 MB, the room
+    octree's node array) packed or one per 128-byte line, and on one word;
+    G operations per second."""
+    import torch
+    from paper_1909_00573_amd import neb
+    out = {}
+    sink = torch.zeros(blocks * 256, dtype=torch.int32, device="cuda")
+    for label, n_words, stride, nblk, k_ops in (("2^20 words packed", 1 << 20, 1, blocks, ops),
+                                                 ("2^20 words, one per line", 1 << 20, 32, blocks, ops),
+                                                 ("one word", 1, 1, 64, 4)):
+        words = torch.zeros(n_words * stride, dtype=torch.int32, device="cuda")
+        row = {}
+        for kind, kname in ((0, "add"), (1, "cas")):
+            neb.atomic_probe(words, n_words, stride, nblk, 1, kind, sink, stream=stream)
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            neb.atomic_probe(words, n_words, stride, nblk, k_ops, kind, sink, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            t = a.elapsed_time(b) / 1e3
+            n = nblk * 256 * k_ops
+            row[kname + "_G_per_s"] = round(n / t / 1e9, 3)
+        out[label] = row
+        del words
+    return out
+
+
+def octree_saturation(stream, steps=16):
+    """How the room's octree capacity (2^20 nodes, which its first iteration
+    fills) moves the density: the robust query of the default tree against
+    the same workload's tree with 2^23 nodes after `steps` iterations, at
+    the surface points of the first iteration's view vertices; and both
+    against the k-nearest-neighbour estimate (k = 8) over those vertices
+    (one iteration's worth, so noisier, but with no tree)."""
+    import numpy as np
+    import torch
+    from neb_inputs import room
+    from paper_1909_00573_amd import neb
+    sc = room()
+    dens, info = {}, {}
+    pts = nrm = None
+    for cap in (1 << 20, 1 << 23):
+        R = neb.Renderer(sc.with_settings(octree_capacity=cap), flags=neb.FLAG_RECORD_PATHS)
+        R.render(steps, stream=stream)
+        st = R.stats()
+        info[cap] = {"nodes": st["oct_allocated"], "split_failures": st["oct_overflow"], "depth": st["oct_depth"]}
+        if pts is None:
+            rec = R.records()
+            live = (rec["type"] >= 1) & (rec["type"] <= 4)
+            pos = rec["pos"][live].astype(np.float32)
+            prim = rec["prim"][live]
+            v = sc.vertices.astype(np.float64)
+            t = sc.tris[prim]
+            n = np.cross(v[t[:, 1]] - v[t[:, 0]], v[t[:, 2]] - v[t[:, 0]])
+            n /= np.linalg.norm(n, axis=1, keepdims=True)
+            pts = torch.from_numpy(pos).cuda()
+            nrm = torch.from_numpy(n.astype(np.float32)).cuda()
+        dens[cap] = R.query_density(pts, nrm, stream=stream).cpu().numpy().astype(np.float64)
+        R.close()
+    knn = neb.point_density(pts, pts, neb.DENSITY_KNN, 0.04, k=8, stream=stream).cpu().numpy().astype(np.float64)
+    a, b = dens[1 << 20], dens[1 << 23]
+    ok = (a > 0) & (b > 0) & (knn > 0)
+
+    def rel(x, y):
+        d = np.abs(x[ok] / y[ok] - 1)
+        return {"median": round(float(np.median(d)), 4), "p90": round(float(np.quantile(d, 0.9)), 4),
+                "over_10pct": round(float(np.mean(d > 0.1)), 4)}
+
+    return {"points": int(len(a)), "trees": {str(k): v for k, v in info.items()},
+            "default_vs_2^23": rel(a, b), "default_vs_knn": rel(a, knn), "2^23_vs_knn": rel(b, knn),
+            "note": "relative differences of the robust octree density at the first iteration's view vertices "
+                    "after %d iterations; knn over those vertices only (one iteration)" % steps}
+
+
+def tiny_box_run(stream, reps=50):
+    """The tiny box workload whole (64 x 64, its 4 spp, path length 5,
+    octree capacity 4096, robust density): reset and render its 4
+    iterations, `reps` times; inputs resident."""
+    import torch
+    from neb_inputs import tiny_box
+    from paper_1909_00573_amd import neb
+    sc = tiny_box()
+    R = neb.Renderer(sc)
+    R.render(sc.spp, stream=stream)
+    torch.cuda.synchronize()
+    R.reset()
+    s0 = R.stats()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        R.reset()
+        R.render(sc.spp, stream=stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    sec = a.elapsed_time(b) / 1e3
+    st = R.stats()
+    R.close()
+    paths = sc.width * sc.height * sc.spp * reps
+    return {"workload": "tiny box: unit box, %d triangles, mirror sphere, 0.1 m ceiling light; %dx%d, %d spp, "
+                        "path length %d, octree capacity %d, robust octree density" %
+                        (sc.n_tris, sc.width, sc.height, sc.spp, sc.max_path_len, sc.octree_capacity),
+            "renders": reps, "ms_per_render": round(1e3 * sec / reps, 3),
+            "camera_paths_per_s": round(paths / sec, 1),
+            # the statistics restart at each reset: st holds the last render's work
+            "photons_per_s": round(st["photons"] * reps / sec, 1),
+            "work_per_render": {k: st[k] for k in ("vertices", "photons", "photon_segments", "merges")},
+            "octree": {"nodes": st["oct_allocated"], "capacity": st["oct_capacity"], "overflow": st["oct_overflow"]},
+            "note": "each render is the whole 4-spp job after a reset (the reset included)"}
+
+
 def city_block_run(stream, graph, steps=8, warmup=2):
-    """Throughput on the city block (100 x 100 m, ~1.01 M triangles, 1024
-    point lights sampled by power, 1024 x 1024, path length 10, octree 2^24
-    nodes, merge radius 0.1 m): the largest workload, timed like the room
-    (inputs resident, warm-up, then a reset).  Its recipe covers the
-    ground many times over with boxes (83 000 footprints of 0.3-5 m on
-    10 000 m^2) and puts the lights at 0.5-10 m, mostly inside that mass,
-    so few NEE connections are unoccluded: it measures traversal and the
-    octree at a million triangles more than photon transport."""
+    """Throughput on the city block (288 x 288 lots of 2.1 m, one box each,
+    ~1.05 M triangles, a 50k-triangle mirror torus, 1024 point lights
+    sampled by power 150-250 m above the block, 1024 x 1024, path length
+    10, octree 2^24 nodes, merge radius 0.2 m): the largest workload, timed
+    like the room (inputs resident, warm-up, then a reset)."""
     import torch
     from neb_inputs import city_block
     from paper_1909_00573_amd import neb
@@ -211,8 +381,9 @@ def city_block_run(stream, graph, steps=8, warmup=2):
     st = R.stats()
     R.close()
     npix = sc.width * sc.height
-    return {"workload": "city block: 100x100 m, %d triangles, mirror torus, %d point lights; %dx%d, path length %d, "
-                        "octree 2^24 nodes, merge radius %.2f m, robust octree density" %
+    return {"workload": "city block: 605x605 m of 2.1 m lots, one box per lot, %d triangles, mirror torus, %d point "
+                        "lights 150-250 m up; %dx%d, path length %d, octree 2^24 nodes, merge radius %.2f m, robust "
+                        "octree density" %
                         (sc.n_tris, len(sc.point_lights), sc.width, sc.height, sc.max_path_len, sc.merge_radius),
             "steps": steps, "ms_per_step": round(1e3 * sec / steps, 3),
             "camera_paths_per_s": round(npix * steps / sec, 1),
@@ -282,7 +453,7 @@ def batch_comparison(stream, cfg_trials=1):
             "photons": int(st["photons"]), "launch_config": cfg,
             "batched_s": round(t_batch, 4), "batched_graph_serialized_s": round(t_graph, 4), "sequential_s": round(t_seq, 4),
             "batched_paths_per_s": round(paths / t_batch, 1), "sequential_paths_per_s": round(paths / t_seq, 1),
-            "speedup": round(t_seq / min(t_batch, t_graph), 3),
+            "speedup": round(t_seq / t_batch, 3), "speedup_graph": round(t_seq / t_graph, 3),
             "host_setup_s": {"generate": round(t_gen, 1), "bvh_and_pools": round(t_build, 1)}}
 
 
@@ -291,8 +462,18 @@ def rel_rmse(img, ref):
     return float(np.sqrt(np.mean((img.astype(np.float64) - ref) ** 2)) / np.mean(ref))
 
 
-def quality_comparison(stream, spp=64, ref_spp=1024, train_iterations=4, check_every=4):
-    """Error against time on the room for four forms, each rendered to
+def block_rel_rmse(img, ref, k=8):
+    """Relative RMSE of k x k pixel block means: insensitive to single bright
+    pixels, sensitive to bias."""
+    import numpy as np
+    H, W = ref.shape[:2]
+    a = img[:H - H % k, :W - W % k].astype(np.float64).reshape(H // k, k, W // k, k, -1).mean(axis=(1, 3))
+    r = ref[:H - H % k, :W - W % k].reshape(H // k, k, W // k, k, -1).mean(axis=(1, 3))
+    return float(np.sqrt(np.mean((a - r) ** 2)) / np.mean(r))
+
+
+def quality_comparison(stream, spp=64, ref_spp=1024, target_spp=16, train_iterations=4, check_every=4):
+    """Error against time on the room for several forms, each rendered to
     `spp` and checked every `check_every` iterations against a reference:
     - plain: NEB with the robust octree density (the headline form);
     - single_probe: NEB with the one-probe octree density;
@@ -302,21 +483,18 @@ def quality_comparison(stream, spp=64, ref_spp=1024, train_iterations=4, check_e
       first `train_iterations` iterations, then used with region-gated
       octree fallback);
     - fixed_radius, knn: NEB with the two estimators Sec. 5 tried before
-      the octree, over each iteration's NEE vertices (radius 0.04 m; k = 8
-      within 0.04 m);
+      the octree (radius 0.04 m; k = 8 within 0.04 m);
     - path_tracing, path_tracing_recycled: no photons, NEE as usual or
       recycled from the NEE vertices within 0.02 m (Sec. 6's experiment).
-    Each form also reports its density stage per iteration (octree
-    deposits and queries, or density-grid build and queries; GPU events).
     The reference is path tracing with NEE and light photons (no NEB
-    photons, so no density estimate enters it) at `ref_spp` with another
-    seed.  Reports each form's relative RMSE and mean deviation at `spp`,
-    and the time each form needs to reach the lowest RMSE the plain form
-    reaches on its way to `spp` (its error grows again later: the robust
-    query's density on curved and edged geometry decays over the
-    iterations), with the speedup over the plain form's time to that RMSE
-    (render time only: GPU events around the render calls, the checks
-    excluded)."""
+    photons, so no density estimate enters it) at `ref_spp`, seed + 1000;
+    the same estimator equals the FP64 oracle element by element at a
+    reduced size (tests/test_gpu_room_parity.py), and a second reference
+    from seed + 2000 gives its own error.  Errors: relative RMSE (R22) and
+    the same over 8 x 8 pixel block means.  The target is the plain form's
+    error at `target_spp` (the workload's spp); each form reports the
+    samples and the render time (GPU events around the render calls, the
+    checks excluded) to reach it, by either measure."""
     import numpy as np
     import torch
     from neb_inputs import room
@@ -333,11 +511,17 @@ def quality_comparison(stream, spp=64, ref_spp=1024, train_iterations=4, check_e
 
     sc = room()
     nlp = sc.width * sc.height
-    ref_sc = sc.with_settings(seed=sc.seed + 1000)
-    R = neb.Renderer(ref_sc, flags=neb.FLAG_NO_PHOTONS, light_photons=nlp)
-    ref_s = timed(lambda: R.render(ref_spp, stream=stream))
-    ref = R.image_host().astype(np.float64)
-    R.close()
+    refs = []
+    ref_s = 0.0
+    for off in (1000, 2000):
+        R = neb.Renderer(sc.with_settings(seed=sc.seed + off), flags=neb.FLAG_NO_PHOTONS, light_photons=nlp)
+        ref_s += timed(lambda: R.render(ref_spp, stream=stream))
+        refs.append(R.image_host().astype(np.float64))
+        R.close()
+    ref = refs[0]
+    # two independent references: their difference has sqrt(2) x the error of one
+    ref_err = rel_rmse(refs[1], ref) / np.sqrt(2.0)
+    ref_err_block = block_rel_rmse(refs[1], ref) / np.sqrt(2.0)
 
     density_ms = {}
 
@@ -347,7 +531,7 @@ def quality_comparison(stream, spp=64, ref_spp=1024, train_iterations=4, check_e
         for it in range(check_every, spp + 1, check_every):
             t += timed(lambda: R.render(check_every, stream=stream))
             img = R.image_host().astype(np.float64)
-            curve.append((it, t, rel_rmse(img, ref), img.mean() / ref.mean() - 1))
+            curve.append((it, t, rel_rmse(img, ref), block_rel_rmse(img, ref), img.mean() / ref.mean() - 1))
         prof = R.kernel_profile()
         R.profile_kernels(False)
         density_ms[name] = round(sum(prof.get(k, {"total_ms": 0.0})["total_ms"]
@@ -369,34 +553,43 @@ def quality_comparison(stream, spp=64, ref_spp=1024, train_iterations=4, check_e
     curves["learned"] = progression("learned", M)
     status = M.mlp_status()
     M.close()
-    best = min(curves["plain"], key=lambda r: r[2])
-    target = best[2]
+    at = next(r for r in curves["plain"] if r[0] == target_spp)
+    target, target_block = at[2], at[3]
 
-    def time_to(curve):
-        for it, t, e, _ in curve:
-            if e <= target:
-                return it, t
+    def time_to(curve, idx, tgt):
+        for r in curve:
+            if r[idx] <= tgt:
+                return r[0], r[1]
         return None, None
 
     forms = {}
     for name, c in curves.items():
-        it, t = time_to(c)
-        forms[name] = {"rel_rmse": round(c[-1][2], 5), "mean_deviation": round(c[-1][3], 5),
+        it, t = time_to(c, 2, target)
+        itb, tb = time_to(c, 3, target_block)
+        forms[name] = {"rel_rmse": round(c[-1][2], 5), "block_rel_rmse": round(c[-1][3], 5),
+                       "mean_deviation": round(c[-1][4], 5),
                        "s": round(c[-1][1], 4), "ms_per_spp": round(1e3 * c[-1][1] / spp, 3),
-                       "min_rel_rmse": round(min(r[2] for r in c), 5),
                        "density_ms_per_spp": density_ms[name],
                        "spp_to_target": it, "s_to_target": None if t is None else round(t, 4),
-                       "speedup_to_target": None if t is None else round(best[1] / t, 3),
-                       "curve": [[i, round(tt, 4), round(e, 5)] for i, tt, e, _ in c]}
+                       "speedup_to_target": None if t is None else round(at[1] / t, 3),
+                       "spp_to_block_target": itb, "s_to_block_target": None if tb is None else round(tb, 4),
+                       "speedup_to_block_target": None if tb is None else round(at[1] / tb, 3),
+                       "curve": [[i, round(tt, 4), round(e, 5), round(eb, 5), round(md, 5)]
+                                 for i, tt, e, eb, md in c]}
     return {"workload": "room 512x512, %d spp per form; light photons: %d per iteration; learned density "
                         "trained on the octree for %d iterations (250 Adam steps x 65536 each)" %
                         (spp, nlp, train_iterations),
-            "reference": "path tracing with NEE and %d light photons per iteration, %d spp, seed %d (%.1f s)" %
-                         (nlp, ref_spp, ref_sc.seed, ref_s),
-            "target": "the plain form's lowest relative RMSE, %.5f at %d spp" % (target, best[0]),
+            "reference": "path tracing with NEE and %d light photons per iteration, %d spp, seed %d (two references "
+                         "%.1f s); its own relative RMSE %.5f, block %.5f" %
+                         (nlp, ref_spp, sc.seed + 1000, ref_s, ref_err, ref_err_block),
+            "reference_rel_rmse": round(ref_err, 5), "reference_block_rel_rmse": round(ref_err_block, 5),
+            "target": "the plain form's error at %d spp: relative RMSE %.5f, block %.5f" %
+                      (target_spp, target, target_block),
+            "curve_columns": ["spp", "s", "rel_rmse", "block_rel_rmse", "mean_deviation"],
             "forms": forms,
             "learned_model": {k: status[k] for k in ("adam_steps", "last_loss", "probes", "probes_bad",
-                                                     "regions_probed", "regions_disabled", "fallback_queries")}}
+                                                     "regions_probed", "regions_disabled", "fallback_queries",
+                                                     "probes_served", "probes_served_bad")}}
 
 
 def main():
@@ -410,6 +603,10 @@ def main():
     ap.add_argument("--no-quality", "--no-learned", dest="no_quality", action="store_true",
                     help="skip the error-against-time comparison (plain, light photons, learned density)")
     ap.add_argument("--no-city", action="store_true", help="skip the city-block throughput run")
+    ap.add_argument("--no-tiny", action="store_true", help="skip the tiny-box throughput run")
+    ap.add_argument("--no-mlp", action="store_true", help="skip the learned density's matrix-core roofline")
+    ap.add_argument("--no-octree-extra", action="store_true",
+                    help="skip the atomic-throughput probe and the octree capacity comparison")
     ap.add_argument("--graph", action="store_true",
                     help="replay the captured iteration as a HIP graph (default: launch from the host)")
     ap.add_argument("--no-serialized", action="store_true",
@@ -500,12 +697,28 @@ def main():
                    "depth": st["oct_depth"], "overflow": st["oct_overflow"]},
         "work_per_step": {k: round((st[k] - s0[k]) / args.steps) for k in
                           ("vertices", "photons", "photon_segments", "merges", "candidates", "grid_cells",
-                           "camera_rays", "shadow_rays", "bvh_nodes", "bvh_tris")},
+                           "camera_rays", "shadow_rays", "bvh_nodes", "bvh_tris", "bvh_nodes_camera",
+                           "bvh_nodes_photon", "bvh_nodes_shadow", "bvh_tris_camera", "bvh_tris_photon",
+                           "bvh_tris_shadow")},
         "roofline": roof, "kernels": kernels, "launch_config": launch_cfg,
         "timed_launches": "graph replay" if args.graph else "eager",
         "roofline_serialized": roof_ser, "kernels_serialized": kernels_ser,
     }
     R.close()
+    if not args.no_mlp:
+        out["roofline_mlp"] = mlp_roofline(stream)
+    if not args.no_octree_extra:
+        out["atomics"] = atomics_run(stream)
+        ins = kernels_ser.get("octree_insert") if kernels_ser else None
+        if ins:
+            # deposits of the serialised pass over the same steps, per second of octree_insert alone
+            rate = (st["oct_deposits"] - s0["oct_deposits"]) / (ins["ms"] * 1e-3) / 1e9
+            cas = out["atomics"]["2^20 words packed"]["cas_G_per_s"]
+            out["atomics"]["octree_insert_deposits_G_per_s"] = round(rate, 3)
+            out["atomics"]["octree_insert_frac_of_cas"] = round(rate / cas, 4)
+        out["octree_saturation"] = octree_saturation(stream)
+    if not args.no_tiny:
+        out["tiny_box"] = tiny_box_run(stream)
     if not args.no_city:
         out["city_block"] = city_block_run(stream, args.graph)
     if not args.no_batch:

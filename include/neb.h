@@ -163,6 +163,9 @@ typedef struct {
     /* conventional light photons emitted (their segments and merges are
      * counted with the NEB photons') */
     int64_t light_photons;
+    /* bvh_nodes and bvh_tris split by the rays that did the work: camera
+     * rays, photon rays (NEB and light photons), NEE shadow rays */
+    int64_t bvh_nodes_camera, bvh_nodes_photon, bvh_nodes_shadow, bvh_tris_camera, bvh_tris_photon, bvh_tris_shadow;
 } neb_stats;
 
 /* per-kernel device time, collected with HIP events on the launch stream */
@@ -493,6 +496,22 @@ neb_status neb_octree_clear_counters(neb_octree oct, void* stream);
 neb_status neb_octree_export(neb_octree oct, int32_t* nodes, int32_t cap, int64_t info[8], void* stream);
 
 void neb_octree_destroy(neb_octree oct);
+
+/* ---------------------------------------------------------------------- */
+/* measurement                                                             */
+/* ---------------------------------------------------------------------- */
+
+/* Device-scope atomic throughput, the ceiling of the octree's lock-free
+ * counting (Sec. 5.1, 5.2): blocks x 256 threads each make `ops`
+ * increments of words picked by a hash of (thread, k) among n_words words
+ * spaced `stride` ints apart; kind 0: returning atomic add, kind 1: a
+ * compare-and-swap loop (load, CAS old -> old + 1 until it succeeds).
+ * words: device, at least n_words * stride ints (the caller's, counts
+ * accumulate); sink: device, blocks * 256 ints (each thread's fold of the
+ * returned values).  Enqueued on `stream`; the caller times it.
+ * NEB_ERR_INVALID_ARG for null pointers, sizes < 1 or kind out of range. */
+neb_status neb_atomic_probe(int32_t* words, int32_t n_words, int32_t stride, int32_t blocks, int32_t ops,
+                            int32_t kind, int32_t* sink, void* stream);
 
 #ifdef __cplusplus
 }

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libneb.so")
-SOURCES = ["neb_render.hip", "neb_octree.hip", "neb_mlp.hip", "neb_bvh.cpp"]
+SOURCES = ["neb_render.hip", "neb_octree.hip", "neb_mlp.hip", "neb_microbench.hip", "neb_bvh.cpp"]
 
 
 def hipcc():

@@ -105,7 +105,9 @@ struct alignas(128) StatLine {
     unsigned long long paths, vertices, photons, photon_segments, merges, nee_visible, events;
     unsigned long long camera_rays, shadow_rays, photon_rays;
     unsigned long long photon_items, photon_continued, grid_cells, candidates;
-    unsigned long long bvh_nodes, bvh_tris;   // traversal work of closest-hit and shadow rays
+    // traversal work (nodes fetched, triangles tested) by ray kind: camera,
+    // photon and shadow rays (the ray_kind of k_extend)
+    unsigned long long bvh_nodes[3], bvh_tris[3];
     unsigned long long light_photons;
 };
 

@@ -407,8 +407,8 @@ __global__ void __launch_bounds__(kTraceBlock) k_extend(SceneView S, const Scene
     }
     StatLine& L = stat_line(cnt);
     wave_add_u64(ray_kind == 0 ? &L.camera_rays : (ray_kind == 1 ? &L.photon_rays : &L.shadow_rays), traced);
-    wave_add_u64(&L.bvh_nodes, nodes);
-    wave_add_u64(&L.bvh_tris, tris);
+    wave_add_u64(&L.bvh_nodes[ray_kind], nodes);
+    wave_add_u64(&L.bvh_tris[ray_kind], tris);
 }
 
 // One thread per path.  The three appends (emitter event, NEE vertex,
@@ -3375,8 +3375,10 @@ extern "C" neb_status neb_get_stats(neb_ctx c, neb_stats* out) {
         h.photon_continued += L.photon_continued;
         h.grid_cells += L.grid_cells;
         h.candidates += L.candidates;
-        h.bvh_nodes += L.bvh_nodes;
-        h.bvh_tris += L.bvh_tris;
+        for (int r = 0; r < 3; ++r) {
+            h.bvh_nodes[r] += L.bvh_nodes[r];
+            h.bvh_tris[r] += L.bvh_tris[r];
+        }
         h.light_photons += L.light_photons;
     }
     std::memset(out, 0, sizeof(*out));
@@ -3391,8 +3393,14 @@ extern "C" neb_status neb_get_stats(neb_ctx c, neb_stats* out) {
     out->rays = (int64_t)(h.camera_rays + h.shadow_rays + h.photon_rays);
     out->camera_rays = (int64_t)h.camera_rays;
     out->shadow_rays = (int64_t)h.shadow_rays;
-    out->bvh_nodes = (int64_t)h.bvh_nodes;
-    out->bvh_tris = (int64_t)h.bvh_tris;
+    out->bvh_nodes = (int64_t)(h.bvh_nodes[0] + h.bvh_nodes[1] + h.bvh_nodes[2]);
+    out->bvh_tris = (int64_t)(h.bvh_tris[0] + h.bvh_tris[1] + h.bvh_tris[2]);
+    out->bvh_nodes_camera = (int64_t)h.bvh_nodes[0];
+    out->bvh_nodes_photon = (int64_t)h.bvh_nodes[1];
+    out->bvh_nodes_shadow = (int64_t)h.bvh_nodes[2];
+    out->bvh_tris_camera = (int64_t)h.bvh_tris[0];
+    out->bvh_tris_photon = (int64_t)h.bvh_tris[1];
+    out->bvh_tris_shadow = (int64_t)h.bvh_tris[2];
     out->photon_items = (int64_t)h.photon_items;
     out->photon_continued = (int64_t)h.photon_continued;
     out->grid_cells = (int64_t)h.grid_cells;

@@ -29,7 +29,7 @@ EXPORTS = [
     "neb_configure_mlp", "neb_get_mlp_status", "neb_get_mlp_weights", "neb_set_mlp_model", "neb_get_mlp_gates", "neb_mlp_create", "neb_mlp_set_normalization",
     "neb_mlp_infer", "neb_mlp_gradient", "neb_mlp_train_step", "neb_mlp_get_params", "neb_mlp_destroy",
     "neb_octree_create", "neb_octree_set_iteration", "neb_octree_increment", "neb_octree_density",
-    "neb_octree_clear_counters", "neb_octree_export", "neb_octree_destroy",
+    "neb_octree_clear_counters", "neb_octree_export", "neb_octree_destroy", "neb_atomic_probe",
 ]
 
 
@@ -60,7 +60,8 @@ class Stats(ctypes.Structure):
         "iterations", "paths", "vertices", "photons", "photon_segments", "merges", "nee_visible", "events",
         "rays", "oct_capacity", "oct_allocated", "oct_depth", "oct_overflow", "oct_ledger", "oct_deposits",
         "oct_rejected", "oct_lost", "photon_items", "photon_continued", "grid_cells", "candidates",
-        "camera_rays", "shadow_rays", "bvh_nodes", "bvh_tris", "light_photons")]
+        "camera_rays", "shadow_rays", "bvh_nodes", "bvh_tris", "light_photons", "bvh_nodes_camera",
+        "bvh_nodes_photon", "bvh_nodes_shadow", "bvh_tris_camera", "bvh_tris_photon", "bvh_tris_shadow")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -155,6 +156,7 @@ def lib():
             "neb_octree_clear_counters": ([_P, _P], i32),
             "neb_octree_export": ([_P, _P, i32, _P, _P], i32),
             "neb_octree_destroy": ([_P], None),
+            "neb_atomic_probe": ([_P, i32, i32, i32, i32, i32, _P, _P], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -434,6 +436,14 @@ class Renderer(BatchRenderer):
         out = np.zeros(n, RECORD_DTYPE)
         _check(lib().neb_get_path_records(self.h, _np_ptr(out), n))
         return out.reshape(self.params.width * self.params.height, self.params.max_path_len)
+
+
+def atomic_probe(words, n_words, stride, blocks, ops, kind, sink, stream=None):
+    """neb_atomic_probe on int32 device tensors `words` (>= n_words * stride)
+    and `sink` (>= blocks * 256)."""
+    assert words.numel() >= n_words * stride and sink.numel() >= blocks * 256
+    _check(lib().neb_atomic_probe(_dev_ptr(words), int(n_words), int(stride), int(blocks), int(ops), int(kind),
+                                  _dev_ptr(sink), _stream(stream)))
 
 
 class Mlp:

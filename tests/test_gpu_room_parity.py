@@ -96,12 +96,18 @@ def _octree(g, o):
     assert agree > 0.99
 
 
-@pytest.mark.parametrize("mode", ["analytic", "octree"])
+@pytest.mark.parametrize("mode", ["analytic", "octree", "pt_lp"])
 def test_room_64_iterations_match_oracle(neb, oracle, mode):
+    """pt_lp is path tracing with NEE and light photons, no NEB photons:
+    the estimator of the bench's error reference (no density enters it)."""
     sc = room(width=32, height=32)
     n_iter, nlp = 64, 32 * 32
-    g = _gpu(neb, sc, mode, n_iter, light_photons=nlp)
-    o = _oracle(oracle, sc, oracle.OracleScene(sc), mode, n_iter, light_photons=nlp)
+    if mode == "pt_lp":
+        g = _gpu(neb, sc, "analytic", n_iter, light_photons=nlp, flags=neb.FLAG_NO_PHOTONS)
+        o = oracle.render(sc, n_iter=n_iter, enable_photons=False, light_photons=nlp)
+    else:
+        g = _gpu(neb, sc, mode, n_iter, light_photons=nlp)
+        o = _oracle(oracle, sc, oracle.OracleScene(sc), mode, n_iter, light_photons=nlp)
     err = rel_rmse(g["img"], o["mean"])
     terr = technique_errors(g["tech"], o["tech"], n_iter)
     print(f"\nroom 32x32, 64 iterations, {mode}: image {err:.2e}, techniques {terr}", flush=True)
@@ -111,6 +117,9 @@ def test_room_64_iterations_match_oracle(neb, oracle, mode):
     tot = o["sum"].sum()
     # the workload is exercised: every technique carries light
     for t in ("e", "E", "P", "LP"):
+        if mode == "pt_lp" and t == "P":
+            assert o["tech"][t].sum() == 0 and np.abs(g["tech"][t]).sum() == 0
+            continue
         assert o["tech"][t].sum() > 1e-3 * tot, t
     assert err < TOL, err
     for t, v in terr.items():
