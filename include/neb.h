@@ -389,9 +389,13 @@ typedef struct neb_mlp_s* neb_mlp;
  * iteration, depth)), is compared with the robust octree query.  A probe is
  * over the bound when |rho_model - rho_octree| > max_rel_error * rho_octree
  * (or rho_octree = 0 < rho_model).  Each of the 32^3 regions of the octree
- * box keeps the model while at most a tenth of its probes so far are over
- * the bound (the 90th percentile of their relative errors is within it),
- * else its vertices take the octree query. */
+ * box keeps the model while the model's densities summed over the region's
+ * probes so far are within max_rel_error of the octree's summed over the
+ * same probes (the model's bias in the region; the octree's per-cell
+ * counting noise, larger than a 10 % bound probe by probe, averages out
+ * there), else its vertices take the octree query.  The status reports the
+ * probes of the regions that keep the model and how many of them are over
+ * the bound one by one. */
 typedef struct {
     int32_t train_iterations;    /* default 4 */
     int32_t steps_per_iteration; /* default 250 */

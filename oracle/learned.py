@@ -22,8 +22,11 @@ the model step by step, for the oracle's density hook:
    probe is over the bound when |rho_model - rho_octree| > bound *
    rho_octree, or rho_octree = 0 < rho_model;
 4. gate: the octree box is cut into 32^3 regions; a region keeps the model
-   while at most a tenth of its probes so far are over the bound (none
-   probed: it keeps it); elsewhere rho is the robust octree's.
+   while the model's densities summed over its probes so far lie within the
+   bound of the octree's densities summed over the same probes (none probed:
+   it keeps it); elsewhere rho is the robust octree's.  Probe by probe the
+   octree's counting noise exceeds a 10 % bound, so the gate judges the
+   model's bias over the region, where that noise averages out.
 
 Region indices are taken in FP32 like the octree's cell addressing
 (integers decided by floating point are decided in one precision on both
@@ -83,6 +86,8 @@ class LearnedDensity:
         n = REGION_RES ** 3
         self.total = np.zeros(n, np.int64)
         self.bad = np.zeros(n, np.int64)
+        self.sum_model = np.zeros(n)
+        self.sum_octree = np.zeros(n)
         self.gate = np.ones(n, bool)
         self.collect = collect
         self.pool = []          # training iterations: (pos, nrm, log rho) of rho > 0
@@ -112,9 +117,13 @@ class LearnedDensity:
             over = np.where(ro > 0, np.abs(rm - ro) > self.max_rel * ro, rm > 0)
             np.add.at(self.total, reg[probed], 1)
             np.add.at(self.bad, reg[probed & over], 1)
+            np.add.at(self.sum_model, reg[probed], rm[probed])
+            np.add.at(self.sum_octree, reg[probed], ro[probed])
             self.n_probes += int(probed.sum())
             self.n_bad += int((probed & over).sum())
-            self.gate = (self.total == 0) | (10 * self.bad <= self.total)
+            so, sm = self.sum_octree, self.sum_model
+            within = np.where(so > 0, np.abs(sm - so) <= self.max_rel * so, ~(sm > 0))
+            self.gate = (self.total == 0) | within
         keep = self.gate[reg]
         self.served += int(keep.sum())
         self.fallback += int((~keep).sum())

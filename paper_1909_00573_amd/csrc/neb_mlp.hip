@@ -6,8 +6,12 @@
 // 2^f pi c for the six coordinates c and octaves f = 0..5, two zero pads)
 // -> 64 -> 64 -> 64 (ReLU) -> 1, output log rho = mu + sigma * y.
 //
-// gfx950 mapping.  The three 64-wide layers run on the matrix cores
-// (v_mfma_f32_16x16x16_bf16: bf16 operands, FP32 accumulation).  A wave
+// gfx950 mapping.  The three 64-wide layers run on the matrix cores, bf16
+// operands and FP32 accumulation: inference on v_mfma_f32_16x16x32_bf16
+// (v_mfma_f32_16x16x16_bf16 for the last 16 inputs of layer 1), training
+// on v_mfma_f32_16x16x16_bf16 (its loss came out wrong with the 16 x 16 x 32
+// form in the training kernel under this toolchain, while inference with it
+// matches the reference).  A wave
 // evaluates 16 samples at a time with the transposed product
 //     Z^T (64 x 16) = W^T (64 x K) . X^T (K x 16),
 // so the weights are the A operand and the samples the B operand.  The
@@ -26,12 +30,18 @@
 
 namespace neb {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x4 __attribute__((ext_vector_type(4)));  // bf16 bit patterns
+typedef short bf16x8b __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// round to nearest, ties to even.  (gfx950's v_cvt_pk_bf16_f32 rounds the
+// same way, but with this toolchain its results fed to the 16 x 16 x 32
+// product below gave wrong outputs, while each alone was right; the integer
+// rounding is kept.)
 __device__ __forceinline__ uint16_t to_bf16(float x) {
     uint32_t b = __float_as_uint(x);
-    b += 0x7FFFu + ((b >> 16) & 1u);  // round to nearest, ties to even
+    b += 0x7FFFu + ((b >> 16) & 1u);
     return (uint16_t)(b >> 16);
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
@@ -45,8 +55,21 @@ __device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
     return r;
 }
 
+// 16 x 16 x 16 product (four k per lane)
 __device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// 16 x 16 x 32 product of gfx950 (eight k per lane, twice the k of the
+// instruction above in the same issue time).  The eight k of lane l are
+// the four of the first 16 x 16 x 16 fragment pair (a0, b0) followed by the
+// four of the second (a1, b1): the product sums the same terms as the two
+// 16 x 16 x 16 products, the reduction only runs over a permuted k.
+__device__ __forceinline__ f32x4 mfma2(bf16x4 a0, bf16x4 a1, bf16x4 b0, bf16x4 b1, f32x4 c) {
+    const bf16x8b a = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+    const bf16x8b b = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
 }
 
 // Encoded input features f0 and f0 + 1 (f0 even) of (q, n): a raw pair,
@@ -153,6 +176,10 @@ struct TileFwd {
     float y;
 };
 
+// kK32: the layer products on the 16 x 16 x 32 instruction (inference);
+// else on 16 x 16 x 16 (training: with the 16 x 16 x 32 form its loss came
+// out wrong under this toolchain, see below)
+template <bool kK32>
 __device__ __forceinline__ void tile_forward(const uint16_t* lds, const float* __restrict__ theta, const float q[3],
                                              const float n[3], TileFwd& T) {
     const int lane = threadIdx.x & 63, g = lane >> 4;
@@ -168,8 +195,16 @@ __device__ __forceinline__ void tile_forward(const uint16_t* lds, const float* _
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        if (kK32) {
 #pragma unroll
-        for (int ks = 0; ks < 5; ++ks) acc = mfma(frag(lds, kFragF1, ob * 5 + ks, lane), T.x[ks], acc);
+            for (int ks = 0; ks < 4; ks += 2)
+                acc = mfma2(frag(lds, kFragF1, ob * 5 + ks, lane), frag(lds, kFragF1, ob * 5 + ks + 1, lane), T.x[ks],
+                            T.x[ks + 1], acc);
+            acc = mfma(frag(lds, kFragF1, ob * 5 + 4, lane), T.x[4], acc);
+        } else {
+#pragma unroll
+            for (int ks = 0; ks < 5; ++ks) acc = mfma(frag(lds, kFragF1, ob * 5 + ks, lane), T.x[ks], acc);
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[i] += theta[kMlpB1 + 16 * ob + 4 * g + i];
         T.z1[ob] = acc;
@@ -184,7 +219,10 @@ __device__ __forceinline__ void tile_forward(const uint16_t* lds, const float* _
     for (int ob = 0; ob < 4; ++ob) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) acc = mfma(frag(lds, kFragF2, ob * 4 + ks, lane), h[ks], acc);
+        for (int ks = 0; ks < 4; ks += kK32 ? 2 : 1)
+            acc = kK32 ? mfma2(frag(lds, kFragF2, ob * 4 + ks, lane), frag(lds, kFragF2, ob * 4 + ks + 1, lane), h[ks],
+                               h[ks + 1], acc)
+                       : mfma(frag(lds, kFragF2, ob * 4 + ks, lane), h[ks], acc);
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[i] += theta[kMlpB2 + 16 * ob + 4 * g + i];
         T.z2[ob] = acc;
@@ -199,7 +237,10 @@ __device__ __forceinline__ void tile_forward(const uint16_t* lds, const float* _
     for (int ob = 0; ob < 4; ++ob) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) acc = mfma(frag(lds, kFragF3, ob * 4 + ks, lane), h[ks], acc);
+        for (int ks = 0; ks < 4; ks += kK32 ? 2 : 1)
+            acc = kK32 ? mfma2(frag(lds, kFragF3, ob * 4 + ks, lane), frag(lds, kFragF3, ob * 4 + ks + 1, lane), h[ks],
+                               h[ks + 1], acc)
+                       : mfma(frag(lds, kFragF3, ob * 4 + ks, lane), h[ks], acc);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             acc[i] += theta[kMlpB3 + 16 * ob + 4 * g + i];
@@ -227,7 +268,7 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const uint16_t* __restrict__ 
         float q[3] = {0.f, 0.f, 0.f}, nn[3] = {0.f, 0.f, 1.f};
         if (i < n) load_input(in, i, q, nn);
         TileFwd T;
-        tile_forward(lds, theta, q, nn, T);
+        tile_forward<true>(lds, theta, q, nn, T);
         if (lane < 16 && i < n) {
             float lr = mu + sigma * T.y;
             out[i] = mode ? __expf(lr) : lr;
@@ -288,7 +329,7 @@ __global__ void __launch_bounds__(256) k_mlp_train_fb(const uint16_t* __restrict
             t = (B.target[item] - mu) * inv_sigma;
         }
         TileFwd T;
-        tile_forward(lds, theta, q, nn, T);
+        tile_forward<false>(lds, theta, q, nn, T);
         float e = live ? T.y - t : 0.f;
         float dy = e * inv_n;
         if (g == 0) {

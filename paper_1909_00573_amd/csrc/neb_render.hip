@@ -1705,7 +1705,7 @@ __global__ void __launch_bounds__(256) k_mlp_probe(VertexStore V, const int32_t*
                                                    const int32_t* __restrict__ nodes, const OctState* ost,
                                                    OctParams P, const OctDyn* dyn, int all, int n_probe, uint32_t k0,
                                                    uint32_t k1, const Counters* cnt, int32_t* total, int32_t* bad,
-                                                   float max_rel, unsigned long long* mc) {
+                                                   float* sums, float max_rel, unsigned long long* mc) {
     const int nv = *n_vertices;
     const int depth = ost->depth;
     const float scale = dyn->density_scale;
@@ -1726,6 +1726,8 @@ __global__ void __launch_bounds__(256) k_mlp_probe(VertexStore V, const int32_t*
         int r = region_of(P, x);
         atomicAdd(total + r, 1);
         if (b) atomicAdd(bad + r, 1);
+        atomicAdd(sums + r, rm);
+        atomicAdd(sums + kRegions + r, ro);
         ++probes;
         nbad += b;
     }
@@ -1733,15 +1735,22 @@ __global__ void __launch_bounds__(256) k_mlp_probe(VertexStore V, const int32_t*
     wave_add_u64(mc + kMlpCntBad, nbad);
 }
 
-// A region keeps the model while at most a tenth of its probes so far exceed
-// the bound (the 90th percentile of their relative errors is within it); a
-// region without probes keeps it.  Also tallies the probes of the regions
-// that keep the model, and how many of those exceed the bound.
-__global__ void k_mlp_gate(const int32_t* total, const int32_t* bad, int32_t* gate, unsigned long long* mc) {
+// A region keeps the model while the model's densities summed over the
+// region's probes so far are within the bound of the octree's summed over
+// the same probes: the model's bias there, relative.  (Probe by probe the
+// octree's own counting noise -- a leaf of c deposits, c of the order of the
+// split threshold, is a Poisson count -- is larger than a 10 % bound, so a
+// per-probe rule would also reject an exact model; summed over a region's
+// probes it averages out.)  A region without probes keeps the model.  Also
+// tallies the probes of the regions that keep the model, and how many of
+// those exceed the bound one by one.
+__global__ void k_mlp_gate(const int32_t* total, const int32_t* bad, const float* sums, float max_rel, int32_t* gate,
+                           unsigned long long* mc) {
     unsigned off = 0, probed = 0, served = 0, served_bad = 0;
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < kRegions; r += gridDim.x * blockDim.x) {
-        int t = total[r], b = bad[r];
-        bool on = t == 0 || 10 * b <= t;
+        const int t = total[r], b = bad[r];
+        const float sm = sums[r], so = sums[kRegions + r];
+        const bool on = t == 0 || (so > 0.f ? fabsf(sm - so) <= max_rel * so : !(sm > 0.f));
         gate[r] = on ? 1 : 0;
         off += !on;
         probed += t > 0;
@@ -1929,6 +1938,7 @@ struct neb_ctx_s {
     float *tpos = nullptr, *tnrm = nullptr, *ttgt = nullptr;  // training pool
     int32_t* tcount = nullptr;
     int32_t *reg_total = nullptr, *reg_bad = nullptr, *reg_gate = nullptr;
+    float* reg_sum = nullptr;  // per region: model and octree densities summed over its probes (2 x kRegions)
     unsigned long long* mlp_cnt = nullptr;
     int32_t last_train_steps = 0;
     // kernel profiling
@@ -2311,6 +2321,7 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
         ALLOC(c->reg_total, kRegions);
         ALLOC(c->reg_bad, kRegions);
         ALLOC(c->reg_gate, kRegions);
+        ALLOC(c->reg_sum, 2 * kRegions);
         ALLOC(c->mlp_cnt, kMlpCnt);
         if (e == hipSuccess) e = mlp_alloc(c->mlp, c->mcfg.batch);
     }
@@ -2513,6 +2524,8 @@ static neb_status restart(neb_ctx c, hipStream_t s) {
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(kRegions, 256)), dim3(256), 0, s, c->reg_total, 0, (int64_t)kRegions);
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(kRegions, 256)), dim3(256), 0, s, c->reg_bad, 0, (int64_t)kRegions);
         hipLaunchKernelGGL(k_fill_i32, dim3(grid_of(kRegions, 256)), dim3(256), 0, s, c->reg_gate, 1, (int64_t)kRegions);
+        hipLaunchKernelGGL(k_fill_f32, dim3(grid_of(2 * kRegions, 256)), dim3(256), 0, s, c->reg_sum, 0.f,
+                           (int64_t)(2 * kRegions));
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int32_t*)c->mlp_cnt, 0, (int64_t)(2 * kMlpCnt));
         c->last_train_steps = 0;
     }
@@ -2901,10 +2914,11 @@ static neb_status enqueue_iteration(neb_ctx c, hipStream_t s, int parity, bool c
                                (const int32_t*)nv, (const int32_t*)c->oct_nodes,
                                (const OctState*)c->oct_states, P0, (const OctDyn*)c->oct_dyn, j == 1 ? 1 : 0,
                                c->mcfg.probes, c->mcfg.seed, 0x50524F42u, (const Counters*)cnt, c->reg_total,
-                               c->reg_bad, c->mcfg.max_rel_error, c->mlp_cnt);
+                               c->reg_bad, c->reg_sum, c->mcfg.max_rel_error, c->mlp_cnt);
             hipLaunchKernelGGL(k_mlp_clear_gate_counts, dim3(1), dim3(1), 0, s, c->mlp_cnt);
             hipLaunchKernelGGL(k_mlp_gate, dim3(grid_of(kRegions, 256)), dim3(256), 0, s, (const int32_t*)c->reg_total,
-                               (const int32_t*)c->reg_bad, c->reg_gate, c->mlp_cnt);
+                               (const int32_t*)c->reg_bad, (const float*)c->reg_sum, c->mcfg.max_rel_error,
+                               c->reg_gate, c->mlp_cnt);
         }
         hipLaunchKernelGGL(k_density_fallback, dim3(grid_of(vcap, 256)), dim3(256), 0, s, c->V,
                            (const int32_t*)nv, (const int32_t*)c->reg_gate,
