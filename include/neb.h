@@ -187,10 +187,14 @@ typedef struct {
 /* rendering context                                                       */
 /* ---------------------------------------------------------------------- */
 
-/* Validates the parameters and allocates the per-iteration device pools
- * (queues, NEE-vertex store, photon state, merge grid, images) on the
- * current device.  NEB_ERR_INVALID_ARG on bad parameters,
- * NEB_ERR_OUT_OF_MEMORY if the pools do not fit.  Same as
+/* Validates the parameters and allocates, on the current device, the pools
+ * of one iteration of the method's three passes (Sec. 3: the view-path
+ * queues and the NEE-vertex store of pass 1, Sec. 3.1; the shadow rays and
+ * photon queues of pass 2, Sec. 3.2; the emitter-hit events of pass 3,
+ * Sec. 3.3), the merge grid of the photon merges (Sec. 4, eq. photonpdf),
+ * the density octree's node pool (Sec. 5.1, 5.4) and the images.  The
+ * context owns them until neb_destroy.  NEB_ERR_INVALID_ARG on bad
+ * parameters, NEB_ERR_OUT_OF_MEMORY if the pools do not fit.  Same as
  * neb_create_batch(params, 1, out). */
 neb_status neb_create(const neb_params* params, neb_ctx* out);
 
@@ -259,8 +263,13 @@ neb_status neb_set_launch_config(neb_ctx ctx, const neb_launch_config* cfg);
 neb_status neb_get_launch_config(neb_ctx ctx, neb_launch_config* cfg);
 
 /* Mean radiance over the rendered iterations, height*width*3 floats,
- * row-major from the top-left pixel.  rgb is device memory if
- * is_device_ptr, else host memory (then the call synchronises). */
+ * row-major from the top-left pixel: the progressive estimate of the
+ * method, each iteration's random hits (e), NEE (E), NEB photon merges (P)
+ * and light-photon merges (LP) combined with the balance heuristic
+ * (Sec. 4, eq. misweight over the techniques of eq. misw).  rgb is
+ * device memory if is_device_ptr, else host memory (then the call
+ * synchronises); the caller owns it.  NEB_ERR_STATE before the first
+ * neb_set_scene. */
 neb_status neb_get_image(neb_ctx ctx, float* rgb, int32_t is_device_ptr, void* stream);
 
 /* neb_get_image for scene `scene` of a batch: its own height*width*3
@@ -312,15 +321,25 @@ neb_status neb_get_scene_light_photon_image(neb_ctx ctx, int32_t scene, float* L
                                             void* stream);
 
 /* Density of NEE vertices at n surface points from the context's octree in
- * its current state (robust five-probe query; tangents from the normal).
- * pos, nrm: n*3 floats; out: n floats; all device memory if is_device_ptr,
- * else host memory. */
+ * its current state: the robust query of Appendix B (get_density_robust:
+ * the median of five probes, the point and four offsets along tangents
+ * taken from the normal), each probe the count of the leaf it lands in
+ * over the area of the surface's plane inside that leaf's box (Sec. 5.3,
+ * eq. octdensity, the area by eq. area and Appendix A), scaled to one
+ * iteration.  pos, nrm: n*3 floats; out: n floats; all device memory if
+ * is_device_ptr, else host memory (then the call synchronises).
+ * NEB_ERR_INVALID_ARG for n < 0 or a null pointer, NEB_ERR_STATE before
+ * the scene is set. */
 neb_status neb_query_density(neb_ctx ctx, const float* pos, const float* nrm, int32_t n, float* out,
                              int32_t is_device_ptr, void* stream);
 
 /* Counters accumulated since the last reset, over all scenes of the
- * context (octree fields summed over the scenes' octrees, depth the
- * deepest); synchronises the context's last stream. */
+ * context: the work of the passes of Sec. 3 (paths, NEE vertices, shadow
+ * rays, photons and their segments, merge candidates and accepted merges,
+ * traversal fetches) and the state of the density octrees of Sec. 5
+ * (nodes, depth, the Appendix B insert ledger; fields summed over the
+ * scenes' octrees, depth the deepest).  out: host memory, owned by the
+ * caller.  Synchronises the context's last stream. */
 neb_status neb_get_stats(neb_ctx ctx, neb_stats* out);
 
 /* Copies the path records of the first rendered iteration to host memory:

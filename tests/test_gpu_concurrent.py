@@ -35,13 +35,14 @@ def _close(a, b, rtol=2e-4):
     return np.all(np.abs(a - b) <= rtol * np.abs(a) + 1e-6 * max(np.abs(a).max(), 1e-30))
 
 
-def _pair(neb, make, n_iter, graph=False):
+def _pair(neb, make, n_iter, graph=False, order=None):
     out = []
     for conc in (1, 0):
         R = make()
         cfg = R.launch_config()
         R.set_launch_config(cfg["bvh_stack"], cfg["trace_blocks_per_cu"], cfg["photon_blocks_per_cu"],
-                            cfg["photon_order"], cfg["nee_blocks_per_cu"], concurrent=conc)
+                            cfg["photon_order"] if order is None else order, cfg["nee_blocks_per_cu"],
+                            concurrent=conc)
         if graph:
             R.use_graph(True)
         R.render(n_iter)
@@ -61,6 +62,21 @@ def test_concurrent_equals_serial(neb, kw):
     for t in ("e", "E", "P", "LP"):
         assert _close(ta[t], tb[t]), t
     assert sa["merges"] > 0
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_concurrent_equals_serial_photon_orders(neb, order):
+    """Merges in queue order and in Morton-bin order, each with the
+    bounce's merges beside the next bounce's closest hits: the shared order
+    array is rewritten only after the merges of the bounce before."""
+    sc = tiny_box(width=48, height=40, max_path_len=8)
+    (ta, sa, oa), (tb, sb, ob) = _pair(
+        neb, lambda: neb.Renderer(sc, flags=neb.FLAG_SINGLE_THREAD_OCTREE, light_photons=4096), 4, order=order)
+    assert np.array_equal(oa, ob)
+    for k in ("photons", "photon_segments", "merges", "candidates", "light_photons"):
+        assert sa[k] == sb[k], k
+    for t in ("e", "E", "P", "LP"):
+        assert _close(ta[t], tb[t]), t
 
 
 def test_concurrent_equals_serial_batch_and_graph(neb):
