@@ -377,38 +377,51 @@ void orc_octree_increment(o_octree* o, const float* pos, int64_t n) {
     for (int64_t i = 0; i < n; ++i) octree_insert(o, pos + 3 * i);
 }
 
-/* Density at p with normal n (FP64 area, FP32 cell addressing).
- * want_size: nonzero selects the 1/10 minimum-area clamp and returns the
- * cell diagonal through size_out when the cell is non-empty. */
-static double octree_density(const o_octree* o, v3 p, v3 n, int want_size, double* size_out) {
+/* The leaf holding the normalised point q: the word of the leaf and, in
+ * *level, its depth.  Below level L the descent takes the child
+ * (floor(q * 2^(L+1)) & 1) per axis in FP32, the child the deposits take. */
+static int32_t find_leaf(const o_octree* o, const float q[3], int* level) {
+    int32_t w = o->nodes[0];
+    int L = 0;
+    while (w < 0) {
+        ++L;
+        const float cells = (float)(1 << L);
+        int child = 0;
+        for (int a = 0; a < 3; ++a) child |= (((int)(q[a] * cells)) & 1) << a;
+        w = o->nodes[-w + child];
+    }
+    *level = L;
+    return w;
+}
+
+/* Floor under the plane's area in a leaf of diagonal diag, so that a
+ * surface grazing a cell does not give an unbounded density (Appendix B):
+ * a tenth of diag^2 for the probe at the query point, a hundredth for the
+ * offset probes. */
+static double area_floor(double diag, int centre) { return diag * diag * (centre ? 0.1 : 0.01); }
+
+/* eq. (octdensity): the count of the leaf holding p over the area of the
+ * plane through p (normal n) inside the leaf's box (exact clipping,
+ * Appendix A), times the density scale.  centre: the probe at the query
+ * point; then *diag_out receives the leaf's diagonal if the leaf has a
+ * count.  Cell addressing in FP32, the area in FP64. */
+static double leaf_density(const o_octree* o, v3 p, v3 n, int centre, double* diag_out) {
     float pf[3] = {(float)p.x, (float)p.y, (float)p.z}, q[3];
     if (!norm_pos(o, pf, q)) return 0.0;
-    int32_t grid = 1 << o->depth;
-    int32_t ip[3];
-    for (int i = 0; i < 3; ++i) ip[i] = (int32_t)(q[i] * (float)grid);
-    int32_t v = o->nodes[0];
-    int32_t mask = grid;
-    while (v < 0) {
-        mask >>= 1;
-        int32_t c = ((ip[0] & mask) ? 1 : 0) + ((ip[1] & mask) ? 2 : 0) + ((ip[2] & mask) ? 4 : 0);
-        v = o->nodes[-v + c];
+    int level;
+    const int32_t count = find_leaf(o, q, &level) & OCT_COUNT_MASK;
+    if (count <= 0) return 0.0;
+    const double cells = (double)(1 << level);
+    double lo[3], hi[3], rel[3], pp[3] = {p.x, p.y, p.z}, nn[3] = {n.x, n.y, n.z};
+    for (int a = 0; a < 3; ++a) {
+        const double edge = 1.0 / (cells * (double)o->size_inv[a]);
+        lo[a] = (double)(int32_t)(q[a] * (float)(1 << level)) * edge;
+        hi[a] = lo[a] + edge;
+        rel[a] = pp[a] - (double)o->min_bound[a];
     }
-    int32_t cnt = v & OCT_COUNT_MASK;
-    if (cnt <= 0) return 0.0;
-    int32_t res = grid / mask;
-    double bmin[3], bmax[3], off[3], nn[3] = {n.x, n.y, n.z};
-    double pp[3] = {p.x, p.y, p.z};
-    for (int i = 0; i < 3; ++i) {
-        double cs = 1.0 / ((double)res * (double)o->size_inv[i]);
-        bmin[i] = (double)(ip[i] / mask) * cs;
-        bmax[i] = bmin[i] + cs;
-        off[i] = pp[i] - (double)o->min_bound[i];
-    }
-    double area = orc_exact_area(bmin, bmax, off, nn);
-    double diag = (double)o->scene_scale / (double)res;
-    double min_area = diag * diag * (want_size ? 0.1 : 0.01);
-    if (want_size && size_out) *size_out = diag;
-    return (double)o->density_scale * (double)cnt / fmax(min_area, area);
+    const double diag = (double)o->scene_scale / cells;
+    if (centre && diag_out) *diag_out = diag;
+    return (double)o->density_scale * (double)count / fmax(area_floor(diag, centre), orc_exact_area(lo, hi, rel, nn));
 }
 
 /* branchless orthonormal basis (Duff et al., JCGT 6(1), 2017) */
@@ -420,32 +433,39 @@ static void onb(v3 n, v3* t1, v3* t2) {
     *t2 = mk(b, sgn + n.y * n.y * a, -n.y);
 }
 
+/* the (k/2)-th smallest of k values (the upper median); sorts v */
+static double upper_median(double* v, int k) {
+    for (int i = 1; i < k; ++i) {
+        const double x = v[i];
+        int j = i;
+        for (; j > 0 && v[j - 1] > x; --j) v[j] = v[j - 1];
+        v[j] = x;
+    }
+    return v[k / 2];
+}
+
+/* Appendix B get_density_robust: eq. (octdensity) at p and at the four
+ * points 1.1 leaf diagonals (of p's leaf; 1e-3 scene units when it is
+ * empty) away along the tangents; the upper median of the non-zero ones. */
 static double octree_density_robust(const o_octree* o, v3 p, v3 n) {
     v3 tx, ty;
     onb(n, &tx, &ty);
-    double d[5], diag = 1e-3;
-    int count = 0;
-    d[0] = octree_density(o, p, n, 1, &diag);
-    double off = diag * 1.1;
-    if (d[0] > 0.0) ++count;
-    v3 probe[4] = {add(p, scl(tx, off)), sub(p, scl(tx, off)), add(p, scl(ty, off)), sub(p, scl(ty, off))};
+    double diag = 1e-3, found[5];
+    int k = 0;
+    const double centre = leaf_density(o, p, n, 1, &diag);
+    if (centre > 0.0) found[k++] = centre;
+    const double step = diag * 1.1;
+    const v3 away[4] = {add(p, scl(tx, step)), sub(p, scl(tx, step)), add(p, scl(ty, step)), sub(p, scl(ty, step))};
     for (int i = 0; i < 4; ++i) {
-        double r = octree_density(o, probe[i], n, 0, NULL);
-        d[count] = r;
-        if (r > 0.0) ++count;
+        const double r = leaf_density(o, away[i], n, 0, NULL);
+        if (r > 0.0) found[k++] = r;
     }
-    if (count == 0) return 0.0;
-    /* upper median of the non-zero probes */
-    double s[5];
-    memcpy(s, d, sizeof(double) * (size_t)count);
-    for (int i = 1; i < count; ++i)
-        for (int j = i; j > 0 && s[j] < s[j - 1]; --j) { double t = s[j]; s[j] = s[j - 1]; s[j - 1] = t; }
-    return s[count / 2];
+    return k ? upper_median(found, k) : 0.0;
 }
 
 double orc_octree_density(o_octree* o, const double p[3], const double n[3], int32_t robust) {
     v3 P = mk(p[0], p[1], p[2]), N = nrm(mk(n[0], n[1], n[2]));
-    return robust ? octree_density_robust(o, P, N) : octree_density(o, P, N, 0, NULL);
+    return robust ? octree_density_robust(o, P, N) : leaf_density(o, P, N, 0, NULL);
 }
 
 void orc_octree_density_batch(o_octree* o, const float* pos, const float* nrmv, int64_t n,
@@ -1131,7 +1151,7 @@ static double set_density(const double* pts, int n, v3 x, int mode, double R, in
 static double query_density(const o_iter* it, v3 x, v3 n) {
     const o_params* p = it->prm;
     switch (p->density_mode) {
-    case 0: return octree_density(it->oct, x, n, 0, NULL);
+    case 0: return leaf_density(it->oct, x, n, 0, NULL);
     case 1: return octree_density_robust(it->oct, x, n);
     case 3: return p->analytic_rho0 + p->analytic_cam_weight * camera_hit_density(&it->cam, x, n);
     case 4:

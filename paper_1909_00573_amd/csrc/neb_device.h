@@ -261,103 +261,135 @@ __device__ __forceinline__ bool oct_norm(const OctParams& P, f3 p, float q[3]) {
     return true;
 }
 
-// density of the leaf that a descent ended in: its word v, reached at mask
-// (grid / mask cells per axis), for the point p with integer cell
-// coordinates (ix, iy, iz) at the finest grid
-__device__ __forceinline__ float oct_leaf_density(const OctParams& P, float density_scale, int32_t grid, int32_t ix,
-                                                  int32_t iy, int32_t iz, int32_t v, int32_t mask, f3 p, f3 n,
-                                                  bool want_size, float* size_out) {
-    int32_t cnt = v & kOctCountMask;
-    if (cnt <= 0) return 0.f;
-    int32_t res = grid / mask;
-    float csx = 1.0f / ((float)res * P.size_inv[0]);
-    float csy = 1.0f / ((float)res * P.size_inv[1]);
-    float csz = 1.0f / ((float)res * P.size_inv[2]);
-    f3 cmin = mk3((float)(ix / mask) * csx, (float)(iy / mask) * csy, (float)(iz / mask) * csz);
-    f3 cmax = cmin + mk3(csx, csy, csz);
-    f3 off = mk3(p.x - P.min_bound[0], p.y - P.min_bound[1], p.z - P.min_bound[2]);
-    float area = plane_box_area(cmin, cmax, off, n);
-    float diag = P.scene_scale / (float)res;
-    float min_area = diag * diag * (want_size ? 0.1f : 0.01f);
-    if (want_size) *size_out = diag;
-    return density_scale * (float)cnt / fmaxf(min_area, area);
-}
+// A point's cell at the octree's finest level: integer coordinates
+// floor(q * 2^depth) of its normalised position q.  The leaf reached at level
+// L holds the cell c >> (depth - L); the child taken below level L is bit
+// depth - L - 1 of each coordinate (the same child as the deposits take from
+// floor(q * 2^(L+1)) & 1, as scaling by a power of two is exact).
+struct OctCell {
+    int32_t c[3];
+};
 
-__device__ __forceinline__ float oct_query(const int32_t* __restrict__ nodes, const OctParams& P, float density_scale,
-                                           int depth, f3 p, f3 n, bool want_size, float* size_out) {
+__device__ __forceinline__ bool oct_cell(const OctParams& P, int depth, f3 p, OctCell& k) {
     float q[3];
-    if (!oct_norm(P, p, q)) return 0.f;
-    int32_t grid = 1 << depth;
-    int32_t ix = (int32_t)(q[0] * (float)grid), iy = (int32_t)(q[1] * (float)grid),
-            iz = (int32_t)(q[2] * (float)grid);
-    int32_t v = nodes[P.root];
-    int32_t mask = grid;
-    while (v < 0) {
-        mask >>= 1;
-        int32_t c = ((ix & mask) ? 1 : 0) | ((iy & mask) ? 2 : 0) | ((iz & mask) ? 4 : 0);
-        v = nodes[c - v];
-    }
-    return oct_leaf_density(P, density_scale, grid, ix, iy, iz, v, mask, p, n, want_size, size_out);
+    if (!oct_norm(P, p, q)) return false;
+    const float fine = (float)(1 << depth);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) k.c[a] = (int32_t)(q[a] * fine);
+    return true;
 }
 
-// five probes in the tangent plane, upper median of the non-zero ones
+// the node word below inner node word w (< 0) on the way to cell k, `shift`
+// = depth - (level of the child)
+__device__ __forceinline__ int32_t oct_child(const int32_t* __restrict__ nodes, int32_t w, const OctCell& k,
+                                             int shift) {
+    const int32_t child = ((k.c[0] >> shift) & 1) | (((k.c[1] >> shift) & 1) << 1) | (((k.c[2] >> shift) & 1) << 2);
+    return nodes[child - w];
+}
+
+// Floor under the area of the surface inside a leaf of diagonal `diag`, so
+// that a surface grazing a cell does not give an unbounded density: a tenth
+// of diag^2 for the probe at the query point, a hundredth for the offset
+// probes (Appendix B).
+__device__ __forceinline__ float oct_area_floor(float diag, bool centre) {
+    return diag * diag * (centre ? 0.1f : 0.01f);
+}
+
+// eq. (octdensity) at the leaf (word w, level `level`) holding cell k of the
+// point p with normal n: the leaf's count over the area of the plane through
+// p inside the leaf's box (eq. area), times the density scale.  centre: the
+// probe at the query point; then *diag_out receives the leaf's diagonal (if
+// the leaf has a count).
+__device__ __forceinline__ float oct_leaf_density(const OctParams& P, float density_scale, int depth,
+                                                  const OctCell& k, int level, int32_t w, f3 p, f3 n, bool centre,
+                                                  float* diag_out) {
+    const int32_t count = w & kOctCountMask;
+    if (count <= 0) return 0.f;
+    const int32_t cells = 1 << level;  // per axis at this level
+    const int shift = depth - level;
+    float edge[3], lo[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        edge[a] = 1.0f / ((float)cells * P.size_inv[a]);
+        lo[a] = (float)(k.c[a] >> shift) * edge[a];
+    }
+    const f3 bmin = mk3(lo[0], lo[1], lo[2]);
+    const f3 bmax = bmin + mk3(edge[0], edge[1], edge[2]);
+    const f3 rel = mk3(p.x - P.min_bound[0], p.y - P.min_bound[1], p.z - P.min_bound[2]);
+    const float area = plane_box_area(bmin, bmax, rel, n);
+    const float diag = P.scene_scale / (float)cells;
+    if (centre) *diag_out = diag;
+    return density_scale * (float)count / fmaxf(oct_area_floor(diag, centre), area);
+}
+
+// upper median of n (1..5) values: the (n/2)-th smallest (sorts v)
+__device__ __forceinline__ float upper_median(float* v, int n) {
+    for (int i = 1; i < n; ++i) {
+        const float x = v[i];
+        int j = i;
+        for (; j > 0 && v[j - 1] > x; --j) v[j] = v[j - 1];
+        v[j] = x;
+    }
+    return v[n / 2];
+}
+
+// eq. (octdensity) at the leaf holding p (Appendix B get_density)
+__device__ __forceinline__ float oct_query(const int32_t* __restrict__ nodes, const OctParams& P, float density_scale,
+                                           int depth, f3 p, f3 n, bool centre, float* diag_out) {
+    OctCell k;
+    if (!oct_cell(P, depth, p, k)) return 0.f;
+    int32_t w = nodes[P.root];
+    int level = 0;
+    while (w < 0) {
+        ++level;
+        w = oct_child(nodes, w, k, depth - level);
+    }
+    return oct_leaf_density(P, density_scale, depth, k, level, w, p, n, centre, diag_out);
+}
+
+// Appendix B get_density_robust: the densities at p and at four points
+// offset along the tangents by 1.1 leaf diagonals of p's leaf (1.1e-3
+// scene units when that leaf is empty); the upper median of the non-zero
+// ones (0 if none)
 __device__ __forceinline__ float oct_query_robust(const int32_t* __restrict__ nodes, const OctParams& P,
                                                   float density_scale, int depth, f3 p, f3 n) {
     f3 tx, ty;
     basis(n, tx, ty);
     float diag = 1e-3f;
-    float d[5];
-    int cnt = 0;
-    float c0 = oct_query(nodes, P, density_scale, depth, p, n, true, &diag);
-    if (c0 > 0.f) d[cnt++] = c0;
-    float off = diag * 1.1f;
-    f3 probe[4] = {p + tx * off, p - tx * off, p + ty * off, p - ty * off};
-    // the four tangent probes descend together, one level per step, so that
-    // their node loads are in flight at once (each is the descent of
-    // oct_query; a probe outside the octree's box has density 0)
-    const int32_t grid = 1 << depth;
-    int32_t ix[4], iy[4], iz[4], v[4], mask[4];
+    float found[5];
+    int nf = 0;
+    const float centre = oct_query(nodes, P, density_scale, depth, p, n, true, &diag);
+    if (centre > 0.f) found[nf++] = centre;
+    const float step = diag * 1.1f;
+    const f3 probe[4] = {p + tx * step, p - tx * step, p + ty * step, p - ty * step};
+    // the four offset probes descend together, one level per step, so that
+    // their node loads are in flight at once (a probe outside the octree's
+    // box stops at once with density 0)
+    OctCell k[4];
+    int32_t w[4];
+    int level[4];
     const int32_t root = nodes[P.root];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        float q[3];
-        const bool in = oct_norm(P, probe[i], q);
-        ix[i] = in ? (int32_t)(q[0] * (float)grid) : 0;
-        iy[i] = in ? (int32_t)(q[1] * (float)grid) : 0;
-        iz[i] = in ? (int32_t)(q[2] * (float)grid) : 0;
-        v[i] = in ? root : 0;
-        mask[i] = grid;
+        const bool in = oct_cell(P, depth, probe[i], k[i]);
+        if (!in) k[i].c[0] = k[i].c[1] = k[i].c[2] = 0;
+        w[i] = in ? root : 0;
+        level[i] = 0;
     }
-    bool more = v[0] < 0 || v[1] < 0 || v[2] < 0 || v[3] < 0;
-    while (more) {
+    while (w[0] < 0 || w[1] < 0 || w[2] < 0 || w[3] < 0) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            if (v[i] < 0) {
-                mask[i] >>= 1;
-                const int32_t c = ((ix[i] & mask[i]) ? 1 : 0) | ((iy[i] & mask[i]) ? 2 : 0) | ((iz[i] & mask[i]) ? 4 : 0);
-                v[i] = nodes[c - v[i]];
+        for (int i = 0; i < 4; ++i)
+            if (w[i] < 0) {
+                ++level[i];
+                w[i] = oct_child(nodes, w[i], k[i], depth - level[i]);
             }
-        }
-        more = v[0] < 0 || v[1] < 0 || v[2] < 0 || v[3] < 0;
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        float r = oct_leaf_density(P, density_scale, grid, ix[i], iy[i], iz[i], v[i], mask[i], probe[i], n, false,
-                                   nullptr);
-        if (r > 0.f) d[cnt++] = r;
+        const float r = oct_leaf_density(P, density_scale, depth, k[i], level[i], w[i], probe[i], n, false, nullptr);
+        if (r > 0.f) found[nf++] = r;
     }
-    if (cnt == 0) return 0.f;
-    // insertion sort of at most five values, then the upper median
-    for (int i = 1; i < cnt; ++i) {
-        float x = d[i];
-        int j = i - 1;
-        while (j >= 0 && d[j] > x) {
-            d[j + 1] = d[j];
-            --j;
-        }
-        d[j + 1] = x;
-    }
-    return d[cnt / 2];
+    return nf ? upper_median(found, nf) : 0.f;
 }
 
 // ---------------------------------------------------------------------------
