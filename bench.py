@@ -276,6 +276,37 @@ def atomics_run(stream, blocks=2048, ops=16):
     return out
 
 
+def gather_run(stream, blocks=4096, ops=64):
+    """Random-access read throughput (neb_gather_probe): 16- and 64-byte
+    records at hashed indices over buffers of 32 MB (the room's merge cell
+    table), 192 MB (the merge kernel's working set: table, sorted
+    positions and merge records) and 1 GiB (beyond the chip's caches);
+    G records and GB of records per second."""
+    import torch
+    from paper_1909_00573_amd import neb
+    out = {}
+    sink = torch.zeros(blocks * 256, dtype=torch.float32, device="cuda")
+    for label, nbytes in (("32 MB", 32 << 20), ("192 MB", 192 << 20), ("1 GiB", 1 << 30)):
+        buf = torch.rand(nbytes // 4, dtype=torch.float32, device="cuda")
+        row = {}
+        for width in (1, 4):
+            neb.gather_probe(buf, width, blocks, 8, sink, stream=stream)
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            neb.gather_probe(buf, width, blocks, ops, sink, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            t = a.elapsed_time(b) / 1e3
+            n = blocks * 256 * ops
+            row["%dB_G_per_s" % (16 * width)] = round(n / t / 1e9, 2)
+            row["%dB_GB_per_s" % (16 * width)] = round(n * 16 * width / t / 1e9, 1)
+        out[label] = row
+        del buf
+    return out
+
+
 def octree_saturation(stream, steps=16):
     """How the room's octree capacity (2^20 nodes, which its first iteration
     fills) moves the density: the robust query of the default tree against
@@ -742,6 +773,18 @@ def main():
             out["atomics"]["octree_insert_deposits_G_per_s"] = round(rate, 3)
             out["atomics"]["octree_insert_frac_of_cas"] = round(rate / cas, 4)
         out["octree_saturation"] = octree_saturation(stream)
+        out["gather"] = gather_run(stream)
+        pm = kernels_ser.get("photon_merge") if kernels_ser else None
+        if pm:
+            # the merge kernel's random reads: per cell lookup its row of the
+            # start table and its run of candidates, per accepted merge its
+            # record (photon state is read in queue order, not counted)
+            work = {k: st[k] - s0[k] for k in ("grid_cells", "merges")}
+            reads = 2 * work["grid_cells"] + work["merges"]
+            rate = reads / (pm["ms"] * 1e-3) / 1e9
+            ceil = out["gather"]["192 MB"]["64B_G_per_s"]
+            out["gather"]["photon_merge_random_reads_G_per_s"] = round(rate, 2)
+            out["gather"]["photon_merge_frac_of_64B_gather"] = round(rate / ceil, 4)
     if not args.no_tiny:
         out["tiny_box"] = tiny_box_run(stream)
     if not args.no_city:

@@ -536,6 +536,19 @@ void neb_octree_destroy(neb_octree oct);
 neb_status neb_atomic_probe(int32_t* words, int32_t n_words, int32_t stride, int32_t blocks, int32_t ops,
                             int32_t kind, int32_t* sink, void* stream);
 
+/* Random-access read throughput, the ceiling of the photon merges' lookups
+ * (Sec. 3.2: each photon hit reads the cell table, candidate runs and merge
+ * records of the view vertices near it): blocks x 256 threads each read
+ * `ops` records of `width` 16-byte words (1 or 4: 16 or 64 bytes, aligned
+ * to their size) at indices picked by a hash of (thread, k) among the
+ * n_words 16-byte words of buf, eight reads in flight per thread.  buf:
+ * device, n_words * 16 bytes (the caller's, only read); sink: device,
+ * blocks * 256 floats (each thread's sum of what it read).  Enqueued on
+ * `stream`; the caller times it.  NEB_ERR_INVALID_ARG for null pointers,
+ * n_words < 4, width not 1 or 4, blocks or ops < 1. */
+neb_status neb_gather_probe(const float* buf, int64_t n_words, int32_t width, int32_t blocks, int32_t ops,
+                            float* sink, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

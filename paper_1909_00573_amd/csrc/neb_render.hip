@@ -1340,23 +1340,24 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
         int dst = -1;
         f3 val = mk3(0.f, 0.f, 0.f);
         if (lane < count) {
-            int2 pr = queue[lane];
-            float4 t0 = tp[pr.x][0], t1 = tp[pr.x][1];
-            const float4* mr = G.mrec + 4 * (size_t)pr.y;  // one 64-byte record
-            float4 v1 = mr[0];
-            int tg = fbits(v1.w);
-            int k = tag_depth(tg);
+            const int2 pr = queue[lane];
+            // the whole 64-byte record at once (one line), so that the
+            // material is the only load that waits for another
+            const float4* mr = G.mrec + 4 * (size_t)pr.y;
+            const float4 v1 = mr[0], v2 = mr[1], v3 = mr[2];
+            const int pix = fbits(mr[3].x);
+            const float4 t0 = tp[pr.x][0], t1 = tp[pr.x][1];
+            const int tg = fbits(v1.w);
+            const int k = tag_depth(tg);
             const int km = fbits(t1.w);
             if (k <= (km & 255)) {
                 const neb_material& mv = S.mats[tag_mat(tg)];
-                float4 v2 = mr[1];
-                f3 nv = xyz(v1), wv = xyz(v2), wd = xyz(t0);
-                f3 f = bsdf_f(mv, nv, wv, wd);
+                const f3 nv = xyz(v1), wv = xyz(v2), wd = xyz(t0);
+                const f3 f = bsdf_f(mv, nv, wv, wd);
                 if (!is_zero3(f)) {
-                    float4 v3 = mr[2];
-                    float T = bsdf_pdf(mv, nv, wv, wd) * t0.w;
-                    float C = te[pr.x] + ((k >= 2) ? bsdf_pdf(mv, nv, wd, wv) * v3.w * v2.w : 0.f);
-                    dst = fbits(mr[3].x) | ((km & 256) ? (1 << 30) : 0);
+                    const float T = bsdf_pdf(mv, nv, wv, wd) * t0.w;
+                    const float C = te[pr.x] + ((k >= 2) ? bsdf_pdf(mv, nv, wd, wv) * v3.w * v2.w : 0.f);
+                    dst = pix | ((km & 256) ? (1 << 30) : 0);
                     val = xyz(v3) * f * xyz(t1) * (1.0f / (C + T));
                     ++merges;
                 }
@@ -1432,9 +1433,12 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
         tp[lane][0] = f4(-d, X);
         tp[lane][1] = f4(xyz(b2) * (1.0f / I.r2pi), ibits(kmax | (light ? 256 : 0)));
         te[lane] = ef;
-        // candidate ranges of the (at most 8) cells the ball touches
+        // candidate ranges of the (at most 8) cells the ball touches.  The
+        // lookups do not wait for the hit's material: a hit on a specular
+        // surface (rare) drops its ranges afterwards
         int lo[8], pre[9];
         pre[0] = 0;
+        unsigned looked = 0;
         {
             float rr = r * 1.00001f;
             int lx = (int)floorf((y.x - rr) * inv_cell), hx = min((int)floorf((y.x + rr) * inv_cell), lx + 1);
@@ -1444,7 +1448,7 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
                 int cx = lx + (c & 1), cy = ly + ((c >> 1) & 1), cz = lz + ((c >> 2) & 1);
-                bool use = mergeable && kmax >= 1 && cx <= hx && cy <= hy && cz <= hz;
+                bool use = hit && kmax >= 1 && cx <= hx && cy <= hy && cz <= hz;
                 // skip cells whose box is farther than r from the hit
                 float dx = fmaxf(fmaxf(cx * cell - y.x, y.x - (cx + 1) * cell), 0.f);
                 float dy = fmaxf(fmaxf(cy * cell - y.y, y.y - (cy + 1) * cell), 0.f);
@@ -1459,12 +1463,18 @@ __global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const i
                     int64_t key = grid_key(G, hc, 1);
                     e0 = G.start[key];
                     e1 = G.start[key + kmax];
-                    ++cells;
+                    ++looked;
                 }
                 lo[c] = e0;
                 pre[c + 1] = pre[c] + (e1 - e0);
             }
         }
+        if (!mergeable) {
+#pragma unroll
+            for (int c = 1; c <= 8; ++c) pre[c] = 0;
+            looked = 0;
+        }
+        cells += looked;
         int total = pre[8];
         cands += (unsigned)total;
         // the wave's candidate list: photon p's entries start at wbase[p];

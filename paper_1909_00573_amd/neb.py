@@ -29,7 +29,7 @@ EXPORTS = [
     "neb_configure_mlp", "neb_get_mlp_status", "neb_get_mlp_weights", "neb_set_mlp_model", "neb_get_mlp_gates", "neb_mlp_create", "neb_mlp_set_normalization",
     "neb_mlp_infer", "neb_mlp_gradient", "neb_mlp_train_step", "neb_mlp_get_params", "neb_mlp_destroy",
     "neb_octree_create", "neb_octree_set_iteration", "neb_octree_increment", "neb_octree_density",
-    "neb_octree_clear_counters", "neb_octree_export", "neb_octree_destroy", "neb_atomic_probe",
+    "neb_octree_clear_counters", "neb_octree_export", "neb_octree_destroy", "neb_atomic_probe", "neb_gather_probe",
 ]
 
 
@@ -157,6 +157,7 @@ def lib():
             "neb_octree_export": ([_P, _P, i32, _P, _P], i32),
             "neb_octree_destroy": ([_P], None),
             "neb_atomic_probe": ([_P, i32, i32, i32, i32, i32, _P, _P], i32),
+            "neb_gather_probe": ([_P, ctypes.c_int64, i32, i32, i32, _P, _P], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -443,6 +444,14 @@ def atomic_probe(words, n_words, stride, blocks, ops, kind, sink, stream=None):
     and `sink` (>= blocks * 256)."""
     assert words.numel() >= n_words * stride and sink.numel() >= blocks * 256
     _check(lib().neb_atomic_probe(_dev_ptr(words), int(n_words), int(stride), int(blocks), int(ops), int(kind),
+                                  _dev_ptr(sink), _stream(stream)))
+
+
+def gather_probe(buf, width, blocks, ops, sink, stream=None):
+    """neb_gather_probe on a float32 device tensor `buf` (its size in 16-byte
+    words is n_words) and `sink` (>= blocks * 256 floats)."""
+    assert buf.numel() % 4 == 0 and sink.numel() >= blocks * 256
+    _check(lib().neb_gather_probe(_dev_ptr(buf), int(buf.numel() // 4), int(width), int(blocks), int(ops),
                                   _dev_ptr(sink), _stream(stream)))
 
 
