@@ -156,6 +156,8 @@ def cpu_baseline(target_s=11.0):
     return {"value": paths / dt, "unit": "camera paths/s", "cores": cores, "kind": "oracle", "host_cpu": host,
             "sample": f"{side}x{side} pixel window at the centre of the 512x512 room, 1 iteration, full NEB "
                       f"(photons {int(r['stats']['photons'])}, merges {int(r['stats']['merges'])}) in {dt:.2f} s",
+            "note": "the oracle's merge search is brute force over the window's view vertices, so its rate per "
+                    "path falls as the window grows: the full image would run slower per path than this sample",
             "photons_per_s": r["stats"]["photons"] / dt}
 
 
