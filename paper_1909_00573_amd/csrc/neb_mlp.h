@@ -41,7 +41,8 @@ struct Mlp {
     double* moments = nullptr;
     uint16_t* acts = nullptr;  // feature-major bf16 activations and deltas of one batch
     float* part = nullptr;     // per-wave partial sums of the small gradients and the loss
-    int32_t max_batch = 0, npad = 0, max_waves = 0;
+    float* wpart = nullptr;    // per-slice partial weight gradients of W1..W3 (summed by a second launch)
+    int32_t max_batch = 0, npad = 0, max_waves = 0, max_slices = 0;
     int64_t step = 0;          // Adam steps taken
 };
 

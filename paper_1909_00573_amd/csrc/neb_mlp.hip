@@ -435,16 +435,22 @@ __global__ void __launch_bounds__(256) k_mlp_train_fb(const uint16_t* __restrict
 // Block (layer, slice) is one wave that reads each row of its slice of the
 // batch once (per 16-sample tile: the layer's delta rows as A fragments,
 // its input rows as B fragments) and accumulates every 16 x 16 tile of
-// dW^T of that layer in registers; the tiles are added to the gradient at
-// the end.  Blocks past the three layers sum the training kernel's
-// per-wave partials, each slice a share of the waves.
-constexpr int kWgSlice = 1024;
+// dW^T of that layer in registers, then stores them as its slice's part
+// (k_mlp_wreduce sums the slices: per-lane atomics of every wave on the
+// 13 312 weights took as long as the products).  Blocks past the three layers sum the
+// training kernel's per-wave partials, each slice a share of the waves.
+constexpr int kWgSlice = 512;
 constexpr int kWgLayers = 3;
 constexpr int kWgReduce = (kPartStride + 63) / 64;
+// a slice's partial weight gradients: W1^T rows 0..79 (the input's two pads
+// included, never read), then W2^T and W3^T, k-major (k * 64 + n)
+constexpr int kWPartW2 = (kMlpEnc + 2) * kMlpWidth;
+constexpr int kWPartW3 = kWPartW2 + kMlpWidth * kMlpWidth;
+constexpr int kWPart = kWPartW3 + kMlpWidth * kMlpWidth;
 
 template <int KB>
 __device__ __forceinline__ void wgrad_layer(const uint16_t* __restrict__ acts, int t_begin, int t_end, int hrow,
-                                            int drow, int woff, int kmax, float* __restrict__ grad) {
+                                            int drow, int kmax, float* __restrict__ wpart) {
     const int lane = threadIdx.x, g = lane >> 4, r = lane & 15;
     constexpr size_t kTile = (size_t)kRowsTile * 16;
     f32x4 acc[4][KB];
@@ -486,21 +492,21 @@ __device__ __forceinline__ void wgrad_layer(const uint16_t* __restrict__ acts, i
 #pragma unroll
             for (int kb = 0; kb < KB; ++kb) acc[nb][kb] = mfma(a[nb], b[kb], acc[nb][kb]);
     }
-    // acc[nb][kb][i] = dW^T[16 nb + 4 g + i][16 kb + r]
+    // acc[nb][kb][i] = dW^T[16 nb + 4 g + i][16 kb + r]: this slice's part,
+    // four consecutive n per store
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) {
         const int k = 16 * kb + r;
         if (k >= kmax) continue;  // the zero pads of the input carry no gradient
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) atomicAdd(grad + woff + k * kMlpWidth + 16 * nb + 4 * g + i, acc[nb][kb][i]);
+            *reinterpret_cast<f32x4*>(wpart + k * kMlpWidth + 16 * nb + 4 * g) = acc[nb][kb];
     }
 }
 
 __global__ void __launch_bounds__(64) k_mlp_wgrad(const uint16_t* __restrict__ acts, int npad,
                                                   float* __restrict__ grad, const float* __restrict__ part,
-                                                  int n_waves, float* loss_sum) {
+                                                  int n_waves, float* loss_sum, float* __restrict__ wpart) {
     const int lane = threadIdx.x;
     const int job = blockIdx.x;
     const int slice = blockIdx.y;
@@ -523,9 +529,35 @@ __global__ void __launch_bounds__(64) k_mlp_wgrad(const uint16_t* __restrict__ a
         return;
     }
     const int t_begin = (slice * kWgSlice) >> 4, t_end = min(npad, (slice + 1) * kWgSlice) >> 4;
-    if (job == 0) wgrad_layer<5>(acts, t_begin, t_end, kRowsX, kRowsD1, kMlpW1, kMlpEnc, grad);
-    else if (job == 1) wgrad_layer<4>(acts, t_begin, t_end, kRowsH1, kRowsD2, kMlpW2, kMlpWidth, grad);
-    else wgrad_layer<4>(acts, t_begin, t_end, kRowsH2, kRowsD3, kMlpW3, kMlpWidth, grad);
+    float* wp = wpart + (size_t)slice * kWPart;
+    if (job == 0) wgrad_layer<5>(acts, t_begin, t_end, kRowsX, kRowsD1, kMlpEnc, wp);
+    else if (job == 1) wgrad_layer<4>(acts, t_begin, t_end, kRowsH1, kRowsD2, kMlpWidth, wp + kWPartW2);
+    else wgrad_layer<4>(acts, t_begin, t_end, kRowsH2, kRowsD3, kMlpWidth, wp + kWPartW3);
+}
+
+// The weight gradients: block (x, y) sums slices kWrGroup y .. + kWrGroup - 1
+// of weights 256 x .. 256 x + 255 (one thread per weight, the slices' rows
+// read coalesced, their loads in flight together) and adds the sum to grad.
+constexpr int kWrGroup = 8;
+__global__ void __launch_bounds__(256) k_mlp_wreduce(const float* __restrict__ wpart, int n_slices,
+                                                     float* __restrict__ grad) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= kWPart) return;
+    int dst;
+    if (j < kWPartW2) {
+        if (j >= kMlpEnc * kMlpWidth) return;  // the pads' rows
+        dst = kMlpW1 + j;
+    } else {
+        dst = (j < kWPartW3 ? kMlpW2 + (j - kWPartW2) : kMlpW3 + (j - kWPartW3));
+    }
+    const int s0 = blockIdx.y * kWrGroup;
+    float v[kWrGroup];
+#pragma unroll
+    for (int u = 0; u < kWrGroup; ++u) v[u] = s0 + u < n_slices ? wpart[(size_t)(s0 + u) * kWPart + j] : 0.f;
+    float sum = 0.f;
+#pragma unroll
+    for (int u = 0; u < kWrGroup; ++u) sum += v[u];
+    atomicAdd(grad + dst, sum);
 }
 
 // One Adam step on the FP32 master parameters; re-packs the bf16 operand
@@ -610,11 +642,13 @@ hipError_t mlp_alloc(Mlp& m, int32_t max_batch) {
     // one partial row per wave of the training kernel at its largest grid
     m.max_waves = 4 * std::max(1, std::min((m.npad / 16 + 15) / 16, 1 << 16));
     if (e == hipSuccess) e = hipMalloc(&m.part, 4 * (size_t)kPartStride * m.max_waves);
+    m.max_slices = (m.npad + kWgSlice - 1) / kWgSlice;
+    if (e == hipSuccess) e = hipMalloc(&m.wpart, 4 * (size_t)kWPart * m.max_slices);
     return e;
 }
 
 void mlp_free(Mlp& m) {
-    void* ps[] = {m.theta, m.m, m.v, m.grad, m.blob, m.norm, m.loss, m.moments, m.acts, m.part};
+    void* ps[] = {m.theta, m.m, m.v, m.grad, m.blob, m.norm, m.loss, m.moments, m.acts, m.part, m.wpart};
     for (void* p : ps)
         if (p) (void)hipFree(p);
     m = Mlp();
@@ -697,8 +731,12 @@ hipError_t mlp_gradient(Mlp& m, const float* pos, int pos_stride, const float* n
     if (n_waves > m.max_waves) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_mlp_train_fb, dim3(blocks), dim3(256), 0, s, (const uint16_t*)m.blob, (const float*)m.theta,
                        (const MlpNorm*)m.norm, B, m.acts, npad, m.part);
-    hipLaunchKernelGGL(k_mlp_wgrad, dim3(kWgLayers + kWgReduce, (npad + kWgSlice - 1) / kWgSlice), dim3(64), 0, s,
-                       (const uint16_t*)m.acts, npad, m.grad, (const float*)m.part, n_waves, m.loss);
+    const int slices = (npad + kWgSlice - 1) / kWgSlice;
+    if (slices > m.max_slices) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3(kWgLayers + kWgReduce, slices), dim3(64), 0, s, (const uint16_t*)m.acts,
+                       npad, m.grad, (const float*)m.part, n_waves, m.loss, m.wpart);
+    hipLaunchKernelGGL(k_mlp_wreduce, dim3((kWPart + 255) / 256, (slices + kWrGroup - 1) / kWrGroup), dim3(256), 0, s,
+                       (const float*)m.wpart, slices, m.grad);
     return hipGetLastError();
 }
 
