@@ -463,79 +463,12 @@ __device__ __forceinline__ bool box_hit(const RayPre& r, float lx, float ly, flo
     return tnear <= tfar * 1.00000024f;
 }
 
-// closest hit; ties on t go to the lowest primitive id.  stack: this lane's
-// kStack LDS slots, stride kTraceBlock (the BVH must be shallower than
-// kStack).  any_hit: stop at the first hit below tmax.
-template <bool kAnyHit, int kStack>
-__device__ __forceinline__ int trace(const SceneView& S, int root, f3 o, f3 d, float tmax, float& t_out, int* stack,
-                                     unsigned& nodes, unsigned& tris) {
-    RayPre r = ray_pre(o, d);
-    float best = tmax;
-    int prim = -1;
-    int node = root, sp = 0;
-    for (;;) {
-        const float4* nd = S.bvh + 4 * node;
-        ++nodes;
-        float4 a = nd[0], b = nd[1], c = nd[2];
-        int4 lk = *reinterpret_cast<const int4*>(nd + 3);
-        float tn0, tn1;
-        bool h0 = box_hit(r, a.x, a.y, a.z, a.w, b.x, b.y, best, tn0);
-        bool h1 = box_hit(r, b.z, b.w, c.x, c.y, c.z, c.w, best, tn1);
-        // leaves are tested in place
-        if (h0 && lk.z > 0) {
-            tris += lk.z;
-            for (int k = lk.x; k < lk.x + lk.z; ++k) {
-                const float4* tp = S.tri + 3 * k;
-                float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
-                float t = tri_hit(r, xyz(p0), xyz(p1), xyz(p2), kAnyHit ? best : best * 1.0000001f);
-                int id = __float_as_int(p0.w);
-                if (t > 0.f && (t < best || (t == best && id < prim))) {
-                    best = t;
-                    prim = id;
-                    if (kAnyHit) { t_out = t; return prim; }
-                }
-            }
-            h0 = false;
-        }
-        if (h1 && lk.w > 0) {
-            tris += lk.w;
-            for (int k = lk.y; k < lk.y + lk.w; ++k) {
-                const float4* tp = S.tri + 3 * k;
-                float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
-                float t = tri_hit(r, xyz(p0), xyz(p1), xyz(p2), kAnyHit ? best : best * 1.0000001f);
-                int id = __float_as_int(p0.w);
-                if (t > 0.f && (t < best || (t == best && id < prim))) {
-                    best = t;
-                    prim = id;
-                    if (kAnyHit) { t_out = t; return prim; }
-                }
-            }
-            h1 = false;
-        }
-        h0 = h0 && lk.x >= 0 && tn0 < best;
-        h1 = h1 && lk.y >= 0 && tn1 < best;
-        if (h0 && h1) {
-            int nearc = tn0 <= tn1 ? lk.x : lk.y;
-            int farc = tn0 <= tn1 ? lk.y : lk.x;
-            if (sp < kStack) stack[(sp++) * kTraceBlock] = farc;
-            node = nearc;
-        } else if (h0) {
-            node = lk.x;
-        } else if (h1) {
-            node = lk.y;
-        } else {
-            if (sp == 0) break;
-            node = stack[(--sp) * kTraceBlock];
-        }
-    }
-    t_out = best;
-    return prim;
-}
-
-// Resumable closest-hit traversal (same steps and tie rule as trace): the
-// state of one ray, advanced by up to max_steps node visits per call, so a
-// lane whose ray ends can take a new one while the rest of its wave is
-// still traversing.
+// Resumable closest-hit traversal: the state of one ray, advanced by up to
+// max_steps node visits per call, so a lane whose ray ends can take a new
+// one while the rest of its wave is still traversing.  Ties on t go to the
+// lowest primitive id; the stack is the lane's kStack LDS slots, stride
+// kTraceBlock (the BVH must be shallower than kStack); kAnyHit stops at the
+// first hit below tmax.
 struct TraceState {
     RayPre r;
     float best;
@@ -567,11 +500,23 @@ __device__ __forceinline__ bool trace_steps(const SceneView& S, TraceState& T, i
         float tn0, tn1;
         bool h0 = box_hit(r, a.x, a.y, a.z, a.w, b.x, b.y, T.best, tn0);
         bool h1 = box_hit(r, b.z, b.w, c.x, c.y, c.z, c.w, T.best, tn1);
-        if (h0 && lk.z > 0) {
-            tris += lk.z;
-            for (int k = lk.x; k < lk.x + lk.z; ++k) {
-                const float4* tp = S.tri + 3 * k;
-                float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
+        // the hit leaf children's triangles (child 0's first) in one loop,
+        // each triangle's three words loaded one iteration ahead of its test,
+        // so that a leaf costs one load latency, not one per triangle
+        const int n0 = (h0 && lk.z > 0) ? lk.z : 0, n1 = (h1 && lk.w > 0) ? lk.w : 0;
+        if (n0 + n1 > 0) {
+            const int nt = n0 + n1;
+            tris += nt;
+            const float4* tp = S.tri + 3 * (n0 > 0 ? lk.x : lk.y);
+            float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
+            for (int m = 0; m < nt; ++m) {
+                float4 q0 = p0, q1 = p1, q2 = p2;
+                if (m + 1 < nt) {
+                    const float4* tq = S.tri + 3 * (m + 1 < n0 ? lk.x + m + 1 : lk.y + (m + 1 - n0));
+                    q0 = tq[0];
+                    q1 = tq[1];
+                    q2 = tq[2];
+                }
                 float t = tri_hit(r, xyz(p0), xyz(p1), xyz(p2), kAnyHit ? T.best : T.best * 1.0000001f);
                 int id = __float_as_int(p0.w);
                 if (t > 0.f && (t < T.best || (t == T.best && id < T.prim))) {
@@ -579,23 +524,12 @@ __device__ __forceinline__ bool trace_steps(const SceneView& S, TraceState& T, i
                     T.prim = id;
                     if (kAnyHit) return true;
                 }
+                p0 = q0;
+                p1 = q1;
+                p2 = q2;
             }
-            h0 = false;
-        }
-        if (h1 && lk.w > 0) {
-            tris += lk.w;
-            for (int k = lk.y; k < lk.y + lk.w; ++k) {
-                const float4* tp = S.tri + 3 * k;
-                float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
-                float t = tri_hit(r, xyz(p0), xyz(p1), xyz(p2), kAnyHit ? T.best : T.best * 1.0000001f);
-                int id = __float_as_int(p0.w);
-                if (t > 0.f && (t < T.best || (t == T.best && id < T.prim))) {
-                    T.best = t;
-                    T.prim = id;
-                    if (kAnyHit) return true;
-                }
-            }
-            h1 = false;
+            if (n0) h0 = false;
+            if (n1) h1 = false;
         }
         h0 = h0 && lk.x >= 0 && tn0 < T.best;
         h1 = h1 && lk.y >= 0 && tn1 < T.best;
