@@ -93,6 +93,7 @@ struct SceneView {
     const neb_material* mats;
     const float4* lights;      // 5 float4 per light
     const float* light_cdf;    // per scene: inclusive cumulative selection probabilities
+    const int32_t* light_guide; // per scene, same layout: where pick_light starts its search
 };
 
 // device counters of one context

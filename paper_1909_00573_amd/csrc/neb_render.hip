@@ -710,16 +710,18 @@ struct LightSample {
 };
 
 // lights of one scene: [base, base + count) of the light pool, selected by
-// the scene's cumulative power table (the first entry whose cdf exceeds u)
+// the scene's cumulative power table: the first entry whose cdf exceeds u.
+// The search starts at the guide entry of u's bucket floor(u count), the
+// first light that the smallest uniform of the bucket can pick (so never
+// past the answer), and steps forward: one or two table reads instead of a
+// binary search's chain of dependent ones.  The bucket is taken from u's
+// 24-bit grid value in integers, exactly.
 __device__ __forceinline__ int pick_light(const SceneView& S, int base, int count, float u) {
-    int lo = 0, hi = count - 1;
+    const uint32_t m = (uint32_t)(u * 16777216.0f);
+    int i = S.light_guide[base + (int)(((uint64_t)m * (uint32_t)count) >> 24)];
     const float* cdf = S.light_cdf + base;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (u < cdf[mid]) hi = mid;
-        else lo = mid + 1;
-    }
-    return base + lo;
+    while (i < count - 1 && !(u < cdf[i])) ++i;
+    return base + i;
 }
 
 // Light pool entry (5 float4): l0 (p0 or position, selection probability),
@@ -2567,6 +2569,7 @@ static neb_status prepare(neb_ctx c) {
         return fail(NEB_ERR_CAPACITY, "geometry pools over 2^31 entries");
     std::vector<float> nodes(16 * (size_t)n_nodes), tri(12 * (size_t)n_tris), prim_n(4 * (size_t)n_tris),
         lights(20 * (size_t)n_lights), cdf((size_t)n_lights);
+    std::vector<int32_t> guide((size_t)n_lights);
     std::vector<int32_t> prim_light((size_t)n_tris);
     std::vector<neb_material> mats((size_t)n_mats);
     int64_t nb = 0, tb = 0, mb = 0, lb = 0;
@@ -2605,6 +2608,18 @@ static neb_status prepare(neb_ctx c) {
         std::copy(H.mats.begin(), H.mats.end(), mats.begin() + mb);
         std::copy(H.lights.begin(), H.lights.end(), lights.begin() + 20 * lb);
         std::copy(H.cdf.begin(), H.cdf.end(), cdf.begin() + lb);
+        {
+            // guide entry k: the first light whose cumulative value (c / 2^24,
+            // c an integer: the table lies on the uniforms' grid) exceeds the
+            // smallest uniform m_min / 2^24 of bucket k, m_min = ceil(k 2^24 / n)
+            const int n = (int)H.cdf.size();
+            int i = 0;
+            for (int k = 0; k < n; ++k) {
+                const uint64_t m_min = (((uint64_t)k << 24) + (uint64_t)n - 1) / (uint64_t)n;
+                while (i < n - 1 && (uint64_t)std::llround((double)H.cdf[i] * 16777216.0) <= m_min) ++i;
+                guide[lb + k] = i;
+            }
+        }
         SceneInfo& I = c->sc_host[s];
         std::memset(&I, 0, sizeof(I));
         I.cam = H.cam;
@@ -2642,6 +2657,7 @@ static neb_status prepare(neb_ctx c) {
     float4 *d_nodes = nullptr, *d_tri = nullptr, *d_pn = nullptr, *d_lights = nullptr;
     int32_t* d_pl = nullptr;
     float* d_cdf = nullptr;
+    int32_t* d_guide = nullptr;
     neb_material* d_mats = nullptr;
     hipError_t e = dalloc(c->scene_allocs, &d_nodes, 4 * (size_t)n_nodes);
     if (e == hipSuccess) e = dalloc(c->scene_allocs, &d_tri, 3 * (size_t)n_tris);
@@ -2650,6 +2666,7 @@ static neb_status prepare(neb_ctx c) {
     if (e == hipSuccess) e = dalloc(c->scene_allocs, &d_mats, (size_t)n_mats);
     if (e == hipSuccess) e = dalloc(c->scene_allocs, &d_lights, 5 * (size_t)n_lights);
     if (e == hipSuccess) e = dalloc(c->scene_allocs, &d_cdf, (size_t)n_lights);
+    if (e == hipSuccess) e = dalloc(c->scene_allocs, &d_guide, (size_t)n_lights);
     if (e != hipSuccess) return oom_or_device(e, "scene upload");
     HIP_TRY(hipMemcpy(d_nodes, nodes.data(), nodes.size() * 4, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(d_tri, tri.data(), tri.size() * 4, hipMemcpyHostToDevice));
@@ -2658,6 +2675,7 @@ static neb_status prepare(neb_ctx c) {
     HIP_TRY(hipMemcpy(d_mats, mats.data(), mats.size() * sizeof(neb_material), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(d_lights, lights.data(), lights.size() * 4, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(d_cdf, cdf.data(), cdf.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(d_guide, guide.data(), guide.size() * 4, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->sc_dev, c->sc_host.data(), sizeof(SceneInfo) * c->sc_host.size(), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->oct_prm_dev, c->oct_prm.data(), sizeof(OctParams) * c->oct_prm.size(), hipMemcpyHostToDevice));
     c->view.bvh = d_nodes;
@@ -2667,6 +2685,7 @@ static neb_status prepare(neb_ctx c) {
     c->view.mats = d_mats;
     c->view.lights = d_lights;
     c->view.light_cdf = d_cdf;
+    c->view.light_guide = d_guide;
     c->forest_depth = depth;
     // the shallowest stack that holds the deepest tree
     if (c->cfg.stack <= depth) c->cfg.stack = depth < 32 ? 32 : (depth < 48 ? 48 : 64);
