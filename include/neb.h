@@ -100,7 +100,7 @@ typedef struct {
 
 /* Launch shapes of the traversal and photon kernels (neb_autotune picks
  * them; results do not depend on them).  Defaults: the shallowest stack
- * that holds every BVH, 16 resident closest-hit and 16 NEE blocks per CU
+ * that holds every BVH, 10 resident closest-hit and 16 NEE blocks per CU
  * (at most as many as the LDS holds for the stack), 24 photon-merge blocks
  * per CU, queue order, concurrent. */
 typedef struct {
@@ -252,9 +252,14 @@ neb_status neb_render(neb_ctx ctx, int32_t n_iterations, void* stream);
 neb_status neb_use_graph(neb_ctx ctx, int32_t enable);
 
 /* Times trial_iterations (1..64) real iterations of the context for each
- * candidate launch shape (traversal stack depth and blocks per CU, then the
- * photon-merge grid), keeps the fastest, writes it to *chosen (may be NULL)
- * and resets the context as neb_reset does.  Synchronises `stream`. */
+ * candidate launch shape — traversal stack depth and closest-hit blocks per
+ * CU, then NEE blocks per CU, then the photon stage (order and merge grid),
+ * each by the time of its own kernels; then the photon order and the
+ * closest-hit and merge blocks per CU once more by the time of whole
+ * iterations with the launches as they run (beside each other, the shape
+ * fastest alone is not the iteration's) — keeps the fastest, writes it to
+ * *chosen (may be NULL) and resets the context as neb_reset does.
+ * Synchronises `stream`. */
 neb_status neb_autotune(neb_ctx ctx, int32_t trial_iterations, void* stream, neb_launch_config* chosen);
 
 /* Sets or reads the launch shapes (NEB_ERR_INVALID_ARG out of range,

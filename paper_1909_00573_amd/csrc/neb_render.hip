@@ -1851,7 +1851,7 @@ struct HostScene {
 // stack is raised to the shallowest that holds the deepest tree)
 struct LaunchCfg {
     int stack = 32;        // LDS traversal stack entries per lane: 32, 48 or 64
-    int trace_bpc = 16;    // closest-hit blocks (one wave each) per CU; 0 = one block per 64 queue slots,
+    int trace_bpc = 10;    // closest-hit blocks (one wave each) per CU; 0 = one block per 64 queue slots,
                            // -1 = as many as the LDS holds (clamped to that for deeper stacks)
     int nee_bpc = 16;      // NEE (shadow-ray) blocks per CU, same conventions
     int photon_bpc = 24;   // photon-merge blocks (one wave each) per CU; 0 = one block per 256 queue slots
@@ -3596,11 +3596,37 @@ static neb_status time_config(neb_ctx c, const neb_launch_config& cfg, int n, co
     return NEB_OK;
 }
 
+// whole iterations with the launches as they run (no event pairs around
+// each launch): the span of `n` iterations on s
+static neb_status time_iterations(neb_ctx c, const neb_launch_config& cfg, int n, hipStream_t s, double& ms) {
+    neb_status st = apply_config(c, cfg);
+    if (st != NEB_OK) return st;
+    hipEvent_t a = nullptr, b = nullptr;
+    HIP_TRY(hipEventCreate(&a));
+    hipError_t e = hipEventCreate(&b);
+    if (e == hipSuccess) e = hipEventRecord(a, s);
+    if (e == hipSuccess) st = render_n(c, n, s);
+    if (e == hipSuccess && st == NEB_OK) e = hipEventRecord(b, s);
+    if (e == hipSuccess && st == NEB_OK) e = hipEventSynchronize(b);
+    float t = 0.f;
+    if (e == hipSuccess && st == NEB_OK) e = hipEventElapsedTime(&t, a, b);
+    (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    if (st != NEB_OK) return st;
+    if (e != hipSuccess) return fail(NEB_ERR_DEVICE, std::string("autotune timing: ") + hipGetErrorString(e));
+    ms = t;
+    return NEB_OK;
+}
+
 // Picks the launch shapes by timing real iterations of this context:
 // first the traversal stack depth and resident closest-hit blocks per CU,
 // then the NEE (shadow-ray) blocks per CU, then the photon stage (order
-// and merge grid).  The context is reset afterwards (images, statistics,
-// octrees, iteration counter).
+// and merge grid), each by the time of its own kernels; then the photon
+// order and the closest-hit and merge blocks per CU once more by the time
+// of whole iterations with the launches as they run, since beside each
+// other the shape that is fastest alone is not the iteration's (fewer
+// closest-hit blocks leave the merges more of the chip).  The context is reset
+// afterwards (images, statistics, octrees, iteration counter).
 extern "C" neb_status neb_autotune(neb_ctx c, int32_t trial_iterations, void* stream, neb_launch_config* chosen) {
     if (!c) return fail(NEB_ERR_INVALID_ARG, "null context");
     if (trial_iterations < 1 || trial_iterations > 64) return fail(NEB_ERR_INVALID_ARG, "trial_iterations out of range (1..64)");
@@ -3667,6 +3693,30 @@ extern "C" neb_status neb_autotune(neb_ctx c, int32_t trial_iterations, void* st
         }
     }
     prof_clear(c);
+    c->prof_on = false;
+    if (st == NEB_OK) {
+        const neb_launch_config base = best;
+        const int maxb = lds_blocks_per_cu(base.bvh_stack);
+        best_ms = 1e300;
+        for (int order : {base.photon_order, 1 - base.photon_order})
+            for (int tb : {base.trace_blocks_per_cu, 8, 10, 12, 16}) {
+                for (int pb : {base.photon_blocks_per_cu, 16, 24, 32}) {
+                    if (st != NEB_OK) break;
+                    if (tb > maxb) continue;
+                    neb_launch_config cfg = base;
+                    cfg.photon_order = order;
+                    cfg.trace_blocks_per_cu = tb;
+                    cfg.photon_blocks_per_cu = pb;
+                    double ms = 0.0;
+                    st = time_iterations(c, cfg, trial_iterations, s, ms);
+                    if (st != NEB_OK) break;
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best = cfg;
+                    }
+                }
+            }
+    }
     c->prof_on = was_on;
     if (st != NEB_OK) {
         c->cfg = keep;
