@@ -11,8 +11,9 @@ The 16 steps after the warm-up reproduce the workload's 16 spp.
 Launch shapes are the library's defaults (tuned for this workload), or
 tuned afresh with --autotune (they change the speed, not the result).  The
 timed iterations are launched from the host, each forking the next one's
-camera pass onto a third stream (--graph replays the captured iteration
-instead, which runs these branches less concurrently); the per-kernel
+camera pass onto a third stream (--graph 1 replays the captured
+iteration, --graph 2 launches the whole timed call as one captured graph;
+HIP's graph replay runs these branches less concurrently); the per-kernel
 passes launch eagerly too (their events need it).
 
 Prints one JSON line with camera paths/s (value), photons/s, the roofline
@@ -366,8 +367,8 @@ def tiny_box_run(stream, reps=50):
     sc = tiny_box()
     R = neb.Renderer(sc)
     secs = {}
-    for graph in (False, True):
-        # (the graph variant's first render captures its iterations, untimed)
+    for graph in (0, 1, 2):
+        # (a graph variant's first render captures its graphs, untimed)
         R.use_graph(graph)
         R.reset()
         R.render(sc.spp, stream=stream)
@@ -381,7 +382,7 @@ def tiny_box_run(stream, reps=50):
         b.record(stream)
         torch.cuda.synchronize()
         secs[graph] = a.elapsed_time(b) / 1e3
-    sec = secs[False]
+    sec = secs[0]
     st = R.stats()
     R.close()
     paths = sc.width * sc.height * sc.spp * reps
@@ -390,10 +391,13 @@ def tiny_box_run(stream, reps=50):
                         (sc.n_tris, sc.width, sc.height, sc.spp, sc.max_path_len, sc.octree_capacity),
             "renders": reps, "ms_per_render": round(1e3 * sec / reps, 3),
             "camera_paths_per_s": round(paths / sec, 1),
-            # launch-bound: replaying the captured iterations instead of
-            # launching their kernels one by one
-            "ms_per_render_graph": round(1e3 * secs[True] / reps, 3),
-            "graph_speedup": round(secs[False] / secs[True], 3),
+            # launch-bound: replaying the captured iterations (graph) or the
+            # captured render call (call_graph) instead of launching their
+            # kernels one by one
+            "ms_per_render_graph": round(1e3 * secs[1] / reps, 3),
+            "graph_speedup": round(secs[0] / secs[1], 3),
+            "ms_per_render_call_graph": round(1e3 * secs[2] / reps, 3),
+            "call_graph_speedup": round(secs[0] / secs[2], 3),
             # the statistics restart at each reset: st holds the last render's work
             "photons_per_s": round(st["photons"] * reps / sec, 1),
             "work_per_render": {k: st[k] for k in ("vertices", "photons", "photon_segments", "merges")},
@@ -416,6 +420,9 @@ def city_block_run(stream, graph, steps=8, warmup=2):
     setup = time.perf_counter() - t0
     R.use_graph(graph)  # with graphs the warm-up captures the iteration
     R.render(warmup, stream=stream)
+    if graph == 2:  # the timed call's own graph, captured untimed
+        R.reset()
+        R.render(steps, stream=stream)
     torch.cuda.synchronize()
     R.reset()
     s0 = R.stats()
@@ -476,13 +483,20 @@ def batch_comparison(stream, cfg_trials=1):
     t_batch = timed(lambda: B.render(n_iter, stream=stream))
     st = B.stats()
     # the same as graph replays of the captured iterations (captured by a
-    # first untimed render); the iterations' kernels are long, so launching
-    # them is not what limits a graph here
-    B.use_graph(True)
+    # first untimed render), and as one launch of a graph holding the whole
+    # call (captured by an untimed call of the same length); the
+    # iterations' kernels are long, so launching them is not what limits a
+    # graph here
+    B.use_graph(1)
     B.reset()
     B.render(2, stream=stream)
     B.reset()
     t_graph = timed(lambda: B.render(n_iter, stream=stream))
+    B.use_graph(2)
+    B.reset()
+    B.render(n_iter, stream=stream)
+    B.reset()
+    t_call = timed(lambda: B.render(n_iter, stream=stream))
     B.close()
     del B
     # the same scenes one after another (contexts built beforehand, not timed)
@@ -498,9 +512,11 @@ def batch_comparison(stream, cfg_trials=1):
     return {"scenes": len(scenes), "triangles": int(sum(s.n_tris for s in scenes)),
             "pixels": int(sum(s.width * s.height for s in scenes)), "camera_paths": int(paths),
             "photons": int(st["photons"]), "launch_config": cfg,
-            "batched_s": round(t_batch, 4), "batched_graph_s": round(t_graph, 4), "sequential_s": round(t_seq, 4),
+            "batched_s": round(t_batch, 4), "batched_graph_s": round(t_graph, 4),
+            "batched_call_graph_s": round(t_call, 4), "sequential_s": round(t_seq, 4),
             "batched_paths_per_s": round(paths / t_batch, 1), "sequential_paths_per_s": round(paths / t_seq, 1),
             "speedup": round(t_seq / t_batch, 3), "speedup_graph": round(t_seq / t_graph, 3),
+            "speedup_call_graph": round(t_seq / t_call, 3),
             "host_setup_s": {"generate": round(t_gen, 1), "bvh_and_pools": round(t_build, 1)}}
 
 
@@ -660,8 +676,9 @@ def main():
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned density's matrix-core roofline")
     ap.add_argument("--no-octree-extra", action="store_true",
                     help="skip the atomic-throughput probe and the octree capacity comparison")
-    ap.add_argument("--graph", action="store_true",
-                    help="replay the captured iteration as a HIP graph (default: launch from the host)")
+    ap.add_argument("--graph", type=int, nargs="?", const=1, default=0, choices=(0, 1, 2),
+                    help="1: replay the captured iteration as a HIP graph, 2: the whole timed call as one graph "
+                         "(default 0: launch from the host)")
     ap.add_argument("--no-serialized", action="store_true",
                     help="skip the per-kernel pass with every launch on one stream")
     ap.add_argument("--autotune", action="store_true",
@@ -704,6 +721,11 @@ def main():
     # warm-up on a throw-away progression (it captures the graph), then start
     # the 16-spp render afresh
     R.render(args.warmup, stream=stream)
+    if args.graph == 2:
+        # a whole-call graph is captured per iteration count: capture the
+        # timed call's, untimed
+        R.reset()
+        R.render(args.steps, stream=stream)
     torch.cuda.synchronize()
     R.reset()
     s0 = R.stats()
@@ -759,7 +781,7 @@ def main():
                            "bvh_nodes_photon", "bvh_nodes_shadow", "bvh_tris_camera", "bvh_tris_photon",
                            "bvh_tris_shadow")},
         "roofline": roof, "kernels": kernels, "launch_config": launch_cfg,
-        "timed_launches": "graph replay" if args.graph else "eager",
+        "timed_launches": {0: "eager", 1: "graph replay per iteration", 2: "one graph per call"}[args.graph],
         "roofline_serialized": roof_ser, "kernels_serialized": kernels_ser,
     }
     R.close()

@@ -245,11 +245,17 @@ neb_status neb_set_batch_scene(neb_ctx ctx, int32_t scene, const float* vertices
  * Returns after enqueueing; NEB_ERR_STATE unless every scene is set. */
 neb_status neb_render(neb_ctx ctx, int32_t n_iterations, void* stream);
 
-/* enable != 0: neb_render replays one captured iteration (a HIP graph,
- * captured on first use) instead of launching its kernels one by one.
- * The results are those of the eager launches; iterations that record
- * paths or kernel times are always launched eagerly. */
-neb_status neb_use_graph(neb_ctx ctx, int32_t enable);
+/* mode 1: neb_render replays one captured iteration per iteration (a HIP
+ * graph, captured on first use) instead of launching its kernels one by
+ * one; mode 2: each neb_render call is one launch of a graph that holds
+ * the whole call (its iterations, and the camera passes forked beside
+ * them, exactly as the eager launches order them; captured on the first
+ * call with that iteration count, the graphs of the last four counts are
+ * kept); mode 0: eager launches (the default).  The results are those of
+ * the eager launches; calls or iterations that record paths or kernel
+ * times, and the learned density's iterations, are always launched
+ * eagerly.  NEB_ERR_INVALID_ARG for another mode. */
+neb_status neb_use_graph(neb_ctx ctx, int32_t mode);
 
 /* Times trial_iterations (1..64) real iterations of the context for each
  * candidate launch shape — traversal stack depth and closest-hit blocks per

@@ -1314,7 +1314,11 @@ __global__ void __launch_bounds__(256) k_bin_scatter(const int32_t* __restrict__
 // b, b + 8, b + 16, ... run on one XCD (round-robin dispatch), so each XCD
 // takes one contiguous eighth of the ordered photons: neighbouring photons
 // then share that XCD's L2 for their cells and candidates.
-__global__ void __launch_bounds__(64) k_photon(RenderArgs A, PhotonQ in, const int32_t* count_in, const int2* hits,
+// Four waves per SIMD (at most 128 VGPRs): with 10 000 bytes of LDS per
+// block that is also the LDS limit, 16 resident blocks per CU.  Alone the
+// kernel runs as fast with three; beside the closest hits and the camera
+// pass the fourth keeps more of its loads in flight.
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) k_photon(RenderArgs A, PhotonQ in, const int32_t* count_in, const int2* hits,
                                                Grid G, Images img, const int32_t* __restrict__ order) {
     __shared__ int2 queue[128];
     __shared__ float4 tp[64][2];  // per lane's photon: (-d, X), (Phi / (pi r^2), deepest mergeable depth | light bit)
@@ -1934,9 +1938,15 @@ struct neb_ctx_s {
     std::vector<void*> allocs;
     LaunchCfg cfg;
     // captured iterations, by (parity, camera pass inline, next camera pass forked)
-    bool use_graph = false;
+    int use_graph = 0;  // 1: one graph per iteration, 2: one graph per call
     hipGraph_t graph[8]{};
     hipGraphExec_t gexec[8]{};
+    // captured calls (use_graph 2), by their iteration count
+    static constexpr int kCallGraphs = 4;
+    int32_t call_n[kCallGraphs]{};
+    hipGraph_t call_graph[kCallGraphs]{};
+    hipGraphExec_t call_exec[kCallGraphs]{};
+    int call_next = 0;  // slot the next capture replaces
     hipStream_t cap_stream = nullptr;
     // learned density (NEB_DENSITY_MLP)
     bool mlp_mode = false;
@@ -2083,6 +2093,14 @@ static void drop_graph(neb_ctx c) {
         c->gexec[k] = nullptr;
         c->graph[k] = nullptr;
     }
+    for (int k = 0; k < neb_ctx_s::kCallGraphs; ++k) {
+        if (c->call_exec[k]) (void)hipGraphExecDestroy(c->call_exec[k]);
+        if (c->call_graph[k]) (void)hipGraphDestroy(c->call_graph[k]);
+        c->call_exec[k] = nullptr;
+        c->call_graph[k] = nullptr;
+        c->call_n[k] = 0;
+    }
+    c->call_next = 0;
 }
 
 static void destroy_ctx(neb_ctx c) {
@@ -3100,13 +3118,70 @@ static neb_status capture(neb_ctx c, int parity, bool cam_inline, bool next, int
 // parity's stores and the model's own buffers, so its iterations overlap
 // the same way; they are launched eagerly, since they differ from one
 // another.)
+// The eager sequence of a whole call: iteration k uses parity k & 1 and,
+// but for the last, forks the next iteration's camera pass.
+static neb_status enqueue_call(neb_ctx c, int32_t n_iterations, hipStream_t s) {
+    bool cam_done = false;
+    for (int i = 0; i < n_iterations; ++i) {
+        const bool next = i + 1 < n_iterations && c->cfg.concurrent;
+        neb_status st = enqueue_iteration(c, s, i & 1, !cam_done, next, false);
+        if (st != NEB_OK) return st;
+        cam_done = next;
+    }
+    return NEB_OK;
+}
+
+// the graph of a whole call of n_iterations (captured on first use; the
+// last kCallGraphs counts are kept)
+static neb_status call_graph(neb_ctx c, int32_t n_iterations, hipGraphExec_t* out) {
+    for (int k = 0; k < neb_ctx_s::kCallGraphs; ++k)
+        if (c->call_exec[k] && c->call_n[k] == n_iterations) {
+            *out = c->call_exec[k];
+            return NEB_OK;
+        }
+    if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+    neb_status st = enqueue_call(c, n_iterations, c->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (st != NEB_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        if (st != NEB_OK) return st;
+        return fail(NEB_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(NEB_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    const int k = c->call_next;
+    c->call_next = (k + 1) % neb_ctx_s::kCallGraphs;
+    if (c->call_exec[k]) (void)hipGraphExecDestroy(c->call_exec[k]);
+    if (c->call_graph[k]) (void)hipGraphDestroy(c->call_graph[k]);
+    c->call_graph[k] = g;
+    c->call_exec[k] = x;
+    c->call_n[k] = n_iterations;
+    *out = x;
+    return NEB_OK;
+}
+
 static neb_status render_n(neb_ctx c, int32_t n_iterations, hipStream_t s) {
+    const bool record_pending = c->recs && c->first_iter_recorded == 0;
+    if (c->use_graph == 2 && n_iterations > 0 && !c->prof_on && !record_pending && !c->mlp_mode) {
+        hipGraphExec_t x = nullptr;
+        neb_status st = call_graph(c, n_iterations, &x);
+        if (st != NEB_OK) return st;
+        HIP_TRY(hipGraphLaunch(x, s));
+        c->iter += n_iterations;
+        return NEB_OK;
+    }
     bool cam_done = false;  // this iteration's camera pass ran beside the iteration before
     for (int i = 0; i < n_iterations; ++i) {
         const int parity = i & 1;
         const bool record = c->recs && c->first_iter_recorded == 0 && !cam_done;
         const bool next = i + 1 < n_iterations && c->cfg.concurrent;
-        if (c->use_graph && !c->prof_on && !record && !c->mlp_mode) {
+        if (c->use_graph == 1 && !c->prof_on && !record && !c->mlp_mode) {
             const int key = 4 * parity + 2 * (cam_done ? 0 : 1) + (next ? 1 : 0);
             neb_status st = capture(c, parity, !cam_done, next, key);
             if (st != NEB_OK) return st;
@@ -3536,9 +3611,10 @@ extern "C" neb_status neb_reset(neb_ctx c) {
     return NEB_OK;
 }
 
-extern "C" neb_status neb_use_graph(neb_ctx c, int32_t enable) {
+extern "C" neb_status neb_use_graph(neb_ctx c, int32_t mode) {
     if (!c) return fail(NEB_ERR_INVALID_ARG, "null context");
-    c->use_graph = enable != 0;
+    if (mode < 0 || mode > 2) return fail(NEB_ERR_INVALID_ARG, "graph mode must be 0, 1 or 2");
+    c->use_graph = mode;
     return NEB_OK;
 }
 

@@ -291,8 +291,10 @@ class BatchRenderer:
     def render(self, n_iterations, stream=None):
         _check(lib().neb_render(self.h, int(n_iterations), _stream(stream)))
 
-    def use_graph(self, enable=True):
-        _check(lib().neb_use_graph(self.h, int(enable)))
+    def use_graph(self, mode=1):
+        """0: eager launches, 1 (or True): one graph per iteration, 2: one
+        graph per render call."""
+        _check(lib().neb_use_graph(self.h, int(mode)))
 
     def autotune(self, trial_iterations=2, stream=None):
         cfg = LaunchConfig()

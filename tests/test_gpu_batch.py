@@ -11,8 +11,8 @@ same estimator as alone:
   identical to the one it builds alone;
 - with the concurrent octree, every scene's ledger is conserved;
 - one batched scene matches the FP64 oracle.
-A captured iteration replayed as a HIP graph reproduces the eager
-launches after every replay, and the autotuner's launch shapes change the
+A captured iteration, or a captured call of several iterations, replayed
+as a HIP graph reproduces the eager launches after every replay, and the autotuner's launch shapes change the
 speed, not the results.
 """
 import numpy as np
@@ -148,17 +148,20 @@ def test_batched_scene_matches_oracle(neb, oracle, batch_scenes):
     B.close()
 
 
-def test_graph_replays_match_eager_launches(neb, batch_scenes):
-    """Every replay of the captured iteration is checked against the eager
-    context, with eager device work and synchronisations between replays."""
+@pytest.mark.parametrize("mode,per_call", [(1, 1), (2, 2)])
+def test_graph_replays_match_eager_launches(neb, batch_scenes, mode, per_call):
+    """Every replay of the captured iteration (mode 1) or of the captured
+    two-iteration call (mode 2: the next camera pass forked inside the
+    graph) is checked against the eager context, with eager device work and
+    synchronisations between replays."""
     import torch
     scenes, spp = batch_scenes
     E = neb.BatchRenderer(scenes, flags=neb.FLAG_SINGLE_THREAD_OCTREE, spp=spp)
     G = neb.BatchRenderer(scenes, flags=neb.FLAG_SINGLE_THREAD_OCTREE, spp=spp)
-    G.use_graph(True)
+    G.use_graph(mode)
     for it in range(1, 5):
-        E.render(1)
-        G.render(1)
+        E.render(per_call)
+        G.render(per_call)
         x = torch.randn(1 << 16, device="cuda")
         float(x.square().sum())  # unrelated eager work between replays
         torch.cuda.synchronize()

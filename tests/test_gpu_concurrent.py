@@ -5,7 +5,8 @@ stream.  The two orders of execution must give the same estimator: with
 the deterministic single-thread octree the trees, the work statistics and
 the per-technique images agree up to the order of floating-point
 additions, for plain NEB, with light photons, with NEE recycling and for a
-batch of scenes; eager launches and graph replays agree too.  With the
+batch of scenes; eager launches and graph replays (of one iteration, or
+of a whole call) agree too.  With the
 second stream on, each iteration of a call but the last also runs the next
 iteration's camera pass on a third stream (from the iteration's start, or
 after the deposits when single-thread deposits share their slots with it);
@@ -82,7 +83,7 @@ def test_concurrent_equals_serial_photon_orders(neb, order):
 def test_concurrent_equals_serial_batch_and_graph(neb):
     scenes = [box_room(n_tris=2000, n_lights=3, res=64, seed=5 + k, scene_id=k) for k in range(3)]
     make = lambda: neb.BatchRenderer(scenes, flags=neb.FLAG_SINGLE_THREAD_OCTREE)
-    for graph in (False, True):
+    for graph in (0, 1, 2):
         (ta, sa), (tb, sb) = _pair_batch(neb, make, 3, graph)
         assert sa["merges"] == sb["merges"] and sa["vertices"] == sb["vertices"]
         for s in range(len(scenes)):
@@ -97,8 +98,7 @@ def _pair_batch(neb, make, n_iter, graph):
         cfg = B.launch_config()
         B.set_launch_config(cfg["bvh_stack"], cfg["trace_blocks_per_cu"], cfg["photon_blocks_per_cu"],
                             cfg["photon_order"], cfg["nee_blocks_per_cu"], concurrent=conc)
-        if graph:
-            B.use_graph(True)
+        B.use_graph(graph)
         B.render(n_iter)
         out.append(([B.technique_images_host(s) for s in range(len(B.scenes))], B.stats()))
         B.close()
@@ -119,7 +119,7 @@ def _analytic(neb, conc, graph, calls):
     return out
 
 
-@pytest.mark.parametrize("graph", [False, True])
+@pytest.mark.parametrize("graph", [0, 1, 2])
 def test_next_camera_pass_beside_iteration(neb, graph):
     ta, sa = _analytic(neb, 1, graph, [5])
     tb, sb = _analytic(neb, 0, graph, [5])
