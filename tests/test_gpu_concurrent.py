@@ -162,3 +162,18 @@ def test_concurrent_equals_serial_learned_density(neb):
         assert np.array_equal(ga[k], gb[k]), k
     for t in ("e", "E", "P"):
         assert _close(ta[t], tb[t]), t
+
+
+def test_graph_mode_is_checked(neb):
+    """Graph modes are 0 (eager), 1 (one graph per iteration) and 2 (one
+    graph per call); another mode is refused and leaves the context as it
+    was."""
+    sc = tiny_box(width=16, height=16, max_path_len=3)
+    R = neb.Renderer(sc, density_mode=neb.DENSITY_ANALYTIC, rho0=3000.0, cam_weight=1.0)
+    for bad in (-1, 3):
+        with pytest.raises(neb.NebError):
+            R.use_graph(bad)
+    R.use_graph(2)
+    R.render(2)
+    assert R.stats()["iterations"] == 2
+    R.close()
