@@ -168,10 +168,13 @@ __device__ __forceinline__ int oct_insert_wave(int32_t* nodes, OctState* st, con
         const bool grouped = active && v >= 0;
         bool want = grouped;
         unsigned long long pend = __ballot(want);
-        // phase 1: one CAS per group
+        // phase 1: the lanes at the same word form a group (its first lane
+        // leads) and take m of its free counts; then every leader issues its
+        // group's CAS at once, so the wave waits for one atomic round trip,
+        // not one per group
         int my_leader = lane, my_rank = 0, my_m = 0;
-        int l_ok = 0, l_split = 0;
-        int32_t l_cur = v, l_full = v;
+        int lead_m = 0;  // this lane leads a group taking lead_m counts
+        bool lead_split = false;
         while (pend) {
             int leader = __ffsll((long long)pend) - 1;
             int32_t lidx = __shfl(idx, leader, 64);
@@ -188,16 +191,22 @@ __device__ __forceinline__ int oct_insert_wave(int32_t* nodes, OctState* st, con
                 my_rank = __popcll(gm & below);
                 my_m = m;
             }
-            if (lane == leader && m > 0) {
-                int32_t e = lv;
-                l_ok = __hip_atomic_compare_exchange_strong(nodes + lidx, &e, lv + m, __ATOMIC_RELAXED,
-                                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                l_cur = e;
-                l_full = lv + m;
-                l_split = l_ok && can_split && cnt + m == D.split_count;
+            if (lane == leader) {
+                lead_m = m;
+                lead_split = can_split && cnt + m == D.split_count;
             }
             want = want && !in;
             pend &= ~gm;
+        }
+        int l_ok = 0, l_split = 0;
+        int32_t l_cur = v, l_full = v;
+        if (lead_m > 0) {  // a leader's own idx and v are its group's
+            int32_t e = v;
+            l_ok = __hip_atomic_compare_exchange_strong(nodes + idx, &e, v + lead_m, __ATOMIC_RELAXED,
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            l_cur = e;
+            l_full = v + lead_m;
+            l_split = l_ok && lead_split;
         }
         // phase 2: the pass's splits, one allocation per octree
         int32_t l_after = l_full;
