@@ -274,7 +274,7 @@ __global__ void k_scale_image(const float* a, float* out, int64_t n, float scale
 // are compacted into the queue
 // camera rays of the scenes active in this iteration, queue slots reserved
 // once per block of kCameraBlock threads
-constexpr int kCameraBlock = 1024;
+constexpr int kCameraBlock = 512;
 __global__ void __launch_bounds__(kCameraBlock) k_camera(RenderArgs A, PathQ q) {
     __shared__ int wc[kCameraBlock / 64];
     __shared__ int bb;
@@ -412,12 +412,14 @@ __global__ void __launch_bounds__(kTraceBlock) k_extend(SceneView S, const Scene
 }
 
 // One thread per path.  The three appends (emitter event, NEE vertex,
-// continuing path) are reserved once per block and queue: the four waves'
+// continuing path) are reserved once per block and queue: the eight waves'
 // counts meet in LDS and one thread per queue takes the block's slots with
-// one atomic, sixteen times fewer than one per wave (returning atomics on one
+// one atomic, eight times fewer than one per wave (returning atomics on one
 // counter are serialised).  Every thread runs the same number of rounds so
-// that the block can meet at its barriers.
-constexpr int kShadeBlock = 1024;
+// that the block can meet at its barriers.  Blocks of 512 threads: larger
+// ones wait longer for a CU with room beside the other streams' kernels,
+// smaller ones take more atomics.
+constexpr int kShadeBlock = 512;
 __global__ void __launch_bounds__(kShadeBlock) k_shade(RenderArgs A, PathQ in, const int32_t* count_in,
                                                        const int2* hits, PathQ out, int32_t* count_out,
                                                        VertexStore V, int32_t* n_vertices, float4* ev0, float4* ev1,
@@ -781,12 +783,12 @@ __device__ __forceinline__ LightSample sample_light(const SceneView& S, int base
 
 // NEE (Sec. 3.1) in three launches over the vertices: k_nee_rays draws each
 // vertex's light sample and queues a shadow ray where the sample carries
-// energy (slots reserved once per block of 1024); a closest-hit launch in
+// energy (slots reserved once per block of 512 threads); a closest-hit launch in
 // any-hit mode traces the queue (a lane takes the next ray when its own
 // ends, so vertices without a ray leave no lane idle during traversal);
 // k_nee_finish draws the same sample again (same stream), adds L_E and emits
 // the NEB photon of every visible vertex.
-constexpr int kNeeBlock = 1024;
+constexpr int kNeeBlock = 512;
 __global__ void __launch_bounds__(kNeeBlock) k_nee_rays(RenderArgs A, VertexStore V, const int32_t* n_vertices,
                                                         float4* __restrict__ s0, float4* __restrict__ s1,
                                                         float* __restrict__ stmax, int32_t* n_shadow) {
@@ -1578,7 +1580,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) k_
 // can run beside the next bounce's closest-hit launch.  Slots are reserved
 // once per block; count_copy receives the input count for the merge launch
 // (the closest-hit launch that follows clears the count it read).
-constexpr int kScatterBlock = 1024;
+constexpr int kScatterBlock = 512;
 __global__ void __launch_bounds__(kScatterBlock) k_pscatter(RenderArgs A, PhotonQ in, const int32_t* count_in,
                                                             const int2* __restrict__ hits, PhotonQ out,
                                                             int32_t* count_out, int32_t* count_copy) {
