@@ -690,8 +690,8 @@ def main():
                     help="run a plain 256 MiB device copy first (for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the path would shard by iterations, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: the renderer runs on one GPU; --gpus {args.gpus} is not supported (several GPUs "
+              "would each render their own iterations or scenes in a context of their own)", file=sys.stderr)
         sys.exit(2)
 
     import torch

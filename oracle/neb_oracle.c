@@ -41,7 +41,7 @@
  *     the plain definition: the area of the convex polygon obtained by
  *     clipping the plane with the box (the GPU uses eq. (area)).
  *
- * Readings where the paper is silent (each one is listed in the design doc):
+ * Readings where the paper is silent:
  *   - the octree counts NEE (view) vertices; later photon hits are merged
  *     against view vertices, never deposited.
  *   - concurrent-split semantics: a split that cannot allocate marks the
