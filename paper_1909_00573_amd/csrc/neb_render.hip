@@ -2084,7 +2084,9 @@ static int lds_blocks_per_cu(int stack) { return (160 * 1024) / (stack * kTraceB
 // blocks per CU (0: one block per 64 queue slots, -1: as many as the LDS holds)
 static int trace_grid(neb_ctx c, int64_t cap, int bpc) {
     if (bpc < 0 || bpc > lds_blocks_per_cu(c->cfg.stack)) bpc = lds_blocks_per_cu(c->cfg.stack);
-    if (bpc > 0) return std::max(1, c->cus * bpc);
+    // never more blocks than the queue has lanes' worth of rays: a small
+    // queue would leave most blocks without work
+    if (bpc > 0) return std::max(1, (int)std::min<int64_t>((int64_t)c->cus * bpc, (cap + kTraceBlock - 1) / kTraceBlock));
     return grid_of(cap, kTraceBlock, 1 << 20);
 }
 
