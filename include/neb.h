@@ -107,7 +107,8 @@ typedef struct {
     int32_t bvh_stack;            /* LDS traversal stack entries per lane: 32, 48 or 64; must
                                      exceed the depth of every scene's BVH */
     int32_t trace_blocks_per_cu;  /* resident closest-hit blocks (one wave each) per compute unit;
-                                     0 = one block per 64 queue slots, -1 = as many as the LDS holds */
+                                     0 = one block per 64 queue slots, -1 = as many as the LDS holds;
+                                     a launch never has more blocks than one per 64 queue slots */
     int32_t nee_blocks_per_cu;    /* resident NEE (shadow-ray) blocks per compute unit, same
                                      conventions */
     int32_t photon_blocks_per_cu; /* photon-merge blocks (one wave each) per compute unit, 0..64;
