@@ -504,11 +504,7 @@ __device__ __forceinline__ void wgrad_layer(const uint16_t* __restrict__ acts, i
     }
 }
 
-// At least three waves per SIMD asked of the compiler: it then keeps the
-// accumulators in 112 VGPRs instead of 74 VGPRs and 110 AGPRs (four waves
-// per SIMD instead of two, no spills; the streaming of the activations
-// hides better).
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_mlp_wgrad(const uint16_t* __restrict__ acts, int npad,
+__global__ void __launch_bounds__(64) k_mlp_wgrad(const uint16_t* __restrict__ acts, int npad,
                                                   float* __restrict__ grad, const float* __restrict__ part,
                                                   int n_waves, float* loss_sum, float* __restrict__ wpart) {
     const int lane = threadIdx.x;
