@@ -59,15 +59,15 @@ def algorithmic_bytes(stats, name, npix, vertices):
         rays = s["rays_camera"]
         return rays * (64 + 8) + vertices * 64 + s["continued_camera"] * 64 + s["events"] * 32
     if name == "nee":
-        # light samples and shadow rays, their traversal (64-byte nodes,
-        # 48-byte triangles), contributions and photons
+        # light samples and shadow rays, their traversal (128-byte four-wide
+        # nodes, 48-byte triangles), contributions and photons
         return (vertices * (64 + 4) + s["photons"] * 52 + s["nee_visible"] * 24 +
-                s["bvh_nodes_shadow"] * 64 + s["bvh_tris_shadow"] * 48)
+                s["bvh_nodes_shadow"] * 128 + s["bvh_tris_shadow"] * 48)
     if name in ("extend_camera", "extend_photon"):
-        # ray in, hit out, and the traversal's node and triangle fetches
+        # ray in, hit out, and the traversal's node (128 B) and triangle (48 B) fetches
         kind = "camera" if name == "extend_camera" else "photon"
         rays = s["rays_camera"] if kind == "camera" else s["photon_items"]
-        return rays * (16 + 16 + 8) + s["bvh_nodes_" + kind] * 64 + s["bvh_tris_" + kind] * 48
+        return rays * (16 + 16 + 8) + s["bvh_nodes_" + kind] * 128 + s["bvh_tris_" + kind] * 48
     if name == "density":
         return vertices * (16 + 16 + 4)
     if name == "octree_insert":

@@ -105,7 +105,8 @@ typedef struct {
  * per CU, queue order, concurrent. */
 typedef struct {
     int32_t bvh_stack;            /* LDS traversal stack entries per lane: 32, 48 or 64; must
-                                     exceed the depth of every scene's BVH */
+                                     exceed the entries every scene's BVH needs (a node visit
+                                     pushes all but the nearest of its inner children) */
     int32_t trace_blocks_per_cu;  /* resident closest-hit blocks (one wave each) per compute unit;
                                      0 = one block per 64 queue slots, -1 = as many as the LDS holds;
                                      a launch never has more blocks than one per 64 queue slots */
@@ -270,7 +271,7 @@ neb_status neb_use_graph(neb_ctx ctx, int32_t mode);
 neb_status neb_autotune(neb_ctx ctx, int32_t trial_iterations, void* stream, neb_launch_config* chosen);
 
 /* Sets or reads the launch shapes (NEB_ERR_INVALID_ARG out of range,
- * NEB_ERR_CAPACITY if the stack is not deeper than a scene's BVH). */
+ * NEB_ERR_CAPACITY if the stack is not deeper than a scene's BVH needs). */
 neb_status neb_set_launch_config(neb_ctx ctx, const neb_launch_config* cfg);
 neb_status neb_get_launch_config(neb_ctx ctx, neb_launch_config* cfg);
 

@@ -1,8 +1,8 @@
 // Host BVH builder: binned SAH over triangle centroids (32 bins on each
-// axis, the cheapest split of the three), flattened into
-// 64-byte nodes that hold the boxes of both children (one node fetch tests
-// two boxes).  Subtrees deeper than kSahDepth switch to object-median
-// splits so that the depth stays below the device traversal stack.
+// axis, the cheapest split of the three), collapsed into four-wide
+// 128-byte nodes that hold the boxes of up to four children (one node
+// fetch, one cache line, tests four boxes).  Subtrees deeper than kSahDepth
+// switch to object-median splits so that the traversal stack stays short.
 #include "neb_bvh.h"
 
 #include <algorithm>
@@ -51,7 +51,6 @@ struct Builder {
     std::vector<float> cent;  // 3 per prim
     std::vector<int> idx;
     std::vector<BuildNode> nodes;
-    int max_depth = 0;
 
     int make_leaf(int first, int count, const Box& b) {
         BuildNode n;
@@ -69,7 +68,6 @@ struct Builder {
             b.grow(pbox[idx[i]]);
             cb.grow(&cent[3 * idx[i]]);
         }
-        max_depth = std::max(max_depth, depth);
         if (count <= 1) return make_leaf(first, count, b);
         int axis = 0;
         float ext[3];
@@ -178,28 +176,72 @@ bool build_bvh(const float* vertices, int32_t nv, const int32_t* tris, int32_t n
     }
     B.nodes.reserve(2 * (size_t)nt);
     int root = B.build(0, nt, 0);
-    out.max_depth = B.max_depth + 1;
 
-    // flatten: one device node per internal build node (a leaf root gets a
-    // synthetic parent with an empty second child)
-    std::vector<int> dev_of(B.nodes.size(), -1);
-    std::vector<int> order;
-    std::vector<int> stack;
-    int n_internal = 0;
-    bool leaf_root = B.nodes[root].child[0] < 0;
-    if (!leaf_root) {
-        stack.push_back(root);
-        while (!stack.empty()) {
-            int n = stack.back();
-            stack.pop_back();
-            dev_of[n] = n_internal++;
-            order.push_back(n);
-            for (int c = 1; c >= 0; --c)
-                if (B.nodes[B.nodes[n].child[c]].child[0] >= 0) stack.push_back(B.nodes[n].child[c]);
+    // Collapse to four-wide nodes: a binary inner node gathers its children,
+    // and while it holds fewer than four, the inner one with the largest
+    // surface area is replaced by its two children.  One device node (one
+    // 128-byte line) then tests up to four boxes, about halving the
+    // dependent node fetches of a ray.  A leaf root gets a parent of its own.
+    auto inner = [&](int n) { return B.nodes[n].child[0] >= 0; };
+    auto collapse = [&](int n, int* ch) {
+        int k = 2;
+        ch[0] = B.nodes[n].child[0];
+        ch[1] = B.nodes[n].child[1];
+        while (k < 4) {
+            int pick = -1;
+            float best = -1.0f;
+            for (int i = 0; i < k; ++i)
+                if (inner(ch[i]) && B.nodes[ch[i]].box.area() > best) {
+                    best = B.nodes[ch[i]].box.area();
+                    pick = i;
+                }
+            if (pick < 0) break;
+            const int p = ch[pick];
+            ch[pick] = B.nodes[p].child[0];
+            ch[k++] = B.nodes[p].child[1];
         }
+        return k;
+    };
+    // device order: depth first, a node before its subtrees
+    std::vector<int> order;
+    std::vector<int> kids;  // four per wide node (-1: empty slot)
+    std::vector<int> dev_of(B.nodes.size(), -1);
+    if (inner(root)) {
+        std::vector<int> stack{root};
+        while (!stack.empty()) {
+            const int n = stack.back();
+            stack.pop_back();
+            dev_of[n] = (int)order.size();
+            order.push_back(n);
+            int ch[4] = {-1, -1, -1, -1};
+            collapse(n, ch);
+            kids.insert(kids.end(), ch, ch + 4);
+            for (int c = 3; c >= 0; --c)
+                if (ch[c] >= 0 && inner(ch[c])) stack.push_back(ch[c]);
+        }
+    } else {
+        order.push_back(-1);
+        kids.insert(kids.end(), {root, -1, -1, -1});
     }
-    int n_dev = leaf_root ? 1 : n_internal;
-    out.nodes.assign(16 * (size_t)n_dev, 0.0f);
+    const int n_dev = (int)order.size();
+    // traversal stack entries a ray can need: a visit pushes all but the
+    // nearest of the inner children it enters, so below a node the stack
+    // grows by (inner children - 1) plus the most any inner child needs
+    std::vector<int> need(n_dev, 0);
+    for (int d = n_dev - 1; d >= 0; --d) {
+        int ic = 0, sub = 0;
+        for (int c = 0; c < 4; ++c) {
+            const int ch = kids[4 * (size_t)d + c];
+            if (ch >= 0 && inner(ch)) {
+                ++ic;
+                sub = std::max(sub, need[dev_of[ch]]);
+            }
+        }
+        need[d] = std::max(0, ic - 1) + sub;
+    }
+    out.stack_need = need[0];
+
+    out.nodes.assign(32 * (size_t)n_dev, 0.0f);
     out.tris.assign(12 * (size_t)nt, 0.0f);
     int tri_cursor = 0;
     auto emit_leaf = [&](int bn, int& first, int& count) {
@@ -221,38 +263,28 @@ bool build_bvh(const float* vertices, int32_t nv, const int32_t* tris, int32_t n
             ++tri_cursor;
         }
     };
-    auto write_node = [&](int d, const Box& b0, const Box& b1, int32_t l0, int32_t l1, int32_t c0, int32_t c1) {
-        float* dst = &out.nodes[16 * (size_t)d];
-        float bx[12];
-        put_box(bx, b0);
-        put_box(bx + 6, b1);
-        std::memcpy(dst, bx, sizeof(bx));
-        int32_t lk[4] = {l0, l1, c0, c1};
-        std::memcpy(dst + 12, lk, sizeof(lk));
-    };
-    if (leaf_root) {
-        int first, count;
-        emit_leaf(root, first, count);
-        Box empty;
-        write_node(0, B.nodes[root].box, empty, first, -1, count, 0);
-    } else {
-        for (int n : order) {
-            int32_t link[2], cnt[2];
-            for (int c = 0; c < 2; ++c) {
-                int ch = B.nodes[n].child[c];
-                if (B.nodes[ch].child[0] < 0) {
-                    int first, count;
-                    emit_leaf(ch, first, count);
-                    link[c] = first;
-                    cnt[c] = count;
-                } else {
+    for (int d = 0; d < n_dev; ++d) {
+        float* dst = &out.nodes[32 * (size_t)d];
+        int32_t link[4] = {-1, -1, -1, -1}, cnt[4] = {0, 0, 0, 0};
+        for (int c = 0; c < 4; ++c) {
+            const int ch = kids[4 * (size_t)d + c];
+            Box b;  // an empty slot (link -1) is never entered; its box is zero
+            if (ch >= 0) {
+                b = B.nodes[ch].box;
+                if (inner(ch)) {
                     link[c] = dev_of[ch];
-                    cnt[c] = 0;
+                } else {
+                    emit_leaf(ch, link[c], cnt[c]);
+                    if (cnt[c] == 0) link[c] = -1;
                 }
             }
-            write_node(dev_of[n], B.nodes[B.nodes[n].child[0]].box, B.nodes[B.nodes[n].child[1]].box, link[0],
-                       link[1], cnt[0], cnt[1]);
+            for (int a = 0; a < 3; ++a) {
+                dst[4 * a + c] = link[c] < 0 ? 0.0f : b.lo[a];
+                dst[12 + 4 * a + c] = link[c] < 0 ? 0.0f : b.hi[a];
+            }
         }
+        std::memcpy(dst + 24, link, sizeof(link));
+        std::memcpy(dst + 28, cnt, sizeof(cnt));
     }
     out.n_nodes = n_dev;
     return tri_cursor == nt;

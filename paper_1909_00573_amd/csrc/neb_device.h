@@ -393,7 +393,7 @@ __device__ __forceinline__ float oct_query_robust(const int32_t* __restrict__ no
 }
 
 // ---------------------------------------------------------------------------
-// BVH traversal: two child boxes per 64-byte node, per-lane stack in LDS,
+// BVH traversal: four child boxes per 128-byte node, per-lane stack in LDS,
 // watertight ray-triangle test (Woop, Benthin, Wald, JCGT 2(1), 2013).
 // ---------------------------------------------------------------------------
 struct RayPre {
@@ -467,8 +467,8 @@ __device__ __forceinline__ bool box_hit(const RayPre& r, float lx, float ly, flo
 // max_steps node visits per call, so a lane whose ray ends can take a new
 // one while the rest of its wave is still traversing.  Ties on t go to the
 // lowest primitive id; the stack is the lane's kStack LDS slots, stride
-// kTraceBlock (the BVH must be shallower than kStack); kAnyHit stops at the
-// first hit below tmax.
+// kTraceBlock (the BVH's stack need must be below kStack); kAnyHit stops at
+// the first hit below tmax.
 struct TraceState {
     RayPre r;
     float best;
@@ -488,31 +488,52 @@ __device__ __forceinline__ void trace_begin(TraceState& T, int root, f3 o, f3 d,
 // returns true when the ray is done (T.best, T.prim hold the closest hit
 // below the tmax of trace_begin; kAnyHit: T.prim >= 0 once any hit below
 // tmax is found, which ends the ray)
+// (distance, node) pair of a child still to visit; compare-exchange by distance
+__device__ __forceinline__ void near_first(float& da, int& na, float& db, int& nb) {
+    const bool sw = db < da;
+    const float d = sw ? db : da;
+    const int n = sw ? nb : na;
+    db = sw ? da : db;
+    nb = sw ? na : nb;
+    da = d;
+    na = n;
+}
+
 template <int kStack, bool kAnyHit = false>
 __device__ __forceinline__ bool trace_steps(const SceneView& S, TraceState& T, int* stack, int max_steps,
                                             unsigned& nodes, unsigned& tris) {
     const RayPre& r = T.r;
     for (int step = 0; step < max_steps; ++step) {
-        const float4* nd = S.bvh + 4 * T.node;
+        // one 128-byte node: the four children's boxes coordinate by
+        // coordinate, their links and leaf counts
+        const float4* nd = S.bvh + 8 * T.node;
         ++nodes;
-        float4 a = nd[0], b = nd[1], c = nd[2];
-        int4 lk = *reinterpret_cast<const int4*>(nd + 3);
-        float tn0, tn1;
-        bool h0 = box_hit(r, a.x, a.y, a.z, a.w, b.x, b.y, T.best, tn0);
-        bool h1 = box_hit(r, b.z, b.w, c.x, c.y, c.z, c.w, T.best, tn1);
-        // the hit leaf children's triangles (child 0's first) in one loop,
-        // each triangle's three words loaded one iteration ahead of its test,
-        // so that a leaf costs one load latency, not one per triangle
-        const int n0 = (h0 && lk.z > 0) ? lk.z : 0, n1 = (h1 && lk.w > 0) ? lk.w : 0;
-        if (n0 + n1 > 0) {
-            const int nt = n0 + n1;
+        const float4 lx = nd[0], ly = nd[1], lz = nd[2], hx = nd[3], hy = nd[4], hz = nd[5];
+        const int4 lk = *reinterpret_cast<const int4*>(nd + 6);
+        const int4 ct = *reinterpret_cast<const int4*>(nd + 7);
+        float t0, t1, t2, t3;
+        const bool h0 = box_hit(r, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, T.best, t0) && lk.x >= 0;
+        const bool h1 = box_hit(r, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, T.best, t1) && lk.y >= 0;
+        const bool h2 = box_hit(r, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, T.best, t2) && lk.z >= 0;
+        const bool h3 = box_hit(r, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, T.best, t3) && lk.w >= 0;
+        // the hit leaf children's triangles in one loop, each triangle's
+        // three words loaded one iteration ahead of its test, so that the
+        // leaves of a node cost one load latency, not one per triangle
+        const int n0 = (h0 && ct.x > 0) ? ct.x : 0, n1 = (h1 && ct.y > 0) ? ct.y : 0;
+        const int n2 = (h2 && ct.z > 0) ? ct.z : 0, n3 = (h3 && ct.w > 0) ? ct.w : 0;
+        const int e0 = n0, e1 = e0 + n1, e2 = e1 + n2, nt = e2 + n3;
+        if (nt > 0) {
             tris += nt;
-            const float4* tp = S.tri + 3 * (n0 > 0 ? lk.x : lk.y);
+            // m-th triangle of the hit leaves, slot by slot
+            auto tri_of = [&](int m) {
+                return m < e0 ? lk.x + m : (m < e1 ? lk.y + (m - e0) : (m < e2 ? lk.z + (m - e1) : lk.w + (m - e2)));
+            };
+            const float4* tp = S.tri + 3 * tri_of(0);
             float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
             for (int m = 0; m < nt; ++m) {
                 float4 q0 = p0, q1 = p1, q2 = p2;
                 if (m + 1 < nt) {
-                    const float4* tq = S.tri + 3 * (m + 1 < n0 ? lk.x + m + 1 : lk.y + (m + 1 - n0));
+                    const float4* tq = S.tri + 3 * tri_of(m + 1);
                     q0 = tq[0];
                     q1 = tq[1];
                     q2 = tq[2];
@@ -528,24 +549,30 @@ __device__ __forceinline__ bool trace_steps(const SceneView& S, TraceState& T, i
                 p1 = q1;
                 p2 = q2;
             }
-            if (n0) h0 = false;
-            if (n1) h1 = false;
         }
-        h0 = h0 && lk.x >= 0 && tn0 < T.best;
-        h1 = h1 && lk.y >= 0 && tn1 < T.best;
-        if (h0 && h1) {
-            int nearc = tn0 <= tn1 ? lk.x : lk.y;
-            int farc = tn0 <= tn1 ? lk.y : lk.x;
-            if (T.sp < kStack) stack[(T.sp++) * kTraceBlock] = farc;
-            T.node = nearc;
-        } else if (h0) {
-            T.node = lk.x;
-        } else if (h1) {
-            T.node = lk.y;
-        } else {
+        // inner children still in reach, sorted nearest first (five
+        // compare-exchanges); the nearest is next, the others are pushed
+        // farthest first
+        float d0 = (h0 && ct.x == 0 && t0 < T.best) ? t0 : INFINITY;
+        float d1 = (h1 && ct.y == 0 && t1 < T.best) ? t1 : INFINITY;
+        float d2 = (h2 && ct.z == 0 && t2 < T.best) ? t2 : INFINITY;
+        float d3 = (h3 && ct.w == 0 && t3 < T.best) ? t3 : INFINITY;
+        const int k = (d0 < INFINITY) + (d1 < INFINITY) + (d2 < INFINITY) + (d3 < INFINITY);
+        if (k == 0) {
             if (T.sp == 0) return true;
             T.node = stack[(--T.sp) * kTraceBlock];
+            continue;
         }
+        int c0 = lk.x, c1 = lk.y, c2 = lk.z, c3 = lk.w;
+        near_first(d0, c0, d1, c1);
+        near_first(d2, c2, d3, c3);
+        near_first(d0, c0, d2, c2);
+        near_first(d1, c1, d3, c3);
+        near_first(d1, c1, d2, c2);
+        if (k > 3 && T.sp < kStack) stack[(T.sp++) * kTraceBlock] = c3;
+        if (k > 2 && T.sp < kStack) stack[(T.sp++) * kTraceBlock] = c2;
+        if (k > 1 && T.sp < kStack) stack[(T.sp++) * kTraceBlock] = c1;
+        T.node = c0;
     }
     return false;
 }

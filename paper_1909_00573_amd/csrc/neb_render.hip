@@ -1878,7 +1878,7 @@ struct neb_ctx_s {
     int cus = 256;
     // per-scene device tables and the shared geometry pools
     bool ready = false;  // forest uploaded and octrees initialised since the last scene change
-    int forest_depth = 0;
+    int forest_depth = 0;  // traversal stack entries the forest's deepest descent needs
     SceneInfo* sc_dev = nullptr;
     int32_t* pix_base_dev = nullptr;
     int32_t* lp_base_dev = nullptr;
@@ -2461,7 +2461,7 @@ static neb_status build_host_scene(const neb_params& prm, const float* vertices,
 
     // BVH
     if (!build_bvh(vertices, nv, tris, nt, H.bvh)) return fail(NEB_ERR_INVALID_ARG, "BVH build failed");
-    if (H.bvh.max_depth >= kBvhStackMax) return fail(NEB_ERR_CAPACITY, "BVH deeper than the traversal stack");
+    if (H.bvh.stack_need >= kBvhStackMax) return fail(NEB_ERR_CAPACITY, "BVH needs a deeper traversal stack");
     // per-prim normals and light table (emissive triangles, then point lights)
     H.nt = nt;
     H.prim_n.assign(4 * (size_t)nt, 0.f);
@@ -2584,12 +2584,12 @@ static neb_status prepare(neb_ctx c) {
         n_tris += H.nt;
         n_mats += (int64_t)H.mats.size();
         n_lights += (int64_t)H.cdf.size();
-        depth = std::max(depth, H.bvh.max_depth);
+        depth = std::max(depth, H.bvh.stack_need);
     }
     if (n_mats > kMaxMaterials) return fail(NEB_ERR_CAPACITY, "more than 65536 materials over the batch");
-    if (n_nodes * 4 > (int64_t)INT32_MAX || n_tris * 3 > (int64_t)INT32_MAX || n_lights * 5 > (int64_t)INT32_MAX)
+    if (n_nodes * 8 > (int64_t)INT32_MAX || n_tris * 3 > (int64_t)INT32_MAX || n_lights * 5 > (int64_t)INT32_MAX)
         return fail(NEB_ERR_CAPACITY, "geometry pools over 2^31 entries");
-    std::vector<float> nodes(16 * (size_t)n_nodes), tri(12 * (size_t)n_tris), prim_n(4 * (size_t)n_tris),
+    std::vector<float> nodes(32 * (size_t)n_nodes), tri(12 * (size_t)n_tris), prim_n(4 * (size_t)n_tris),
         lights(20 * (size_t)n_lights), cdf((size_t)n_lights);
     std::vector<int32_t> guide((size_t)n_lights);
     std::vector<int32_t> prim_light((size_t)n_tris);
@@ -2600,16 +2600,17 @@ static neb_status prepare(neb_ctx c) {
         const neb_params& P = c->prm[s];
         // nodes: child links are node indices (inner) or triangle indices (leaves)
         for (int i = 0; i < H.bvh.n_nodes; ++i) {
-            const float* src = &H.bvh.nodes[16 * (size_t)i];
-            float* dst = &nodes[16 * (size_t)(nb + i)];
-            std::memcpy(dst, src, 12 * 4);
-            int32_t lk[4];
-            std::memcpy(lk, src + 12, 16);
-            for (int ch = 0; ch < 2; ++ch) {
-                if (lk[2 + ch] > 0) lk[ch] += (int32_t)tb;
+            const float* src = &H.bvh.nodes[32 * (size_t)i];
+            float* dst = &nodes[32 * (size_t)(nb + i)];
+            std::memcpy(dst, src, 32 * 4);
+            int32_t lk[4], ct[4];
+            std::memcpy(lk, src + 24, 16);
+            std::memcpy(ct, src + 28, 16);
+            for (int ch = 0; ch < 4; ++ch) {
+                if (ct[ch] > 0) lk[ch] += (int32_t)tb;
                 else if (lk[ch] >= 0) lk[ch] += (int32_t)nb;
             }
-            std::memcpy(dst + 12, lk, 16);
+            std::memcpy(dst + 24, lk, 16);
         }
         for (int t = 0; t < H.nt; ++t) {
             const float* src = &H.bvh.tris[12 * (size_t)t];
@@ -2681,7 +2682,7 @@ static neb_status prepare(neb_ctx c) {
     float* d_cdf = nullptr;
     int32_t* d_guide = nullptr;
     neb_material* d_mats = nullptr;
-    hipError_t e = dalloc(c->scene_allocs, &d_nodes, 4 * (size_t)n_nodes);
+    hipError_t e = dalloc(c->scene_allocs, &d_nodes, 8 * (size_t)n_nodes);
     if (e == hipSuccess) e = dalloc(c->scene_allocs, &d_tri, 3 * (size_t)n_tris);
     if (e == hipSuccess) e = dalloc(c->scene_allocs, &d_pn, (size_t)n_tris);
     if (e == hipSuccess) e = dalloc(c->scene_allocs, &d_pl, (size_t)n_tris);
@@ -2709,7 +2710,7 @@ static neb_status prepare(neb_ctx c) {
     c->view.light_cdf = d_cdf;
     c->view.light_guide = d_guide;
     c->forest_depth = depth;
-    // the shallowest stack that holds the deepest tree
+    // the shallowest stack that holds every tree's deepest descent
     if (c->cfg.stack <= depth) c->cfg.stack = depth < 32 ? 32 : (depth < 48 ? 48 : 64);
     neb_status st = restart(c, nullptr);
     if (st != NEB_OK) return st;
@@ -3626,7 +3627,7 @@ static neb_status apply_config(neb_ctx c, const neb_launch_config& cfg) {
     if (cfg.bvh_stack != 32 && cfg.bvh_stack != 48 && cfg.bvh_stack != 64)
         return fail(NEB_ERR_INVALID_ARG, "bvh_stack must be 32, 48 or 64");
     if (c->ready && cfg.bvh_stack <= c->forest_depth)
-        return fail(NEB_ERR_CAPACITY, "bvh_stack must exceed the deepest BVH");
+        return fail(NEB_ERR_CAPACITY, "bvh_stack must exceed the stack entries every BVH needs");
     if (cfg.trace_blocks_per_cu < -1 || cfg.trace_blocks_per_cu > lds_blocks_per_cu(cfg.bvh_stack))
         return fail(NEB_ERR_INVALID_ARG, "trace_blocks_per_cu out of range for this stack");
     if (cfg.nee_blocks_per_cu < -1 || cfg.nee_blocks_per_cu > lds_blocks_per_cu(cfg.bvh_stack))
