@@ -109,20 +109,22 @@ struct SceneInfo {
     int32_t pad4;
 };
 
-// Merge grid keyed by (hash of scene and cell, depth - 1): the records of
-// one cell are ordered by view-vertex depth, so the vertices a photon after
-// j bounces may merge with (depth <= maxlen - 1 - j) form one contiguous
-// prefix.
+// Merge grid keyed by (hash of scene and cell, depth class): the records of
+// one cell are ordered by view-vertex depth class (depth - 1, the last of
+// the D classes also holding every deeper vertex), so the vertices a photon
+// after j bounces may merge with (depth <= maxlen - 1 - j) lie in one
+// contiguous prefix; only the last class's deeper vertices are filtered by
+// the depth each entry carries.
 struct Grid {
     int32_t* count;   // T * D + 1 entries (the last stays 0); zeroed by the scan that reads them
     int32_t* start;   // T * D + 1 entries
     int32_t* rank;    // per view vertex: its place among the vertices of its key
-    float4* sorted;   // (pos, scene) in (cell, depth) order
+    float4* sorted;   // (pos, scene | depth << 24) in (cell, depth class) order
     float4* mrec;     // 4 per record, same order: what a merge needs of the view vertex:
                       // (n, tag), (wo, B), (tau, g), (pixel, -, -, -)
     int32_t* sums;    // scan block sums, all levels
     int32_t T;        // hash buckets (power of two)
-    int32_t D;        // depth classes: longest maxlen - 1, rounded up to a multiple of 8
+    int32_t D;        // depth classes: 8 (a cell's row is one aligned 32-byte sector)
 };
 
 // prefix sums are scanned in tiles of kScanTile elements (a tile per block
@@ -1119,7 +1121,7 @@ __global__ void __launch_bounds__(256) k_nee_recycle(RenderArgs A, VertexStore V
 // start[key] + rank)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int64_t grid_key(const Grid& G, uint32_t h, int depth) {
-    return (int64_t)h * G.D + (depth - 1);
+    return (int64_t)h * G.D + (min(depth, G.D) - 1);
 }
 
 __global__ void __launch_bounds__(256) k_grid_count(const neb_material* mats, const SceneInfo* sc, VertexStore V,
@@ -1145,7 +1147,7 @@ __global__ void __launch_bounds__(256) k_grid_scatter(const neb_material* mats, 
         f3 p = xyz(a0);
         int64_t key = grid_key(G, point_hash(p, sc[s].inv_cell, s, G.T), tag_depth(tg));
         int pos = G.start[key] + G.rank[i];
-        G.sorted[pos] = f4(p, ibits(s));
+        G.sorted[pos] = f4(p, ibits(s | (tag_depth(tg) << 24)));
         float4* m = G.mrec + 4 * (size_t)pos;
         m[0] = a1;
         m[1] = V.v2[i];
@@ -1331,7 +1333,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) k_
     __shared__ int coff[64][8];   // per lane's cell c: first record minus its offset in the lane's list
     __shared__ int cend[64][8];   // per lane's cell c: end of its range in the lane's list
     __shared__ float4 ty[64];     // per lane's photon: hit point, r^2
-    __shared__ int tsid[64];      // per lane's photon: scene
+    __shared__ int tsid[64];      // per lane's photon: scene | deepest mergeable depth << 24
     const int lane = threadIdx.x;
     const unsigned long long below = (1ull << lane) - 1ull;
     const int n = *count_in;
@@ -1470,7 +1472,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) k_
                 if (use) {
                     int64_t key = grid_key(G, hc, 1);
                     e0 = G.start[key];
-                    e1 = G.start[key + kmax];
+                    e1 = G.start[key + min(kmax, G.D)];
                     ++looked;
                 }
                 lo[c] = e0;
@@ -1503,7 +1505,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) k_
             cend[lane][c] = pre[c + 1];
         }
         ty[lane] = f4(y, r2);
-        tsid[lane] = sid;
+        tsid[lane] = sid | (max(kmax, 0) << 24);
         __syncthreads();
         // eight positions per lane per step, their loads independent (measured
         // on the room: 4 and 8 equal, both 22 % faster than one photon's list
@@ -1538,8 +1540,10 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) k_
                 if (ev[u] >= 0) {
                     const float4 yp = ty[pv[u]];
                     f3 dv = xyz(cd[u]) - xyz(yp);
-                    // a bucket may also hold another scene's cell
-                    acc = dot3(dv, dv) < yp.w && fbits(cd[u].w) == tsid[pv[u]];
+                    // a bucket may also hold another scene's cell, and the
+                    // last depth class deeper vertices than the photon may reach
+                    const int w = fbits(cd[u].w), ts = tsid[pv[u]];
+                    acc = dot3(dv, dv) < yp.w && (w & 0xFFFFFF) == (ts & 0xFFFFFF) && (w >> 24) <= (ts >> 24);
                 }
                 unsigned long long m = __ballot(acc);
                 if (m) {
@@ -2292,8 +2296,10 @@ extern "C" neb_status neb_create_batch(const neb_params* params, int32_t n_scene
     }
     if (c->flags & NEB_FLAG_SINGLE_THREAD_OCTREE) ALLOC(c->slots, slot_cap);
     if (c->flags & NEB_FLAG_RECORD_PATHS) ALLOC(c->recs, npix * L);
-    // depth classes padded to 8: a cell's row is one aligned 32-byte sector
-    c->G.D = (std::max(1, L - 1) + 7) & ~7;
+    // eight depth classes whatever the path length: a cell's row is one
+    // aligned 32-byte sector, and the table's size does not grow with the
+    // path length (longer paths share the last class)
+    c->G.D = 8;
     c->G.T = (int32_t)std::max<uint64_t>(1024, std::min<uint64_t>(next_pow2((uint64_t)vcap) / 2, 1u << 23));
     int64_t gkeys = (int64_t)c->G.T * c->G.D + 1;
     ALLOC(c->G.count, gkeys);
