@@ -100,7 +100,7 @@ typedef struct {
 
 /* Launch shapes of the traversal and photon kernels (neb_autotune picks
  * them; results do not depend on them).  Defaults: the shallowest stack
- * that holds every BVH, 10 resident closest-hit and 16 NEE blocks per CU
+ * that holds every BVH, 8 resident closest-hit and 16 NEE blocks per CU
  * (at most as many as the LDS holds for the stack), 24 photon-merge blocks
  * per CU, queue order, concurrent. */
 typedef struct {

@@ -1861,7 +1861,7 @@ struct HostScene {
 // stack is raised to the shallowest that holds the deepest tree)
 struct LaunchCfg {
     int stack = 32;        // LDS traversal stack entries per lane: 32, 48 or 64
-    int trace_bpc = 10;    // closest-hit blocks (one wave each) per CU; 0 = one block per 64 queue slots,
+    int trace_bpc = 8;     // closest-hit blocks (one wave each) per CU; 0 = one block per 64 queue slots,
                            // -1 = as many as the LDS holds (clamped to that for deeper stacks)
     int nee_bpc = 16;      // NEE (shadow-ray) blocks per CU, same conventions
     int photon_bpc = 24;   // photon-merge blocks (one wave each) per CU; 0 = one block per 256 queue slots
