@@ -86,7 +86,7 @@ struct CamParams {
 
 // read-only geometry and light pools shared by every scene of a context
 struct SceneView {
-    const float4* bvh;         // 4 float4 per node (two child boxes + child links), all scenes
+    const float4* bvh;         // 8 float4 per node (four child boxes, child links, leaf counts), all scenes
     const float4* tri;         // 3 float4 per triangle in leaf order; tri[0].w = global prim id bits
     const float4* prim_n;      // per prim: unit geometric normal, .w = global material id bits
     const int32_t* prim_light; // per prim: global light index or -1
