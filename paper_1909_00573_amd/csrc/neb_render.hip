@@ -1507,10 +1507,11 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) k_
         ty[lane] = f4(y, r2);
         tsid[lane] = sid | (max(kmax, 0) << 24);
         __syncthreads();
-        // eight positions per lane per step, their loads independent (measured
-        // on the room: 4 and 8 equal, both 22 % faster than one photon's list
-        // per lane with eight loads in flight)
-        constexpr int kU = 8;
+        // four positions per lane per step, their loads independent (measured
+        // on the room alone: 4 and 8 equal, both 22 % faster than one photon's
+        // list per lane with eight loads in flight; beside the other streams
+        // four is 1 % faster, sixteen 25 % slower)
+        constexpr int kU = 4;
         for (int t = 0; t < wsum; t += 64 * kU) {
             int ev[kU], pv[kU];
             float4 cd[kU];
